@@ -1,0 +1,227 @@
+"""ctypes wrapper of the CPU FP64 oracle (test infrastructure only).
+
+Only the test suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` use this module.  It loads ``liboracle.so`` built from
+``gks_oracle.cpp`` by ``oracle/build.py`` and shares nothing with the HIP path.
+
+Arrays follow the layout [component][z][y][x] (x fastest), components
+(rho, rho U, rho V, rho W, rho E) truncated to D+2.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+
+BC = {"periodic": 0, "transmissive": 1, "reflective": 2}
+TAU = {"inviscid": 0, "viscous": 1, "zero": 2}
+
+
+class OrcParams(C.Structure):
+    _fields_ = [
+        ("ndim", C.c_int), ("n", C.c_int * 3), ("dx", C.c_double * 3),
+        ("bc_lo", C.c_int * 3), ("bc_hi", C.c_int * 3),
+        ("gamma", C.c_double), ("mu", C.c_double), ("prandtl", C.c_double),
+        ("tau_mode", C.c_int), ("c1", C.c_double), ("c2", C.c_double),
+        ("ct1", C.c_double), ("ct2", C.c_double), ("ct1_tan", C.c_double), ("ct2_tan", C.c_double),
+        ("eps", C.c_double), ("q", C.c_int),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from . import build as _b
+            _b.build()
+        L = C.CDLL(LIB_PATH)
+        dp = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+        u8 = np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")
+        P = C.POINTER(OrcParams)
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_beta.argtypes = [dp, dp]
+        L.orc_teno_select.argtypes = [dp, C.c_double, C.c_double, C.c_double, C.c_int]
+        L.orc_teno_face.argtypes = [dp, C.c_double, C.c_double, C.c_double, C.c_int, dp]
+        L.orc_teno_gauss.argtypes = [dp, C.c_double, C.c_double, C.c_double, C.c_int, dp]
+        L.orc_teno_eval.argtypes = [dp, C.c_int, C.c_int, dp]
+        L.orc_moments.argtypes = [C.c_double, C.c_double, C.c_int, dp]
+        L.orc_micro_slope.argtypes = [C.c_int, C.c_double, dp, dp, dp]
+        L.orc_moment_mono.argtypes = [C.c_int, C.c_double, dp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]
+        L.orc_moment_mono.restype = C.c_double
+        L.orc_gp_flux.argtypes = [P, dp, dp, dp, dp, C.c_double, C.c_int, dp, dp, dp, dp]
+        L.orc_flag_bytes.argtypes = [P]
+        L.orc_flag_bytes.restype = C.c_long
+        L.orc_step.argtypes = [P, dp, dp, C.c_double, C.c_void_p, C.c_void_p]
+        L.orc_step.restype = C.c_long
+        L.orc_step_dual.argtypes = [P, dp, dp, dp, dp, C.c_double]
+        L.orc_step_dual.restype = C.c_long
+        L.orc_cfl_dt.argtypes = [P, dp, C.c_double, C.POINTER(C.c_double)]
+        L.orc_run.argtypes = [P, dp, C.c_int, C.c_double, C.c_double, C.c_double,
+                              C.POINTER(C.c_double), C.POINTER(C.c_int)]
+        L.orc_run.restype = C.c_long
+        _ = u8
+        _lib = L
+    return _lib
+
+
+def set_threads(n: int) -> int:
+    return lib().orc_set_threads(int(n))
+
+
+def make_params(shape, dx, bc="transmissive", gamma=1.4, mu=0.0, prandtl=1.0, tau="inviscid",
+                c1=0.01, c2=1.0, ct1=1e-7, ct2=1e-5, ct1_tan=None, ct2_tan=None, eps=1e-40, q=7):
+    """shape: cells per axis (x, y, z) truncated to D; bc: one name or a list of
+    (lo, hi) names per axis."""
+    p = OrcParams()
+    D = len(shape)
+    p.ndim = D
+    for d in range(3):
+        p.n[d] = int(shape[d]) if d < D else 1
+        p.dx[d] = float(dx[d]) if d < D else 1.0
+        if isinstance(bc, str):
+            lo = hi = bc
+        else:
+            lo, hi = bc[d] if d < D else ("transmissive", "transmissive")
+        p.bc_lo[d] = BC[lo]
+        p.bc_hi[d] = BC[hi]
+    p.gamma, p.mu, p.prandtl = gamma, mu, prandtl
+    p.tau_mode = TAU[tau]
+    p.c1, p.c2 = c1, c2
+    p.ct1, p.ct2 = ct1, ct2
+    p.ct1_tan = ct1 if ct1_tan is None else ct1_tan
+    p.ct2_tan = ct2 if ct2_tan is None else ct2_tan
+    p.eps, p.q = eps, q
+    return p
+
+
+def _arr(W):
+    return np.ascontiguousarray(W, dtype=np.float64)
+
+
+def teno_face(Q, ct1=1e-7, ct2=1e-5, eps=1e-40, q=7):
+    out = np.zeros(4)
+    f = lib().orc_teno_face(_arr(Q), ct1, ct2, eps, q, out)
+    return out, f
+
+
+def teno_gauss(Q, ct1=1e-7, ct2=1e-5, eps=1e-40, q=7):
+    out = np.zeros(4)
+    f = lib().orc_teno_gauss(_arr(Q), ct1, ct2, eps, q, out)
+    return out, f
+
+
+def teno_eval(Q, flag, gauss=False):
+    out = np.zeros(4)
+    lib().orc_teno_eval(_arr(Q), int(flag), int(bool(gauss)), out)
+    return out
+
+
+def teno_select(Q, ct1=1e-7, ct2=1e-5, eps=1e-40, q=7):
+    return lib().orc_teno_select(_arr(Q), ct1, ct2, eps, q)
+
+
+def beta(Q):
+    out = np.zeros(4)
+    lib().orc_beta(_arr(Q), out)
+    return out
+
+
+def moments(U, lam, kind):
+    out = np.zeros(10)
+    lib().orc_moments(float(U), float(lam), int(kind), out)
+    return out
+
+
+def micro_slope(D, gamma, W, b):
+    a = np.zeros(5)
+    Wp = np.zeros(5)
+    Wp[: D + 2] = W
+    bp = np.zeros(5)
+    bp[: D + 2] = b
+    lib().orc_micro_slope(D, gamma, Wp, bp, a)
+    return a[: D + 2]
+
+
+def moment_mono(D, gamma, W, kind, e):
+    Wp = np.zeros(5)
+    Wp[: D + 2] = W
+    return lib().orc_moment_mono(D, gamma, Wp, kind, *[int(x) for x in e])
+
+
+def gp_flux(params, Wl, Wr, dWl, dWr, dt, deltas):
+    """Flux at one Gauss point in the face frame.  dWl, dWr: (D, D+2)."""
+    D = params.ndim
+    nc = D + 2
+
+    def pad(v):
+        o = np.zeros(5)
+        o[:nc] = v
+        return o
+
+    def padd(m):
+        o = np.zeros((3, 5))
+        m = np.asarray(m, dtype=np.float64)
+        o[: m.shape[0], :nc] = m
+        return o.ravel()
+
+    deltas = np.asarray(deltas, dtype=np.float64)
+    F = np.zeros((2, 5))
+    W0 = np.zeros(5)
+    dW0 = np.zeros((3, 5))
+    bad = lib().orc_gp_flux(C.byref(params), pad(Wl), pad(Wr), padd(dWl), padd(dWr), float(dt),
+                            len(deltas), deltas, F.ravel(), W0, dW0.ravel())
+    if bad < 0:
+        raise ValueError("invalid parameters")
+    return F[: len(deltas), :nc].copy(), W0[:nc].copy(), dW0[:D, :nc].copy(), bad
+
+
+def flag_bytes(params):
+    return lib().orc_flag_bytes(C.byref(params))
+
+
+def step(params, W, dt, want_flags=False, want_wstar=False):
+    W = _arr(W)
+    out = np.empty_like(W)
+    flags = np.zeros(flag_bytes(params), dtype=np.uint8) if want_flags else None
+    ws = np.empty_like(W) if want_wstar else None
+    bad = lib().orc_step(C.byref(params), W, out, float(dt),
+                         flags.ctypes.data if flags is not None else None,
+                         ws.ctypes.data if ws is not None else None)
+    if bad < 0:
+        raise ValueError("invalid parameters or dt")
+    return out, flags, ws, bad
+
+
+def step_dual(params, W, dW, dt):
+    W = _arr(W)
+    dW = _arr(dW)
+    out = np.empty_like(W)
+    dout = np.empty_like(W)
+    bad = lib().orc_step_dual(C.byref(params), W, dW, out, dout, float(dt))
+    if bad < 0:
+        raise ValueError("invalid parameters or dt")
+    return out, dout, bad
+
+
+def cfl_dt(params, W, cfl):
+    dt = C.c_double()
+    if lib().orc_cfl_dt(C.byref(params), _arr(W), float(cfl), C.byref(dt)) != 0:
+        raise ValueError("invalid parameters")
+    return dt.value
+
+
+def run(params, W, max_steps, cfl=0.5, t_end=0.0, fixed_dt=0.0):
+    """Advance a copy of W; returns (W, t, steps, failures)."""
+    W = _arr(W).copy()
+    t = C.c_double()
+    s = C.c_int()
+    bad = lib().orc_run(C.byref(params), W, int(max_steps), float(cfl), float(t_end),
+                        float(fixed_dt), C.byref(t), C.byref(s))
+    if bad < 0:
+        raise ValueError("invalid parameters or non-positive dt")
+    return W, t.value, s.value, bad
