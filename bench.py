@@ -1,0 +1,139 @@
+#!/usr/bin/env python3
+"""Benchmark: 2-D TENO-D GKS + S2O4 on one MI355X.
+
+Workload: the 2-D Euler four-quadrant Riemann problem, FP64, 1024 x 1024
+cells on [0,1]^2, gamma 1.4, quadrant states seeded (seed 0: rho log-uniform
+[0.1, 2], u, v uniform [-1, 1], p log-uniform [0.03, 1.5]), transmissive
+boundaries, CFL 0.5 with the time step computed on the device before every
+step.  A step is one full S2O4 step (both stages, both directions, update
+and CFL reduction); the timed region runs K steps from t = 0 on a state
+already resident in HBM.
+
+Prints one JSON line: throughput in Mcell-updates/s, the roofline of the
+dominant kernel (face fluxes, FP64 VALU bound; algorithmic flops from the
+library's own op count over the per-launch faces and cells, duration from HIP
+events recorded on the library's stream around every launch in the timed
+region) and the CPU oracle timed on a bounded sample on the host cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mcell-updates/s per S2O4 step FP64 vs roofline; batched and adjoint/forward ratio"
+FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector peak (256 CU x 2.4 GHz x 128 flop/clk)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=1024, help="cells per axis")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
+    return ap.parse_args()
+
+
+def cpu_baseline(W0, dx, n, target_s):
+    """The oracle, as it is, on a bounded sample: one S2O4 step on a strip of
+    rows of the same field (the strip's own transmissive boundaries), all host
+    threads."""
+    import numpy as np
+
+    from oracle import oracle as O
+    threads = O.set_threads(os.cpu_count() or 1)
+    # calibrate on 8 rows, then size the strip to about target_s
+    def run(rows):
+        Ws = np.ascontiguousarray(W0[:, n // 2 - rows // 2:n // 2 - rows // 2 + rows, :])
+        P = O.make_params([n, rows], [dx, dx])
+        dt = O.cfl_dt(P, Ws, 0.5)
+        t0 = time.perf_counter()
+        O.step(P, Ws, dt)
+        return time.perf_counter() - t0
+    t8 = run(8)
+    rows = int(max(8, min(n, 8 * target_s / max(t8, 1e-3))))
+    el = run(rows)
+    cells = n * rows
+    return {"value": cells / el / 1e6, "unit": "Mcell-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"one S2O4 step on a {n}x{rows} strip (rows {n // 2 - rows // 2}..{n // 2 - rows // 2 + rows - 1}) "
+                      f"of the same initial field, {el:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                          "(the multi-GPU decomposition is a design, not measured)"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2309_10534_amd import inputs as I
+    from paper_2309_10534_amd import tgks
+
+    n = args.n
+    W0, dx, states = I.quadrant_riemann(n, seed=args.seed)
+    p = tgks.tgks_params_default(2, [n, n], [dx, dx])
+    ctx = tgks.tgks_create(p)
+    ncell = n * n
+    Wdev0 = torch.from_numpy(W0).cuda()
+    W = Wdev0.clone()
+    tdev = torch.zeros(2, dtype=torch.float64, device="cuda")
+
+    # warm-up (untimed) from the initial state
+    if args.warmup > 0:
+        tgks.tgks_run(ctx, W, args.warmup, cfl=0.5, time_dev=tdev)
+    torch.cuda.synchronize()
+    W.copy_(Wdev0)
+    tgks.tgks_reset_status(ctx)
+    tgks.tgks_timing(ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tgks.tgks_run(ctx, W, args.steps, cfl=0.5, time_dev=tdev)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    fails = tgks.tgks_status(ctx)
+    kt = {k: tgks.tgks_kernel_time(ctx, k) for k in ("face_x", "face_y", "update1", "update2", "cfl")}
+    tgks.tgks_timing(ctx, False)
+    t_sim = float(tdev[0].cpu())
+    ok = bool(torch.isfinite(W).all().item())
+    flops = tgks.tgks_flop_counts(p)
+    tgks.tgks_destroy(ctx)
+
+    value = ncell * args.steps / el / 1e6
+    # dominant kernel: face fluxes along x or y
+    dom = max(("face_x", "face_y"), key=lambda k: kt[k][0])
+    ms, launches = kt[dom]
+    ax = 0 if dom == "face_x" else 1
+    nface = (n + (ax == 0)) * (n + (ax == 1))
+    per_launch = nface * flops["face"] + ncell * 4 * flops["normal"]
+    avg_s = ms / 1e3 / max(launches, 1)
+    achieved = per_launch / avg_s / 1e12
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "Mcell-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(el * 1e3 / args.steps, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"2d_euler_four_quadrant_riemann_{n}x{n}_seed{args.seed}", "cells": ncell,
+                   "gamma": 1.4, "cfl": 0.5, "bc": "transmissive", "t_end_reached": t_sim,
+                   "failures": fails, "finite": ok},
+        "roofline": {"bound": "alu", "kernel": f"face2d_kernel ({dom}, both stages)",
+                     "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                     "flops_per_launch": per_launch, "avg_launch_ms": round(ms / max(launches, 1), 5),
+                     "launches": launches},
+        "kernel_ms_per_step": {k: round(v[0] / args.steps, 5) for k, v in kt.items()},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(W0, dx, n, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

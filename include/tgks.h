@@ -1,0 +1,139 @@
+/* tgks.h -- C ABI of the MI355X (gfx950) TENO-D gas-kinetic scheme library.
+ *
+ * The library advances the compressible Euler or Navier-Stokes equations
+ *     W_t = -div F(W),  W(0, x) = W0(x)
+ * (Sec. 2.2 of Mu et al., "High-order gas-kinetic scheme with TENO class
+ * reconstruction for the Euler and Navier-Stokes equations",
+ * arXiv:2309.10534) on a uniform 1-D, 2-D or 3-D grid with the fifth-order
+ * TENO-D reconstruction (Sec. 4.2), the gas-kinetic interface flux with the
+ * kinetic-weighted equilibrium state (Sec. 2.1, Sec. 3.2) and the two-stage
+ * fourth-order (S2O4) time stepping (Sec. 2.2).  Every step runs in HIP
+ * kernels on the device; this header uses no torch or HIP types.
+ *
+ * Data layout.  A state W is FP64, structure of arrays, [nc][nz][ny][nx] with
+ * x fastest, contiguous, interior cells only; nc = ndim + 2 and the
+ * components are (rho, rho U, rho V, rho W, rho E) truncated to nc.
+ *
+ * Pointers.  Every array argument is a DEVICE pointer owned by the caller
+ * unless stated otherwise; the library never frees it.  Work is enqueued on
+ * the HIP stream given at creation (tgks_set_stream changes it) and the
+ * calls return before it completes; a context must not be used from two
+ * host threads at once.
+ *
+ * Errors.  A negative return value means a caller error (invalid parameter,
+ * null pointer, size mismatch) or a HIP error; in the first case nothing was
+ * enqueued.  Numerical failure (rho <= 0, p <= 0 or a non-finite value in a
+ * reconstructed or equilibrium state at a Gauss point) is not reported
+ * synchronously: it increments a device counter read by tgks_status.
+ */
+#ifndef TGKS_H
+#define TGKS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TGKS_OK 0
+#define TGKS_EINVAL (-1) /* invalid argument: nothing enqueued */
+#define TGKS_EHIP (-2)   /* a HIP runtime call failed */
+
+/* boundary kinds (Sec. 5): periodic; transmissive = the non-reflecting
+ * zero-gradient condition (ghost cells copy the nearest interior cell);
+ * reflective = mirror image with the wall-normal momentum negated. */
+#define TGKS_BC_PERIODIC 0
+#define TGKS_BC_TRANSMISSIVE 1
+#define TGKS_BC_REFLECTIVE 2
+
+/* collision time (Sec. 5 preamble):
+ * INVISCID: tau = c1 dt + c2 |p_l - p_r| / (p_l + p_r) dt
+ * VISCOUS:  tau = mu / p0 + c2 |p_l - p_r| / (p_l + p_r) dt
+ * ZERO:     tau = 0 (smooth inviscid accuracy tests, Sec. 5.1)
+ * p_l, p_r: reconstructed pressures at the Gauss point; p0: pressure of the
+ * kinetic-weighted equilibrium state; dt is the full step in both stages. */
+#define TGKS_TAU_INVISCID 0
+#define TGKS_TAU_VISCOUS 1
+#define TGKS_TAU_ZERO 2
+
+typedef struct tgks_params {
+  int32_t ndim;      /* 1, 2 or 3 */
+  int32_t n[3];      /* cells per axis, >= 3 on every used axis (1 on unused ones) */
+  double dx[3];      /* cell widths, > 0 */
+  int32_t bc_lo[3];  /* TGKS_BC_* at the low and high end of each axis; */
+  int32_t bc_hi[3];  /* periodic must be set on both ends of an axis     */
+  double gamma;      /* ratio of specific heats, > 1 (1.4 in Sec. 5) */
+  double mu;         /* constant dynamic viscosity, >= 0 (0: Euler) */
+  double prandtl;    /* Prandtl number, > 0; the energy flux is corrected by (1/Pr - 1) q when mu > 0 */
+  int32_t tau_mode;  /* TGKS_TAU_* */
+  double c1, c2;     /* collision-time constants, 0.01 and 1 in Sec. 5 */
+  double ct1, ct2;   /* TENO-D cut-offs C_T1, C_T2 (1e-7, 1e-5: Eqs. 4.7, 4.12), normal direction */
+  double ct1_tan, ct2_tan; /* cut-offs of the tangential reconstruction */
+  double eps;        /* epsilon of Eq. 4.5 (1e-40) */
+  int32_t q;         /* power of Eq. 4.5 (7) */
+} tgks_params;
+
+typedef struct tgks_ctx tgks_ctx;
+
+/* Fill p with the paper's constants for an ndim-dimensional Euler problem
+ * (gamma 1.4, tau inviscid, c1 0.01, c2 1, C_T 1e-7 / 1e-5, eps 1e-40, q 7,
+ * transmissive boundaries); the caller sets n and dx. */
+int tgks_params_default(tgks_params* p, int32_t ndim);
+
+/* Create a context for one grid.  Allocates the device work buffers of one
+ * step (about 3 states plus face fluxes); hip_stream may be NULL for the
+ * default stream.  Returns TGKS_EINVAL for invalid parameters. */
+int tgks_create(const tgks_params* p, void* hip_stream, tgks_ctx** out);
+int tgks_destroy(tgks_ctx* ctx);
+int tgks_set_stream(tgks_ctx* ctx, void* hip_stream);
+
+/* Number of doubles of one state (nc * cells) and bytes of the flag buffer
+ * of tgks_step. */
+int64_t tgks_state_size(const tgks_ctx* ctx);
+int64_t tgks_flag_bytes(const tgks_ctx* ctx);
+
+/* CFL time step (Sec. 5 preamble): dt = cfl * min over cells of
+ * min(dx_min / (|U| + a), dx_min^2 rho / (4 mu)), a = sqrt(gamma p / rho);
+ * if t_end > 0 it is clipped to t_end - t.  Writes one double to dt_dev. */
+int tgks_cfl_dt(tgks_ctx* ctx, const double* W, double cfl, double t, double t_end, double* dt_dev);
+
+/* One S2O4 step W_out = S(W_in, dt) with dt read from the device scalar
+ * dt_dev (dt <= 0 or NaN: W_out = W_in).  W_in and W_out must not overlap.
+ * flags (device, tgks_flag_bytes bytes, or NULL): stage-1 stencil
+ * selections, one byte per decision: bit0 = delta_{3,1} (Eq. 4.7); when it
+ * is 0, bits 1..3 = delta_{0,2}, delta_{1,2}, delta_{2,2} (Eq. 4.12).
+ * Layout: normal reconstruction [ndim][nc][cells], then for ndim == 2 the
+ * tangential reconstructions of each direction d (x-faces, then y-faces) as
+ * [quantity (W, dW/dn)][side (left, right)][nc][faces_d], faces_d indexed
+ * like a state whose axis d has n[d] + 1 entries.
+ * W_star (device, one state, or NULL) receives the intermediate state W*
+ * of Sec. 2.2. */
+int tgks_step(tgks_ctx* ctx, const double* W_in, double* W_out, const double* dt_dev, uint8_t* flags,
+              double* W_star);
+
+/* Advance W in place by n_steps S2O4 steps with the CFL step computed on the
+ * device before every step (cfl > 0), the last step clipped so that the
+ * time does not pass t_end when t_end > 0 (further steps are no-ops), or
+ * with the constant step fixed_dt when cfl <= 0.  time_dev (device, 2
+ * doubles, or NULL) receives (t, dt of the next step).  use_graph != 0
+ * captures the n_steps loop into a HIP graph on first use and replays it. */
+int tgks_run(tgks_ctx* ctx, double* W, int32_t n_steps, double cfl, double t_end, double fixed_dt,
+             double* time_dev, int32_t use_graph);
+
+/* Failure count since creation or the last tgks_reset_status (synchronises
+ * the stream). */
+int tgks_status(tgks_ctx* ctx, int64_t* failures);
+int tgks_reset_status(tgks_ctx* ctx);
+
+/* Per-kernel timing with HIP events recorded on the context's stream around
+ * every launch while enabled.  kind: 0 face fluxes along x, 1 along y, 2
+ * along z, 3 normal reconstruction (3-D), 4 stage-1 update, 5 stage-2
+ * update, 6 CFL reduction.  tgks_kernel_time synchronises and returns the
+ * summed milliseconds and launch count of one kind since it was enabled. */
+int tgks_timing(tgks_ctx* ctx, int32_t enable);
+int tgks_kernel_time(tgks_ctx* ctx, int32_t kind, double* ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TGKS_H */

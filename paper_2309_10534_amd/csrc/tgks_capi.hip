@@ -1,0 +1,585 @@
+// tgks_capi.hip -- C ABI of the TENO-D GKS library (declared in include/tgks.h).
+//
+// A context owns the device work buffers of one grid: the intermediate state
+// W* and the accumulator P of the S2O4 step (Sec. 2.2), a ping-pong state for
+// tgks_run, the per-direction face flux arrays, the 3-D normal
+// reconstruction buffer, CFL partial minima, a device clock {t, dt} and the
+// failure counter.  All launches go to the context's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "tgks.h"
+#include "tgks_kernels.hpp"
+
+using namespace tgks;
+
+namespace {
+
+constexpr int NKIND = 7;
+
+struct EventPair {
+  hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct tgks_ctx {
+  tgks_params p;
+  Geom g;
+  FluxCfg fc;
+  TenoCfg tn, tt;
+  bool ns;
+  hipStream_t stream;
+  int nc;
+  long long ncell;
+  long long nface[3];
+  double* Ws = nullptr;
+  double* P = nullptr;
+  double* W2 = nullptr;
+  double* FA[3] = {nullptr, nullptr, nullptr};
+  double* FB[3] = {nullptr, nullptr, nullptr};
+  double* R = nullptr;
+  double* partial = nullptr;
+  int nblk = 0;
+  double* clock = nullptr;
+  unsigned long long* fail = nullptr;
+  // graph cache of tgks_run
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  int g_steps = -1;
+  double g_cfl = 0, g_tend = 0, g_fixed = 0;
+  double* g_W = nullptr;
+  double* g_time = nullptr;
+  // timing
+  bool timing = false;
+  std::vector<EventPair> ev[NKIND];
+  std::vector<hipEvent_t> pool;
+};
+
+#define HIPCHK(x)                                                                  \
+  do {                                                                             \
+    hipError_t e_ = (x);                                                           \
+    if (e_ != hipSuccess) {                                                        \
+      fprintf(stderr, "tgks: %s failed: %s\n", #x, hipGetErrorString(e_));         \
+      return TGKS_EHIP;                                                            \
+    }                                                                              \
+  } while (0)
+
+static int check_params(const tgks_params* p) {
+  if (!p || p->ndim < 1 || p->ndim > 3) return TGKS_EINVAL;
+  for (int d = 0; d < 3; ++d) {
+    if (d < p->ndim) {
+      if (p->n[d] < 3 || !(p->dx[d] > 0.0)) return TGKS_EINVAL;
+      if (p->bc_lo[d] < 0 || p->bc_lo[d] > 2 || p->bc_hi[d] < 0 || p->bc_hi[d] > 2) return TGKS_EINVAL;
+      if ((p->bc_lo[d] == TGKS_BC_PERIODIC) != (p->bc_hi[d] == TGKS_BC_PERIODIC)) return TGKS_EINVAL;
+    } else if (p->n[d] != 1) {
+      return TGKS_EINVAL;
+    }
+  }
+  if (!(p->gamma > 1.0) || !(p->mu >= 0.0) || !(p->prandtl > 0.0)) return TGKS_EINVAL;
+  if (p->tau_mode < 0 || p->tau_mode > 2) return TGKS_EINVAL;
+  if (p->tau_mode == TGKS_TAU_VISCOUS && !(p->mu > 0.0)) return TGKS_EINVAL;
+  if (p->q < 1 || p->q > 16 || !(p->eps >= 0.0)) return TGKS_EINVAL;
+  double cells = 1.0;
+  for (int d = 0; d < p->ndim; ++d) cells *= p->n[d];
+  if (cells > 4.0e9) return TGKS_EINVAL;
+  return TGKS_OK;
+}
+
+static hipEvent_t take_event(tgks_ctx* c) {
+  if (!c->pool.empty()) {
+    hipEvent_t e = c->pool.back();
+    c->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// begin/end markers around one launch of a kernel kind
+struct Timer {
+  tgks_ctx* c;
+  int kind;
+  hipEvent_t a = nullptr;
+  Timer(tgks_ctx* c_, int k) : c(c_), kind(k) {
+    if (c->timing) {
+      a = take_event(c);
+      if (a) (void)hipEventRecord(a, c->stream);
+    }
+  }
+  ~Timer() {
+    if (c->timing && a) {
+      hipEvent_t b = take_event(c);
+      if (b) {
+        (void)hipEventRecord(b, c->stream);
+        c->ev[kind].push_back({a, b});
+      }
+    }
+  }
+};
+
+static StageArgs stage_args(tgks_ctx* c, const double* W, int ax, const double* dt) {
+  StageArgs a;
+  a.g = c->g;
+  a.fc = c->fc;
+  a.tn = c->tn;
+  a.tt = c->tt;
+  a.W = W;
+  a.FA = c->FA[ax];
+  a.FB = c->FB[ax];
+  a.dt = dt;
+  a.fail = c->fail;
+  a.nflags = nullptr;
+  a.tflags = nullptr;
+  a.R = c->R;
+  a.Rout = c->R;
+  return a;
+}
+
+#define LAUNCH(kern, grid, block, args) hipLaunchKernelGGL(kern, grid, block, 0, c->stream, args)
+
+// face fluxes of one stage in every direction
+static int launch_faces(tgks_ctx* c, const double* W, const double* dt, int stage, uint8_t* flags) {
+  const int D = c->g.D;
+  for (int ax = 0; ax < D; ++ax) {
+    StageArgs a = stage_args(c, W, ax, dt);
+    const bool fl = flags != nullptr && stage == 1;
+    if (fl) {
+      a.nflags = flags;
+      if (D == 2) {
+        long long off = (long long)D * c->nc * c->ncell;
+        for (int d = 0; d < ax; ++d) off += 4LL * c->nc * c->nface[d];
+        a.tflags = flags + off;
+      }
+    }
+    if (D == 1) {
+      Timer tm(c, 0);
+      dim3 grid((unsigned)((c->g.n[0] + 1 + 255) / 256));
+      if (stage == 1) {
+        if (fl) {
+          if (c->ns) LAUNCH((face1d_kernel<1, true, true>), grid, dim3(256), a);
+          else LAUNCH((face1d_kernel<1, false, true>), grid, dim3(256), a);
+        } else {
+          if (c->ns) LAUNCH((face1d_kernel<1, true, false>), grid, dim3(256), a);
+          else LAUNCH((face1d_kernel<1, false, false>), grid, dim3(256), a);
+        }
+      } else {
+        if (c->ns) LAUNCH((face1d_kernel<2, true, false>), grid, dim3(256), a);
+        else LAUNCH((face1d_kernel<2, false, false>), grid, dim3(256), a);
+      }
+    } else if (D == 2) {
+      Timer tm(c, ax);
+      const int nN = c->g.n[ax], nT = c->g.n[1 - ax];
+      dim3 grid((unsigned)((nN + 1 + TN2 - 1) / TN2), (unsigned)((nT + TT2 - 1) / TT2));
+#define F2(AXV)                                                                                  \
+  if (stage == 1) {                                                                              \
+    if (fl) {                                                                                    \
+      if (c->ns) LAUNCH((face2d_kernel<AXV, 1, true, true>), grid, dim3(256), a);                \
+      else LAUNCH((face2d_kernel<AXV, 1, false, true>), grid, dim3(256), a);                     \
+    } else {                                                                                     \
+      if (c->ns) LAUNCH((face2d_kernel<AXV, 1, true, false>), grid, dim3(256), a);               \
+      else LAUNCH((face2d_kernel<AXV, 1, false, false>), grid, dim3(256), a);                    \
+    }                                                                                            \
+  } else {                                                                                       \
+    if (c->ns) LAUNCH((face2d_kernel<AXV, 2, true, false>), grid, dim3(256), a);                 \
+    else LAUNCH((face2d_kernel<AXV, 2, false, false>), grid, dim3(256), a);                      \
+  }
+      if (ax == 0) {
+        F2(0)
+      } else {
+        F2(1)
+      }
+#undef F2
+    } else {
+      int ext[3] = {c->g.n[0], c->g.n[1], c->g.n[2]};
+      ext[ax] += 2;
+      const long long nr = (long long)ext[0] * ext[1] * ext[2];
+      {
+        Timer tm(c, 3);
+        dim3 grid((unsigned)((nr * 5 + 255) / 256));
+#define R3(AXV)                                                                   \
+  if (fl) LAUNCH((recon3d_kernel<AXV, true>), grid, dim3(256), a);                \
+  else LAUNCH((recon3d_kernel<AXV, false>), grid, dim3(256), a);
+        if (ax == 0) {
+          R3(0)
+        } else if (ax == 1) {
+          R3(1)
+        } else {
+          R3(2)
+        }
+#undef R3
+      }
+      {
+        Timer tm(c, ax);
+        dim3 grid((unsigned)((c->nface[ax] * 4 + 255) / 256));
+#define F3(AXV)                                                                       \
+  if (stage == 1) {                                                                   \
+    if (c->ns) LAUNCH((face3d_kernel<AXV, 1, true>), grid, dim3(256), a);             \
+    else LAUNCH((face3d_kernel<AXV, 1, false>), grid, dim3(256), a);                  \
+  } else {                                                                            \
+    if (c->ns) LAUNCH((face3d_kernel<AXV, 2, true>), grid, dim3(256), a);             \
+    else LAUNCH((face3d_kernel<AXV, 2, false>), grid, dim3(256), a);                  \
+  }
+        if (ax == 0) {
+          F3(0)
+        } else if (ax == 1) {
+          F3(1)
+        } else {
+          F3(2)
+        }
+#undef F3
+      }
+    }
+  }
+  HIPCHK(hipGetLastError());
+  return TGKS_OK;
+}
+
+static UpdateArgs update_args(tgks_ctx* c, const double* W, double* o1, double* o2, const double* dt,
+                              double* partial) {
+  UpdateArgs u;
+  u.g = c->g;
+  u.W = W;
+  u.out1 = o1;
+  u.out2 = o2;
+  for (int d = 0; d < 3; ++d) {
+    u.FA[d] = c->FA[d];
+    u.FB[d] = c->FB[d];
+  }
+  u.dt = dt;
+  u.gamma = c->p.gamma;
+  u.mu = c->p.mu;
+  u.partial = partial;
+  return u;
+}
+
+static int launch_update(tgks_ctx* c, int stage, const double* W, double* o1, double* o2, const double* dt,
+                         bool cfl) {
+  UpdateArgs u = update_args(c, W, o1, o2, dt, c->partial);
+  dim3 grid((unsigned)c->nblk);
+  Timer tm(c, stage == 1 ? 4 : 5);
+#define UPD(DV)                                                                 \
+  if (stage == 1) LAUNCH((update_kernel<DV, 1, false>), grid, dim3(256), u);    \
+  else if (cfl) LAUNCH((update_kernel<DV, 2, true>), grid, dim3(256), u);       \
+  else LAUNCH((update_kernel<DV, 2, false>), grid, dim3(256), u);
+  if (c->g.D == 1) {
+    UPD(1)
+  } else if (c->g.D == 2) {
+    UPD(2)
+  } else {
+    UPD(3)
+  }
+#undef UPD
+  HIPCHK(hipGetLastError());
+  return TGKS_OK;
+}
+
+static int launch_cfl_partial(tgks_ctx* c, const double* W) {
+  Timer tm(c, 6);
+  dim3 grid((unsigned)c->nblk);
+  if (c->g.D == 1)
+    hipLaunchKernelGGL((cfl_partial_kernel<1>), grid, dim3(256), 0, c->stream, c->g, W, c->p.gamma, c->p.mu, c->partial);
+  else if (c->g.D == 2)
+    hipLaunchKernelGGL((cfl_partial_kernel<2>), grid, dim3(256), 0, c->stream, c->g, W, c->p.gamma, c->p.mu, c->partial);
+  else
+    hipLaunchKernelGGL((cfl_partial_kernel<3>), grid, dim3(256), 0, c->stream, c->g, W, c->p.gamma, c->p.mu, c->partial);
+  HIPCHK(hipGetLastError());
+  return TGKS_OK;
+}
+
+static int launch_finalize(tgks_ctx* c, double cfl, double t_in, double t_end, double* clock, double* dt_out,
+                           int mode) {
+  Timer tm(c, 6);
+  hipLaunchKernelGGL(cfl_finalize_kernel, dim3(1), dim3(256), 0, c->stream, c->partial, c->nblk, cfl, t_in, t_end,
+                     clock, dt_out, mode);
+  HIPCHK(hipGetLastError());
+  return TGKS_OK;
+}
+
+// one S2O4 step W -> out, dt read from dt_dev
+static int do_step(tgks_ctx* c, const double* W, double* out, const double* dt, uint8_t* flags, bool cfl) {
+  int r;
+  if ((r = launch_faces(c, W, dt, 1, flags))) return r;
+  if ((r = launch_update(c, 1, W, c->Ws, c->P, dt, false))) return r;
+  if ((r = launch_faces(c, c->Ws, dt, 2, nullptr))) return r;
+  if ((r = launch_update(c, 2, c->P, out, nullptr, dt, cfl))) return r;
+  return TGKS_OK;
+}
+
+static void free_ctx(tgks_ctx* c) {
+  if (!c) return;
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  (void)hipFree(c->Ws);
+  (void)hipFree(c->P);
+  (void)hipFree(c->W2);
+  for (int d = 0; d < 3; ++d) {
+    (void)hipFree(c->FA[d]);
+    (void)hipFree(c->FB[d]);
+  }
+  (void)hipFree(c->R);
+  (void)hipFree(c->partial);
+  (void)hipFree(c->clock);
+  (void)hipFree(c->fail);
+  for (int k = 0; k < NKIND; ++k)
+    for (auto& e : c->ev[k]) {
+      (void)hipEventDestroy(e.a);
+      (void)hipEventDestroy(e.b);
+    }
+  for (auto e : c->pool) (void)hipEventDestroy(e);
+  delete c;
+}
+
+extern "C" {
+
+int tgks_params_default(tgks_params* p, int32_t ndim) {
+  if (!p || ndim < 1 || ndim > 3) return TGKS_EINVAL;
+  memset(p, 0, sizeof(*p));
+  p->ndim = ndim;
+  for (int d = 0; d < 3; ++d) {
+    p->n[d] = 1;
+    p->dx[d] = 1.0;
+    p->bc_lo[d] = p->bc_hi[d] = TGKS_BC_TRANSMISSIVE;
+  }
+  p->gamma = 1.4;
+  p->mu = 0.0;
+  p->prandtl = 1.0;
+  p->tau_mode = TGKS_TAU_INVISCID;
+  p->c1 = 0.01;
+  p->c2 = 1.0;
+  p->ct1 = p->ct1_tan = 1e-7;
+  p->ct2 = p->ct2_tan = 1e-5;
+  p->eps = 1e-40;
+  p->q = 7;
+  return TGKS_OK;
+}
+
+int tgks_create(const tgks_params* p, void* stream, tgks_ctx** out) {
+  if (!out || check_params(p)) return TGKS_EINVAL;
+  *out = nullptr;
+  tgks_ctx* c = new (std::nothrow) tgks_ctx();
+  if (!c) return TGKS_EHIP;
+  c->p = *p;
+  c->stream = (hipStream_t)stream;
+  const int D = p->ndim;
+  c->nc = D + 2;
+  Geom& g = c->g;
+  g.D = D;
+  g.ncell = 1;
+  for (int d = 0; d < 3; ++d) {
+    g.n[d] = d < D ? p->n[d] : 1;
+    g.dx[d] = d < D ? p->dx[d] : 1.0;
+    g.bclo[d] = p->bc_lo[d];
+    g.bchi[d] = p->bc_hi[d];
+    g.ncell *= g.n[d];
+  }
+  c->ncell = g.ncell;
+  const double N = 2.0 / (p->gamma - 1.0);
+  c->fc.N = N;
+  c->fc.K = N - D;
+  c->fc.mu = p->mu;
+  c->ns = p->mu > 0.0 && p->prandtl != 1.0;
+  c->fc.pr_fix = c->ns ? 1.0 / p->prandtl - 1.0 : 0.0;
+  c->fc.c1 = p->c1;
+  c->fc.c2 = p->c2;
+  c->fc.tau_mode = p->tau_mode;
+  c->tn = {p->ct1, p->ct2, p->eps, p->q};
+  c->tt = {p->ct1_tan, p->ct2_tan, p->eps, p->q};
+  const size_t state = (size_t)c->nc * g.ncell * sizeof(double);
+  bool ok = hipMalloc(&c->Ws, state) == hipSuccess && hipMalloc(&c->P, state) == hipSuccess &&
+            hipMalloc(&c->W2, state) == hipSuccess;
+  for (int d = 0; d < D && ok; ++d) {
+    long long nf = 1;
+    for (int e = 0; e < 3; ++e) nf *= (long long)(g.n[e] + (e == d));
+    c->nface[d] = nf;
+    ok = hipMalloc(&c->FA[d], (size_t)c->nc * nf * sizeof(double)) == hipSuccess &&
+         hipMalloc(&c->FB[d], (size_t)c->nc * nf * sizeof(double)) == hipSuccess;
+  }
+  if (ok && D == 3) {
+    long long mx = 0;
+    for (int d = 0; d < 3; ++d) {
+      long long nr = 1;
+      for (int e = 0; e < 3; ++e) nr *= (long long)(g.n[e] + 2 * (e == d));
+      mx = nr > mx ? nr : mx;
+    }
+    ok = hipMalloc(&c->R, (size_t)mx * 4 * 5 * sizeof(double)) == hipSuccess;
+  }
+  c->nblk = (int)((g.ncell + 255) / 256);
+  if (ok)
+    ok = hipMalloc(&c->partial, (size_t)c->nblk * sizeof(double)) == hipSuccess &&
+         hipMalloc(&c->clock, 4 * sizeof(double)) == hipSuccess &&
+         hipMalloc(&c->fail, sizeof(unsigned long long)) == hipSuccess;
+  if (ok) ok = hipMemsetAsync(c->fail, 0, sizeof(unsigned long long), c->stream) == hipSuccess;
+  if (ok) ok = hipStreamSynchronize(c->stream) == hipSuccess;
+  if (!ok) {
+    free_ctx(c);
+    return TGKS_EHIP;
+  }
+  *out = c;
+  return TGKS_OK;
+}
+
+int tgks_destroy(tgks_ctx* c) {
+  if (!c) return TGKS_EINVAL;
+  (void)hipStreamSynchronize(c->stream);
+  free_ctx(c);
+  return TGKS_OK;
+}
+
+int tgks_set_stream(tgks_ctx* c, void* stream) {
+  if (!c) return TGKS_EINVAL;
+  c->stream = (hipStream_t)stream;
+  if (c->gexec) {
+    (void)hipGraphExecDestroy(c->gexec);
+    (void)hipGraphDestroy(c->graph);
+    c->gexec = nullptr;
+    c->graph = nullptr;
+    c->g_steps = -1;
+  }
+  return TGKS_OK;
+}
+
+int64_t tgks_state_size(const tgks_ctx* c) { return c ? (int64_t)c->nc * c->ncell : TGKS_EINVAL; }
+
+int64_t tgks_flag_bytes(const tgks_ctx* c) {
+  if (!c) return TGKS_EINVAL;
+  int64_t nb = (int64_t)c->g.D * c->nc * c->ncell;
+  if (c->g.D == 2) nb += 4LL * c->nc * (c->nface[0] + c->nface[1]);
+  return nb;
+}
+
+int tgks_cfl_dt(tgks_ctx* c, const double* W, double cfl, double t, double t_end, double* dt_dev) {
+  if (!c || !W || !dt_dev || !(cfl > 0.0)) return TGKS_EINVAL;
+  int r;
+  if ((r = launch_cfl_partial(c, W))) return r;
+  return launch_finalize(c, cfl, t, t_end, nullptr, dt_dev, 0);
+}
+
+int tgks_step(tgks_ctx* c, const double* W_in, double* W_out, const double* dt_dev, uint8_t* flags,
+              double* W_star) {
+  if (!c || !W_in || !W_out || !dt_dev || W_in == W_out) return TGKS_EINVAL;
+  int r = do_step(c, W_in, W_out, dt_dev, flags, false);
+  if (r) return r;
+  if (W_star)
+    HIPCHK(hipMemcpyAsync(W_star, c->Ws, (size_t)c->nc * c->ncell * sizeof(double), hipMemcpyDeviceToDevice,
+                          c->stream));
+  return TGKS_OK;
+}
+
+static int enqueue_run(tgks_ctx* c, double* W, int n_steps, double cfl, double t_end, double fixed_dt,
+                       double* time_dev) {
+  int r;
+  const bool use_cfl = cfl > 0.0;
+  if (use_cfl) {
+    if ((r = launch_cfl_partial(c, W))) return r;
+    if ((r = launch_finalize(c, cfl, 0.0, t_end, c->clock, nullptr, 0))) return r;
+  } else {
+    hipLaunchKernelGGL(set_clock_kernel, dim3(1), dim3(1), 0, c->stream, c->clock, 0.0, fixed_dt);
+    HIPCHK(hipGetLastError());
+  }
+  double* src = W;
+  double* dst = c->W2;
+  for (int s = 0; s < n_steps; ++s) {
+    if ((r = do_step(c, src, dst, c->clock + 1, nullptr, use_cfl))) return r;
+    if ((r = launch_finalize(c, cfl, 0.0, t_end, c->clock, nullptr, use_cfl ? 1 : 2))) return r;
+    double* t = src;
+    src = dst;
+    dst = t;
+  }
+  if (src != W)
+    HIPCHK(hipMemcpyAsync(W, src, (size_t)c->nc * c->ncell * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  if (time_dev)
+    HIPCHK(hipMemcpyAsync(time_dev, c->clock, 2 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  return TGKS_OK;
+}
+
+int tgks_run(tgks_ctx* c, double* W, int32_t n_steps, double cfl, double t_end, double fixed_dt, double* time_dev,
+             int32_t use_graph) {
+  if (!c || !W || n_steps < 0) return TGKS_EINVAL;
+  if (!(cfl > 0.0) && !(fixed_dt > 0.0)) return TGKS_EINVAL;
+  if (!use_graph || c->timing) return enqueue_run(c, W, n_steps, cfl, t_end, fixed_dt, time_dev);
+  const bool same = c->gexec && c->g_steps == n_steps && c->g_cfl == cfl && c->g_tend == t_end &&
+                    c->g_fixed == fixed_dt && c->g_W == W && c->g_time == time_dev;
+  if (!same) {
+    if (c->gexec) {
+      (void)hipGraphExecDestroy(c->gexec);
+      (void)hipGraphDestroy(c->graph);
+      c->gexec = nullptr;
+      c->graph = nullptr;
+    }
+    if (c->stream == nullptr) return enqueue_run(c, W, n_steps, cfl, t_end, fixed_dt, time_dev);
+    HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    const int r = enqueue_run(c, W, n_steps, cfl, t_end, fixed_dt, time_dev);
+    hipGraph_t gr = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->stream, &gr);
+    if (r) {
+      if (gr) (void)hipGraphDestroy(gr);
+      return r;
+    }
+    if (e != hipSuccess) {
+      fprintf(stderr, "tgks: graph capture failed: %s\n", hipGetErrorString(e));
+      return TGKS_EHIP;
+    }
+    c->graph = gr;
+    HIPCHK(hipGraphInstantiate(&c->gexec, gr, nullptr, nullptr, 0));
+    c->g_steps = n_steps;
+    c->g_cfl = cfl;
+    c->g_tend = t_end;
+    c->g_fixed = fixed_dt;
+    c->g_W = W;
+    c->g_time = time_dev;
+  }
+  HIPCHK(hipGraphLaunch(c->gexec, c->stream));
+  return TGKS_OK;
+}
+
+int tgks_status(tgks_ctx* c, int64_t* failures) {
+  if (!c || !failures) return TGKS_EINVAL;
+  unsigned long long h = 0;
+  HIPCHK(hipMemcpyAsync(&h, c->fail, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  *failures = (int64_t)h;
+  return TGKS_OK;
+}
+
+int tgks_reset_status(tgks_ctx* c) {
+  if (!c) return TGKS_EINVAL;
+  HIPCHK(hipMemsetAsync(c->fail, 0, sizeof(unsigned long long), c->stream));
+  return TGKS_OK;
+}
+
+int tgks_timing(tgks_ctx* c, int32_t enable) {
+  if (!c) return TGKS_EINVAL;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  for (int k = 0; k < NKIND; ++k) {
+    for (auto& e : c->ev[k]) {
+      c->pool.push_back(e.a);
+      c->pool.push_back(e.b);
+    }
+    c->ev[k].clear();
+  }
+  c->timing = enable != 0;
+  return TGKS_OK;
+}
+
+int tgks_kernel_time(tgks_ctx* c, int32_t kind, double* ms, int64_t* launches) {
+  if (!c || kind < 0 || kind >= NKIND || !ms || !launches) return TGKS_EINVAL;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  double s = 0.0;
+  for (auto& e : c->ev[kind]) {
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, e.a, e.b));
+    s += t;
+  }
+  *ms = s;
+  *launches = (int64_t)c->ev[kind].size();
+  return TGKS_OK;
+}
+
+}  // extern "C"

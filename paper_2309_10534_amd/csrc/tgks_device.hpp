@@ -1,0 +1,590 @@
+// tgks_device.hpp -- device math of the TENO-D gas-kinetic scheme (gfx950, FP64).
+//
+// Mu et al., "High-order gas-kinetic scheme with TENO class reconstruction for
+// the Euler and Navier-Stokes equations", arXiv:2309.10534.
+//
+//   * TENO-D selection and candidate values (Sec. 4.2, Eqs. 4.5-4.14; the
+//     candidate polynomials of Sec. 3.1-3.2, slopes Eqs. 3.22-3.24).
+//   * Tangential Gauss-point reconstruction (Sec. 3.2 Steps 1-3).
+//   * Gas-kinetic flux at one Gauss point (Sec. 2.1, Eqs. 2.2-2.9 with the
+//     kinetic weighting of Eqs. 3.25-3.26), in closed form: Maxwellian moment
+//     tables by the half-space erfc/exp recursion, closed-form solution of the
+//     micro-slope systems, moment sums over psi.
+//
+// The selection arithmetic (smoothness indicators, gamma_k, cut-offs) and the
+// candidate values follow one fixed evaluation order with floating-point
+// contraction disabled, so that the stencil flags are a deterministic
+// function of the input bits.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tgks {
+
+struct TenoCfg {
+  double ct1, ct2, eps;
+  int q;
+};
+
+// ---------------------------------------------------------------------------
+// TENO-D selection (Sec. 4.2).  q[0..4] = Q_{-2..2}.
+// flag bit0 = delta_{3,1}; if it is 0, bits 1..3 = delta_{0,2}, delta_{1,2},
+// delta_{2,2}.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned teno_flag(const double* Q, const TenoCfg& c) {
+#pragma clang fp contract(off)
+  const double a = Q[0], b = Q[1], cc = Q[2], d = Q[3], e = Q[4];
+  const double k13 = 13.0 / 12.0;
+  double t1, t2, beta[4];
+  t1 = (a - 2.0 * b) + cc;
+  t2 = (a - 4.0 * b) + 3.0 * cc;
+  beta[0] = k13 * (t1 * t1) + 0.25 * (t2 * t2);
+  t1 = (b - 2.0 * cc) + d;
+  t2 = b - d;
+  beta[1] = k13 * (t1 * t1) + 0.25 * (t2 * t2);
+  t1 = (cc - 2.0 * d) + e;
+  t2 = (3.0 * cc - 4.0 * d) + e;
+  beta[2] = k13 * (t1 * t1) + 0.25 * (t2 * t2);
+  // quartic indicator (Eq. 3.7, q = 4) as a sum of squares of its derivatives
+  const double P1 = (82.0 * (d - b) - 11.0 * (e - a)) / 120.0;
+  const double P2 = ((((40.0 * b - 3.0 * a) - 74.0 * cc) + 40.0 * d) - 3.0 * e) / 56.0;
+  const double P3 = ((e - a) - 2.0 * (d - b)) / 12.0;
+  const double P4 = ((((a - 4.0 * b) + 6.0 * cc) - 4.0 * d) + e) / 24.0;
+  const double s1 = P1 + P3 / 10.0;
+  const double s2 = P2 + (123.0 / 455.0) * P4;
+  beta[3] = (((s1 * s1) + (13.0 / 3.0) * (s2 * s2)) + (781.0 / 20.0) * (P3 * P3)) +
+            (1421461.0 / 2275.0) * (P4 * P4);
+  double g[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double bb = beta[k] + c.eps;
+    double pw;
+    if (c.q == 7) {
+      const double b2 = bb * bb;
+      const double b4 = b2 * b2;
+      pw = (b4 * b2) * bb;
+    } else {
+      pw = 1.0;
+      for (int r = 0; r < c.q; ++r) pw = pw * bb;
+    }
+    g[k] = 1.0 / pw;  // gamma_k = (beta_k + eps)^-q  (Eq. 4.5)
+  }
+  const double s4 = ((g[0] + g[1]) + g[2]) + g[3];
+  if (!(g[3] < c.ct1 * s4)) return 1u;  // large stencil kept (Eqs. 4.6-4.7)
+  const double s3 = (g[0] + g[1]) + g[2];
+  unsigned f = 0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    if (!(g[k] < c.ct2 * s3)) f |= 2u << k;  // Eqs. 4.11-4.12
+  return f;
+}
+
+// Values and slopes (cell units) at x_{i-1/2} and x_{i+1/2} of the selected
+// reconstruction: out = {v(-1/2), s(-1/2), v(+1/2), s(+1/2)}.
+__device__ __forceinline__ void teno_face(const double* Q, unsigned flag, double* out) {
+#pragma clang fp contract(off)
+  const double a = Q[0], b = Q[1], c = Q[2], d = Q[3], e = Q[4];
+  if (flag & 1u) {
+    // Eq. 4.8, Eq. 4.9 and their mirror images
+    out[2] = ((((2.0 * a - 13.0 * b) + 47.0 * c) + 27.0 * d) - 3.0 * e) / 60.0;
+    out[3] = (((b - 15.0 * c) + 15.0 * d) - e) / 12.0;
+    out[0] = ((((27.0 * b - 3.0 * a) + 47.0 * c) - 13.0 * d) + 2.0 * e) / 60.0;
+    out[1] = (((a - 15.0 * b) + 15.0 * c) - d) / 12.0;
+    return;
+  }
+  // surviving small stencils averaged with d_k = 1/3 (Eqs. 4.13-4.14)
+  double w[3], ws = 0.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    w[k] = ((flag >> (k + 1)) & 1u) ? 1.0 / 3.0 : 0.0;
+    ws += w[k];
+  }
+  const double o0 = w[0] / ws, o1 = w[1] / ws, o2 = w[2] / ws;
+  const double vp0 = ((2.0 * a - 7.0 * b) + 11.0 * c) / 6.0;
+  const double vp1 = ((5.0 * c - b) + 2.0 * d) / 6.0;
+  const double vp2 = ((2.0 * c + 5.0 * d) - e) / 6.0;
+  const double dp0 = (a - 3.0 * b) + 2.0 * c;
+  const double dp12 = d - c;
+  const double vm0 = ((5.0 * b - a) + 2.0 * c) / 6.0;
+  const double vm1 = ((2.0 * b + 5.0 * c) - d) / 6.0;
+  const double vm2 = ((11.0 * c - 7.0 * d) + 2.0 * e) / 6.0;
+  const double dm01 = c - b;
+  const double dm2 = (3.0 * d - 2.0 * c) - e;
+  out[0] = ((0.0 + o0 * vm0) + o1 * vm1) + o2 * vm2;
+  out[1] = ((0.0 + o0 * dm01) + o1 * dm01) + o2 * dm2;
+  out[2] = ((0.0 + o0 * vp0) + o1 * vp1) + o2 * vp2;
+  out[3] = ((0.0 + o0 * dp0) + o1 * dp12) + o2 * dp12;
+}
+
+// Selected polynomial at the Gauss points s = -+1/(2 sqrt 3) (cell units):
+// val[m], der[m] for m = 0 (s-) and 1 (s+).  The values feed only the flux,
+// so contraction is allowed here.
+__device__ __forceinline__ void teno_gauss(const double* Q, unsigned flag, double* val, double* der) {
+  const double a = Q[0], b = Q[1], c = Q[2], d = Q[3], e = Q[4];
+  const double s = 0.28867513459481288225;  // 1/(2 sqrt 3)
+  double c0, c1, c2, c3 = 0.0, c4 = 0.0;
+  if (flag & 1u) {
+    c0 = ((2134.0 * c - 116.0 * (d + b)) + 9.0 * (e + a)) * (1.0 / 1920.0);
+    c1 = (34.0 * (d - b) - 5.0 * (e - a)) * (1.0 / 48.0);
+    c2 = ((12.0 * (d + b) - 22.0 * c) - (e + a)) * (1.0 / 16.0);
+    c3 = ((e - a) - 2.0 * (d - b)) * (1.0 / 12.0);
+    c4 = ((((a - 4.0 * b) + 6.0 * c) - 4.0 * d) + e) * (1.0 / 24.0);
+  } else {
+    const bool k0 = flag & 2u, k1 = flag & 4u, k2 = flag & 8u;
+    const double inv = 1.0 / (double)((int)k0 + (int)k1 + (int)k2);
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    if (k0) {
+      s0 += (23.0 * c + 2.0 * b - a) * (1.0 / 24.0);
+      s1 += (3.0 * c - 4.0 * b + a) * 0.5;
+      s2 += (c - 2.0 * b + a) * 0.5;
+    }
+    if (k1) {
+      s0 += (26.0 * c - d - b) * (1.0 / 24.0);
+      s1 += (d - b) * 0.5;
+      s2 += (d + b - 2.0 * c) * 0.5;
+    }
+    if (k2) {
+      s0 += (23.0 * c + 2.0 * d - e) * (1.0 / 24.0);
+      s1 += (4.0 * d - 3.0 * c - e) * 0.5;
+      s2 += (c - 2.0 * d + e) * 0.5;
+    }
+    c0 = s0 * inv;
+    c1 = s1 * inv;
+    c2 = s2 * inv;
+  }
+  const double ss = s * s;
+  const double even = c0 + ss * (c2 + ss * c4);          // p(s) + p(-s) halves
+  const double odd = s * (c1 + ss * c3);
+  val[0] = even - odd;
+  val[1] = even + odd;
+  const double deven = c1 + 3.0 * ss * c3;               // p'(s) even part
+  const double dodd = s * (2.0 * c2 + 4.0 * ss * c4);
+  der[0] = deven - dodd;
+  der[1] = deven + dodd;
+}
+
+// ---------------------------------------------------------------------------
+// Gas-kinetic flux at one Gauss point (Sec. 2.1), face frame: u1 is normal.
+// ---------------------------------------------------------------------------
+struct FluxCfg {
+  double N;          // K + D = 2/(gamma - 1)
+  double K;          // internal degrees of freedom
+  double mu, pr_fix; // viscosity; (1/Pr - 1) for the energy flux, 0 if Euler
+  double c1, c2;
+  int tau_mode;      // 0 inviscid, 1 viscous, 2 zero
+};
+
+constexpr int NM1 = 7;  // normal moment table <u1^n>, n = 0..6
+constexpr int NMT = 6;  // tangential tables <u_t^n>, n = 0..5
+
+template <int D>
+struct Gas {
+  double rho, irho, U[D], lam, h;  // h = 1/(2 lambda) = p / rho
+  bool ok;
+};
+
+template <int D>
+__device__ __forceinline__ void make_gas(const double* W, double N, Gas<D>& g) {
+  g.rho = W[0];
+  g.irho = 1.0 / g.rho;
+  double ru2 = 0.0;
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    g.U[d] = W[d + 1] * g.irho;
+    ru2 += g.U[d] * W[d + 1];
+  }
+  const double eint = W[D + 1] - 0.5 * ru2;  // rho E - rho |U|^2 / 2 = N p / 2
+  g.h = (2.0 / N) * eint * g.irho;           // p / rho = 1/(2 lambda)
+  g.lam = 0.5 / g.h;
+  g.ok = (g.rho > 0.0) && (eint > 0.0) && (g.rho < INFINITY) && (eint < INFINITY);
+}
+
+__device__ __forceinline__ void full_table(double U, double h, double* m, int n) {
+  m[0] = 1.0;
+  m[1] = U;
+  for (int k = 1; k + 1 < n; ++k) m[k + 1] = U * m[k] + (double)k * h * m[k - 1];
+}
+
+// half-space table from its first two entries
+__device__ __forceinline__ void half_table(double U, double h, double m0, double m1, double* m) {
+  m[0] = m0;
+  m[1] = m1;
+#pragma unroll
+  for (int k = 1; k + 1 < NM1; ++k) m[k + 1] = U * m[k] + (double)k * h * m[k - 1];
+}
+
+// first two half-space moments: sgn = +1 (u1 > 0) or -1 (u1 < 0)
+__device__ __forceinline__ void half_seed(double U, double lam, double sgn, double& m0, double& m1) {
+  const double sl = sqrt(lam);
+  m0 = 0.5 * erfc(-sgn * sl * U);
+  m1 = U * m0 + sgn * 0.5 * exp(-lam * U * U) / (sl * 1.7724538509055160273);
+}
+
+template <int D>
+struct MomSet {
+  double m1[NM1];
+  double mt[D > 1 ? D - 1 : 1][NMT];
+  double xi1, xi2;  // <xi^2>, <xi^4>
+};
+
+template <int D>
+__device__ __forceinline__ double mono(const MomSet<D>& S, int i, int j, int k) {
+  double v = S.m1[i];
+  if (D >= 2) v *= S.mt[0][j];
+  if (D >= 3) v *= S.mt[D >= 3 ? 1 : 0][k];
+  return v;
+}
+
+// g[alpha] = <psi_alpha u1^i u2^j u3^k xi^(2l)>, l in {0, 1}
+template <int D>
+__device__ __forceinline__ void gpsi(const MomSet<D>& S, int i, int j, int k, int l, double* g) {
+  const double xl = l == 0 ? 1.0 : S.xi1;
+  const double xl1 = l == 0 ? S.xi1 : S.xi2;
+  const double base = mono(S, i, j, k);
+  g[0] = base * xl;
+  g[1] = mono(S, i + 1, j, k) * xl;
+  if (D >= 2) g[2] = mono(S, i, j + 1, k) * xl;
+  if (D >= 3) g[3] = mono(S, i, j, k + 1) * xl;
+  double e = mono(S, i + 2, j, k);
+  if (D >= 2) e += mono(S, i, j + 2, k);
+  if (D >= 3) e += mono(S, i, j, k + 2);
+  g[D + 1] = 0.5 * (e * xl + base * xl1);
+}
+
+// out[alpha] (+)= s * <psi_alpha a(psi) u1^i u2^j u3^k>
+template <int D, bool ACC>
+__device__ __forceinline__ void mpsia(const MomSet<D>& S, const double* a, int i, int j, int k, double s,
+                                      double* out) {
+  constexpr int NC = D + 2;
+  double g[NC], t[NC], r[NC];
+  gpsi<D>(S, i, j, k, 0, g);
+#pragma unroll
+  for (int q = 0; q < NC; ++q) r[q] = a[0] * g[q];
+  gpsi<D>(S, i + 1, j, k, 0, g);
+#pragma unroll
+  for (int q = 0; q < NC; ++q) r[q] += a[1] * g[q];
+  if (D >= 2) {
+    gpsi<D>(S, i, j + 1, k, 0, g);
+#pragma unroll
+    for (int q = 0; q < NC; ++q) r[q] += a[2] * g[q];
+  }
+  if (D >= 3) {
+    gpsi<D>(S, i, j, k + 1, 0, g);
+#pragma unroll
+    for (int q = 0; q < NC; ++q) r[q] += a[D >= 3 ? 3 : 0] * g[q];
+  }
+  gpsi<D>(S, i + 2, j, k, 0, t);
+  if (D >= 2) {
+    gpsi<D>(S, i, j + 2, k, 0, g);
+#pragma unroll
+    for (int q = 0; q < NC; ++q) t[q] += g[q];
+  }
+  if (D >= 3) {
+    gpsi<D>(S, i, j, k + 2, 0, g);
+#pragma unroll
+    for (int q = 0; q < NC; ++q) t[q] += g[q];
+  }
+  gpsi<D>(S, i, j, k, 1, g);
+  const double ae = 0.5 * a[NC - 1];
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+    const double v = r[q] + ae * (t[q] + g[q]);
+    out[q] = ACC ? out[q] + s * v : s * v;
+  }
+}
+
+// closed-form solution a of <a psi> = b (per unit density) over the full
+// Maxwellian (U, lambda), N = K + D.
+template <int D>
+__device__ __forceinline__ void micro_solve(const Gas<D>& g, double N, const double* b, double* a) {
+  double ub = 0.0, u2 = 0.0;
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    ub += g.U[d] * b[d + 1];
+    u2 += g.U[d] * g.U[d];
+  }
+  const double lam = g.lam;
+  const double aE = (4.0 * lam * lam / N) * (2.0 * b[D + 1] - 2.0 * ub + (u2 - N * g.h) * b[0]);
+  double ua = 0.0;
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    a[d + 1] = 2.0 * lam * (b[d + 1] - g.U[d] * b[0]) - g.U[d] * aE;
+    ua += g.U[d] * a[d + 1];
+  }
+  a[D + 1] = aE;
+  a[0] = b[0] - ua - 0.5 * aE * (u2 + N * g.h);
+}
+
+template <int D>
+__device__ __forceinline__ void tangential_tables(const Gas<D>& g, MomSet<D>& S) {
+#pragma unroll
+  for (int d = 1; d < D; ++d) full_table(g.U[d], g.h, S.mt[d - 1], NMT);
+}
+
+template <int D>
+__device__ __forceinline__ void xi_moments(const Gas<D>& g, double K, MomSet<D>& S) {
+  S.xi1 = K * g.h;
+  S.xi2 = K * (K + 2.0) * g.h * g.h;
+}
+
+// index helper: (i, j, k) offsets of u_d
+template <int D>
+__device__ __forceinline__ void unit(int d, int& i, int& j, int& k) {
+  i = d == 0;
+  j = d == 1;
+  k = d == 2;
+}
+
+// heat-flux moment <phi X> from <u1 psi X> (f1) and <psi X> (f0):
+// phi = (u1 - c1)(psi_E - c.u + |c|^2/2), c = U0 (face frame)
+template <int D>
+__device__ __forceinline__ double heat_combine(const double* f1, const double* f0, const double* c) {
+  double c2 = 0.0, s1 = f1[D + 1], s0 = f0[D + 1];
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    c2 += c[d] * c[d];
+    s1 -= c[d] * f1[d + 1];
+    s0 -= c[d] * f0[d + 1];
+  }
+  s1 += 0.5 * c2 * f1[0];
+  s0 += 0.5 * c2 * f0[0];
+  return s1 - c[0] * s0;
+}
+
+// Time-integrated flux F(dt) and F(dt/2) at one Gauss point.
+// Wl, Wr: states; dWl[d], dWr[d]: derivatives along frame axis d.
+// Returns false when a state is non-physical.
+template <int D, bool NS>
+__device__ __forceinline__ bool gp_flux(const double* Wl, const double* Wr, const double (*dWl)[D + 2],
+                                        const double (*dWr)[D + 2], const FluxCfg& P, double dt,
+                                        double* Fdt, double* Fh) {
+  constexpr int NC = D + 2;
+  const double N = P.N;
+  Gas<D> gl, gr;
+  make_gas<D>(Wl, N, gl);
+  make_gas<D>(Wr, N, gr);
+  double hl0, hl1, hr0, hr1;
+  half_seed(gl.U[0], gl.lam, 1.0, hl0, hl1);
+  half_seed(gr.U[0], gr.lam, -1.0, hr0, hr1);
+
+  // equilibrium state by kinetic weighting (Eq. 2.6): rho_l <psi>_{>0} + rho_r <psi>_{<0}
+  double W0[NC];
+  {
+    MomSet<D> S;
+    half_table(gl.U[0], gl.h, hl0, hl1, S.m1);
+    tangential_tables<D>(gl, S);
+    xi_moments<D>(gl, P.K, S);
+    double g[NC];
+    gpsi<D>(S, 0, 0, 0, 0, g);
+#pragma unroll
+    for (int q = 0; q < NC; ++q) W0[q] = gl.rho * g[q];
+    half_table(gr.U[0], gr.h, hr0, hr1, S.m1);
+    tangential_tables<D>(gr, S);
+    xi_moments<D>(gr, P.K, S);
+    gpsi<D>(S, 0, 0, 0, 0, g);
+#pragma unroll
+    for (int q = 0; q < NC; ++q) W0[q] += gr.rho * g[q];
+  }
+  Gas<D> g0;
+  make_gas<D>(W0, N, g0);
+
+  // side contributions: dW0 (Eq. 2.6), A^s (Eq. 2.7), and the moments of the
+  // non-equilibrium part of Eq. 2.5
+  double dW0[D][NC], S1[NC], S2[NC], S3[NC];
+  double H1 = 0.0, H2 = 0.0, H3 = 0.0;  // heat-flux moments (NS)
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    const Gas<D>& gs = side == 0 ? gl : gr;
+    const double(*dW)[NC] = side == 0 ? dWl : dWr;
+    MomSet<D> Sh, Sf;
+    if (side == 0)
+      half_table(gs.U[0], gs.h, hl0, hl1, Sh.m1);
+    else
+      half_table(gs.U[0], gs.h, hr0, hr1, Sh.m1);
+    tangential_tables<D>(gs, Sh);
+    xi_moments<D>(gs, P.K, Sh);
+    full_table(gs.U[0], gs.h, Sf.m1, NM1);
+#pragma unroll
+    for (int d = 1; d < D; ++d)
+#pragma unroll
+      for (int n = 0; n < NMT; ++n) Sf.mt[d - 1][n] = Sh.mt[d - 1][n];
+    Sf.xi1 = Sh.xi1;
+    Sf.xi2 = Sh.xi2;
+    double a[D][NC];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      double b[NC];
+#pragma unroll
+      for (int q = 0; q < NC; ++q) b[q] = dW[d][q] * gs.irho;
+      micro_solve<D>(gs, N, b, a[d]);
+      if (side == 0)
+        mpsia<D, false>(Sh, a[d], 0, 0, 0, gs.rho, dW0[d]);
+      else
+        mpsia<D, true>(Sh, a[d], 0, 0, 0, gs.rho, dW0[d]);
+    }
+    // A^s: <A psi> = -sum_d <u_d a_d psi> over the full g_s
+    double rhs[NC], A[NC];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      int i, j, k;
+      unit<D>(d, i, j, k);
+      if (d == 0)
+        mpsia<D, false>(Sf, a[d], i, j, k, -1.0, rhs);
+      else
+        mpsia<D, true>(Sf, a[d], i, j, k, -1.0, rhs);
+    }
+    micro_solve<D>(gs, N, rhs, A);
+    // <u1 psi>, sum_d <u1 u_d psi a_d>, <u1 psi A> over the half space
+    double g[NC];
+    gpsi<D>(Sh, 1, 0, 0, 0, g);
+    double v2[NC];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      int i, j, k;
+      unit<D>(d, i, j, k);
+      if (d == 0)
+        mpsia<D, false>(Sh, a[d], 1 + i, j, k, 1.0, v2);
+      else
+        mpsia<D, true>(Sh, a[d], 1 + i, j, k, 1.0, v2);
+    }
+    double v3[NC];
+    mpsia<D, false>(Sh, A, 1, 0, 0, 1.0, v3);
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      S1[q] = side == 0 ? gs.rho * g[q] : S1[q] + gs.rho * g[q];
+      S2[q] = side == 0 ? gs.rho * v2[q] : S2[q] + gs.rho * v2[q];
+      S3[q] = side == 0 ? gs.rho * v3[q] : S3[q] + gs.rho * v3[q];
+    }
+    if (NS) {
+      double f0[NC], w2[NC], w3[NC];
+      gpsi<D>(Sh, 0, 0, 0, 0, f0);
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        int i, j, k;
+        unit<D>(d, i, j, k);
+        if (d == 0)
+          mpsia<D, false>(Sh, a[d], i, j, k, 1.0, w2);
+        else
+          mpsia<D, true>(Sh, a[d], i, j, k, 1.0, w2);
+      }
+      mpsia<D, false>(Sh, A, 0, 0, 0, 1.0, w3);
+      H1 += gs.rho * heat_combine<D>(g, f0, g0.U);
+      H2 += gs.rho * heat_combine<D>(v2, w2, g0.U);
+      H3 += gs.rho * heat_combine<D>(v3, w3, g0.U);
+    }
+  }
+
+  // equilibrium part: abar_d, Abar (Eq. 2.7) and its moments
+  double V1[NC], V2[NC], V3[NC];
+  double G1 = 0.0, G2 = 0.0, G3 = 0.0;
+  {
+    MomSet<D> S;
+    full_table(g0.U[0], g0.h, S.m1, NM1);
+    tangential_tables<D>(g0, S);
+    xi_moments<D>(g0, P.K, S);
+    double ab[D][NC];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      double b[NC];
+#pragma unroll
+      for (int q = 0; q < NC; ++q) b[q] = dW0[d][q] * g0.irho;
+      micro_solve<D>(g0, N, b, ab[d]);
+    }
+    double rhs[NC], Ab[NC];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      int i, j, k;
+      unit<D>(d, i, j, k);
+      if (d == 0)
+        mpsia<D, false>(S, ab[d], i, j, k, -1.0, rhs);
+      else
+        mpsia<D, true>(S, ab[d], i, j, k, -1.0, rhs);
+    }
+    micro_solve<D>(g0, N, rhs, Ab);
+    gpsi<D>(S, 1, 0, 0, 0, V1);
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      int i, j, k;
+      unit<D>(d, i, j, k);
+      if (d == 0)
+        mpsia<D, false>(S, ab[d], 1 + i, j, k, 1.0, V2);
+      else
+        mpsia<D, true>(S, ab[d], 1 + i, j, k, 1.0, V2);
+    }
+    mpsia<D, false>(S, Ab, 1, 0, 0, 1.0, V3);
+    if (NS) {
+      double f0[NC], w3[NC];
+      gpsi<D>(S, 0, 0, 0, 0, f0);
+      mpsia<D, false>(S, Ab, 0, 0, 0, 1.0, w3);
+      // <psi sum_d u_d abar_d> = -<psi Abar> by the compatibility condition
+      double w2[NC];
+#pragma unroll
+      for (int q = 0; q < NC; ++q) w2[q] = -w3[q];
+      G1 = heat_combine<D>(V1, f0, g0.U);
+      G2 = heat_combine<D>(V2, w2, g0.U);
+      G3 = heat_combine<D>(V3, w3, g0.U);
+    }
+  }
+
+  // collision time (Sec. 5 preamble); dt is the full step in both stages
+  const double pl = gl.rho * gl.h, pr = gr.rho * gr.h;
+  const double jump = fabs(pl - pr) / (pl + pr);
+  double tau;
+  if (P.tau_mode == 2)
+    tau = 0.0;
+  else if (P.tau_mode == 1)
+    tau = P.mu / (g0.rho * g0.h) + P.c2 * jump * dt;
+  else
+    tau = (P.c1 + P.c2 * jump) * dt;
+
+#pragma unroll
+  for (int id = 0; id < 2; ++id) {
+    const double dl = id == 0 ? dt : 0.5 * dt;
+    double e, ome;
+    if (tau == 0.0) {
+      e = 0.0;
+      ome = 1.0;
+    } else {
+      const double x = -dl / tau;
+      e = exp(x);
+      ome = -expm1(x);
+    }
+    const double tt = tau * tau * ome;
+    const double C1 = dl - tau * ome;
+    const double C2 = 2.0 * tt - tau * dl * (1.0 + e);
+    const double C3 = 0.5 * dl * dl - tau * dl + tt;
+    const double C4 = tau * ome;
+    const double C5 = tau * dl * e - 2.0 * tt;
+    const double C6 = -tt;
+    double* F = id == 0 ? Fdt : Fh;
+#pragma unroll
+    for (int q = 0; q < NC; ++q)
+      F[q] = g0.rho * (C1 * V1[q] + C2 * V2[q] + C3 * V3[q]) + (C4 * S1[q] + C5 * S2[q] + C6 * S3[q]);
+    if (NS) {
+      const double q = g0.rho * (C1 * G1 + C2 * G2 + C3 * G3) + (C4 * H1 + C5 * H2 + C6 * H3);
+      F[NC - 1] += P.pr_fix * q;
+    }
+  }
+  return gl.ok && gr.ok && g0.ok;
+}
+
+// ---------------------------------------------------------------------------
+// Boundary index map (ghost cells): periodic, transmissive (copy of the
+// nearest cell) or reflective (mirror image, normal momentum negated).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int map_index(int i, int n, int bclo, int bchi, int& flip) {
+  if (i >= 0 && i < n) return i;
+  const int bc = i < 0 ? bclo : bchi;
+  if (bc == 0) {
+    int r = i % n;
+    return r < 0 ? r + n : r;
+  }
+  if (bc == 1) return i < 0 ? 0 : n - 1;
+  flip ^= 1;
+  // mirror image; cells farther than n outside are never used by a face and
+  // are clamped into the domain so that every load stays in bounds
+  const int r = i < 0 ? -1 - i : 2 * n - 1 - i;
+  return r < 0 ? 0 : (r >= n ? n - 1 : r);
+}
+
+}  // namespace tgks

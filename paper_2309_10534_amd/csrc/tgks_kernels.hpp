@@ -1,0 +1,547 @@
+// tgks_kernels.hpp -- HIP kernels of one S2O4 step of the TENO-D GKS (gfx950).
+//
+// Per stage and direction a face kernel produces, for every face, the
+// Gauss-point averaged time-integrated fluxes combined as the S2O4 update
+// needs them (Sec. 2.2):
+//   stage 1:  FA = F(W^n, dt/2),  FB = 8/3 F(W^n, dt/2) - 1/3 F(W^n, dt)
+//   stage 2:  FA = 4/3 F(W*, dt) - 8/3 F(W*, dt/2)
+// so that  W* = W^n - sum_d D_d FA / dx_d,  P = W^n - sum_d D_d FB / dx_d,
+// W^{n+1} = P - sum_d D_d FA* / dx_d, algebraically the update of Sec. 2.2.
+// The update kernels apply the flux differences; the stage-2 update also
+// reduces the CFL time step of the new state (Sec. 5 preamble).
+#pragma once
+#include "tgks_device.hpp"
+
+namespace tgks {
+
+struct Geom {
+  int D;
+  int n[3];
+  double dx[3];
+  int bclo[3], bchi[3];
+  long long ncell;
+};
+
+struct StageArgs {
+  Geom g;
+  FluxCfg fc;
+  TenoCfg tn;  // normal reconstruction
+  TenoCfg tt;  // tangential reconstruction
+  const double* W;
+  double* FA;
+  double* FB;
+  const double* dt;
+  unsigned long long* fail;
+  uint8_t* nflags;  // normal flags [D][nc][cells] or null
+  uint8_t* tflags;  // tangential flags of this direction or null
+  const double* R;  // 3-D: normal reconstruction of this direction
+  double* Rout;
+};
+
+__device__ __forceinline__ long long face_count(const Geom& g, int ax) {
+  long long c = 1;
+  for (int d = 0; d < 3; ++d) c *= (long long)(d == ax ? g.n[d] + 1 : g.n[d]);
+  return c;
+}
+
+// value of component c (global order) of the cell (i, j, k), ghost cells by
+// the boundary index map
+__device__ __forceinline__ double load_cell(const Geom& g, const double* W, int c, int i, int j, int k) {
+  int f0 = 0, f1 = 0, f2 = 0;
+  const int ii = map_index(i, g.n[0], g.bclo[0], g.bchi[0], f0);
+  const int jj = g.D >= 2 ? map_index(j, g.n[1], g.bclo[1], g.bchi[1], f1) : 0;
+  const int kk = g.D >= 3 ? map_index(k, g.n[2], g.bclo[2], g.bchi[2], f2) : 0;
+  double v = W[(long long)c * g.ncell + ((long long)kk * g.n[1] + jj) * g.n[0] + ii];
+  const int fl = c == 1 ? f0 : c == 2 ? f1 : c == 3 ? f2 : 0;
+  if (c >= 1 && c <= g.D && fl) v = -v;
+  return v;
+}
+
+template <int NC>
+__device__ __forceinline__ void write_combined(int STAGE, const double* Fdt, const double* Fh, double w,
+                                               double* accA, double* accB) {
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+    if (STAGE == 1) {
+      accA[q] += w * Fh[q];
+      accB[q] += w * ((8.0 / 3.0) * Fh[q] - (1.0 / 3.0) * Fdt[q]);
+    } else {
+      accA[q] += w * ((4.0 / 3.0) * Fdt[q] - (8.0 / 3.0) * Fh[q]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 1-D: one thread per face.
+// ---------------------------------------------------------------------------
+template <int STAGE, bool NS, bool FLAGS>
+__global__ __launch_bounds__(256) void face1d_kernel(StageArgs a) {
+  const double dt = *a.dt;
+  if (!(dt > 0.0)) return;
+  const int n = a.g.n[0];
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f > n) return;
+  double Wl[3], Wr[3], dWl[1][3], dWr[1][3];
+  const double dx = a.g.dx[0];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    double Q[6];
+#pragma unroll
+    for (int r = 0; r < 6; ++r) Q[r] = load_cell(a.g, a.W, c, f - 3 + r, 0, 0);
+    double o[4];
+    const unsigned fl = teno_flag(Q, a.tn);
+    teno_face(Q, fl, o);
+    Wl[c] = o[2];
+    dWl[0][c] = o[3] / dx;
+    const unsigned fr = teno_flag(Q + 1, a.tn);
+    teno_face(Q + 1, fr, o);
+    Wr[c] = o[0];
+    dWr[0][c] = o[1] / dx;
+    if (FLAGS && f < n) a.nflags[(long long)c * n + f] = (uint8_t)fr;
+  }
+  double Fdt[3], Fh[3], A[3] = {0, 0, 0}, B[3] = {0, 0, 0};
+  const bool ok = gp_flux<1, NS>(Wl, Wr, dWl, dWr, a.fc, dt, Fdt, Fh);
+  if (!ok) atomicAdd(a.fail, 1ull);
+  write_combined<3>(STAGE, Fdt, Fh, 1.0, A, B);
+  const long long nf = n + 1;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    a.FA[c * nf + f] = A[c];
+    if (STAGE == 1) a.FB[c * nf + f] = B[c];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 2-D: fused face kernel.  A block owns TN faces along the normal axis AX by
+// TT rows along the tangential axis.  It stages the cells of the tile with a
+// halo of 3 (normal) and 2 (tangential) in LDS, reconstructs every needed
+// cell once along AX into LDS (values and normal slopes on both faces), and
+// then each thread reconstructs its face's left and right states along the
+// face at the two Gauss points and evaluates the two Gauss-point fluxes.
+// ---------------------------------------------------------------------------
+constexpr int TN2 = 16, TT2 = 16;
+
+template <int AX, int STAGE, bool NS, bool FLAGS>
+__global__ __launch_bounds__(256) void face2d_kernel(StageArgs a) {
+  constexpr int NC = 4;
+  constexpr int LN = TN2 + 5, LT = TT2 + 4, RN = TN2 + 1;
+  __shared__ double sW[NC][LT][LN];
+  __shared__ double sR[NC][LT][RN][4];
+  const double dt = *a.dt;
+  if (!(dt > 0.0)) return;
+  const Geom& g = a.g;
+  const int TA = 1 - AX;                      // tangential axis
+  const int nN = g.n[AX], nT = g.n[TA];
+  const int f0 = blockIdx.x * TN2, t0 = blockIdx.y * TT2;
+  const int tid = threadIdx.x;
+
+  // 1. cells of the tile, ghost cells by the index map
+  for (int L = tid; L < NC * LN * LT; L += 256) {
+    int c, nl, tl;
+    if (AX == 0) {
+      nl = L % LN;
+      tl = (L / LN) % LT;
+    } else {
+      tl = L % LT;
+      nl = (L / LT) % LN;
+    }
+    c = L / (LN * LT);
+    const int pn = f0 - 3 + nl, pt = t0 - 2 + tl;
+    const int x = AX == 0 ? pn : pt, y = AX == 0 ? pt : pn;
+    sW[c][tl][nl] = load_cell(g, a.W, c, x, y, 0);
+  }
+  __syncthreads();
+
+  // 2. normal reconstruction of cells f0-1 .. f0+TN2-1 on every staged row
+  const double dn = g.dx[AX];
+  for (int L = tid; L < NC * LT * RN; L += 256) {
+    const int nr = L % RN;
+    const int tl = (L / RN) % LT;
+    const int c = L / (RN * LT);
+    const double* Q = &sW[c][tl][nr];
+    const unsigned fl = teno_flag(Q, a.tn);
+    double o[4];
+    teno_face(Q, fl, o);
+    sR[c][tl][nr][0] = o[0];
+    sR[c][tl][nr][1] = o[1] / dn;
+    sR[c][tl][nr][2] = o[2];
+    sR[c][tl][nr][3] = o[3] / dn;
+    if (FLAGS) {
+      const int cell = f0 - 1 + nr, row = t0 - 2 + tl;
+      if (nr >= 1 && cell < nN && tl >= 2 && tl < TT2 + 2 && row < nT) {
+        const long long lin = AX == 0 ? (long long)row * g.n[0] + cell : (long long)cell * g.n[0] + row;
+        a.nflags[((long long)AX * NC + c) * g.ncell + lin] = (uint8_t)fl;
+      }
+    }
+  }
+  __syncthreads();
+
+  // 3. tangential reconstruction and Gauss-point fluxes, one face per thread
+  const int fn = tid % TN2, ft = tid / TN2;
+  const int f = f0 + fn, t = t0 + ft;
+  if (f > nN || t >= nT) return;
+  const double dtan = g.dx[TA];
+  // frame component q -> global component
+  const int perm[NC] = {0, 1 + AX, 1 + TA, 3};
+  double Wg[2][2][NC], Dg[2][2][2][NC];  // [gp][side][q], [gp][side][axis n/t][q]
+  const long long nf = face_count(g, AX);
+  const long long fidx = AX == 0 ? (long long)t * (g.n[0] + 1) + f : (long long)f * g.n[0] + t;
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    const int nr = side == 0 ? fn : fn + 1;
+    const int vo = side == 0 ? 2 : 0;
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      const int c = perm[q];
+      double Qw[5], Qn[5];
+#pragma unroll
+      for (int r = 0; r < 5; ++r) {
+        Qw[r] = sR[c][ft + r][nr][vo];
+        Qn[r] = sR[c][ft + r][nr][vo + 1];
+      }
+      const unsigned fw = teno_flag(Qw, a.tt);
+      const unsigned fq = teno_flag(Qn, a.tt);
+      if (FLAGS) {
+        a.tflags[((long long)(0 * 2 + side) * NC + c) * nf + fidx] = (uint8_t)fw;
+        a.tflags[((long long)(1 * 2 + side) * NC + c) * nf + fidx] = (uint8_t)fq;
+      }
+      double v[2], dv[2], vn[2], dvn[2];
+      teno_gauss(Qw, fw, v, dv);
+      teno_gauss(Qn, fq, vn, dvn);
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        Wg[m][side][q] = v[m];
+        Dg[m][side][1][q] = dv[m] / dtan;
+        Dg[m][side][0][q] = vn[m];
+      }
+    }
+  }
+  double A[NC] = {0, 0, 0, 0}, B[NC] = {0, 0, 0, 0};
+  unsigned bad = 0;
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    double Fdt[NC], Fh[NC];
+    if (!gp_flux<2, NS>(Wg[m][0], Wg[m][1], Dg[m][0], Dg[m][1], a.fc, dt, Fdt, Fh)) ++bad;
+    write_combined<NC>(STAGE, Fdt, Fh, 0.5, A, B);
+  }
+  if (bad) atomicAdd(a.fail, (unsigned long long)bad);
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+    a.FA[(long long)perm[q] * nf + fidx] = A[q];
+    if (STAGE == 1) a.FB[(long long)perm[q] * nf + fidx] = B[q];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 3-D.  (a) normal reconstruction along AX of every cell with AX index in
+// [-1, n] (interior in the other axes): R[c][4][k][j][i'] with the AX index
+// shifted by one, values and slopes on both faces.
+// ---------------------------------------------------------------------------
+template <int AX, bool FLAGS>
+__global__ __launch_bounds__(256) void recon3d_kernel(StageArgs a) {
+  const Geom& g = a.g;
+  int ext[3] = {g.n[0], g.n[1], g.n[2]};
+  ext[AX] += 2;
+  const long long nr = (long long)ext[0] * ext[1] * ext[2];
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= nr * 5) return;
+  const int c = (int)(id / nr);
+  long long r = id % nr;
+  int p[3];
+  p[0] = (int)(r % ext[0]);
+  r /= ext[0];
+  p[1] = (int)(r % ext[1]);
+  p[2] = (int)(r / ext[1]);
+  p[AX] -= 1;
+  double Q[5];
+#pragma unroll
+  for (int s = 0; s < 5; ++s) {
+    int q3[3] = {p[0], p[1], p[2]};
+    q3[AX] += s - 2;
+    Q[s] = load_cell(g, a.W, c, q3[0], q3[1], q3[2]);
+  }
+  const unsigned fl = teno_flag(Q, a.tn);
+  double o[4];
+  teno_face(Q, fl, o);
+  const double dn = g.dx[AX];
+  const long long base = (long long)c * 4 * nr + (id % nr);
+  a.Rout[base] = o[0];
+  a.Rout[base + nr] = o[1] / dn;
+  a.Rout[base + 2 * nr] = o[2];
+  a.Rout[base + 3 * nr] = o[3] / dn;
+  if (FLAGS && p[AX] >= 0 && p[AX] < g.n[AX])
+    a.nflags[((long long)AX * 5 + c) * g.ncell + ((long long)p[2] * g.n[1] + p[1]) * g.n[0] + p[0]] = (uint8_t)fl;
+}
+
+// (b) face kernel: four lanes per face, one Gauss point each.  The
+// tangential reconstruction runs along t1 and then t2 with the cyclic axis
+// order (x-faces: y, z; y-faces: z, x; z-faces: x, y).
+template <int AX, int STAGE, bool NS>
+__global__ __launch_bounds__(256) void face3d_kernel(StageArgs a) {
+  constexpr int NC = 5;
+  const double dt = *a.dt;
+  if (!(dt > 0.0)) return;
+  const Geom& g = a.g;
+  constexpr int T1 = (AX + 1) % 3, T2 = (AX + 2) % 3;
+  const long long nf = face_count(g, AX);
+  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int gp = (int)(gid & 3);
+  const long long fid = gid >> 2;
+  const bool live = fid < nf;
+  int fp[3] = {0, 0, 0};
+  if (live) {
+    long long r = fid;
+    int nfa[3] = {g.n[0], g.n[1], g.n[2]};
+    nfa[AX] += 1;
+    fp[0] = (int)(r % nfa[0]);
+    r /= nfa[0];
+    fp[1] = (int)(r % nfa[1]);
+    fp[2] = (int)(r / nfa[1]);
+  }
+  const int m1 = gp & 1, m2 = gp >> 1;
+  int ext[3] = {g.n[0], g.n[1], g.n[2]};
+  ext[AX] += 2;
+  const long long nr = (long long)ext[0] * ext[1] * ext[2];
+  const int perm[NC] = {0, 1 + AX, 1 + T1, 1 + T2, 4};
+  const double d1 = g.dx[T1], d2 = g.dx[T2];
+  double Wg[2][NC], Dg[2][3][NC];
+  if (live) {
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const int pa = fp[AX] - 1 + side;  // cell index along AX (may be -1 or n)
+      const int vo = side == 0 ? 2 : 0;
+#pragma unroll 1
+      for (int q = 0; q < NC; ++q) {
+        const int c = perm[q];
+        double S1w[5], S1d[5], S1n[5];
+#pragma unroll
+        for (int r2 = 0; r2 < 5; ++r2) {
+          double Qw[5], Qn[5];
+#pragma unroll
+          for (int r1 = 0; r1 < 5; ++r1) {
+            int pc[3];
+            pc[AX] = pa;
+            int fl1 = 0, fl2 = 0;
+            pc[T1] = map_index(fp[T1] - 2 + r1, g.n[T1], g.bclo[T1], g.bchi[T1], fl1);
+            pc[T2] = map_index(fp[T2] - 2 + r2, g.n[T2], g.bclo[T2], g.bchi[T2], fl2);
+            int e[3] = {pc[0], pc[1], pc[2]};
+            e[AX] += 1;
+            const long long off = ((long long)e[2] * ext[1] + e[1]) * ext[0] + e[0];
+            double vw = a.R[(long long)c * 4 * nr + vo * nr + off];
+            double vn = a.R[(long long)c * 4 * nr + (vo + 1) * nr + off];
+            const bool flip = (c == 1 + T1 && fl1) ^ (c == 1 + T2 && fl2);
+            if (flip) {
+              vw = -vw;
+              vn = -vn;
+            }
+            Qw[r1] = vw;
+            Qn[r1] = vn;
+          }
+          double v[2], dv[2], vn2[2], dvn2[2];
+          teno_gauss(Qw, teno_flag(Qw, a.tt), v, dv);
+          teno_gauss(Qn, teno_flag(Qn, a.tt), vn2, dvn2);
+          S1w[r2] = v[m1];
+          S1d[r2] = dv[m1] / d1;
+          S1n[r2] = vn2[m1];
+        }
+        double v[2], dv[2], x[2], dx_[2];
+        teno_gauss(S1w, teno_flag(S1w, a.tt), v, dv);
+        Wg[side][q] = v[m2];
+        Dg[side][2][q] = dv[m2] / d2;
+        teno_gauss(S1d, teno_flag(S1d, a.tt), x, dx_);
+        Dg[side][1][q] = x[m2];
+        teno_gauss(S1n, teno_flag(S1n, a.tt), x, dx_);
+        Dg[side][0][q] = x[m2];
+      }
+    }
+  }
+  double Fdt[NC] = {0, 0, 0, 0, 0}, Fh[NC] = {0, 0, 0, 0, 0};
+  if (live) {
+    if (!gp_flux<3, NS>(Wg[0], Wg[1], Dg[0], Dg[1], a.fc, dt, Fdt, Fh)) atomicAdd(a.fail, 1ull);
+  }
+  double A[NC] = {0, 0, 0, 0, 0}, B[NC] = {0, 0, 0, 0, 0};
+  write_combined<NC>(STAGE, Fdt, Fh, 0.25, A, B);
+  // sum over the four Gauss points held by lanes 4k..4k+3
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+    A[q] += __shfl_xor(A[q], 1);
+    A[q] += __shfl_xor(A[q], 2);
+    if (STAGE == 1) {
+      B[q] += __shfl_xor(B[q], 1);
+      B[q] += __shfl_xor(B[q], 2);
+    }
+  }
+  if (live && gp == 0) {
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      a.FA[(long long)perm[q] * nf + fid] = A[q];
+      if (STAGE == 1) a.FB[(long long)perm[q] * nf + fid] = B[q];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Updates.  Face arrays of direction d: [nc][faces_d] with the face index of
+// cell (i,j,k)'s low face equal to the cell index in a grid whose axis d has
+// n[d] + 1 entries.
+// ---------------------------------------------------------------------------
+struct UpdateArgs {
+  Geom g;
+  const double* W;    // stage 1: W^n; stage 2: P
+  double* out1;       // stage 1: W*; stage 2: W^{n+1}
+  double* out2;       // stage 1: P
+  const double* FA[3];
+  const double* FB[3];
+  const double* dt;
+  double gamma, mu;
+  double* partial;    // stage 2 with CFL: one minimum per block, or null
+};
+
+__device__ __forceinline__ double block_min(double v, double* red) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (l == 0) red[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < (int)(blockDim.x >> 6); ++i) v = fmin(v, red[i]);
+  }
+  return v;
+}
+
+// local CFL limit of one cell (Sec. 5 preamble); NaN for a non-physical state
+template <int D>
+__device__ __forceinline__ double cell_dt(const double* w, double gamma, double mu, double dxm) {
+  const double rho = w[0];
+  double ke = 0.0;
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    const double u = w[d + 1] / rho;
+    ke += u * u;
+  }
+  const double p = (gamma - 1.0) * (w[D + 1] - 0.5 * rho * ke);
+  if (!(rho > 0.0) || !(p > 0.0)) return NAN;
+  double v = dxm / (sqrt(ke) + sqrt(gamma * p / rho));
+  if (mu > 0.0) v = fmin(v, dxm * dxm * rho / (4.0 * mu));
+  return v;
+}
+
+template <int D, int STAGE, bool CFL>
+__global__ __launch_bounds__(256) void update_kernel(UpdateArgs u) {
+  constexpr int NC = D + 2;
+  __shared__ double red[4];
+  const Geom& g = u.g;
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = id < g.ncell;
+  const double dt = *u.dt;
+  const bool adv = dt > 0.0;
+  double w1[NC];
+  if (live) {
+    const int i = (int)(id % g.n[0]);
+    const int j = D >= 2 ? (int)((id / g.n[0]) % g.n[1]) : 0;
+    const int k = D >= 3 ? (int)(id / ((long long)g.n[0] * g.n[1])) : 0;
+    long long lo[3], hi[3], nf[3];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const int e0 = g.n[0] + (d == 0), e1 = g.n[1] + (d == 1);
+      nf[d] = (long long)e0 * e1 * (g.n[2] + (d == 2));
+      lo[d] = ((long long)k * e1 + j) * e0 + i;
+      hi[d] = lo[d] + (d == 0 ? 1 : d == 1 ? (long long)e0 : (long long)e0 * e1);
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const double w = u.W[(long long)c * g.ncell + id];
+      double a = w, b = w;
+      if (adv) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          const double* FA = u.FA[d] + (long long)c * nf[d];
+          a -= (FA[hi[d]] - FA[lo[d]]) / g.dx[d];
+          if (STAGE == 1) {
+            const double* FB = u.FB[d] + (long long)c * nf[d];
+            b -= (FB[hi[d]] - FB[lo[d]]) / g.dx[d];
+          }
+        }
+      }
+      u.out1[(long long)c * g.ncell + id] = a;
+      if (STAGE == 1) u.out2[(long long)c * g.ncell + id] = b;
+      w1[c] = a;
+    }
+  }
+  if (CFL) {
+    double dxm = g.dx[0];
+    for (int d = 1; d < D; ++d) dxm = fmin(dxm, g.dx[d]);
+    double v = live ? cell_dt<D>(w1, u.gamma, u.mu, dxm) : INFINITY;
+    // NaN (non-physical cell) wins the reduction
+    const bool nan = live && !(v == v);
+    v = block_min(nan ? -INFINITY : v, red);
+    if (threadIdx.x == 0) u.partial[blockIdx.x] = v == -INFINITY ? NAN : v;
+  }
+}
+
+// CFL partial minima of a state (no update)
+template <int D>
+__global__ __launch_bounds__(256) void cfl_partial_kernel(Geom g, const double* W, double gamma, double mu,
+                                                          double* partial) {
+  constexpr int NC = D + 2;
+  __shared__ double red[4];
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  double dxm = g.dx[0];
+  for (int d = 1; d < D; ++d) dxm = fmin(dxm, g.dx[d]);
+  double v = INFINITY;
+  bool nan = false;
+  if (id < g.ncell) {
+    double w[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) w[c] = W[(long long)c * g.ncell + id];
+    v = cell_dt<D>(w, gamma, mu, dxm);
+    nan = !(v == v);
+  }
+  v = block_min(nan ? -INFINITY : v, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = v == -INFINITY ? NAN : v;
+}
+
+// Final reduction.  clock = {t, dt}.  mode 0: dt_out = cfl * min (clipped to
+// t_end - t_in); mode 1 (after a step): t += dt, then the next dt as mode 0;
+// mode 2: fixed step, t += dt only.
+__global__ __launch_bounds__(256) void cfl_finalize_kernel(const double* partial, int nblk, double cfl,
+                                                           double t_in, double t_end, double* clock,
+                                                           double* dt_out, int mode) {
+  __shared__ double red[4];
+  double v = INFINITY;
+  bool nan = false;
+  if (mode != 2)
+    for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
+      const double p = partial[i];
+      if (!(p == p)) nan = true;
+      v = fmin(v, p);
+    }
+  v = block_min(nan ? -INFINITY : v, red);
+  if (threadIdx.x == 0) {
+    double t = t_in;
+    if (mode >= 1) {
+      t = clock[0];
+      const double used = clock[1];
+      if (used > 0.0) t += used;
+    }
+    if (clock) clock[0] = t;
+    if (mode != 2) {
+      double dt = v == -INFINITY ? NAN : cfl * v;
+      if (t_end > 0.0) {
+        if (t >= t_end * (1.0 - 1e-14))
+          dt = 0.0;
+        else if (t + dt > t_end)
+          dt = t_end - t;
+      }
+      if (clock) clock[1] = dt;
+      if (dt_out) *dt_out = dt;
+    }
+  }
+}
+
+__global__ void set_clock_kernel(double* clock, double t, double dt) {
+  clock[0] = t;
+  clock[1] = dt;
+}
+
+}  // namespace tgks

@@ -1,0 +1,182 @@
+"""Python binding of the C ABI in include/tgks.h (argument marshalling only).
+
+Every function has the name of the C entry point it calls.  Arrays are torch
+tensors on the HIP device (float64, contiguous, layout [nc][nz][ny][x]); torch
+supplies device memory and the current stream, every step of the method runs
+in the library's HIP kernels.  A missing library raises; there is no
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libtgks.so")
+
+BC_PERIODIC, BC_TRANSMISSIVE, BC_REFLECTIVE = 0, 1, 2
+TAU_INVISCID, TAU_VISCOUS, TAU_ZERO = 0, 1, 2
+_BC = {"periodic": 0, "transmissive": 1, "reflective": 2}
+_TAU = {"inviscid": 0, "viscous": 1, "zero": 2}
+
+KERNEL_KINDS = {"face_x": 0, "face_y": 1, "face_z": 2, "recon3d": 3, "update1": 4, "update2": 5, "cfl": 6}
+
+
+class TgksParams(C.Structure):
+    """Mirror of struct tgks_params."""
+    _fields_ = [
+        ("ndim", C.c_int32), ("n", C.c_int32 * 3), ("dx", C.c_double * 3),
+        ("bc_lo", C.c_int32 * 3), ("bc_hi", C.c_int32 * 3),
+        ("gamma", C.c_double), ("mu", C.c_double), ("prandtl", C.c_double),
+        ("tau_mode", C.c_int32), ("c1", C.c_double), ("c2", C.c_double),
+        ("ct1", C.c_double), ("ct2", C.c_double), ("ct1_tan", C.c_double), ("ct2_tan", C.c_double),
+        ("eps", C.c_double), ("q", C.c_int32),
+    ]
+
+
+class TgksError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def lib():
+    """Open libtgks.so (built by ``python -m paper_2309_10534_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise TgksError(f"{LIB_PATH} not found: build it with `python -m paper_2309_10534_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    P = C.POINTER(TgksParams)
+    vp = C.c_void_p
+    L.tgks_params_default.argtypes = [P, C.c_int32]
+    L.tgks_create.argtypes = [P, vp, C.POINTER(vp)]
+    L.tgks_destroy.argtypes = [vp]
+    L.tgks_set_stream.argtypes = [vp, vp]
+    L.tgks_state_size.argtypes = [vp]
+    L.tgks_state_size.restype = C.c_int64
+    L.tgks_flag_bytes.argtypes = [vp]
+    L.tgks_flag_bytes.restype = C.c_int64
+    L.tgks_cfl_dt.argtypes = [vp, vp, C.c_double, C.c_double, C.c_double, vp]
+    L.tgks_step.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.tgks_run.argtypes = [vp, vp, C.c_int32, C.c_double, C.c_double, C.c_double, vp, C.c_int32]
+    L.tgks_status.argtypes = [vp, C.POINTER(C.c_int64)]
+    L.tgks_reset_status.argtypes = [vp]
+    L.tgks_timing.argtypes = [vp, C.c_int32]
+    L.tgks_kernel_time.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    for f in ("tgks_params_default", "tgks_create", "tgks_destroy", "tgks_set_stream", "tgks_cfl_dt", "tgks_step",
+              "tgks_run", "tgks_status", "tgks_reset_status", "tgks_timing", "tgks_kernel_time"):
+        getattr(L, f).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise TgksError(f"{what} returned {rc}" + (" (invalid argument)" if rc == -1 else " (HIP error)"))
+
+
+def _ptr(t, numel=None, dtype=None):
+    """Device pointer of a contiguous float64 (or uint8) HIP tensor, or None."""
+    if t is None:
+        return None
+    import torch
+    if not t.is_cuda:
+        raise TgksError("expected a tensor on the HIP device")
+    if not t.is_contiguous():
+        raise TgksError("expected a contiguous tensor")
+    if t.dtype != (dtype or torch.float64):
+        raise TgksError(f"expected dtype {dtype or torch.float64}, got {t.dtype}")
+    if numel is not None and t.numel() != numel:
+        raise TgksError(f"expected {numel} elements, got {t.numel()}")
+    return t.data_ptr()
+
+
+def tgks_params_default(ndim, shape=None, dx=None, bc="transmissive", **kw):
+    """tgks_params filled with the paper's constants; shape / dx / bc / keyword
+    fields (gamma, mu, prandtl, tau, c1, c2, ct1, ct2, ct1_tan, ct2_tan, eps, q)
+    override them."""
+    p = TgksParams()
+    _check(lib().tgks_params_default(C.byref(p), int(ndim)), "tgks_params_default")
+    if shape is not None:
+        for d in range(ndim):
+            p.n[d] = int(shape[d])
+    if dx is not None:
+        for d in range(ndim):
+            p.dx[d] = float(dx[d])
+    for d in range(ndim):
+        lo, hi = (bc, bc) if isinstance(bc, str) else bc[d]
+        p.bc_lo[d], p.bc_hi[d] = _BC[lo], _BC[hi]
+    if "tau" in kw:
+        p.tau_mode = _TAU[kw.pop("tau")]
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def tgks_create(params, stream=None):
+    """Context handle (int).  stream: torch.cuda.Stream or None for the current stream."""
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    h = C.c_void_p()
+    _check(lib().tgks_create(C.byref(params), C.c_void_p(s.cuda_stream), C.byref(h)), "tgks_create")
+    return h.value
+
+
+def tgks_destroy(ctx):
+    _check(lib().tgks_destroy(ctx), "tgks_destroy")
+
+
+def tgks_set_stream(ctx, stream):
+    _check(lib().tgks_set_stream(ctx, C.c_void_p(stream.cuda_stream)), "tgks_set_stream")
+
+
+def tgks_state_size(ctx):
+    return int(lib().tgks_state_size(ctx))
+
+
+def tgks_flag_bytes(ctx):
+    return int(lib().tgks_flag_bytes(ctx))
+
+
+def tgks_cfl_dt(ctx, W, cfl, t, t_end, dt_dev):
+    n = tgks_state_size(ctx)
+    _check(lib().tgks_cfl_dt(ctx, _ptr(W, n), float(cfl), float(t), float(t_end), _ptr(dt_dev, 1)), "tgks_cfl_dt")
+
+
+def tgks_step(ctx, W_in, W_out, dt_dev, flags=None, W_star=None):
+    import torch
+    n = tgks_state_size(ctx)
+    fl = _ptr(flags, tgks_flag_bytes(ctx), torch.uint8) if flags is not None else None
+    _check(lib().tgks_step(ctx, _ptr(W_in, n), _ptr(W_out, n), _ptr(dt_dev, 1), fl, _ptr(W_star, n)), "tgks_step")
+
+
+def tgks_run(ctx, W, n_steps, cfl=0.0, t_end=0.0, fixed_dt=0.0, time_dev=None, use_graph=False):
+    n = tgks_state_size(ctx)
+    _check(lib().tgks_run(ctx, _ptr(W, n), int(n_steps), float(cfl), float(t_end), float(fixed_dt),
+                          _ptr(time_dev, 2), int(bool(use_graph))), "tgks_run")
+
+
+def tgks_status(ctx):
+    v = C.c_int64()
+    _check(lib().tgks_status(ctx, C.byref(v)), "tgks_status")
+    return v.value
+
+
+def tgks_reset_status(ctx):
+    _check(lib().tgks_reset_status(ctx), "tgks_reset_status")
+
+
+def tgks_timing(ctx, enable):
+    _check(lib().tgks_timing(ctx, int(bool(enable))), "tgks_timing")
+
+
+def tgks_kernel_time(ctx, kind):
+    """(milliseconds, launches) summed over the launches of one kernel kind."""
+    ms = C.c_double()
+    n = C.c_int64()
+    k = KERNEL_KINDS[kind] if isinstance(kind, str) else int(kind)
+    _check(lib().tgks_kernel_time(ctx, k, C.byref(ms), C.byref(n)), "tgks_kernel_time")
+    return ms.value, n.value

@@ -1,0 +1,88 @@
+"""Helpers of the GPU parity tests: run the same problem through the HIP
+library (C ABI via paper_2309_10534_amd.tgks) and through the CPU oracle, each
+from its own parameter structure built from one plain dict."""
+import numpy as np
+
+TOL_L1 = 1e-10  # L1-relative tolerance per component (GPU vs oracle, FP64)
+
+
+def problem(shape, dx, bc="transmissive", tau="inviscid", mu=0.0, prandtl=1.0, **kw):
+    d = dict(shape=list(shape), dx=list(dx), bc=bc, tau=tau, mu=mu, prandtl=prandtl)
+    d.update(kw)
+    return d
+
+
+def gpu_params(pr):
+    from paper_2309_10534_amd import tgks
+    kw = {k: v for k, v in pr.items() if k not in ("shape", "dx", "bc")}
+    return tgks.tgks_params_default(len(pr["shape"]), pr["shape"], pr["dx"], pr["bc"], **kw)
+
+
+def orc_params(orc, pr):
+    kw = {k: v for k, v in pr.items() if k not in ("shape", "dx", "bc")}
+    return orc.make_params(pr["shape"], pr["dx"], bc=pr["bc"], **kw)
+
+
+class GpuProblem:
+    """A context plus device buffers for one grid."""
+
+    def __init__(self, pr):
+        import torch
+        from paper_2309_10534_amd import tgks
+        self.t = tgks
+        self.torch = torch
+        self.pr = pr
+        self.ctx = tgks.tgks_create(gpu_params(pr))
+        self.n = tgks.tgks_state_size(self.ctx)
+
+    def close(self):
+        if self.ctx:
+            self.t.tgks_destroy(self.ctx)
+            self.ctx = None
+
+    def dev(self, W):
+        return self.torch.from_numpy(np.ascontiguousarray(W, dtype=np.float64)).cuda()
+
+    def step(self, W, dt, flags=True):
+        torch = self.torch
+        Win = self.dev(W)
+        Wout = torch.empty_like(Win)
+        Ws = torch.empty_like(Win)
+        dtd = torch.tensor([dt], dtype=torch.float64, device="cuda")
+        fl = torch.zeros(self.t.tgks_flag_bytes(self.ctx), dtype=torch.uint8, device="cuda") if flags else None
+        self.t.tgks_reset_status(self.ctx)
+        self.t.tgks_step(self.ctx, Win, Wout, dtd, fl, Ws)
+        bad = self.t.tgks_status(self.ctx)
+        torch.cuda.synchronize()
+        return (Wout.cpu().numpy().reshape(W.shape), Ws.cpu().numpy().reshape(W.shape),
+                fl.cpu().numpy() if flags else None, bad)
+
+    def cfl_dt(self, W, cfl, t=0.0, t_end=0.0):
+        torch = self.torch
+        dtd = torch.zeros(1, dtype=torch.float64, device="cuda")
+        self.t.tgks_cfl_dt(self.ctx, self.dev(W), cfl, t, t_end, dtd)
+        return float(dtd.cpu()[0])
+
+    def run(self, W, n_steps, cfl=0.0, t_end=0.0, fixed_dt=0.0, use_graph=False):
+        torch = self.torch
+        Wd = self.dev(W)
+        td = torch.zeros(2, dtype=torch.float64, device="cuda")
+        self.t.tgks_reset_status(self.ctx)
+        self.t.tgks_run(self.ctx, Wd, n_steps, cfl, t_end, fixed_dt, td, use_graph)
+        bad = self.t.tgks_status(self.ctx)
+        torch.cuda.synchronize()
+        return Wd.cpu().numpy().reshape(W.shape), td.cpu().numpy(), bad
+
+
+def l1rel(a, b):
+    """Per-component L1-relative difference sum|a-b| / sum|b|."""
+    nc = a.shape[0]
+    a2, b2 = a.reshape(nc, -1), b.reshape(nc, -1)
+    return np.abs(a2 - b2).sum(axis=1) / np.maximum(np.abs(b2).sum(axis=1), 1e-300)
+
+
+def assert_close(a, b, tol=TOL_L1, what=""):
+    e = l1rel(a, b)
+    assert np.all(np.isfinite(a)), f"{what}: non-finite GPU values"
+    assert np.all(e <= tol), f"{what}: L1-relative difference {e} > {tol}"
+    return e

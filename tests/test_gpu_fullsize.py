@@ -1,0 +1,106 @@
+"""Full-size parity: one S2O4 step of the benchmark workloads at their real
+sizes, through tgks_run (the launch configuration bench.py times), checked
+on sampled cells against the oracle run on a local patch.
+
+One S2O4 step of a cell depends only on cells within 6 cells of it (3 per
+stage: normal stencil of 3 beyond the face, tangential stencil of 2 plus the
+normal stencils of those rows), so the oracle on a (2R+1)^d patch with
+R >= 7 around the sample reproduces the sample exactly up to rounding; the
+patch keeps the true boundary condition wherever it touches the domain
+boundary."""
+import numpy as np
+import pytest
+
+from gpu_common import GpuProblem, l1rel, orc_params, problem
+from paper_2309_10534_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+R = 8
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    return torch
+
+
+def patch_problem(pr, W, center, R):
+    """Sub-grid around `center` (x, y[, z]): periodic axes are cut out with
+    wrap-around; other axes are clipped at the domain and keep its boundary
+    kind there; every cut side of the patch is transmissive."""
+    D = len(pr["shape"])
+    Wp = W
+    shape, bc, off = [], [], []
+    for d in range(D):
+        n = pr["shape"][d]
+        kind = pr["bc"] if isinstance(pr["bc"], str) else pr["bc"][d][0]
+        axis = W.ndim - 1 - d  # array order [c][z][y][x]
+        if kind == "periodic" and 2 * R + 1 < n:
+            idx = np.arange(center[d] - R, center[d] + R + 1) % n
+            blo = bhi = "transmissive"
+            o = R
+        else:
+            lo, hi = max(0, center[d] - R), min(n, center[d] + R + 1)
+            idx = np.arange(lo, hi)
+            blo = kind if lo == 0 else "transmissive"
+            bhi = kind if hi == n else "transmissive"
+            o = center[d] - lo
+        Wp = np.take(Wp, idx, axis=axis)
+        shape.append(len(idx))
+        bc.append((blo, bhi))
+        off.append(o)
+    sub = dict(pr)
+    sub["shape"] = shape
+    sub["bc"] = bc
+    return sub, np.ascontiguousarray(Wp), off
+
+
+def check_samples(orc, pr, W, samples, cfl):
+    gp = GpuProblem(pr)
+    try:
+        dt = gp.cfl_dt(W, cfl)
+        print(f"[fullsize] shape={pr['shape']} dt={dt:.6e}", flush=True)
+        Wg, td, bad = gp.run(W, 1, cfl=cfl)
+    finally:
+        gp.close()
+    assert bad == 0 and np.all(np.isfinite(Wg))
+    assert abs(td[0] - dt) <= 1e-15 * dt
+    for c in samples:
+        sub, Ws, off = patch_problem(pr, W, c, R)
+        Wo, _, _, bado = orc.step(orc_params(orc, sub), Ws, dt)
+        assert bado == 0
+        got = Wg[(slice(None),) + tuple(reversed(c))]
+        want = Wo[(slice(None),) + tuple(reversed(off))]
+        rel = np.abs(got - want) / np.maximum(np.abs(want), 1e-300)
+        print(f"[fullsize] sample {c}: max rel diff {rel.max():.2e}", flush=True)
+        assert np.all(np.abs(got - want) <= 1e-12 * np.maximum(np.abs(want), np.abs(W[(slice(None),) + tuple(reversed(c))]))), (c, got, want)
+    return Wg
+
+
+def test_2d_riemann_1024(orc, torch_dev):
+    """The benchmark workload: 1024^2 four-quadrant Riemann problem, seed 0."""
+    n = 1024
+    W, dx, _ = I.quadrant_riemann(n, seed=0)
+    pr = problem([n, n], [dx, dx])
+    rng = np.random.default_rng(0)
+    samples = [(511, 511), (512, 512), (511, 512), (0, 0), (1023, 1023), (0, 700), (1023, 300), (400, 0),
+               (600, 1023)] + [tuple(int(v) for v in rng.integers(0, n, 2)) for _ in range(3)]
+    Wg = check_samples(orc, pr, W, samples, 0.5)
+    # conservation in the interior: the flux through the (transmissive)
+    # boundary is the only change of the totals
+    assert np.all(np.isfinite(Wg))
+
+
+def test_3d_taylor_green_128(orc, torch_dev):
+    n = 128
+    W, dx = I.taylor_green_3d(n, m=2)
+    pr = problem([n, n, n], [dx] * 3, bc="periodic", tau="viscous", mu=1 / 1600, prandtl=0.72)
+    samples = [(0, 0, 0), (64, 31, 100), (127, 127, 5)]
+    Wg = check_samples(orc, pr, W, samples, 0.4)
+    # periodic: totals conserved to rounding
+    tot0 = W.reshape(5, -1).sum(axis=1)
+    tot = Wg.reshape(5, -1).sum(axis=1)
+    scale = np.abs(W).reshape(5, -1).sum(axis=1)
+    assert np.all(np.abs(tot - tot0) <= 1e-12 * scale)
