@@ -133,6 +133,17 @@ int tgks_reset_status(tgks_ctx* ctx);
 int tgks_timing(tgks_ctx* ctx, int32_t enable);
 int tgks_kernel_time(tgks_ctx* ctx, int32_t kind, double* ms, int64_t* launches);
 
+/* Algorithmic operation counts of the kernels for parameters p (host only,
+ * no device work), from the kernels' own device math evaluated on the host
+ * with a counting scalar type on smooth data: +, -, *, / and each sqrt, exp,
+ * expm1, erfc count one.  out[0]: normal TENO-D reconstruction per cell,
+ * direction and component; out[1], out[2]: stage-1 / stage-2 face work per
+ * face beyond the normal reconstruction (tangential reconstruction, the
+ * Gauss-point fluxes, the S2O4 combination); out[3], out[4]: stage-1 /
+ * stage-2 update per cell; out[5]: transcendentals and out[6]: divisions per
+ * stage-1 face; out[7]: CFL limit per cell.  nout >= 8. */
+int tgks_flop_counts(const tgks_params* p, double* out, int32_t nout);
+
 #ifdef __cplusplus
 }
 #endif

@@ -37,7 +37,9 @@
 //  * Reconstruction acts component-wise on the conservative variables.
 //  * Cut-off "0 if chi < C_T, 1 otherwise" is evaluated as
 //    !(gamma_k < C_T * sum gamma) (no division, ties keep the stencil).
-//  * The smoothness quantities are evaluated with a fixed operation order and
+//  * The smoothness quantities and the candidate values are evaluated with a
+//    fixed operation order, constant divisors applied as multiplications by
+//    their correctly rounded reciprocals, normal slopes scaled by 1/dx, and
 //    without floating-point contraction (build with -ffp-contract=off).
 //  * Internal degrees of freedom K = 2/(gamma-1) - D (D = 1, 2, 3).
 //  * Navier-Stokes: constant mu; the energy flux is corrected by
@@ -128,11 +130,11 @@ static void teno_beta(const double Q[5], double beta[4]) {
   t2 = (3.0 * c - 4.0 * d) + e;
   beta[2] = k13 * (t1 * t1) + 0.25 * (t2 * t2);
   // p3_x, p3_xx, p3_xxx, p3_xxxx of Sec. 3.2 (cell units)
-  const double P1 = (82.0 * (d - b) - 11.0 * (e - a)) / 120.0;
-  const double P2 = ((((40.0 * b - 3.0 * a) - 74.0 * c) + 40.0 * d) - 3.0 * e) / 56.0;
-  const double P3 = ((e - a) - 2.0 * (d - b)) / 12.0;
-  const double P4 = ((((a - 4.0 * b) + 6.0 * c) - 4.0 * d) + e) / 24.0;
-  const double s1 = P1 + P3 / 10.0;
+  const double P1 = (82.0 * (d - b) - 11.0 * (e - a)) * (1.0 / 120.0);
+  const double P2 = ((((40.0 * b - 3.0 * a) - 74.0 * c) + 40.0 * d) - 3.0 * e) * (1.0 / 56.0);
+  const double P3 = ((e - a) - 2.0 * (d - b)) * (1.0 / 12.0);
+  const double P4 = ((((a - 4.0 * b) + 6.0 * c) - 4.0 * d) + e) * (1.0 / 24.0);
+  const double s1 = P1 + P3 * (1.0 / 10.0);
   const double s2 = P2 + (123.0 / 455.0) * P4;
   beta[3] = (((s1 * s1) + (13.0 / 3.0) * (s2 * s2)) + (781.0 / 20.0) * (P3 * P3)) +
             (1421461.0 / 2275.0) * (P4 * P4);
@@ -174,24 +176,24 @@ static void teno_face_values(const T Q[5], uint8_t flag, T out[4]) {
   const T a = Q[0], b = Q[1], c = Q[2], d = Q[3], e = Q[4];
   if (flag & 1) {
     // large stencil: Eq. 4.8 / 4.9 and the mirrored x_{i-1/2} forms (Eq. 3.24)
-    out[2] = ((((2.0 * a - 13.0 * b) + 47.0 * c) + 27.0 * d) - 3.0 * e) / 60.0;
-    out[3] = (((b - 15.0 * c) + 15.0 * d) - e) / 12.0;
-    out[0] = ((((27.0 * b - 3.0 * a) + 47.0 * c) - 13.0 * d) + 2.0 * e) / 60.0;
-    out[1] = (((a - 15.0 * b) + 15.0 * c) - d) / 12.0;
+    out[2] = ((((2.0 * a - 13.0 * b) + 47.0 * c) + 27.0 * d) - 3.0 * e) * (1.0 / 60.0);
+    out[3] = (((b - 15.0 * c) + 15.0 * d) - e) * (1.0 / 12.0);
+    out[0] = ((((27.0 * b - 3.0 * a) + 47.0 * c) - 13.0 * d) + 2.0 * e) * (1.0 / 60.0);
+    out[1] = (((a - 15.0 * b) + 15.0 * c) - d) * (1.0 / 12.0);
     return;
   }
   // small stencils (Eqs. 3.2, 3.22-3.23) combined with omega_k = d_k delta_k /
   // sum d_k delta_k, d_k = 1/3 (Eqs. 4.13-4.14)
   T vp[3], dp[3], vm[3], dm[3];
-  vp[0] = ((2.0 * a - 7.0 * b) + 11.0 * c) / 6.0;
-  vp[1] = ((5.0 * c - b) + 2.0 * d) / 6.0;
-  vp[2] = ((2.0 * c + 5.0 * d) - e) / 6.0;
+  vp[0] = ((2.0 * a - 7.0 * b) + 11.0 * c) * (1.0 / 6.0);
+  vp[1] = ((5.0 * c - b) + 2.0 * d) * (1.0 / 6.0);
+  vp[2] = ((2.0 * c + 5.0 * d) - e) * (1.0 / 6.0);
   dp[0] = (a - 3.0 * b) + 2.0 * c;
   dp[1] = d - c;
   dp[2] = d - c;
-  vm[0] = ((5.0 * b - a) + 2.0 * c) / 6.0;
-  vm[1] = ((2.0 * b + 5.0 * c) - d) / 6.0;
-  vm[2] = ((11.0 * c - 7.0 * d) + 2.0 * e) / 6.0;
+  vm[0] = ((5.0 * b - a) + 2.0 * c) * (1.0 / 6.0);
+  vm[1] = ((2.0 * b + 5.0 * c) - d) * (1.0 / 6.0);
+  vm[2] = ((11.0 * c - 7.0 * d) + 2.0 * e) * (1.0 / 6.0);
   dm[0] = c - b;
   dm[1] = c - b;
   dm[2] = (3.0 * d - 2.0 * c) - e;
@@ -701,6 +703,7 @@ static long face_fluxes(const orc_params& P, const Grid& g, const T* W, int d, d
   if (D == 3) perm[3] = 1 + t2;
   perm[D + 1] = D + 1;
   const double dn = g.dx[d];
+  const double idn = 1.0 / dn;  // normal slopes per unit length
   const double dt1 = t1 >= 0 ? g.dx[t1] : 1.0, dt2 = t2 >= 0 ? g.dx[t2] : 1.0;
   const double deltas[2] = {dt, 0.5 * dt};
   long nbad = 0;
@@ -728,7 +731,7 @@ static long face_fluxes(const orc_params& P, const Grid& g, const T* W, int d, d
           const uint8_t f = normal_recon(P, g, W, d, c, cc, o);
           if (side == 1 && nflags && cc[d] < g.n[d]) nflags[(long)d * nc * g.ncell + (long)c * g.ncell + g.lin(cc[0], cc[1], cc[2])] = f;
           Wg[0][0][side][a] = o[vo];
-          Dg[0][0][side][0][a] = o[vo + 1] / dn;
+          Dg[0][0][side][0][a] = o[vo + 1] * idn;
         } else if (D == 2) {
           T Wl[5], Nl[5];
           for (int r = -2; r <= 2; ++r) {
@@ -739,7 +742,7 @@ static long face_fluxes(const orc_params& P, const Grid& g, const T* W, int d, d
             if (r == 0 && side == 1 && nflags && cc[d] < g.n[d])
               nflags[(long)d * nc * g.ncell + (long)c * g.ncell + g.lin(cc[0], cc[1], cc[2])] = f;
             Wl[r + 2] = o[vo];
-            Nl[r + 2] = o[vo + 1] / dn;
+            Nl[r + 2] = o[vo + 1] * idn;
           }
           const uint8_t fw = select_T(Wl, P.ct1_tan, P.ct2_tan, P.eps, P.q);
           const uint8_t fn = select_T(Nl, P.ct1_tan, P.ct2_tan, P.eps, P.q);
@@ -770,7 +773,7 @@ static long face_fluxes(const orc_params& P, const Grid& g, const T* W, int d, d
               if (r1 == 0 && r2 == 0 && side == 1 && nflags && cc[d] < g.n[d])
                 nflags[(long)d * nc * g.ncell + (long)c * g.ncell + g.lin(cc[0], cc[1], cc[2])] = f;
               Vw[r2 + 2][r1 + 2] = o[vo];
-              Vn[r2 + 2][r1 + 2] = o[vo + 1] / dn;
+              Vn[r2 + 2][r1 + 2] = o[vo + 1] * idn;
             }
           T S1w[2][5], S1d[2][5], S1n[2][5];  // [m1][r2]
           for (int r2 = 0; r2 < 5; ++r2) {

@@ -15,6 +15,7 @@
 
 #include "tgks.h"
 #include "tgks_kernels.hpp"
+#include "tgks_opcount.hpp"
 
 using namespace tgks;
 
@@ -336,6 +337,120 @@ static void free_ctx(tgks_ctx* c) {
   delete c;
 }
 
+// ---------------------------------------------------------------------------
+// Algorithmic operation counts: the kernels' per-cell and per-face sequences
+// evaluated on the host with the counting scalar type, on smooth data (the
+// large-stencil branch of every selection).
+// ---------------------------------------------------------------------------
+namespace {
+
+using tgks_opcount::F;
+
+F smooth(int c, double x, double y) {
+  // conservative components of a smooth state (rho, rho u, rho v, rho w, rho E)
+  const double rho = 1.0 + 0.1 * std::sin(0.7 * x + 0.3 * y), u = 0.3, v = -0.2, w = 0.1, p = 1.0;
+  switch (c) {
+    case 0: return F(rho);
+    case 1: return F(rho * u);
+    case 2: return F(rho * v);
+    case 3: return F(rho * w);
+    default: return F(p / 0.4 + 0.5 * rho * (u * u + v * v + w * w));
+  }
+}
+
+long long count_normal(const tgks_ctx* c) {
+  F Q[5], o[4];
+  for (int r = 0; r < 5; ++r) Q[r] = smooth(0, 0.1 * r, 0.0);
+  tgks_opcount::tally() = tgks_opcount::Tally();
+  const unsigned fl = teno_flag(Q, c->tn);
+  teno_face(Q, fl, o);
+  const F idn(1.0 / c->g.dx[0]);
+  F s1 = o[1] * idn, s3 = o[3] * idn;
+  (void)s1;
+  (void)s3;
+  return tgks_opcount::tally().total();
+}
+
+template <int D, bool NS>
+long long count_face(const tgks_ctx* c, int stage, tgks_opcount::Tally* detail) {
+  constexpr int NC = D + 2;
+  const int NG = D == 1 ? 1 : (D == 2 ? 2 : 4);
+  F Wg[4][2][NC], Dg[4][2][D][NC];
+  for (int m = 0; m < NG; ++m)
+    for (int s = 0; s < 2; ++s)
+      for (int q = 0; q < NC; ++q) {
+        Wg[m][s][q] = smooth(q < D + 1 ? q : 4, 0.05 * s, 0.1 * m);
+        for (int d = 0; d < D; ++d) Dg[m][s][d][q] = F(0.01 * (q + 1) * (d + 1));
+      }
+  tgks_opcount::tally() = tgks_opcount::Tally();
+  if (D == 2) {
+    // tangential reconstruction: per side and component, two selections, two
+    // Gauss-point evaluations and the slope scaling
+    for (int s = 0; s < 2; ++s)
+      for (int q = 0; q < NC; ++q) {
+        F Qw[5], Qn[5], v[2], dv[2], vn[2], dvn[2];
+        for (int r = 0; r < 5; ++r) {
+          Qw[r] = smooth(q < 3 ? q : 4, 0.1 * r, 0.0);
+          Qn[r] = F(0.01 * r);
+        }
+        teno_gauss(Qw, teno_flag(Qw, c->tt), v, dv);
+        teno_gauss(Qn, teno_flag(Qn, c->tt), vn, dvn);
+        for (int m = 0; m < 2; ++m) dv[m] = dv[m] * F(1.0 / c->g.dx[1]);
+      }
+  } else if (D == 3) {
+    // per Gauss point, side and component: five sweep-1 reconstructions of
+    // (W, W_n) along t1, then three sweep-2 reconstructions along t2
+    for (int m = 0; m < 4; ++m)
+      for (int s = 0; s < 2; ++s)
+        for (int q = 0; q < NC; ++q) {
+          F S1w[5], S1d[5], S1n[5];
+          for (int r2 = 0; r2 < 5; ++r2) {
+            F Qw[5], Qn[5], v[2], dv[2], vn[2], dvn[2];
+            for (int r = 0; r < 5; ++r) {
+              Qw[r] = smooth(q, 0.1 * r, 0.1 * r2);
+              Qn[r] = F(0.01 * r);
+            }
+            teno_gauss(Qw, teno_flag(Qw, c->tt), v, dv);
+            teno_gauss(Qn, teno_flag(Qn, c->tt), vn, dvn);
+            S1w[r2] = v[0];
+            S1d[r2] = dv[0] * F(1.0 / c->g.dx[1]);
+            S1n[r2] = vn[0];
+          }
+          F v[2], dv[2], x[2], dx_[2];
+          teno_gauss(S1w, teno_flag(S1w, c->tt), v, dv);
+          dv[0] = dv[0] * F(1.0 / c->g.dx[2]);
+          teno_gauss(S1d, teno_flag(S1d, c->tt), x, dx_);
+          teno_gauss(S1n, teno_flag(S1n, c->tt), x, dx_);
+        }
+  }
+  FluxCfg fc = c->fc;
+  const F dt(1e-3);
+  F A[NC], B[NC];
+  for (int q = 0; q < NC; ++q) A[q] = B[q] = F(0.0);
+  const double w = 1.0 / NG;
+  for (int m = 0; m < NG; ++m) {
+    F Fdt[NC], Fh[NC];
+    gp_flux<D, NS>(Wg[m][0], Wg[m][1], Dg[m][0], Dg[m][1], fc, dt, Fdt, Fh);
+    for (int q = 0; q < NC; ++q) {
+      if (stage == 1) {
+        A[q] += F(w) * Fh[q];
+        B[q] += F(w) * (F(8.0 / 3.0) * Fh[q] - F(1.0 / 3.0) * Fdt[q]);
+      } else {
+        A[q] += F(w) * (F(4.0 / 3.0) * Fdt[q] - F(8.0 / 3.0) * Fh[q]);
+      }
+    }
+  }
+  if (detail) *detail = tgks_opcount::tally();
+  return tgks_opcount::tally().total();
+}
+
+template <int D>
+long long count_face_dispatch(const tgks_ctx* c, int stage, tgks_opcount::Tally* t) {
+  return c->ns ? count_face<D, true>(c, stage, t) : count_face<D, false>(c, stage, t);
+}
+
+}  // namespace
+
 extern "C" {
 
 int tgks_params_default(tgks_params* p, int32_t ndim) {
@@ -579,6 +694,54 @@ int tgks_kernel_time(tgks_ctx* c, int32_t kind, double* ms, int64_t* launches) {
   }
   *ms = s;
   *launches = (int64_t)c->ev[kind].size();
+  return TGKS_OK;
+}
+
+int tgks_flop_counts(const tgks_params* p, double* out, int32_t nout) {
+  if (!out || nout < 8 || check_params(p)) return TGKS_EINVAL;
+  // a context-like description without device buffers
+  tgks_ctx c;
+  c.p = *p;
+  const int D = p->ndim;
+  c.nc = D + 2;
+  c.g.D = D;
+  for (int d = 0; d < 3; ++d) {
+    c.g.n[d] = d < D ? p->n[d] : 1;
+    c.g.dx[d] = d < D ? p->dx[d] : 1.0;
+  }
+  const double N = 2.0 / (p->gamma - 1.0);
+  c.fc.N = N;
+  c.fc.K = N - D;
+  c.fc.mu = p->mu;
+  c.ns = p->mu > 0.0 && p->prandtl != 1.0;
+  c.fc.pr_fix = c.ns ? 1.0 / p->prandtl - 1.0 : 0.0;
+  c.fc.c1 = p->c1;
+  c.fc.c2 = p->c2;
+  c.fc.tau_mode = p->tau_mode;
+  c.tn = {p->ct1, p->ct2, p->eps, p->q};
+  c.tt = {p->ct1_tan, p->ct2_tan, p->eps, p->q};
+  tgks_opcount::Tally t1;
+  long long f1, f2;
+  if (D == 1) {
+    f1 = count_face_dispatch<1>(&c, 1, &t1);
+    f2 = count_face_dispatch<1>(&c, 2, nullptr);
+  } else if (D == 2) {
+    f1 = count_face_dispatch<2>(&c, 1, &t1);
+    f2 = count_face_dispatch<2>(&c, 2, nullptr);
+  } else {
+    f1 = count_face_dispatch<3>(&c, 1, &t1);
+    f2 = count_face_dispatch<3>(&c, 2, nullptr);
+  }
+  const long long nr = count_normal(&c);
+  const int nc = D + 2;
+  out[0] = (double)nr;                       // normal reconstruction, per cell, direction and component
+  out[1] = (double)f1;                       // stage-1 face work beyond the normal reconstruction, per face
+  out[2] = (double)f2;                       // stage-2 face work, per face
+  out[3] = (double)(nc * D * 6);             // stage-1 update per cell: 2 states x D x (sub, div, sub)
+  out[4] = (double)(nc * D * 3);             // stage-2 update per cell
+  out[5] = (double)(t1.sqrt + t1.exp + t1.expm1 + t1.erfc);  // transcendentals per stage-1 face
+  out[6] = (double)t1.div;                   // divisions per stage-1 face
+  out[7] = (double)(D * 3 + 9);              // CFL limit per cell
   return TGKS_OK;
 }
 

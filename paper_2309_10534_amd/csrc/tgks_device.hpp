@@ -12,12 +12,17 @@
 //     micro-slope systems, moment sums over psi.
 //
 // The selection arithmetic (smoothness indicators, gamma_k, cut-offs) and the
-// candidate values follow one fixed evaluation order with floating-point
+// candidate values follow one fixed evaluation order (constant divisors as
+// multiplications by their correctly rounded reciprocals) with floating-point
 // contraction disabled, so that the stencil flags are a deterministic
 // function of the input bits.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+// Every function is a template on the scalar type R: double in the kernels,
+// an operation-counting type on the host (algorithmic flop counts).
+#define TGKS_HD __host__ __device__ __forceinline__
 
 namespace tgks {
 
@@ -31,11 +36,12 @@ struct TenoCfg {
 // flag bit0 = delta_{3,1}; if it is 0, bits 1..3 = delta_{0,2}, delta_{1,2},
 // delta_{2,2}.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ unsigned teno_flag(const double* Q, const TenoCfg& c) {
+template <class R>
+TGKS_HD unsigned teno_flag(const R* Q, const TenoCfg& c) {
 #pragma clang fp contract(off)
-  const double a = Q[0], b = Q[1], cc = Q[2], d = Q[3], e = Q[4];
+  const R a = Q[0], b = Q[1], cc = Q[2], d = Q[3], e = Q[4];
   const double k13 = 13.0 / 12.0;
-  double t1, t2, beta[4];
+  R t1, t2, beta[4];
   t1 = (a - 2.0 * b) + cc;
   t2 = (a - 4.0 * b) + 3.0 * cc;
   beta[0] = k13 * (t1 * t1) + 0.25 * (t2 * t2);
@@ -46,32 +52,32 @@ __device__ __forceinline__ unsigned teno_flag(const double* Q, const TenoCfg& c)
   t2 = (3.0 * cc - 4.0 * d) + e;
   beta[2] = k13 * (t1 * t1) + 0.25 * (t2 * t2);
   // quartic indicator (Eq. 3.7, q = 4) as a sum of squares of its derivatives
-  const double P1 = (82.0 * (d - b) - 11.0 * (e - a)) / 120.0;
-  const double P2 = ((((40.0 * b - 3.0 * a) - 74.0 * cc) + 40.0 * d) - 3.0 * e) / 56.0;
-  const double P3 = ((e - a) - 2.0 * (d - b)) / 12.0;
-  const double P4 = ((((a - 4.0 * b) + 6.0 * cc) - 4.0 * d) + e) / 24.0;
-  const double s1 = P1 + P3 / 10.0;
-  const double s2 = P2 + (123.0 / 455.0) * P4;
+  const R P1 = (82.0 * (d - b) - 11.0 * (e - a)) * (1.0 / 120.0);
+  const R P2 = ((((40.0 * b - 3.0 * a) - 74.0 * cc) + 40.0 * d) - 3.0 * e) * (1.0 / 56.0);
+  const R P3 = ((e - a) - 2.0 * (d - b)) * (1.0 / 12.0);
+  const R P4 = ((((a - 4.0 * b) + 6.0 * cc) - 4.0 * d) + e) * (1.0 / 24.0);
+  const R s1 = P1 + P3 * (1.0 / 10.0);
+  const R s2 = P2 + (123.0 / 455.0) * P4;
   beta[3] = (((s1 * s1) + (13.0 / 3.0) * (s2 * s2)) + (781.0 / 20.0) * (P3 * P3)) +
             (1421461.0 / 2275.0) * (P4 * P4);
-  double g[4];
+  R g[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    const double bb = beta[k] + c.eps;
-    double pw;
+    const R bb = beta[k] + c.eps;
+    R pw;
     if (c.q == 7) {
-      const double b2 = bb * bb;
-      const double b4 = b2 * b2;
+      const R b2 = bb * bb;
+      const R b4 = b2 * b2;
       pw = (b4 * b2) * bb;
     } else {
-      pw = 1.0;
+      pw = R(1.0);
       for (int r = 0; r < c.q; ++r) pw = pw * bb;
     }
     g[k] = 1.0 / pw;  // gamma_k = (beta_k + eps)^-q  (Eq. 4.5)
   }
-  const double s4 = ((g[0] + g[1]) + g[2]) + g[3];
+  const R s4 = ((g[0] + g[1]) + g[2]) + g[3];
   if (!(g[3] < c.ct1 * s4)) return 1u;  // large stencil kept (Eqs. 4.6-4.7)
-  const double s3 = (g[0] + g[1]) + g[2];
+  const R s3 = (g[0] + g[1]) + g[2];
   unsigned f = 0;
 #pragma unroll
   for (int k = 0; k < 3; ++k)
@@ -81,48 +87,50 @@ __device__ __forceinline__ unsigned teno_flag(const double* Q, const TenoCfg& c)
 
 // Values and slopes (cell units) at x_{i-1/2} and x_{i+1/2} of the selected
 // reconstruction: out = {v(-1/2), s(-1/2), v(+1/2), s(+1/2)}.
-__device__ __forceinline__ void teno_face(const double* Q, unsigned flag, double* out) {
+template <class R>
+TGKS_HD void teno_face(const R* Q, unsigned flag, R* out) {
 #pragma clang fp contract(off)
-  const double a = Q[0], b = Q[1], c = Q[2], d = Q[3], e = Q[4];
+  const R a = Q[0], b = Q[1], c = Q[2], d = Q[3], e = Q[4];
   if (flag & 1u) {
     // Eq. 4.8, Eq. 4.9 and their mirror images
-    out[2] = ((((2.0 * a - 13.0 * b) + 47.0 * c) + 27.0 * d) - 3.0 * e) / 60.0;
-    out[3] = (((b - 15.0 * c) + 15.0 * d) - e) / 12.0;
-    out[0] = ((((27.0 * b - 3.0 * a) + 47.0 * c) - 13.0 * d) + 2.0 * e) / 60.0;
-    out[1] = (((a - 15.0 * b) + 15.0 * c) - d) / 12.0;
+    out[2] = ((((2.0 * a - 13.0 * b) + 47.0 * c) + 27.0 * d) - 3.0 * e) * (1.0 / 60.0);
+    out[3] = (((b - 15.0 * c) + 15.0 * d) - e) * (1.0 / 12.0);
+    out[0] = ((((27.0 * b - 3.0 * a) + 47.0 * c) - 13.0 * d) + 2.0 * e) * (1.0 / 60.0);
+    out[1] = (((a - 15.0 * b) + 15.0 * c) - d) * (1.0 / 12.0);
     return;
   }
   // surviving small stencils averaged with d_k = 1/3 (Eqs. 4.13-4.14)
-  double w[3], ws = 0.0;
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    w[k] = ((flag >> (k + 1)) & 1u) ? 1.0 / 3.0 : 0.0;
-    ws += w[k];
-  }
-  const double o0 = w[0] / ws, o1 = w[1] / ws, o2 = w[2] / ws;
-  const double vp0 = ((2.0 * a - 7.0 * b) + 11.0 * c) / 6.0;
-  const double vp1 = ((5.0 * c - b) + 2.0 * d) / 6.0;
-  const double vp2 = ((2.0 * c + 5.0 * d) - e) / 6.0;
-  const double dp0 = (a - 3.0 * b) + 2.0 * c;
-  const double dp12 = d - c;
-  const double vm0 = ((5.0 * b - a) + 2.0 * c) / 6.0;
-  const double vm1 = ((2.0 * b + 5.0 * c) - d) / 6.0;
-  const double vm2 = ((11.0 * c - 7.0 * d) + 2.0 * e) / 6.0;
-  const double dm01 = c - b;
-  const double dm2 = (3.0 * d - 2.0 * c) - e;
-  out[0] = ((0.0 + o0 * vm0) + o1 * vm1) + o2 * vm2;
-  out[1] = ((0.0 + o0 * dm01) + o1 * dm01) + o2 * dm2;
-  out[2] = ((0.0 + o0 * vp0) + o1 * vp1) + o2 * vp2;
-  out[3] = ((0.0 + o0 * dp0) + o1 * dp12) + o2 * dp12;
+  // omega_k = d_k delta_k / sum d_k delta_k with d_k = 1/3: in double
+  // arithmetic (1/3)/(m/3) is exactly 1, 0.5 or (1/3) for m = 1, 2, 3
+  // surviving stencils
+  const int cnt = (int)((flag >> 1) & 1u) + (int)((flag >> 2) & 1u) + (int)((flag >> 3) & 1u);
+  const double om = cnt == 1 ? 1.0 : (cnt == 2 ? 0.5 : 1.0 / 3.0);
+  const R o0 = R((flag & 2u) ? om : 0.0), o1 = R((flag & 4u) ? om : 0.0), o2 = R((flag & 8u) ? om : 0.0);
+  const R vp0 = ((2.0 * a - 7.0 * b) + 11.0 * c) * (1.0 / 6.0);
+  const R vp1 = ((5.0 * c - b) + 2.0 * d) * (1.0 / 6.0);
+  const R vp2 = ((2.0 * c + 5.0 * d) - e) * (1.0 / 6.0);
+  const R dp0 = (a - 3.0 * b) + 2.0 * c;
+  const R dp12 = d - c;
+  const R vm0 = ((5.0 * b - a) + 2.0 * c) * (1.0 / 6.0);
+  const R vm1 = ((2.0 * b + 5.0 * c) - d) * (1.0 / 6.0);
+  const R vm2 = ((11.0 * c - 7.0 * d) + 2.0 * e) * (1.0 / 6.0);
+  const R dm01 = c - b;
+  const R dm2 = (3.0 * d - 2.0 * c) - e;
+  const R z = R(0.0);
+  out[0] = ((z + o0 * vm0) + o1 * vm1) + o2 * vm2;
+  out[1] = ((z + o0 * dm01) + o1 * dm01) + o2 * dm2;
+  out[2] = ((z + o0 * vp0) + o1 * vp1) + o2 * vp2;
+  out[3] = ((z + o0 * dp0) + o1 * dp12) + o2 * dp12;
 }
 
 // Selected polynomial at the Gauss points s = -+1/(2 sqrt 3) (cell units):
 // val[m], der[m] for m = 0 (s-) and 1 (s+).  The values feed only the flux,
 // so contraction is allowed here.
-__device__ __forceinline__ void teno_gauss(const double* Q, unsigned flag, double* val, double* der) {
-  const double a = Q[0], b = Q[1], c = Q[2], d = Q[3], e = Q[4];
+template <class R>
+TGKS_HD void teno_gauss(const R* Q, unsigned flag, R* val, R* der) {
+  const R a = Q[0], b = Q[1], c = Q[2], d = Q[3], e = Q[4];
   const double s = 0.28867513459481288225;  // 1/(2 sqrt 3)
-  double c0, c1, c2, c3 = 0.0, c4 = 0.0;
+  R c0, c1, c2, c3 = R(0.0), c4 = R(0.0);
   if (flag & 1u) {
     c0 = ((2134.0 * c - 116.0 * (d + b)) + 9.0 * (e + a)) * (1.0 / 1920.0);
     c1 = (34.0 * (d - b) - 5.0 * (e - a)) * (1.0 / 48.0);
@@ -131,8 +139,9 @@ __device__ __forceinline__ void teno_gauss(const double* Q, unsigned flag, doubl
     c4 = ((((a - 4.0 * b) + 6.0 * c) - 4.0 * d) + e) * (1.0 / 24.0);
   } else {
     const bool k0 = flag & 2u, k1 = flag & 4u, k2 = flag & 8u;
-    const double inv = 1.0 / (double)((int)k0 + (int)k1 + (int)k2);
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    const int cnt = (int)k0 + (int)k1 + (int)k2;
+    const double inv = cnt == 1 ? 1.0 : (cnt == 2 ? 0.5 : 1.0 / 3.0);
+    R s0 = R(0.0), s1 = R(0.0), s2 = R(0.0);
     if (k0) {
       s0 += (23.0 * c + 2.0 * b - a) * (1.0 / 24.0);
       s1 += (3.0 * c - 4.0 * b + a) * 0.5;
@@ -153,14 +162,23 @@ __device__ __forceinline__ void teno_gauss(const double* Q, unsigned flag, doubl
     c2 = s2 * inv;
   }
   const double ss = s * s;
-  const double even = c0 + ss * (c2 + ss * c4);          // p(s) + p(-s) halves
-  const double odd = s * (c1 + ss * c3);
+  const R even = c0 + ss * (c2 + ss * c4);  // even part of p at +-s
+  const R odd = s * (c1 + ss * c3);
   val[0] = even - odd;
   val[1] = even + odd;
-  const double deven = c1 + 3.0 * ss * c3;               // p'(s) even part
-  const double dodd = s * (2.0 * c2 + 4.0 * ss * c4);
+  const R deven = c1 + (3.0 * ss) * c3;  // even part of p' at +-s
+  const R dodd = s * (2.0 * c2 + (4.0 * ss) * c4);
   der[0] = deven - dodd;
   der[1] = deven + dodd;
+}
+
+// The selected polynomial at one Gauss point m (0: s-, 1: s+), cell units.
+template <class R>
+TGKS_HD void teno_gauss_at(const R* Q, unsigned flag, int m, R& val, R& der) {
+  R v[2], d[2];
+  teno_gauss(Q, flag, v, d);
+  val = m ? v[1] : v[0];
+  der = m ? d[1] : d[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -177,86 +195,86 @@ struct FluxCfg {
 constexpr int NM1 = 7;  // normal moment table <u1^n>, n = 0..6
 constexpr int NMT = 6;  // tangential tables <u_t^n>, n = 0..5
 
-template <int D>
+template <int D, class R>
 struct Gas {
-  double rho, irho, U[D], lam, h;  // h = 1/(2 lambda) = p / rho
+  R rho, irho, U[D], lam, h;  // h = 1/(2 lambda) = p / rho
   bool ok;
 };
 
-template <int D>
-__device__ __forceinline__ void make_gas(const double* W, double N, Gas<D>& g) {
+template <int D, class R>
+TGKS_HD void make_gas(const R* W, double N, Gas<D, R>& g) {
   g.rho = W[0];
-  g.irho = 1.0 / g.rho;
-  double ru2 = 0.0;
+  g.irho = R(1.0) / g.rho;
+  R ru2 = R(0.0);
 #pragma unroll
   for (int d = 0; d < D; ++d) {
     g.U[d] = W[d + 1] * g.irho;
     ru2 += g.U[d] * W[d + 1];
   }
-  const double eint = W[D + 1] - 0.5 * ru2;  // rho E - rho |U|^2 / 2 = N p / 2
-  g.h = (2.0 / N) * eint * g.irho;           // p / rho = 1/(2 lambda)
+  const R eint = W[D + 1] - 0.5 * ru2;  // rho E - rho |U|^2 / 2 = N p / 2
+  g.h = (2.0 / N) * eint * g.irho;      // p / rho = 1/(2 lambda)
   g.lam = 0.5 / g.h;
   g.ok = (g.rho > 0.0) && (eint > 0.0) && (g.rho < INFINITY) && (eint < INFINITY);
 }
 
-__device__ __forceinline__ void full_table(double U, double h, double* m, int n) {
-  m[0] = 1.0;
+template <class R>
+TGKS_HD void full_table(R U, R h, R* m, int n) {
+  m[0] = R(1.0);
   m[1] = U;
-  for (int k = 1; k + 1 < n; ++k) m[k + 1] = U * m[k] + (double)k * h * m[k - 1];
+  for (int k = 1; k + 1 < n; ++k) m[k + 1] = U * m[k] + ((double)k * h) * m[k - 1];
 }
 
 // half-space table from its first two entries
-__device__ __forceinline__ void half_table(double U, double h, double m0, double m1, double* m) {
+template <class R>
+TGKS_HD void half_table(R U, R h, R m0, R m1, R* m) {
   m[0] = m0;
   m[1] = m1;
 #pragma unroll
-  for (int k = 1; k + 1 < NM1; ++k) m[k + 1] = U * m[k] + (double)k * h * m[k - 1];
+  for (int k = 1; k + 1 < NM1; ++k) m[k + 1] = U * m[k] + ((double)k * h) * m[k - 1];
 }
 
 // first two half-space moments: sgn = +1 (u1 > 0) or -1 (u1 < 0)
-__device__ __forceinline__ void half_seed(double U, double lam, double sgn, double& m0, double& m1) {
-  const double sl = sqrt(lam);
-  m0 = 0.5 * erfc(-sgn * sl * U);
-  m1 = U * m0 + sgn * 0.5 * exp(-lam * U * U) / (sl * 1.7724538509055160273);
+template <class R>
+TGKS_HD void half_seed(R U, R lam, double sgn, R& m0, R& m1) {
+  const R sl = sqrt(lam);
+  m0 = 0.5 * erfc(-sgn * (sl * U));
+  m1 = U * m0 + (sgn * 0.5) * exp(-(lam * U) * U) / (sl * 1.7724538509055160273);
 }
 
-template <int D>
+template <int D, class R>
 struct MomSet {
-  double m1[NM1];
-  double mt[D > 1 ? D - 1 : 1][NMT];
-  double xi1, xi2;  // <xi^2>, <xi^4>
+  R m1[NM1];
+  R mt[D > 1 ? D - 1 : 1][NMT];
+  R xi1, xi2;  // <xi^2>, <xi^4>
 };
 
-template <int D>
-__device__ __forceinline__ double mono(const MomSet<D>& S, int i, int j, int k) {
-  double v = S.m1[i];
-  if (D >= 2) v *= S.mt[0][j];
-  if (D >= 3) v *= S.mt[D >= 3 ? 1 : 0][k];
+template <int D, class R>
+TGKS_HD R mono(const MomSet<D, R>& S, int i, int j, int k) {
+  R v = S.m1[i];
+  if (D >= 2) v = v * S.mt[0][j];
+  if (D >= 3) v = v * S.mt[D >= 3 ? 1 : 0][k];
   return v;
 }
 
 // g[alpha] = <psi_alpha u1^i u2^j u3^k xi^(2l)>, l in {0, 1}
-template <int D>
-__device__ __forceinline__ void gpsi(const MomSet<D>& S, int i, int j, int k, int l, double* g) {
-  const double xl = l == 0 ? 1.0 : S.xi1;
-  const double xl1 = l == 0 ? S.xi1 : S.xi2;
-  const double base = mono(S, i, j, k);
-  g[0] = base * xl;
-  g[1] = mono(S, i + 1, j, k) * xl;
-  if (D >= 2) g[2] = mono(S, i, j + 1, k) * xl;
-  if (D >= 3) g[3] = mono(S, i, j, k + 1) * xl;
-  double e = mono(S, i + 2, j, k);
-  if (D >= 2) e += mono(S, i, j + 2, k);
-  if (D >= 3) e += mono(S, i, j, k + 2);
-  g[D + 1] = 0.5 * (e * xl + base * xl1);
+template <int D, class R>
+TGKS_HD void gpsi(const MomSet<D, R>& S, int i, int j, int k, int l, R* g) {
+  const R base = mono(S, i, j, k);
+  g[0] = l == 0 ? base : base * S.xi1;
+  g[1] = l == 0 ? mono(S, i + 1, j, k) : mono(S, i + 1, j, k) * S.xi1;
+  if (D >= 2) g[2] = l == 0 ? mono(S, i, j + 1, k) : mono(S, i, j + 1, k) * S.xi1;
+  if (D >= 3) g[D >= 3 ? 3 : 0] = l == 0 ? mono(S, i, j, k + 1) : mono(S, i, j, k + 1) * S.xi1;
+  R e = mono(S, i + 2, j, k);
+  if (D >= 2) e = e + mono(S, i, j + 2, k);
+  if (D >= 3) e = e + mono(S, i, j, k + 2);
+  g[D + 1] = l == 0 ? 0.5 * (e + base * S.xi1) : 0.5 * (e * S.xi1 + base * S.xi2);
 }
 
 // out[alpha] (+)= s * <psi_alpha a(psi) u1^i u2^j u3^k>
-template <int D, bool ACC>
-__device__ __forceinline__ void mpsia(const MomSet<D>& S, const double* a, int i, int j, int k, double s,
-                                      double* out) {
+template <int D, bool ACC, class R>
+TGKS_HD void mpsia(const MomSet<D, R>& S, const R* a, int i, int j, int k, R s, R* out) {
   constexpr int NC = D + 2;
-  double g[NC], t[NC], r[NC];
+  R g[NC], t[NC], r[NC];
   gpsi<D>(S, i, j, k, 0, g);
 #pragma unroll
   for (int q = 0; q < NC; ++q) r[q] = a[0] * g[q];
@@ -285,51 +303,53 @@ __device__ __forceinline__ void mpsia(const MomSet<D>& S, const double* a, int i
     for (int q = 0; q < NC; ++q) t[q] += g[q];
   }
   gpsi<D>(S, i, j, k, 1, g);
-  const double ae = 0.5 * a[NC - 1];
+  const R ae = 0.5 * a[NC - 1];
 #pragma unroll
   for (int q = 0; q < NC; ++q) {
-    const double v = r[q] + ae * (t[q] + g[q]);
-    out[q] = ACC ? out[q] + s * v : s * v;
+    const R v = r[q] + ae * (t[q] + g[q]);
+    if (ACC)
+      out[q] += s * v;
+    else
+      out[q] = s * v;
   }
 }
 
 // closed-form solution a of <a psi> = b (per unit density) over the full
 // Maxwellian (U, lambda), N = K + D.
-template <int D>
-__device__ __forceinline__ void micro_solve(const Gas<D>& g, double N, const double* b, double* a) {
-  double ub = 0.0, u2 = 0.0;
+template <int D, class R>
+TGKS_HD void micro_solve(const Gas<D, R>& g, double N, const R* b, R* a) {
+  R ub = R(0.0), u2 = R(0.0);
 #pragma unroll
   for (int d = 0; d < D; ++d) {
     ub += g.U[d] * b[d + 1];
     u2 += g.U[d] * g.U[d];
   }
-  const double lam = g.lam;
-  const double aE = (4.0 * lam * lam / N) * (2.0 * b[D + 1] - 2.0 * ub + (u2 - N * g.h) * b[0]);
-  double ua = 0.0;
+  const R lam = g.lam;
+  const R aE = ((4.0 / N) * (lam * lam)) * ((2.0 * b[D + 1] - 2.0 * ub) + (u2 - N * g.h) * b[0]);
+  R ua = R(0.0);
 #pragma unroll
   for (int d = 0; d < D; ++d) {
-    a[d + 1] = 2.0 * lam * (b[d + 1] - g.U[d] * b[0]) - g.U[d] * aE;
+    a[d + 1] = (2.0 * lam) * (b[d + 1] - g.U[d] * b[0]) - g.U[d] * aE;
     ua += g.U[d] * a[d + 1];
   }
   a[D + 1] = aE;
-  a[0] = b[0] - ua - 0.5 * aE * (u2 + N * g.h);
+  a[0] = (b[0] - ua) - (0.5 * aE) * (u2 + N * g.h);
 }
 
-template <int D>
-__device__ __forceinline__ void tangential_tables(const Gas<D>& g, MomSet<D>& S) {
+template <int D, class R>
+TGKS_HD void tangential_tables(const Gas<D, R>& g, MomSet<D, R>& S) {
 #pragma unroll
   for (int d = 1; d < D; ++d) full_table(g.U[d], g.h, S.mt[d - 1], NMT);
 }
 
-template <int D>
-__device__ __forceinline__ void xi_moments(const Gas<D>& g, double K, MomSet<D>& S) {
+template <int D, class R>
+TGKS_HD void xi_moments(const Gas<D, R>& g, double K, MomSet<D, R>& S) {
   S.xi1 = K * g.h;
-  S.xi2 = K * (K + 2.0) * g.h * g.h;
+  S.xi2 = (K * (K + 2.0)) * (g.h * g.h);
 }
 
-// index helper: (i, j, k) offsets of u_d
-template <int D>
-__device__ __forceinline__ void unit(int d, int& i, int& j, int& k) {
+// (i, j, k) exponents of u_d
+TGKS_HD void unit(int d, int& i, int& j, int& k) {
   i = d == 0;
   j = d == 1;
   k = d == 2;
@@ -337,44 +357,43 @@ __device__ __forceinline__ void unit(int d, int& i, int& j, int& k) {
 
 // heat-flux moment <phi X> from <u1 psi X> (f1) and <psi X> (f0):
 // phi = (u1 - c1)(psi_E - c.u + |c|^2/2), c = U0 (face frame)
-template <int D>
-__device__ __forceinline__ double heat_combine(const double* f1, const double* f0, const double* c) {
-  double c2 = 0.0, s1 = f1[D + 1], s0 = f0[D + 1];
+template <int D, class R>
+TGKS_HD R heat_combine(const R* f1, const R* f0, const R* c) {
+  R c2 = R(0.0), s1 = f1[D + 1], s0 = f0[D + 1];
 #pragma unroll
   for (int d = 0; d < D; ++d) {
     c2 += c[d] * c[d];
     s1 -= c[d] * f1[d + 1];
     s0 -= c[d] * f0[d + 1];
   }
-  s1 += 0.5 * c2 * f1[0];
-  s0 += 0.5 * c2 * f0[0];
+  s1 += (0.5 * c2) * f1[0];
+  s0 += (0.5 * c2) * f0[0];
   return s1 - c[0] * s0;
 }
 
 // Time-integrated flux F(dt) and F(dt/2) at one Gauss point.
 // Wl, Wr: states; dWl[d], dWr[d]: derivatives along frame axis d.
 // Returns false when a state is non-physical.
-template <int D, bool NS>
-__device__ __forceinline__ bool gp_flux(const double* Wl, const double* Wr, const double (*dWl)[D + 2],
-                                        const double (*dWr)[D + 2], const FluxCfg& P, double dt,
-                                        double* Fdt, double* Fh) {
+template <int D, bool NS, class R>
+TGKS_HD bool gp_flux(const R* Wl, const R* Wr, const R (*dWl)[D + 2], const R (*dWr)[D + 2], const FluxCfg& P,
+                     R dt, R* Fdt, R* Fh) {
   constexpr int NC = D + 2;
   const double N = P.N;
-  Gas<D> gl, gr;
+  Gas<D, R> gl, gr;
   make_gas<D>(Wl, N, gl);
   make_gas<D>(Wr, N, gr);
-  double hl0, hl1, hr0, hr1;
+  R hl0, hl1, hr0, hr1;
   half_seed(gl.U[0], gl.lam, 1.0, hl0, hl1);
   half_seed(gr.U[0], gr.lam, -1.0, hr0, hr1);
 
   // equilibrium state by kinetic weighting (Eq. 2.6): rho_l <psi>_{>0} + rho_r <psi>_{<0}
-  double W0[NC];
+  R W0[NC];
   {
-    MomSet<D> S;
+    MomSet<D, R> S;
     half_table(gl.U[0], gl.h, hl0, hl1, S.m1);
     tangential_tables<D>(gl, S);
     xi_moments<D>(gl, P.K, S);
-    double g[NC];
+    R g[NC];
     gpsi<D>(S, 0, 0, 0, 0, g);
 #pragma unroll
     for (int q = 0; q < NC; ++q) W0[q] = gl.rho * g[q];
@@ -385,18 +404,18 @@ __device__ __forceinline__ bool gp_flux(const double* Wl, const double* Wr, cons
 #pragma unroll
     for (int q = 0; q < NC; ++q) W0[q] += gr.rho * g[q];
   }
-  Gas<D> g0;
+  Gas<D, R> g0;
   make_gas<D>(W0, N, g0);
 
   // side contributions: dW0 (Eq. 2.6), A^s (Eq. 2.7), and the moments of the
   // non-equilibrium part of Eq. 2.5
-  double dW0[D][NC], S1[NC], S2[NC], S3[NC];
-  double H1 = 0.0, H2 = 0.0, H3 = 0.0;  // heat-flux moments (NS)
+  R dW0[D][NC], S1[NC], S2[NC], S3[NC];
+  R H1 = R(0.0), H2 = R(0.0), H3 = R(0.0);  // heat-flux moments (NS)
 #pragma unroll
   for (int side = 0; side < 2; ++side) {
-    const Gas<D>& gs = side == 0 ? gl : gr;
-    const double(*dW)[NC] = side == 0 ? dWl : dWr;
-    MomSet<D> Sh, Sf;
+    const Gas<D, R>& gs = side == 0 ? gl : gr;
+    const R(*dW)[NC] = side == 0 ? dWl : dWr;
+    MomSet<D, R> Sh, Sf;
     if (side == 0)
       half_table(gs.U[0], gs.h, hl0, hl1, Sh.m1);
     else
@@ -410,10 +429,10 @@ __device__ __forceinline__ bool gp_flux(const double* Wl, const double* Wr, cons
       for (int n = 0; n < NMT; ++n) Sf.mt[d - 1][n] = Sh.mt[d - 1][n];
     Sf.xi1 = Sh.xi1;
     Sf.xi2 = Sh.xi2;
-    double a[D][NC];
+    R a[D][NC];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-      double b[NC];
+      R b[NC];
 #pragma unroll
       for (int q = 0; q < NC; ++q) b[q] = dW[d][q] * gs.irho;
       micro_solve<D>(gs, N, b, a[d]);
@@ -423,51 +442,57 @@ __device__ __forceinline__ bool gp_flux(const double* Wl, const double* Wr, cons
         mpsia<D, true>(Sh, a[d], 0, 0, 0, gs.rho, dW0[d]);
     }
     // A^s: <A psi> = -sum_d <u_d a_d psi> over the full g_s
-    double rhs[NC], A[NC];
+    R rhs[NC], A[NC];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       int i, j, k;
-      unit<D>(d, i, j, k);
+      unit(d, i, j, k);
       if (d == 0)
-        mpsia<D, false>(Sf, a[d], i, j, k, -1.0, rhs);
+        mpsia<D, false>(Sf, a[d], i, j, k, R(-1.0), rhs);
       else
-        mpsia<D, true>(Sf, a[d], i, j, k, -1.0, rhs);
+        mpsia<D, true>(Sf, a[d], i, j, k, R(-1.0), rhs);
     }
     micro_solve<D>(gs, N, rhs, A);
     // <u1 psi>, sum_d <u1 u_d psi a_d>, <u1 psi A> over the half space
-    double g[NC];
+    R g[NC];
     gpsi<D>(Sh, 1, 0, 0, 0, g);
-    double v2[NC];
+    R v2[NC];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       int i, j, k;
-      unit<D>(d, i, j, k);
+      unit(d, i, j, k);
       if (d == 0)
-        mpsia<D, false>(Sh, a[d], 1 + i, j, k, 1.0, v2);
+        mpsia<D, false>(Sh, a[d], 1 + i, j, k, R(1.0), v2);
       else
-        mpsia<D, true>(Sh, a[d], 1 + i, j, k, 1.0, v2);
+        mpsia<D, true>(Sh, a[d], 1 + i, j, k, R(1.0), v2);
     }
-    double v3[NC];
-    mpsia<D, false>(Sh, A, 1, 0, 0, 1.0, v3);
+    R v3[NC];
+    mpsia<D, false>(Sh, A, 1, 0, 0, R(1.0), v3);
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
-      S1[q] = side == 0 ? gs.rho * g[q] : S1[q] + gs.rho * g[q];
-      S2[q] = side == 0 ? gs.rho * v2[q] : S2[q] + gs.rho * v2[q];
-      S3[q] = side == 0 ? gs.rho * v3[q] : S3[q] + gs.rho * v3[q];
+      if (side == 0) {
+        S1[q] = gs.rho * g[q];
+        S2[q] = gs.rho * v2[q];
+        S3[q] = gs.rho * v3[q];
+      } else {
+        S1[q] += gs.rho * g[q];
+        S2[q] += gs.rho * v2[q];
+        S3[q] += gs.rho * v3[q];
+      }
     }
     if (NS) {
-      double f0[NC], w2[NC], w3[NC];
+      R f0[NC], w2[NC], w3[NC];
       gpsi<D>(Sh, 0, 0, 0, 0, f0);
 #pragma unroll
       for (int d = 0; d < D; ++d) {
         int i, j, k;
-        unit<D>(d, i, j, k);
+        unit(d, i, j, k);
         if (d == 0)
-          mpsia<D, false>(Sh, a[d], i, j, k, 1.0, w2);
+          mpsia<D, false>(Sh, a[d], i, j, k, R(1.0), w2);
         else
-          mpsia<D, true>(Sh, a[d], i, j, k, 1.0, w2);
+          mpsia<D, true>(Sh, a[d], i, j, k, R(1.0), w2);
       }
-      mpsia<D, false>(Sh, A, 0, 0, 0, 1.0, w3);
+      mpsia<D, false>(Sh, A, 0, 0, 0, R(1.0), w3);
       H1 += gs.rho * heat_combine<D>(g, f0, g0.U);
       H2 += gs.rho * heat_combine<D>(v2, w2, g0.U);
       H3 += gs.rho * heat_combine<D>(v3, w3, g0.U);
@@ -475,49 +500,49 @@ __device__ __forceinline__ bool gp_flux(const double* Wl, const double* Wr, cons
   }
 
   // equilibrium part: abar_d, Abar (Eq. 2.7) and its moments
-  double V1[NC], V2[NC], V3[NC];
-  double G1 = 0.0, G2 = 0.0, G3 = 0.0;
+  R V1[NC], V2[NC], V3[NC];
+  R G1 = R(0.0), G2 = R(0.0), G3 = R(0.0);
   {
-    MomSet<D> S;
+    MomSet<D, R> S;
     full_table(g0.U[0], g0.h, S.m1, NM1);
     tangential_tables<D>(g0, S);
     xi_moments<D>(g0, P.K, S);
-    double ab[D][NC];
+    R ab[D][NC];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-      double b[NC];
+      R b[NC];
 #pragma unroll
       for (int q = 0; q < NC; ++q) b[q] = dW0[d][q] * g0.irho;
       micro_solve<D>(g0, N, b, ab[d]);
     }
-    double rhs[NC], Ab[NC];
+    R rhs[NC], Ab[NC];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       int i, j, k;
-      unit<D>(d, i, j, k);
+      unit(d, i, j, k);
       if (d == 0)
-        mpsia<D, false>(S, ab[d], i, j, k, -1.0, rhs);
+        mpsia<D, false>(S, ab[d], i, j, k, R(-1.0), rhs);
       else
-        mpsia<D, true>(S, ab[d], i, j, k, -1.0, rhs);
+        mpsia<D, true>(S, ab[d], i, j, k, R(-1.0), rhs);
     }
     micro_solve<D>(g0, N, rhs, Ab);
     gpsi<D>(S, 1, 0, 0, 0, V1);
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       int i, j, k;
-      unit<D>(d, i, j, k);
+      unit(d, i, j, k);
       if (d == 0)
-        mpsia<D, false>(S, ab[d], 1 + i, j, k, 1.0, V2);
+        mpsia<D, false>(S, ab[d], 1 + i, j, k, R(1.0), V2);
       else
-        mpsia<D, true>(S, ab[d], 1 + i, j, k, 1.0, V2);
+        mpsia<D, true>(S, ab[d], 1 + i, j, k, R(1.0), V2);
     }
-    mpsia<D, false>(S, Ab, 1, 0, 0, 1.0, V3);
+    mpsia<D, false>(S, Ab, 1, 0, 0, R(1.0), V3);
     if (NS) {
-      double f0[NC], w3[NC];
+      R f0[NC], w3[NC];
       gpsi<D>(S, 0, 0, 0, 0, f0);
-      mpsia<D, false>(S, Ab, 0, 0, 0, 1.0, w3);
+      mpsia<D, false>(S, Ab, 0, 0, 0, R(1.0), w3);
       // <psi sum_d u_d abar_d> = -<psi Abar> by the compatibility condition
-      double w2[NC];
+      R w2[NC];
 #pragma unroll
       for (int q = 0; q < NC; ++q) w2[q] = -w3[q];
       G1 = heat_combine<D>(V1, f0, g0.U);
@@ -527,41 +552,41 @@ __device__ __forceinline__ bool gp_flux(const double* Wl, const double* Wr, cons
   }
 
   // collision time (Sec. 5 preamble); dt is the full step in both stages
-  const double pl = gl.rho * gl.h, pr = gr.rho * gr.h;
-  const double jump = fabs(pl - pr) / (pl + pr);
-  double tau;
+  const R pl = gl.rho * gl.h, pr = gr.rho * gr.h;
+  const R jump = fabs(pl - pr) / (pl + pr);
+  R tau;
   if (P.tau_mode == 2)
-    tau = 0.0;
+    tau = R(0.0);
   else if (P.tau_mode == 1)
-    tau = P.mu / (g0.rho * g0.h) + P.c2 * jump * dt;
+    tau = P.mu / (g0.rho * g0.h) + (P.c2 * jump) * dt;
   else
     tau = (P.c1 + P.c2 * jump) * dt;
 
 #pragma unroll
   for (int id = 0; id < 2; ++id) {
-    const double dl = id == 0 ? dt : 0.5 * dt;
-    double e, ome;
+    const R dl = id == 0 ? dt : 0.5 * dt;
+    R e, ome;
     if (tau == 0.0) {
-      e = 0.0;
-      ome = 1.0;
+      e = R(0.0);
+      ome = R(1.0);
     } else {
-      const double x = -dl / tau;
+      const R x = -dl / tau;
       e = exp(x);
       ome = -expm1(x);
     }
-    const double tt = tau * tau * ome;
-    const double C1 = dl - tau * ome;
-    const double C2 = 2.0 * tt - tau * dl * (1.0 + e);
-    const double C3 = 0.5 * dl * dl - tau * dl + tt;
-    const double C4 = tau * ome;
-    const double C5 = tau * dl * e - 2.0 * tt;
-    const double C6 = -tt;
-    double* F = id == 0 ? Fdt : Fh;
+    const R tt = (tau * tau) * ome;
+    const R C1 = dl - tau * ome;
+    const R C2 = 2.0 * tt - (tau * dl) * (1.0 + e);
+    const R C3 = (0.5 * dl) * dl - tau * dl + tt;
+    const R C4 = tau * ome;
+    const R C5 = (tau * dl) * e - 2.0 * tt;
+    const R C6 = -tt;
+    R* F = id == 0 ? Fdt : Fh;
 #pragma unroll
     for (int q = 0; q < NC; ++q)
-      F[q] = g0.rho * (C1 * V1[q] + C2 * V2[q] + C3 * V3[q]) + (C4 * S1[q] + C5 * S2[q] + C6 * S3[q]);
+      F[q] = g0.rho * ((C1 * V1[q] + C2 * V2[q]) + C3 * V3[q]) + ((C4 * S1[q] + C5 * S2[q]) + C6 * S3[q]);
     if (NS) {
-      const double q = g0.rho * (C1 * G1 + C2 * G2 + C3 * G3) + (C4 * H1 + C5 * H2 + C6 * H3);
+      const R q = g0.rho * ((C1 * G1 + C2 * G2) + C3 * G3) + ((C4 * H1 + C5 * H2) + C6 * H3);
       F[NC - 1] += P.pr_fix * q;
     }
   }
@@ -572,7 +597,7 @@ __device__ __forceinline__ bool gp_flux(const double* Wl, const double* Wr, cons
 // Boundary index map (ghost cells): periodic, transmissive (copy of the
 // nearest cell) or reflective (mirror image, normal momentum negated).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int map_index(int i, int n, int bclo, int bchi, int& flip) {
+TGKS_HD int map_index(int i, int n, int bclo, int bchi, int& flip) {
   if (i >= 0 && i < n) return i;
   const int bc = i < 0 ? bclo : bchi;
   if (bc == 0) {

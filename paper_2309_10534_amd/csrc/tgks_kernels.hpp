@@ -82,7 +82,7 @@ __global__ __launch_bounds__(256) void face1d_kernel(StageArgs a) {
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f > n) return;
   double Wl[3], Wr[3], dWl[1][3], dWr[1][3];
-  const double dx = a.g.dx[0];
+  const double idx = 1.0 / a.g.dx[0];  // normal slopes per unit length
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     double Q[6];
@@ -92,11 +92,11 @@ __global__ __launch_bounds__(256) void face1d_kernel(StageArgs a) {
     const unsigned fl = teno_flag(Q, a.tn);
     teno_face(Q, fl, o);
     Wl[c] = o[2];
-    dWl[0][c] = o[3] / dx;
+    dWl[0][c] = o[3] * idx;
     const unsigned fr = teno_flag(Q + 1, a.tn);
     teno_face(Q + 1, fr, o);
     Wr[c] = o[0];
-    dWr[0][c] = o[1] / dx;
+    dWr[0][c] = o[1] * idx;
     if (FLAGS && f < n) a.nflags[(long long)c * n + f] = (uint8_t)fr;
   }
   double Fdt[3], Fh[3], A[3] = {0, 0, 0}, B[3] = {0, 0, 0};
@@ -119,10 +119,10 @@ __global__ __launch_bounds__(256) void face1d_kernel(StageArgs a) {
 // then each thread reconstructs its face's left and right states along the
 // face at the two Gauss points and evaluates the two Gauss-point fluxes.
 // ---------------------------------------------------------------------------
-constexpr int TN2 = 16, TT2 = 16;
+constexpr int TN2 = 16, TT2 = 8;  // 128 faces per block, two lanes (Gauss points) per face
 
 template <int AX, int STAGE, bool NS, bool FLAGS>
-__global__ __launch_bounds__(256) void face2d_kernel(StageArgs a) {
+__global__ __launch_bounds__(256, 2) void face2d_kernel(StageArgs a) {
   constexpr int NC = 4;
   constexpr int LN = TN2 + 5, LT = TT2 + 4, RN = TN2 + 1;
   __shared__ double sW[NC][LT][LN];
@@ -130,14 +130,14 @@ __global__ __launch_bounds__(256) void face2d_kernel(StageArgs a) {
   const double dt = *a.dt;
   if (!(dt > 0.0)) return;
   const Geom& g = a.g;
-  const int TA = 1 - AX;                      // tangential axis
+  const int TA = 1 - AX;  // tangential axis
   const int nN = g.n[AX], nT = g.n[TA];
   const int f0 = blockIdx.x * TN2, t0 = blockIdx.y * TT2;
   const int tid = threadIdx.x;
 
   // 1. cells of the tile, ghost cells by the index map
   for (int L = tid; L < NC * LN * LT; L += 256) {
-    int c, nl, tl;
+    int nl, tl;
     if (AX == 0) {
       nl = L % LN;
       tl = (L / LN) % LT;
@@ -145,7 +145,7 @@ __global__ __launch_bounds__(256) void face2d_kernel(StageArgs a) {
       tl = L % LT;
       nl = (L / LT) % LN;
     }
-    c = L / (LN * LT);
+    const int c = L / (LN * LT);
     const int pn = f0 - 3 + nl, pt = t0 - 2 + tl;
     const int x = AX == 0 ? pn : pt, y = AX == 0 ? pt : pn;
     sW[c][tl][nl] = load_cell(g, a.W, c, x, y, 0);
@@ -153,7 +153,7 @@ __global__ __launch_bounds__(256) void face2d_kernel(StageArgs a) {
   __syncthreads();
 
   // 2. normal reconstruction of cells f0-1 .. f0+TN2-1 on every staged row
-  const double dn = g.dx[AX];
+  const double idn = 1.0 / g.dx[AX];  // normal slopes per unit length
   for (int L = tid; L < NC * LT * RN; L += 256) {
     const int nr = L % RN;
     const int tl = (L / RN) % LT;
@@ -163,9 +163,9 @@ __global__ __launch_bounds__(256) void face2d_kernel(StageArgs a) {
     double o[4];
     teno_face(Q, fl, o);
     sR[c][tl][nr][0] = o[0];
-    sR[c][tl][nr][1] = o[1] / dn;
+    sR[c][tl][nr][1] = o[1] * idn;
     sR[c][tl][nr][2] = o[2];
-    sR[c][tl][nr][3] = o[3] / dn;
+    sR[c][tl][nr][3] = o[3] * idn;
     if (FLAGS) {
       const int cell = f0 - 1 + nr, row = t0 - 2 + tl;
       if (nr >= 1 && cell < nN && tl >= 2 && tl < TT2 + 2 && row < nT) {
@@ -176,20 +176,22 @@ __global__ __launch_bounds__(256) void face2d_kernel(StageArgs a) {
   }
   __syncthreads();
 
-  // 3. tangential reconstruction and Gauss-point fluxes, one face per thread
-  const int fn = tid % TN2, ft = tid / TN2;
+  // 3. lanes 2k and 2k+1 share face k: each selects the tangential stencils of
+  //    one side (left: lane 0, right: lane 1), the pair exchanges the flags,
+  //    then each evaluates the reconstruction and the flux at its own Gauss
+  //    point m and the pair sums the two.
+  const int m = tid & 1;
+  const int fi = tid >> 1;
+  const int fn = fi % TN2, ft = fi / TN2;
   const int f = f0 + fn, t = t0 + ft;
-  if (f > nN || t >= nT) return;
-  const double dtan = g.dx[TA];
-  // frame component q -> global component
+  const bool live = f <= nN && t < nT;
   const int perm[NC] = {0, 1 + AX, 1 + TA, 3};
-  double Wg[2][2][NC], Dg[2][2][2][NC];  // [gp][side][q], [gp][side][axis n/t][q]
   const long long nf = face_count(g, AX);
   const long long fidx = AX == 0 ? (long long)t * (g.n[0] + 1) + f : (long long)f * g.n[0] + t;
-#pragma unroll
-  for (int side = 0; side < 2; ++side) {
-    const int nr = side == 0 ? fn : fn + 1;
-    const int vo = side == 0 ? 2 : 0;
+  unsigned mine = 0;
+  if (live) {
+    const int nr = m == 0 ? fn : fn + 1;
+    const int vo = m == 0 ? 2 : 0;
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
       const int c = perm[q];
@@ -201,34 +203,56 @@ __global__ __launch_bounds__(256) void face2d_kernel(StageArgs a) {
       }
       const unsigned fw = teno_flag(Qw, a.tt);
       const unsigned fq = teno_flag(Qn, a.tt);
+      mine |= (fw | (fq << 4)) << (8 * q);
       if (FLAGS) {
-        a.tflags[((long long)(0 * 2 + side) * NC + c) * nf + fidx] = (uint8_t)fw;
-        a.tflags[((long long)(1 * 2 + side) * NC + c) * nf + fidx] = (uint8_t)fq;
-      }
-      double v[2], dv[2], vn[2], dvn[2];
-      teno_gauss(Qw, fw, v, dv);
-      teno_gauss(Qn, fq, vn, dvn);
-#pragma unroll
-      for (int m = 0; m < 2; ++m) {
-        Wg[m][side][q] = v[m];
-        Dg[m][side][1][q] = dv[m] / dtan;
-        Dg[m][side][0][q] = vn[m];
+        a.tflags[((long long)(0 * 2 + m) * NC + c) * nf + fidx] = (uint8_t)fw;
+        a.tflags[((long long)(1 * 2 + m) * NC + c) * nf + fidx] = (uint8_t)fq;
       }
     }
   }
+  const unsigned other = (unsigned)__shfl_xor((int)mine, 1);
   double A[NC] = {0, 0, 0, 0}, B[NC] = {0, 0, 0, 0};
-  unsigned bad = 0;
+  if (live) {
+    const double idt = 1.0 / g.dx[TA];
+    double Wg[2][NC], Dg[2][2][NC];  // [side][q], [side][axis n/t][q]
 #pragma unroll
-  for (int m = 0; m < 2; ++m) {
+    for (int side = 0; side < 2; ++side) {
+      const unsigned packed = side == m ? mine : other;
+      const int nr = side == 0 ? fn : fn + 1;
+      const int vo = side == 0 ? 2 : 0;
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        const int c = perm[q];
+        double Qw[5], Qn[5];
+#pragma unroll
+        for (int r = 0; r < 5; ++r) {
+          Qw[r] = sR[c][ft + r][nr][vo];
+          Qn[r] = sR[c][ft + r][nr][vo + 1];
+        }
+        const unsigned fw = (packed >> (8 * q)) & 15u, fq = (packed >> (8 * q + 4)) & 15u;
+        double v, dv, vn, dvn;
+        teno_gauss_at(Qw, fw, m, v, dv);
+        teno_gauss_at(Qn, fq, m, vn, dvn);
+        Wg[side][q] = v;
+        Dg[side][1][q] = dv * idt;
+        Dg[side][0][q] = vn;
+      }
+    }
     double Fdt[NC], Fh[NC];
-    if (!gp_flux<2, NS>(Wg[m][0], Wg[m][1], Dg[m][0], Dg[m][1], a.fc, dt, Fdt, Fh)) ++bad;
+    if (!gp_flux<2, NS>(Wg[0], Wg[1], Dg[0], Dg[1], a.fc, dt, Fdt, Fh)) atomicAdd(a.fail, 1ull);
     write_combined<NC>(STAGE, Fdt, Fh, 0.5, A, B);
   }
-  if (bad) atomicAdd(a.fail, (unsigned long long)bad);
 #pragma unroll
   for (int q = 0; q < NC; ++q) {
-    a.FA[(long long)perm[q] * nf + fidx] = A[q];
-    if (STAGE == 1) a.FB[(long long)perm[q] * nf + fidx] = B[q];
+    A[q] += __shfl_xor(A[q], 1);
+    if (STAGE == 1) B[q] += __shfl_xor(B[q], 1);
+  }
+  if (live && m == 0) {
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      a.FA[(long long)perm[q] * nf + fidx] = A[q];
+      if (STAGE == 1) a.FB[(long long)perm[q] * nf + fidx] = B[q];
+    }
   }
 }
 
@@ -263,12 +287,12 @@ __global__ __launch_bounds__(256) void recon3d_kernel(StageArgs a) {
   const unsigned fl = teno_flag(Q, a.tn);
   double o[4];
   teno_face(Q, fl, o);
-  const double dn = g.dx[AX];
+  const double idn = 1.0 / g.dx[AX];
   const long long base = (long long)c * 4 * nr + (id % nr);
   a.Rout[base] = o[0];
-  a.Rout[base + nr] = o[1] / dn;
+  a.Rout[base + nr] = o[1] * idn;
   a.Rout[base + 2 * nr] = o[2];
-  a.Rout[base + 3 * nr] = o[3] / dn;
+  a.Rout[base + 3 * nr] = o[3] * idn;
   if (FLAGS && p[AX] >= 0 && p[AX] < g.n[AX])
     a.nflags[((long long)AX * 5 + c) * g.ncell + ((long long)p[2] * g.n[1] + p[1]) * g.n[0] + p[0]] = (uint8_t)fl;
 }
@@ -303,7 +327,7 @@ __global__ __launch_bounds__(256) void face3d_kernel(StageArgs a) {
   ext[AX] += 2;
   const long long nr = (long long)ext[0] * ext[1] * ext[2];
   const int perm[NC] = {0, 1 + AX, 1 + T1, 1 + T2, 4};
-  const double d1 = g.dx[T1], d2 = g.dx[T2];
+  const double i1 = 1.0 / g.dx[T1], i2 = 1.0 / g.dx[T2];
   double Wg[2][NC], Dg[2][3][NC];
   if (live) {
 #pragma unroll
@@ -341,13 +365,13 @@ __global__ __launch_bounds__(256) void face3d_kernel(StageArgs a) {
           teno_gauss(Qw, teno_flag(Qw, a.tt), v, dv);
           teno_gauss(Qn, teno_flag(Qn, a.tt), vn2, dvn2);
           S1w[r2] = v[m1];
-          S1d[r2] = dv[m1] / d1;
+          S1d[r2] = dv[m1] * i1;
           S1n[r2] = vn2[m1];
         }
         double v[2], dv[2], x[2], dx_[2];
         teno_gauss(S1w, teno_flag(S1w, a.tt), v, dv);
         Wg[side][q] = v[m2];
-        Dg[side][2][q] = dv[m2] / d2;
+        Dg[side][2][q] = dv[m2] * i2;
         teno_gauss(S1d, teno_flag(S1d, a.tt), x, dx_);
         Dg[side][1][q] = x[m2];
         teno_gauss(S1n, teno_flag(S1n, a.tt), x, dx_);

@@ -66,8 +66,10 @@ def lib():
     L.tgks_reset_status.argtypes = [vp]
     L.tgks_timing.argtypes = [vp, C.c_int32]
     L.tgks_kernel_time.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    L.tgks_flop_counts.argtypes = [P, C.POINTER(C.c_double), C.c_int32]
     for f in ("tgks_params_default", "tgks_create", "tgks_destroy", "tgks_set_stream", "tgks_cfl_dt", "tgks_step",
-              "tgks_run", "tgks_status", "tgks_reset_status", "tgks_timing", "tgks_kernel_time"):
+              "tgks_run", "tgks_status", "tgks_reset_status", "tgks_timing", "tgks_kernel_time",
+              "tgks_flop_counts"):
         getattr(L, f).restype = C.c_int
     _lib = L
     return L
@@ -180,3 +182,11 @@ def tgks_kernel_time(ctx, kind):
     k = KERNEL_KINDS[kind] if isinstance(kind, str) else int(kind)
     _check(lib().tgks_kernel_time(ctx, k, C.byref(ms), C.byref(n)), "tgks_kernel_time")
     return ms.value, n.value
+
+
+def tgks_flop_counts(params):
+    """Algorithmic operation counts (see include/tgks.h) as a dict."""
+    out = (C.c_double * 8)()
+    _check(lib().tgks_flop_counts(C.byref(params), out, 8), "tgks_flop_counts")
+    keys = ("normal", "face", "face_stage2", "update1", "update2", "face_transcendentals", "face_divisions", "cfl")
+    return {k: out[i] for i, k in enumerate(keys)}
