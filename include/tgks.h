@@ -120,6 +120,18 @@ int tgks_step(tgks_ctx* ctx, const double* W_in, double* W_out, const double* dt
 int tgks_run(tgks_ctx* ctx, double* W, int32_t n_steps, double cfl, double t_end, double fixed_dt,
              double* time_dev, int32_t use_graph);
 
+/* Tile shape of the 2-D face kernel (faces along the normal x along the
+ * face, two lanes per face): 0 = 16 x 8, 1 = 16 x 16, 2 = 8 x 16; -1 selects
+ * the default (0).  Other dimensions ignore it. */
+int tgks_set_tile(tgks_ctx* ctx, int32_t tile);
+
+/* Autotuner: time every tile shape over `steps` S2O4 steps of the state W
+ * (device; not modified) with HIP events, select the fastest and return its
+ * index in *chosen (host, may be NULL); ms_per_variant (host, 3 floats, or
+ * NULL) receives the milliseconds per step of each shape.  Synchronises the
+ * stream. */
+int tgks_tune(tgks_ctx* ctx, const double* W, int32_t steps, int32_t* chosen, float* ms_per_variant);
+
 /* Failure count since creation or the last tgks_reset_status (synchronises
  * the stream). */
 int tgks_status(tgks_ctx* ctx, int64_t* failures);
@@ -143,6 +155,15 @@ int tgks_kernel_time(tgks_ctx* ctx, int32_t kind, double* ms, int64_t* launches)
  * stage-2 update per cell; out[5]: transcendentals and out[6]: divisions per
  * stage-1 face; out[7]: CFL limit per cell.  nout >= 8. */
 int tgks_flop_counts(const tgks_params* p, double* out, int32_t nout);
+
+/* Host evaluation of the device Gauss-point flux (Sec. 2.1, Eqs. 2.5-2.9,
+ * kinetic weighting Eq. 2.6) for verification without a device: the same
+ * code the kernels run, in double on the host.  Face frame (axis 0 normal);
+ * HOST pointers: Wl, Wr [nc], dWl, dWr [ndim][nc] (derivatives along the
+ * frame axes), F [2][nc] receives F(dt) and F(dt/2).  Returns 0, 1 when a
+ * state is non-physical, or TGKS_EINVAL. */
+int tgks_gp_flux_host(const tgks_params* p, const double* Wl, const double* Wr, const double* dWl,
+                      const double* dWr, double dt, double* F);
 
 #ifdef __cplusplus
 }

@@ -35,6 +35,7 @@ struct tgks_ctx {
   FluxCfg fc;
   TenoCfg tn, tt;
   bool ns;
+  int tile2 = 0;  // 2-D face-kernel tile shape (tile2_tn/tile2_tt index)
   hipStream_t stream;
   int nc;
   long long ncell;
@@ -145,6 +146,32 @@ static StageArgs stage_args(tgks_ctx* c, const double* W, int ax, const double* 
 
 #define LAUNCH(kern, grid, block, args) hipLaunchKernelGGL(kern, grid, block, 0, c->stream, args)
 
+// 2-D face kernel of one direction, stage and tile shape
+template <int TILE>
+static void launch_face2d(tgks_ctx* c, const StageArgs& a, int ax, int stage, bool fl, int nN, int nT) {
+  constexpr int TN = tile2_tn(TILE), TT = tile2_tt(TILE);
+  const dim3 grid((unsigned)((nN + 1 + TN - 1) / TN), (unsigned)((nT + TT - 1) / TT)), block(2 * TN * TT);
+#define F2(AXV)                                                                                     \
+  if (stage == 1) {                                                                                 \
+    if (fl) {                                                                                       \
+      if (c->ns) LAUNCH((face2d_kernel<AXV, 1, true, true, TILE>), grid, block, a);                 \
+      else LAUNCH((face2d_kernel<AXV, 1, false, true, TILE>), grid, block, a);                      \
+    } else {                                                                                        \
+      if (c->ns) LAUNCH((face2d_kernel<AXV, 1, true, false, TILE>), grid, block, a);                \
+      else LAUNCH((face2d_kernel<AXV, 1, false, false, TILE>), grid, block, a);                     \
+    }                                                                                               \
+  } else {                                                                                          \
+    if (c->ns) LAUNCH((face2d_kernel<AXV, 2, true, false, TILE>), grid, block, a);                  \
+    else LAUNCH((face2d_kernel<AXV, 2, false, false, TILE>), grid, block, a);                       \
+  }
+  if (ax == 0) {
+    F2(0)
+  } else {
+    F2(1)
+  }
+#undef F2
+}
+
 // face fluxes of one stage in every direction
 static int launch_faces(tgks_ctx* c, const double* W, const double* dt, int stage, uint8_t* flags) {
   const int D = c->g.D;
@@ -177,26 +204,16 @@ static int launch_faces(tgks_ctx* c, const double* W, const double* dt, int stag
     } else if (D == 2) {
       Timer tm(c, ax);
       const int nN = c->g.n[ax], nT = c->g.n[1 - ax];
-      dim3 grid((unsigned)((nN + 1 + TN2 - 1) / TN2), (unsigned)((nT + TT2 - 1) / TT2));
-#define F2(AXV)                                                                                  \
-  if (stage == 1) {                                                                              \
-    if (fl) {                                                                                    \
-      if (c->ns) LAUNCH((face2d_kernel<AXV, 1, true, true>), grid, dim3(256), a);                \
-      else LAUNCH((face2d_kernel<AXV, 1, false, true>), grid, dim3(256), a);                     \
-    } else {                                                                                     \
-      if (c->ns) LAUNCH((face2d_kernel<AXV, 1, true, false>), grid, dim3(256), a);               \
-      else LAUNCH((face2d_kernel<AXV, 1, false, false>), grid, dim3(256), a);                    \
-    }                                                                                            \
-  } else {                                                                                       \
-    if (c->ns) LAUNCH((face2d_kernel<AXV, 2, true, false>), grid, dim3(256), a);                 \
-    else LAUNCH((face2d_kernel<AXV, 2, false, false>), grid, dim3(256), a);                      \
-  }
-      if (ax == 0) {
-        F2(0)
-      } else {
-        F2(1)
+      switch (c->tile2) {
+        case 1:
+          launch_face2d<1>(c, a, ax, stage, fl, nN, nT);
+          break;
+        case 2:
+          launch_face2d<2>(c, a, ax, stage, fl, nN, nT);
+          break;
+        default:
+          launch_face2d<0>(c, a, ax, stage, fl, nN, nT);
       }
-#undef F2
     } else {
       int ext[3] = {c->g.n[0], c->g.n[1], c->g.n[2]};
       ext[ax] += 2;
@@ -347,21 +364,22 @@ namespace {
 using tgks_opcount::F;
 
 F smooth(int c, double x, double y) {
-  // conservative components of a smooth state (rho, rho u, rho v, rho w, rho E)
+  // conservative components of a smooth state (rho, rho u, rho v, rho w, rho E),
+  // each a distinct input of the dataflow graph
   const double rho = 1.0 + 0.1 * std::sin(0.7 * x + 0.3 * y), u = 0.3, v = -0.2, w = 0.1, p = 1.0;
   switch (c) {
-    case 0: return F(rho);
-    case 1: return F(rho * u);
-    case 2: return F(rho * v);
-    case 3: return F(rho * w);
-    default: return F(p / 0.4 + 0.5 * rho * (u * u + v * v + w * w));
+    case 0: return F::input(rho);
+    case 1: return F::input(rho * u);
+    case 2: return F::input(rho * v);
+    case 3: return F::input(rho * w);
+    default: return F::input(p / 0.4 + 0.5 * rho * (u * u + v * v + w * w));
   }
 }
 
 long long count_normal(const tgks_ctx* c) {
   F Q[5], o[4];
+  tgks_opcount::graph().reset();
   for (int r = 0; r < 5; ++r) Q[r] = smooth(0, 0.1 * r, 0.0);
-  tgks_opcount::tally() = tgks_opcount::Tally();
   const unsigned fl = teno_flag(Q, c->tn);
   teno_face(Q, fl, o);
   const F idn(1.0 / c->g.dx[0]);
@@ -376,13 +394,13 @@ long long count_face(const tgks_ctx* c, int stage, tgks_opcount::Tally* detail) 
   constexpr int NC = D + 2;
   const int NG = D == 1 ? 1 : (D == 2 ? 2 : 4);
   F Wg[4][2][NC], Dg[4][2][D][NC];
+  tgks_opcount::graph().reset();
   for (int m = 0; m < NG; ++m)
     for (int s = 0; s < 2; ++s)
       for (int q = 0; q < NC; ++q) {
         Wg[m][s][q] = smooth(q < D + 1 ? q : 4, 0.05 * s, 0.1 * m);
-        for (int d = 0; d < D; ++d) Dg[m][s][d][q] = F(0.01 * (q + 1) * (d + 1));
+        for (int d = 0; d < D; ++d) Dg[m][s][d][q] = F::input(0.01 * (q + 1) * (d + 1));
       }
-  tgks_opcount::tally() = tgks_opcount::Tally();
   if (D == 2) {
     // tangential reconstruction: per side and component, two selections, two
     // Gauss-point evaluations and the slope scaling
@@ -391,7 +409,7 @@ long long count_face(const tgks_ctx* c, int stage, tgks_opcount::Tally* detail) 
         F Qw[5], Qn[5], v[2], dv[2], vn[2], dvn[2];
         for (int r = 0; r < 5; ++r) {
           Qw[r] = smooth(q < 3 ? q : 4, 0.1 * r, 0.0);
-          Qn[r] = F(0.01 * r);
+          Qn[r] = F::input(0.01 * r);
         }
         teno_gauss(Qw, teno_flag(Qw, c->tt), v, dv);
         teno_gauss(Qn, teno_flag(Qn, c->tt), vn, dvn);
@@ -408,7 +426,7 @@ long long count_face(const tgks_ctx* c, int stage, tgks_opcount::Tally* detail) 
             F Qw[5], Qn[5], v[2], dv[2], vn[2], dvn[2];
             for (int r = 0; r < 5; ++r) {
               Qw[r] = smooth(q, 0.1 * r, 0.1 * r2);
-              Qn[r] = F(0.01 * r);
+              Qn[r] = F::input(0.01 * r);
             }
             teno_gauss(Qw, teno_flag(Qw, c->tt), v, dv);
             teno_gauss(Qn, teno_flag(Qn, c->tt), vn, dvn);
@@ -743,6 +761,104 @@ int tgks_flop_counts(const tgks_params* p, double* out, int32_t nout) {
   out[6] = (double)t1.div;                   // divisions per stage-1 face
   out[7] = (double)(D * 3 + 9);              // CFL limit per cell
   return TGKS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+template <int D>
+int host_flux(const tgks_params* p, const double* Wl, const double* Wr, const double* dWl, const double* dWr,
+              double dt, double* F) {
+  constexpr int NC = D + 2;
+  FluxCfg fc;
+  const double N = 2.0 / (p->gamma - 1.0);
+  fc.N = N;
+  fc.K = N - D;
+  fc.mu = p->mu;
+  const bool ns = p->mu > 0.0 && p->prandtl != 1.0;
+  fc.pr_fix = ns ? 1.0 / p->prandtl - 1.0 : 0.0;
+  fc.c1 = p->c1;
+  fc.c2 = p->c2;
+  fc.tau_mode = p->tau_mode;
+  double l[NC], r[NC], dl[D][NC], dr[D][NC], Fdt[NC], Fh[NC];
+  for (int q = 0; q < NC; ++q) {
+    l[q] = Wl[q];
+    r[q] = Wr[q];
+    for (int d = 0; d < D; ++d) {
+      dl[d][q] = dWl[d * NC + q];
+      dr[d][q] = dWr[d * NC + q];
+    }
+  }
+  const bool ok = ns ? gp_flux<D, true>(l, r, dl, dr, fc, dt, Fdt, Fh) : gp_flux<D, false>(l, r, dl, dr, fc, dt, Fdt, Fh);
+  for (int q = 0; q < NC; ++q) {
+    F[q] = Fdt[q];
+    F[NC + q] = Fh[q];
+  }
+  return ok ? 0 : 1;
+}
+}  // namespace
+
+extern "C" {
+
+int tgks_gp_flux_host(const tgks_params* p, const double* Wl, const double* Wr, const double* dWl, const double* dWr,
+                      double dt, double* F) {
+  if (check_params(p) || !Wl || !Wr || !dWl || !dWr || !F) return TGKS_EINVAL;
+  if (p->ndim == 1) return host_flux<1>(p, Wl, Wr, dWl, dWr, dt, F);
+  if (p->ndim == 2) return host_flux<2>(p, Wl, Wr, dWl, dWr, dt, F);
+  return host_flux<3>(p, Wl, Wr, dWl, dWr, dt, F);
+}
+
+int tgks_set_tile(tgks_ctx* c, int32_t tile) {
+  if (!c || tile < -1 || tile >= NTILE2) return TGKS_EINVAL;
+  const int t = tile < 0 ? 0 : tile;
+  if (t != c->tile2 && c->gexec) {
+    (void)hipGraphExecDestroy(c->gexec);
+    (void)hipGraphDestroy(c->graph);
+    c->gexec = nullptr;
+    c->graph = nullptr;
+    c->g_steps = -1;
+  }
+  c->tile2 = t;
+  return TGKS_OK;
+}
+
+int tgks_tune(tgks_ctx* c, const double* W, int32_t steps, int32_t* chosen, float* ms_per_variant) {
+  if (!c || !W || steps < 1) return TGKS_EINVAL;
+  const int nvar = c->g.D == 2 ? NTILE2 : 1;
+  int r;
+  // dt of W into the clock (no clipping)
+  if ((r = launch_cfl_partial(c, W))) return r;
+  if ((r = launch_finalize(c, 0.5, 0.0, 0.0, c->clock, nullptr, 0))) return r;
+  const bool timing = c->timing;
+  c->timing = false;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  int best = 0;
+  float best_ms = 0.f;
+  const int old = c->tile2;
+  for (int k = 0; k < nvar; ++k) {
+    c->tile2 = k;
+    if ((r = do_step(c, W, c->W2, c->clock + 1, nullptr, false))) break;  // warm-up
+    HIPCHK(hipEventRecord(e0, c->stream));
+    for (int s = 0; s < steps && !r; ++s) r = do_step(c, W, c->W2, c->clock + 1, nullptr, false);
+    HIPCHK(hipEventRecord(e1, c->stream));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    if (ms_per_variant) ms_per_variant[k] = ms / steps;
+    if (k == 0 || ms < best_ms) {
+      best = k;
+      best_ms = ms;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->timing = timing;
+  c->tile2 = old;
+  if (r) return r;
+  if (chosen) *chosen = best;
+  return tgks_set_tile(c, best);
 }
 
 }  // extern "C"

@@ -371,6 +371,86 @@ TGKS_HD R heat_combine(const R* f1, const R* f0, const R* c) {
   return s1 - c[0] * s0;
 }
 
+// Directional derivatives of closed-form moments of a Maxwellian g(W).
+// The derivative of g along a change dW of its conservative variables is
+// g a(psi) with <a psi> = dW / rho, so every full-space moment of g a(psi)
+// is the directional derivative of the corresponding moment of g:
+//   rho <u_k psi a>      = J_k(W) dW     (Euler flux F_k = rho <u_k psi>)
+//   rho <u_1 u_d psi a>  = dG_1d(W) dW   (G_1d = rho <u_1 u_d psi>)
+// which replaces micro-slope solves and moment sums over the full space.
+template <int D, class R>
+struct Prim {
+  R dU[D], dp, dh;
+};
+
+template <int D, class R>
+TGKS_HD void prim_dir(const Gas<D, R>& g, double N, const R* dW, Prim<D, R>& o) {
+  R udm = R(0.0), u2 = R(0.0);
+#pragma unroll
+  for (int e = 0; e < D; ++e) {
+    o.dU[e] = (dW[e + 1] - g.U[e] * dW[0]) * g.irho;
+    udm += g.U[e] * dW[e + 1];
+    u2 += g.U[e] * g.U[e];
+  }
+  // p = (2/N)(E - rho |U|^2 / 2)
+  o.dp = (2.0 / N) * ((dW[D + 1] - udm) + (0.5 * u2) * dW[0]);
+  o.dh = (o.dp - g.h * dW[0]) * g.irho;
+}
+
+// out = J_k(W) dW, the Euler flux along frame axis k differentiated along dW
+template <int D, class R>
+TGKS_HD void euler_jvp(const Gas<D, R>& g, R E, int k, const R* dW, const Prim<D, R>& d, R* out) {
+  const R p = g.rho * g.h;
+  const R mk = g.rho * g.U[k];
+  out[0] = dW[k + 1];
+#pragma unroll
+  for (int e = 0; e < D; ++e) {
+    R v = dW[k + 1] * g.U[e] + mk * d.dU[e];
+    if (e == k) v += d.dp;
+    out[e + 1] = v;
+  }
+  out[D + 1] = d.dU[k] * (E + p) + g.U[k] * (dW[D + 1] + d.dp);
+}
+
+// out = dG_1d(W) dW with G_1d = rho <u_1 u_d psi> (frame axis 0 normal):
+//   alpha 0: rho U1 Ud + p [d=0]
+//   alpha e: rho U1 Ud Ue + p (U1 [d=e] + Ud [e=0] + Ue [d=0])
+//   alpha E: rho U1 Ud (|U|^2 + (N+4) h)/2 + [d=0] p (|U|^2 + (N+2) h)/2
+template <int D, class R>
+TGKS_HD void g1d_jvp(const Gas<D, R>& g, double N, int d, const R* dW, const Prim<D, R>& q, R* out) {
+  const R p = g.rho * g.h;
+  const R dp = q.dp;
+  R u2 = R(0.0), udu = R(0.0);
+#pragma unroll
+  for (int e = 0; e < D; ++e) {
+    u2 += g.U[e] * g.U[e];
+    udu += g.U[e] * q.dU[e];
+  }
+  const R A = g.U[0] * g.U[d];
+  const R dA = q.dU[0] * g.U[d] + g.U[0] * q.dU[d];
+  const R dr = dW[0];
+  const R rdA = dr * A + g.rho * dA;  // d(rho A)
+  out[0] = d == 0 ? rdA + dp : rdA;
+  const R rA = g.rho * A;
+#pragma unroll
+  for (int e = 0; e < D; ++e) {
+    R v = rdA * g.U[e] + rA * q.dU[e];
+    if (d == e) v += dp * g.U[0] + p * q.dU[0];
+    if (e == 0) v += dp * g.U[d] + p * q.dU[d];
+    if (d == 0) v += dp * g.U[e] + p * q.dU[e];
+    out[e + 1] = v;
+  }
+  const R Q = u2 + (N + 4.0) * g.h;
+  const R dQ = 2.0 * udu + (N + 4.0) * q.dh;
+  R vE = rdA * Q + rA * dQ;
+  if (d == 0) {
+    const R Rr = u2 + (N + 2.0) * g.h;
+    const R dRr = 2.0 * udu + (N + 2.0) * q.dh;
+    vE += dp * Rr + p * dRr;
+  }
+  out[D + 1] = 0.5 * vE;
+}
+
 // Time-integrated flux F(dt) and F(dt/2) at one Gauss point.
 // Wl, Wr: states; dWl[d], dWr[d]: derivatives along frame axis d.
 // Returns false when a state is non-physical.
@@ -408,28 +488,23 @@ TGKS_HD bool gp_flux(const R* Wl, const R* Wr, const R (*dWl)[D + 2], const R (*
   make_gas<D>(W0, N, g0);
 
   // side contributions: dW0 (Eq. 2.6), A^s (Eq. 2.7), and the moments of the
-  // non-equilibrium part of Eq. 2.5
+  // non-equilibrium part of Eq. 2.5 over the half space
   R dW0[D][NC], S1[NC], S2[NC], S3[NC];
   R H1 = R(0.0), H2 = R(0.0), H3 = R(0.0);  // heat-flux moments (NS)
 #pragma unroll
   for (int side = 0; side < 2; ++side) {
     const Gas<D, R>& gs = side == 0 ? gl : gr;
+    const R* Ws = side == 0 ? Wl : Wr;
     const R(*dW)[NC] = side == 0 ? dWl : dWr;
-    MomSet<D, R> Sh, Sf;
+    MomSet<D, R> Sh;
     if (side == 0)
       half_table(gs.U[0], gs.h, hl0, hl1, Sh.m1);
     else
       half_table(gs.U[0], gs.h, hr0, hr1, Sh.m1);
     tangential_tables<D>(gs, Sh);
     xi_moments<D>(gs, P.K, Sh);
-    full_table(gs.U[0], gs.h, Sf.m1, NM1);
-#pragma unroll
-    for (int d = 1; d < D; ++d)
-#pragma unroll
-      for (int n = 0; n < NMT; ++n) Sf.mt[d - 1][n] = Sh.mt[d - 1][n];
-    Sf.xi1 = Sh.xi1;
-    Sf.xi2 = Sh.xi2;
     R a[D][NC];
+    R Wt[NC];  // rho <(sum_d u_d a_d) psi> = sum_d J_d dW_d; A^s solves <A psi> = -that / rho
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       R b[NC];
@@ -440,19 +515,25 @@ TGKS_HD bool gp_flux(const R* Wl, const R* Wr, const R (*dWl)[D + 2], const R (*
         mpsia<D, false>(Sh, a[d], 0, 0, 0, gs.rho, dW0[d]);
       else
         mpsia<D, true>(Sh, a[d], 0, 0, 0, gs.rho, dW0[d]);
-    }
-    // A^s: <A psi> = -sum_d <u_d a_d psi> over the full g_s
-    R rhs[NC], A[NC];
+      Prim<D, R> pd;
+      prim_dir<D>(gs, N, dW[d], pd);
+      R jv[NC];
+      euler_jvp<D>(gs, Ws[D + 1], d, dW[d], pd, jv);
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-      int i, j, k;
-      unit(d, i, j, k);
-      if (d == 0)
-        mpsia<D, false>(Sf, a[d], i, j, k, R(-1.0), rhs);
-      else
-        mpsia<D, true>(Sf, a[d], i, j, k, R(-1.0), rhs);
+      for (int q = 0; q < NC; ++q) {
+        if (d == 0)
+          Wt[q] = jv[q];
+        else
+          Wt[q] += jv[q];
+      }
     }
-    micro_solve<D>(gs, N, rhs, A);
+    R A[NC];
+    {
+      R b[NC];
+#pragma unroll
+      for (int q = 0; q < NC; ++q) b[q] = -(Wt[q] * gs.irho);
+      micro_solve<D>(gs, N, b, A);
+    }
     // <u1 psi>, sum_d <u1 u_d psi a_d>, <u1 psi A> over the half space
     R g[NC];
     gpsi<D>(Sh, 1, 0, 0, 0, g);
@@ -499,56 +580,49 @@ TGKS_HD bool gp_flux(const R* Wl, const R* Wr, const R (*dWl)[D + 2], const R (*
     }
   }
 
-  // equilibrium part: abar_d, Abar (Eq. 2.7) and its moments
-  R V1[NC], V2[NC], V3[NC];
-  R G1 = R(0.0), G2 = R(0.0), G3 = R(0.0);
+  // equilibrium part of Eq. 2.5, rho0-weighted moments in closed form:
+  //   T1 = rho0 <u1 psi>_0 = F_1(W0)
+  //   W0t = -sum_d J_d(W0) dW0_d = rho0 <Abar psi>_0 (compatibility, Eq. 2.7)
+  //   T2 = rho0 sum_d <u1 u_d psi abar_d>_0 = sum_d dG_1d(W0) dW0_d
+  //   T3 = rho0 <u1 psi Abar>_0 = J_1(W0) W0t
+  R T1[NC], T2[NC], T3[NC], W0t[NC];
   {
-    MomSet<D, R> S;
-    full_table(g0.U[0], g0.h, S.m1, NM1);
-    tangential_tables<D>(g0, S);
-    xi_moments<D>(g0, P.K, S);
-    R ab[D][NC];
+    const R p0 = g0.rho * g0.h;
+    const R E0 = W0[D + 1];
+    T1[0] = W0[1];
+#pragma unroll
+    for (int e = 0; e < D; ++e) T1[e + 1] = W0[1] * g0.U[e] + (e == 0 ? p0 : R(0.0));
+    T1[D + 1] = g0.U[0] * (E0 + p0);
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-      R b[NC];
+      Prim<D, R> pd;
+      prim_dir<D>(g0, N, dW0[d], pd);
+      R jv[NC], gv[NC];
+      euler_jvp<D>(g0, E0, d, dW0[d], pd, jv);
+      g1d_jvp<D>(g0, N, d, dW0[d], pd, gv);
 #pragma unroll
-      for (int q = 0; q < NC; ++q) b[q] = dW0[d][q] * g0.irho;
-      micro_solve<D>(g0, N, b, ab[d]);
+      for (int q = 0; q < NC; ++q) {
+        if (d == 0) {
+          W0t[q] = -jv[q];
+          T2[q] = gv[q];
+        } else {
+          W0t[q] -= jv[q];
+          T2[q] += gv[q];
+        }
+      }
     }
-    R rhs[NC], Ab[NC];
+    Prim<D, R> pt;
+    prim_dir<D>(g0, N, W0t, pt);
+    euler_jvp<D>(g0, E0, 0, W0t, pt, T3);
+  }
+  R G2 = R(0.0), G3 = R(0.0);  // heat-flux moments of the equilibrium part (the first vanishes)
+  if (NS) {
+    // <psi sum_d u_d abar_d>_0 = -<psi Abar>_0 by the compatibility condition
+    R w2[NC];
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-      int i, j, k;
-      unit(d, i, j, k);
-      if (d == 0)
-        mpsia<D, false>(S, ab[d], i, j, k, R(-1.0), rhs);
-      else
-        mpsia<D, true>(S, ab[d], i, j, k, R(-1.0), rhs);
-    }
-    micro_solve<D>(g0, N, rhs, Ab);
-    gpsi<D>(S, 1, 0, 0, 0, V1);
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-      int i, j, k;
-      unit(d, i, j, k);
-      if (d == 0)
-        mpsia<D, false>(S, ab[d], 1 + i, j, k, R(1.0), V2);
-      else
-        mpsia<D, true>(S, ab[d], 1 + i, j, k, R(1.0), V2);
-    }
-    mpsia<D, false>(S, Ab, 1, 0, 0, R(1.0), V3);
-    if (NS) {
-      R f0[NC], w3[NC];
-      gpsi<D>(S, 0, 0, 0, 0, f0);
-      mpsia<D, false>(S, Ab, 0, 0, 0, R(1.0), w3);
-      // <psi sum_d u_d abar_d> = -<psi Abar> by the compatibility condition
-      R w2[NC];
-#pragma unroll
-      for (int q = 0; q < NC; ++q) w2[q] = -w3[q];
-      G1 = heat_combine<D>(V1, f0, g0.U);
-      G2 = heat_combine<D>(V2, w2, g0.U);
-      G3 = heat_combine<D>(V3, w3, g0.U);
-    }
+    for (int q = 0; q < NC; ++q) w2[q] = -W0t[q];
+    G2 = heat_combine<D>(T2, w2, g0.U);
+    G3 = heat_combine<D>(T3, W0t, g0.U);
   }
 
   // collision time (Sec. 5 preamble); dt is the full step in both stages
@@ -584,9 +658,9 @@ TGKS_HD bool gp_flux(const R* Wl, const R* Wr, const R (*dWl)[D + 2], const R (*
     R* F = id == 0 ? Fdt : Fh;
 #pragma unroll
     for (int q = 0; q < NC; ++q)
-      F[q] = g0.rho * ((C1 * V1[q] + C2 * V2[q]) + C3 * V3[q]) + ((C4 * S1[q] + C5 * S2[q]) + C6 * S3[q]);
+      F[q] = ((C1 * T1[q] + C2 * T2[q]) + C3 * T3[q]) + ((C4 * S1[q] + C5 * S2[q]) + C6 * S3[q]);
     if (NS) {
-      const R q = g0.rho * ((C1 * G1 + C2 * G2) + C3 * G3) + ((C4 * H1 + C5 * H2) + C6 * H3);
+      const R q = (C2 * G2 + C3 * G3) + ((C4 * H1 + C5 * H2) + C6 * H3);
       F[NC - 1] += P.pr_fix * q;
     }
   }

@@ -119,12 +119,17 @@ __global__ __launch_bounds__(256) void face1d_kernel(StageArgs a) {
 // then each thread reconstructs its face's left and right states along the
 // face at the two Gauss points and evaluates the two Gauss-point fluxes.
 // ---------------------------------------------------------------------------
-constexpr int TN2 = 16, TT2 = 8;  // 128 faces per block, two lanes (Gauss points) per face
+// Tile shapes (faces along the normal x faces along the tangential axis),
+// two lanes per face; chosen per grid by the autotuner.
+constexpr int NTILE2 = 3;
+__host__ __device__ constexpr int tile2_tn(int k) { return k == 0 ? 16 : (k == 1 ? 16 : 8); }
+__host__ __device__ constexpr int tile2_tt(int k) { return k == 0 ? 8 : (k == 1 ? 16 : 16); }
 
-template <int AX, int STAGE, bool NS, bool FLAGS>
-__global__ __launch_bounds__(256, 2) void face2d_kernel(StageArgs a) {
+template <int AX, int STAGE, bool NS, bool FLAGS, int TILE>
+__global__ __launch_bounds__(2 * tile2_tn(TILE) * tile2_tt(TILE), 2) void face2d_kernel(StageArgs a) {
+  constexpr int TN = tile2_tn(TILE), TT = tile2_tt(TILE), NT = 2 * TN * TT;
   constexpr int NC = 4;
-  constexpr int LN = TN2 + 5, LT = TT2 + 4, RN = TN2 + 1;
+  constexpr int LN = TN + 5, LT = TT + 4, RN = TN + 1;
   __shared__ double sW[NC][LT][LN];
   __shared__ double sR[NC][LT][RN][4];
   const double dt = *a.dt;
@@ -132,11 +137,11 @@ __global__ __launch_bounds__(256, 2) void face2d_kernel(StageArgs a) {
   const Geom& g = a.g;
   const int TA = 1 - AX;  // tangential axis
   const int nN = g.n[AX], nT = g.n[TA];
-  const int f0 = blockIdx.x * TN2, t0 = blockIdx.y * TT2;
+  const int f0 = blockIdx.x * TN, t0 = blockIdx.y * TT;
   const int tid = threadIdx.x;
 
   // 1. cells of the tile, ghost cells by the index map
-  for (int L = tid; L < NC * LN * LT; L += 256) {
+  for (int L = tid; L < NC * LN * LT; L += NT) {
     int nl, tl;
     if (AX == 0) {
       nl = L % LN;
@@ -152,9 +157,9 @@ __global__ __launch_bounds__(256, 2) void face2d_kernel(StageArgs a) {
   }
   __syncthreads();
 
-  // 2. normal reconstruction of cells f0-1 .. f0+TN2-1 on every staged row
+  // 2. normal reconstruction of cells f0-1 .. f0+TN-1 on every staged row
   const double idn = 1.0 / g.dx[AX];  // normal slopes per unit length
-  for (int L = tid; L < NC * LT * RN; L += 256) {
+  for (int L = tid; L < NC * LT * RN; L += NT) {
     const int nr = L % RN;
     const int tl = (L / RN) % LT;
     const int c = L / (RN * LT);
@@ -168,7 +173,7 @@ __global__ __launch_bounds__(256, 2) void face2d_kernel(StageArgs a) {
     sR[c][tl][nr][3] = o[3] * idn;
     if (FLAGS) {
       const int cell = f0 - 1 + nr, row = t0 - 2 + tl;
-      if (nr >= 1 && cell < nN && tl >= 2 && tl < TT2 + 2 && row < nT) {
+      if (nr >= 1 && cell < nN && tl >= 2 && tl < TT + 2 && row < nT) {
         const long long lin = AX == 0 ? (long long)row * g.n[0] + cell : (long long)cell * g.n[0] + row;
         a.nflags[((long long)AX * NC + c) * g.ncell + lin] = (uint8_t)fl;
       }
@@ -176,68 +181,58 @@ __global__ __launch_bounds__(256, 2) void face2d_kernel(StageArgs a) {
   }
   __syncthreads();
 
-  // 3. lanes 2k and 2k+1 share face k: each selects the tangential stencils of
-  //    one side (left: lane 0, right: lane 1), the pair exchanges the flags,
-  //    then each evaluates the reconstruction and the flux at its own Gauss
-  //    point m and the pair sums the two.
+  // 3. lanes 2k and 2k+1 share face k.  Lane m reconstructs side m (left: 0,
+  //    right: 1) along the face at both Gauss points, keeps Gauss point m and
+  //    hands Gauss point 1-m to its partner; each lane then evaluates the
+  //    flux at its Gauss point m and the pair sums the two.
   const int m = tid & 1;
   const int fi = tid >> 1;
-  const int fn = fi % TN2, ft = fi / TN2;
+  const int fn = fi % TN, ft = fi / TN;
   const int f = f0 + fn, t = t0 + ft;
   const bool live = f <= nN && t < nT;
   const int perm[NC] = {0, 1 + AX, 1 + TA, 3};
   const long long nf = face_count(g, AX);
   const long long fidx = AX == 0 ? (long long)t * (g.n[0] + 1) + f : (long long)f * g.n[0] + t;
-  unsigned mine = 0;
-  if (live) {
+  const double idt = 1.0 / g.dx[TA];
+  double Wg[2][NC], Dg[2][2][NC];  // [side][q], [side][axis n/t][q]
+  {
     const int nr = m == 0 ? fn : fn + 1;
     const int vo = m == 0 ? 2 : 0;
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
       const int c = perm[q];
-      double Qw[5], Qn[5];
-#pragma unroll
-      for (int r = 0; r < 5; ++r) {
-        Qw[r] = sR[c][ft + r][nr][vo];
-        Qn[r] = sR[c][ft + r][nr][vo + 1];
-      }
-      const unsigned fw = teno_flag(Qw, a.tt);
-      const unsigned fq = teno_flag(Qn, a.tt);
-      mine |= (fw | (fq << 4)) << (8 * q);
-      if (FLAGS) {
-        a.tflags[((long long)(0 * 2 + m) * NC + c) * nf + fidx] = (uint8_t)fw;
-        a.tflags[((long long)(1 * 2 + m) * NC + c) * nf + fidx] = (uint8_t)fq;
-      }
-    }
-  }
-  const unsigned other = (unsigned)__shfl_xor((int)mine, 1);
-  double A[NC] = {0, 0, 0, 0}, B[NC] = {0, 0, 0, 0};
-  if (live) {
-    const double idt = 1.0 / g.dx[TA];
-    double Wg[2][NC], Dg[2][2][NC];  // [side][q], [side][axis n/t][q]
-#pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      const unsigned packed = side == m ? mine : other;
-      const int nr = side == 0 ? fn : fn + 1;
-      const int vo = side == 0 ? 2 : 0;
-#pragma unroll
-      for (int q = 0; q < NC; ++q) {
-        const int c = perm[q];
+      double v[2] = {0, 0}, dv[2] = {0, 0}, vn[2] = {0, 0}, dvn[2];
+      if (live) {
         double Qw[5], Qn[5];
 #pragma unroll
         for (int r = 0; r < 5; ++r) {
           Qw[r] = sR[c][ft + r][nr][vo];
           Qn[r] = sR[c][ft + r][nr][vo + 1];
         }
-        const unsigned fw = (packed >> (8 * q)) & 15u, fq = (packed >> (8 * q + 4)) & 15u;
-        double v, dv, vn, dvn;
-        teno_gauss_at(Qw, fw, m, v, dv);
-        teno_gauss_at(Qn, fq, m, vn, dvn);
-        Wg[side][q] = v;
-        Dg[side][1][q] = dv * idt;
-        Dg[side][0][q] = vn;
+        const unsigned fw = teno_flag(Qw, a.tt);
+        const unsigned fq = teno_flag(Qn, a.tt);
+        if (FLAGS) {
+          a.tflags[((long long)(0 * 2 + m) * NC + c) * nf + fidx] = (uint8_t)fw;
+          a.tflags[((long long)(1 * 2 + m) * NC + c) * nf + fidx] = (uint8_t)fq;
+        }
+        teno_gauss(Qw, fw, v, dv);
+        teno_gauss(Qn, fq, vn, dvn);
       }
+      // own side at own Gauss point; the partner's side at this Gauss point
+      // arrives from the partner, which computed it
+      const double sv = m ? v[0] : v[1], sd = m ? dv[0] : dv[1], sn = m ? vn[0] : vn[1];
+      const double rv = __shfl_xor(sv, 1), rd = __shfl_xor(sd, 1), rn = __shfl_xor(sn, 1);
+      const double ov = m ? v[1] : v[0], od = m ? dv[1] : dv[0], on = m ? vn[1] : vn[0];
+      Wg[0][q] = m == 0 ? ov : rv;
+      Wg[1][q] = m == 0 ? rv : ov;
+      Dg[0][1][q] = (m == 0 ? od : rd) * idt;
+      Dg[1][1][q] = (m == 0 ? rd : od) * idt;
+      Dg[0][0][q] = m == 0 ? on : rn;
+      Dg[1][0][q] = m == 0 ? rn : on;
     }
+  }
+  double A[NC] = {0, 0, 0, 0}, B[NC] = {0, 0, 0, 0};
+  if (live) {
     double Fdt[NC], Fh[NC];
     if (!gp_flux<2, NS>(Wg[0], Wg[1], Dg[0], Dg[1], a.fc, dt, Fdt, Fh)) atomicAdd(a.fail, 1ull);
     write_combined<NC>(STAGE, Fdt, Fh, 0.5, A, B);

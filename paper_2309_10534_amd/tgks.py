@@ -67,9 +67,13 @@ def lib():
     L.tgks_timing.argtypes = [vp, C.c_int32]
     L.tgks_kernel_time.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     L.tgks_flop_counts.argtypes = [P, C.POINTER(C.c_double), C.c_int32]
+    L.tgks_set_tile.argtypes = [vp, C.c_int32]
+    L.tgks_tune.argtypes = [vp, vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_float)]
+    dp = C.POINTER(C.c_double)
+    L.tgks_gp_flux_host.argtypes = [P, dp, dp, dp, dp, C.c_double, dp]
     for f in ("tgks_params_default", "tgks_create", "tgks_destroy", "tgks_set_stream", "tgks_cfl_dt", "tgks_step",
               "tgks_run", "tgks_status", "tgks_reset_status", "tgks_timing", "tgks_kernel_time",
-              "tgks_flop_counts"):
+              "tgks_flop_counts", "tgks_gp_flux_host", "tgks_set_tile", "tgks_tune"):
         getattr(L, f).restype = C.c_int
     _lib = L
     return L
@@ -190,3 +194,40 @@ def tgks_flop_counts(params):
     _check(lib().tgks_flop_counts(C.byref(params), out, 8), "tgks_flop_counts")
     keys = ("normal", "face", "face_stage2", "update1", "update2", "face_transcendentals", "face_divisions", "cfl")
     return {k: out[i] for i, k in enumerate(keys)}
+
+
+def tgks_gp_flux_host(params, Wl, Wr, dWl, dWr, dt):
+    """Host evaluation of the device Gauss-point flux (numpy in, numpy out):
+    returns (F[2][nc] for dt and dt/2, ok)."""
+    import numpy as np
+    D = params.ndim
+    nc = D + 2
+
+    def buf(x, n):
+        a = np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(-1))
+        assert a.size == n
+        return a
+
+    l, r = buf(Wl, nc), buf(Wr, nc)
+    dl, dr = buf(dWl, D * nc), buf(dWr, D * nc)
+    F = np.zeros(2 * nc)
+    P = C.POINTER(C.c_double)
+    rc = lib().tgks_gp_flux_host(C.byref(params), l.ctypes.data_as(P), r.ctypes.data_as(P), dl.ctypes.data_as(P),
+                                 dr.ctypes.data_as(P), float(dt), F.ctypes.data_as(P))
+    if rc < 0:
+        raise TgksError("tgks_gp_flux_host: invalid argument")
+    return F.reshape(2, nc), rc == 0
+
+
+def tgks_set_tile(ctx, tile):
+    _check(lib().tgks_set_tile(ctx, int(tile)), "tgks_set_tile")
+
+
+def tgks_tune(ctx, W, steps=3):
+    """Time every 2-D tile shape on the state W, keep the fastest; returns
+    (chosen index, [ms per step of each shape])."""
+    n = tgks_state_size(ctx)
+    ch = C.c_int32()
+    ms = (C.c_float * 3)()
+    _check(lib().tgks_tune(ctx, _ptr(W, n), int(steps), C.byref(ch), ms), "tgks_tune")
+    return ch.value, [ms[i] for i in range(3)]
