@@ -38,6 +38,9 @@ def parse():
                     help="quadrant-state seed; 1 is the first seed whose run is failure-free "
                          "(seed 0 reaches negative pressure: the scheme has no positivity limiter)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched 1-D/2-D Riemann sets")
+    ap.add_argument("--batch-steps", type=int, default=100)
+    ap.add_argument("--batch-instances", type=int, default=256)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     return ap.parse_args()
 
@@ -65,6 +68,78 @@ def cpu_baseline(W0, dx, n, target_s):
     return {"value": cells / el / 1e6, "unit": "Mcell-updates/s", "cores": threads, "kind": "oracle",
             "sample": f"one S2O4 step on a {n}x{rows} strip (rows {n // 2 - rows // 2}..{n // 2 - rows // 2 + rows - 1}) "
                       f"of the same initial field, {el:.1f} s"}
+
+
+def batched(dim, seed, n_inst, steps, ranges=None):
+    """Batched set of seeded uneven Riemann instances (1-D: N ~ U{64..1024};
+    2-D: N x N, N ~ U{64..512}; rho log-uniform [0.1, 10], p log-uniform
+    [0.01, 1000], velocities uniform [-2, 2]; transmissive, CFL 0.5): one
+    graph-captured batched run of `steps` steps against the plain loop of
+    single-grid runs (tgks_run per instance, no graph), outputs compared bit
+    for bit.  Throughput counts the cell-updates actually performed: an
+    instance that reaches a non-physical state stops there (the scheme has no
+    positivity limiter)."""
+    import numpy as np
+    import torch
+
+    from paper_2309_10534_amd import inputs as I
+    from paper_2309_10534_amd import tgks
+
+    inst, rej, _ = I.riemann_instances(n_inst, dim=dim, seed=seed, **(ranges or {}))
+    shapes = [W.shape for W, _ in inst]
+    params = [tgks.tgks_params_default(dim, list(W.shape[1:])[::-1], [dx] * dim) for W, dx in inst]
+    cells = np.array([W[0].size for W, _ in inst], dtype=np.int64)
+    b = tgks.tgks_batch_create(params)
+    W0 = torch.from_numpy(tgks.pack([W for W, _ in inst])).cuda()
+    W = W0.clone()
+    tile, tile_ms = (tgks.tgks_batch_tune(b, W, steps=2) if dim == 2 else (0, None))
+    tgks.tgks_batch_run(b, W, steps, 0.5, use_graph=True)  # capture + warm-up replay
+    torch.cuda.synchronize()
+    W.copy_(W0)
+    tgks.tgks_batch_reset_status(b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tgks.tgks_batch_run(b, W, steps, 0.5, use_graph=True)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    taken = np.array(tgks.tgks_batch_steps(b), dtype=np.int64)
+    fails = tgks.tgks_batch_status(b)
+    offs = tgks.tgks_batch_offsets(b)
+    tgks.tgks_batch_destroy(b)
+    Wb = tgks.unpack(W, offs, shapes)
+
+    # plain per-instance loop on the same stream, same tile shape
+    ctxs = [tgks.tgks_create(p) for p in params]
+    for c in ctxs:
+        tgks.tgks_set_tile(c, tile)
+    Ws = [torch.from_numpy(np.ascontiguousarray(w)).cuda() for w, _ in inst]
+    for c, w in zip(ctxs, Ws):  # warm-up (one step each)
+        tgks.tgks_run(c, w.clone(), 1, cfl=0.5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c, w in zip(ctxs, Ws):
+        tgks.tgks_run(c, w, steps, cfl=0.5)
+    torch.cuda.synchronize()
+    t_single = time.perf_counter() - t0
+    same = sum(bool(torch.equal(torch.nan_to_num(a, nan=7.0), torch.nan_to_num(s_.view(a.shape), nan=7.0)))
+               for a, s_ in zip(Wb, Ws))
+    for c in ctxs:
+        tgks.tgks_destroy(c)
+    updates = int((cells * taken).sum())
+    return {
+        "workload": f"batched_{dim}d_riemann_{n_inst}_instances_seed{seed}_{steps}_steps"
+                    + ("" if ranges is None else "_" + "_".join(f"{k}{v[0]}-{v[1]}" for k, v in ranges.items())),
+        "cells": int(cells.sum()), "cell_updates": updates,
+        "instances_failure_free": int(sum(1 for f, k in zip(fails, taken) if f == 0 and k == steps)),
+        "rejected_draws": rej,
+        "batched": {"value": round(updates / t_batch / 1e6, 3), "unit": "Mcell-updates/s",
+                    "seconds": round(t_batch, 4), "graph": True, "tile": tile,
+                    "tile_ms_per_step": [round(x, 4) for x in tile_ms] if tile_ms else None},
+        "per_instance": {"value": round(updates / t_single / 1e6, 3), "unit": "Mcell-updates/s",
+                         "seconds": round(t_single, 4), "graph": False},
+        "speedup": round(t_single / t_batch, 3),
+        "bitwise_equal_instances": same,
+    }
 
 
 def main():
@@ -137,6 +212,14 @@ def main():
                      "launches": launches},
         "kernel_ms_per_step": {k: round(v[0] / args.steps, 5) for k, v in kt.items()},
     }
+    if not args.no_batched:
+        # the stated state ranges, and a milder 2-D set in which every
+        # instance runs all steps (without a positivity limiter most 2-D
+        # instances of the wide ranges reach a non-physical state)
+        mild = dict(rho_range=(0.5, 2.0), p_range=(0.1, 1.5), vel_range=(-0.5, 0.5))
+        out["batched"] = [batched(1, 1, args.batch_instances, args.batch_steps),
+                          batched(2, 2, args.batch_instances, args.batch_steps),
+                          batched(2, 2, args.batch_instances, args.batch_steps, ranges=mild)]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W0, dx, n, args.cpu_seconds)
     print(json.dumps(out), flush=True)

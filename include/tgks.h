@@ -165,6 +165,55 @@ int tgks_flop_counts(const tgks_params* p, double* out, int32_t nout);
 int tgks_gp_flux_host(const tgks_params* p, const double* Wl, const double* Wr, const double* dWl,
                       const double* dWr, double dt, double* F);
 
+/* ------------------------------------------------------------------------
+ * Batched runs: many independent 1-D or 2-D grids (uneven sizes, each with
+ * its own parameters, boundary kinds, CFL time step, clock and failure
+ * counter) advanced together, one launch per kernel kind and stage for the
+ * whole batch.  A batched step of an instance is bit-identical to the same
+ * step of that instance in its own context.
+ *
+ * Packed layout: the instances' states one after another, instance i at
+ * doubles [offsets[i], offsets[i+1]) of W_packed, each with the layout of a
+ * single state ([nc][ny][nx]).
+ * ------------------------------------------------------------------------ */
+typedef struct tgks_batch tgks_batch;
+
+/* per_instance: host array of n_inst parameter sets, all with the same ndim
+ * (1 or 2) and all Euler or all Navier-Stokes with a Prandtl correction.
+ * Allocates the batch's work buffers (about three packed states plus face
+ * fluxes).  TGKS_EINVAL for invalid or mixed parameters. */
+int tgks_batch_create(const tgks_params* per_instance, int32_t n_inst, void* hip_stream, tgks_batch** out);
+int tgks_batch_destroy(tgks_batch* b);
+int tgks_batch_set_stream(tgks_batch* b, void* hip_stream);
+
+/* Doubles of one packed state; offsets (host, n_inst + 1 entries) of the
+ * instances' states in it. */
+int64_t tgks_batch_state_size(const tgks_batch* b);
+int tgks_batch_offsets(const tgks_batch* b, int64_t* offsets);
+
+/* Advance every instance in place by n_steps S2O4 steps, each with its own
+ * CFL step (cfl > 0) computed on the device before every step, clipped at
+ * t_end when t_end > 0.  time_dev (device, [n_inst][2] doubles, or NULL)
+ * receives each instance's (t, dt of the next step).  use_graph != 0
+ * captures the whole run into a HIP graph on first use and replays it. */
+int tgks_batch_run(tgks_batch* b, double* W_packed, int32_t n_steps, double cfl, double t_end, double* time_dev,
+                   int32_t use_graph);
+
+/* Failure counts per instance (host array of n_inst; synchronises). */
+int tgks_batch_status(tgks_batch* b, int64_t* failures);
+
+/* Steps each instance actually took (dt > 0) in the last run (host array of
+ * n_inst; synchronises): an instance stops at t_end or after a non-physical
+ * state (its dt is then NaN and later steps leave it unchanged). */
+int tgks_batch_steps(tgks_batch* b, int64_t* steps);
+int tgks_batch_reset_status(tgks_batch* b);
+
+/* 2-D tile shape (as tgks_set_tile) and its autotuner over the whole batch:
+ * every shape is timed over `steps` batched steps of W_packed (not
+ * modified); the fastest is kept.  ms_per_variant: host, 3 floats, or NULL. */
+int tgks_batch_set_tile(tgks_batch* b, int32_t tile);
+int tgks_batch_tune(tgks_batch* b, const double* W_packed, int32_t steps, int32_t* chosen, float* ms_per_variant);
+
 #ifdef __cplusplus
 }
 #endif

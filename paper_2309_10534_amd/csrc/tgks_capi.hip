@@ -5,172 +5,12 @@
 // tgks_run, the per-direction face flux arrays, the 3-D normal
 // reconstruction buffer, CFL partial minima, a device clock {t, dt} and the
 // failure counter.  All launches go to the context's stream.
-#include <hip/hip_runtime.h>
-
-#include <cmath>
-#include <cstdio>
-#include <cstring>
-#include <new>
-#include <vector>
-
-#include "tgks.h"
-#include "tgks_kernels.hpp"
+#include "tgks_internal.hpp"
 #include "tgks_opcount.hpp"
 
 using namespace tgks;
 
-namespace {
-
-constexpr int NKIND = 7;
-
-struct EventPair {
-  hipEvent_t a, b;
-};
-
-}  // namespace
-
-struct tgks_ctx {
-  tgks_params p;
-  Geom g;
-  FluxCfg fc;
-  TenoCfg tn, tt;
-  bool ns;
-  int tile2 = 0;  // 2-D face-kernel tile shape (tile2_tn/tile2_tt index)
-  hipStream_t stream;
-  int nc;
-  long long ncell;
-  long long nface[3];
-  double* Ws = nullptr;
-  double* P = nullptr;
-  double* W2 = nullptr;
-  double* FA[3] = {nullptr, nullptr, nullptr};
-  double* FB[3] = {nullptr, nullptr, nullptr};
-  double* R = nullptr;
-  double* partial = nullptr;
-  int nblk = 0;
-  double* clock = nullptr;
-  unsigned long long* fail = nullptr;
-  // graph cache of tgks_run
-  hipGraphExec_t gexec = nullptr;
-  hipGraph_t graph = nullptr;
-  int g_steps = -1;
-  double g_cfl = 0, g_tend = 0, g_fixed = 0;
-  double* g_W = nullptr;
-  double* g_time = nullptr;
-  // timing
-  bool timing = false;
-  std::vector<EventPair> ev[NKIND];
-  std::vector<hipEvent_t> pool;
-};
-
-#define HIPCHK(x)                                                                  \
-  do {                                                                             \
-    hipError_t e_ = (x);                                                           \
-    if (e_ != hipSuccess) {                                                        \
-      fprintf(stderr, "tgks: %s failed: %s\n", #x, hipGetErrorString(e_));         \
-      return TGKS_EHIP;                                                            \
-    }                                                                              \
-  } while (0)
-
-static int check_params(const tgks_params* p) {
-  if (!p || p->ndim < 1 || p->ndim > 3) return TGKS_EINVAL;
-  for (int d = 0; d < 3; ++d) {
-    if (d < p->ndim) {
-      if (p->n[d] < 3 || !(p->dx[d] > 0.0)) return TGKS_EINVAL;
-      if (p->bc_lo[d] < 0 || p->bc_lo[d] > 2 || p->bc_hi[d] < 0 || p->bc_hi[d] > 2) return TGKS_EINVAL;
-      if ((p->bc_lo[d] == TGKS_BC_PERIODIC) != (p->bc_hi[d] == TGKS_BC_PERIODIC)) return TGKS_EINVAL;
-    } else if (p->n[d] != 1) {
-      return TGKS_EINVAL;
-    }
-  }
-  if (!(p->gamma > 1.0) || !(p->mu >= 0.0) || !(p->prandtl > 0.0)) return TGKS_EINVAL;
-  if (p->tau_mode < 0 || p->tau_mode > 2) return TGKS_EINVAL;
-  if (p->tau_mode == TGKS_TAU_VISCOUS && !(p->mu > 0.0)) return TGKS_EINVAL;
-  if (p->q < 1 || p->q > 16 || !(p->eps >= 0.0)) return TGKS_EINVAL;
-  double cells = 1.0;
-  for (int d = 0; d < p->ndim; ++d) cells *= p->n[d];
-  if (cells > 4.0e9) return TGKS_EINVAL;
-  return TGKS_OK;
-}
-
-static hipEvent_t take_event(tgks_ctx* c) {
-  if (!c->pool.empty()) {
-    hipEvent_t e = c->pool.back();
-    c->pool.pop_back();
-    return e;
-  }
-  hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
-  return e;
-}
-
-// begin/end markers around one launch of a kernel kind
-struct Timer {
-  tgks_ctx* c;
-  int kind;
-  hipEvent_t a = nullptr;
-  Timer(tgks_ctx* c_, int k) : c(c_), kind(k) {
-    if (c->timing) {
-      a = take_event(c);
-      if (a) (void)hipEventRecord(a, c->stream);
-    }
-  }
-  ~Timer() {
-    if (c->timing && a) {
-      hipEvent_t b = take_event(c);
-      if (b) {
-        (void)hipEventRecord(b, c->stream);
-        c->ev[kind].push_back({a, b});
-      }
-    }
-  }
-};
-
-static StageArgs stage_args(tgks_ctx* c, const double* W, int ax, const double* dt) {
-  StageArgs a;
-  a.g = c->g;
-  a.fc = c->fc;
-  a.tn = c->tn;
-  a.tt = c->tt;
-  a.W = W;
-  a.FA = c->FA[ax];
-  a.FB = c->FB[ax];
-  a.dt = dt;
-  a.fail = c->fail;
-  a.nflags = nullptr;
-  a.tflags = nullptr;
-  a.R = c->R;
-  a.Rout = c->R;
-  return a;
-}
-
 #define LAUNCH(kern, grid, block, args) hipLaunchKernelGGL(kern, grid, block, 0, c->stream, args)
-
-// 2-D face kernel of one direction, stage and tile shape
-template <int TILE>
-static void launch_face2d(tgks_ctx* c, const StageArgs& a, int ax, int stage, bool fl, int nN, int nT) {
-  constexpr int TN = tile2_tn(TILE), TT = tile2_tt(TILE);
-  const dim3 grid((unsigned)((nN + 1 + TN - 1) / TN), (unsigned)((nT + TT - 1) / TT)), block(2 * TN * TT);
-#define F2(AXV)                                                                                     \
-  if (stage == 1) {                                                                                 \
-    if (fl) {                                                                                       \
-      if (c->ns) LAUNCH((face2d_kernel<AXV, 1, true, true, TILE>), grid, block, a);                 \
-      else LAUNCH((face2d_kernel<AXV, 1, false, true, TILE>), grid, block, a);                      \
-    } else {                                                                                        \
-      if (c->ns) LAUNCH((face2d_kernel<AXV, 1, true, false, TILE>), grid, block, a);                \
-      else LAUNCH((face2d_kernel<AXV, 1, false, false, TILE>), grid, block, a);                     \
-    }                                                                                               \
-  } else {                                                                                          \
-    if (c->ns) LAUNCH((face2d_kernel<AXV, 2, true, false, TILE>), grid, block, a);                  \
-    else LAUNCH((face2d_kernel<AXV, 2, false, false, TILE>), grid, block, a);                       \
-  }
-  if (ax == 0) {
-    F2(0)
-  } else {
-    F2(1)
-  }
-#undef F2
-}
 
 // face fluxes of one stage in every direction
 static int launch_faces(tgks_ctx* c, const double* W, const double* dt, int stage, uint8_t* flags) {
@@ -203,17 +43,7 @@ static int launch_faces(tgks_ctx* c, const double* W, const double* dt, int stag
       }
     } else if (D == 2) {
       Timer tm(c, ax);
-      const int nN = c->g.n[ax], nT = c->g.n[1 - ax];
-      switch (c->tile2) {
-        case 1:
-          launch_face2d<1>(c, a, ax, stage, fl, nN, nT);
-          break;
-        case 2:
-          launch_face2d<2>(c, a, ax, stage, fl, nN, nT);
-          break;
-        default:
-          launch_face2d<0>(c, a, ax, stage, fl, nN, nT);
-      }
+      launch_face2d_any(c, a, ax, stage, fl);
     } else {
       int ext[3] = {c->g.n[0], c->g.n[1], c->g.n[2]};
       ext[ax] += 2;

@@ -1,0 +1,48 @@
+// tgks_face2d.hip -- launches of the 2-D face kernel (all directions,
+// stages and tile shapes), compiled apart from the rest of the library.
+#include "tgks_internal.hpp"
+
+using namespace tgks;
+
+#define LAUNCH(kern, grid, block, args) hipLaunchKernelGGL(kern, grid, block, 0, c->stream, args)
+
+// 2-D face kernel of one direction, stage and tile shape
+template <int TILE>
+static void launch_face2d(tgks_ctx* c, const StageArgs& a, int ax, int stage, bool fl, int nN, int nT) {
+  constexpr int TN = tile2_tn(TILE), TT = tile2_tt(TILE);
+  const dim3 grid((unsigned)((nN + 1 + TN - 1) / TN), (unsigned)((nT + TT - 1) / TT)), block(2 * TN * TT);
+#define F2(AXV)                                                                                     \
+  if (stage == 1) {                                                                                 \
+    if (fl) {                                                                                       \
+      if (c->ns) LAUNCH((face2d_kernel<AXV, 1, true, true, TILE>), grid, block, a);                 \
+      else LAUNCH((face2d_kernel<AXV, 1, false, true, TILE>), grid, block, a);                      \
+    } else {                                                                                        \
+      if (c->ns) LAUNCH((face2d_kernel<AXV, 1, true, false, TILE>), grid, block, a);                \
+      else LAUNCH((face2d_kernel<AXV, 1, false, false, TILE>), grid, block, a);                     \
+    }                                                                                               \
+  } else {                                                                                          \
+    if (c->ns) LAUNCH((face2d_kernel<AXV, 2, true, false, TILE>), grid, block, a);                  \
+    else LAUNCH((face2d_kernel<AXV, 2, false, false, TILE>), grid, block, a);                       \
+  }
+  if (ax == 0) {
+    F2(0)
+  } else {
+    F2(1)
+  }
+#undef F2
+}
+
+int launch_face2d_any(tgks_ctx* c, const StageArgs& a, int ax, int stage, bool fl) {
+  const int nN = c->g.n[ax], nT = c->g.n[1 - ax];
+  switch (c->tile2) {
+    case 1:
+      launch_face2d<1>(c, a, ax, stage, fl, nN, nT);
+      break;
+    case 2:
+      launch_face2d<2>(c, a, ax, stage, fl, nN, nT);
+      break;
+    default:
+      launch_face2d<0>(c, a, ax, stage, fl, nN, nT);
+  }
+  return TGKS_OK;
+}

@@ -1,0 +1,140 @@
+// tgks_internal.hpp -- host-side internals shared by the library's
+// translation units: the context structure, error checking, parameter
+// validation, per-launch timing and the launch helpers of the face kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "tgks.h"
+#include "tgks_kernels.hpp"
+
+using namespace tgks;
+
+constexpr int NKIND = 7;
+
+struct EventPair {
+  hipEvent_t a, b;
+};
+
+struct tgks_ctx {
+  tgks_params p;
+  Geom g;
+  FluxCfg fc;
+  TenoCfg tn, tt;
+  bool ns;
+  int tile2 = 0;  // 2-D face-kernel tile shape (tile2_tn/tile2_tt index)
+  hipStream_t stream;
+  int nc;
+  long long ncell;
+  long long nface[3];
+  double* Ws = nullptr;
+  double* P = nullptr;
+  double* W2 = nullptr;
+  double* FA[3] = {nullptr, nullptr, nullptr};
+  double* FB[3] = {nullptr, nullptr, nullptr};
+  double* R = nullptr;
+  double* partial = nullptr;
+  int nblk = 0;
+  double* clock = nullptr;
+  unsigned long long* fail = nullptr;
+  // graph cache of tgks_run
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  int g_steps = -1;
+  double g_cfl = 0, g_tend = 0, g_fixed = 0;
+  double* g_W = nullptr;
+  double* g_time = nullptr;
+  // timing
+  bool timing = false;
+  std::vector<EventPair> ev[NKIND];
+  std::vector<hipEvent_t> pool;
+};
+
+#define HIPCHK(x)                                                                  \
+  do {                                                                             \
+    hipError_t e_ = (x);                                                           \
+    if (e_ != hipSuccess) {                                                        \
+      fprintf(stderr, "tgks: %s failed: %s\n", #x, hipGetErrorString(e_));         \
+      return TGKS_EHIP;                                                            \
+    }                                                                              \
+  } while (0)
+
+inline int check_params(const tgks_params* p) {
+  if (!p || p->ndim < 1 || p->ndim > 3) return TGKS_EINVAL;
+  for (int d = 0; d < 3; ++d) {
+    if (d < p->ndim) {
+      if (p->n[d] < 3 || !(p->dx[d] > 0.0)) return TGKS_EINVAL;
+      if (p->bc_lo[d] < 0 || p->bc_lo[d] > 2 || p->bc_hi[d] < 0 || p->bc_hi[d] > 2) return TGKS_EINVAL;
+      if ((p->bc_lo[d] == TGKS_BC_PERIODIC) != (p->bc_hi[d] == TGKS_BC_PERIODIC)) return TGKS_EINVAL;
+    } else if (p->n[d] != 1) {
+      return TGKS_EINVAL;
+    }
+  }
+  if (!(p->gamma > 1.0) || !(p->mu >= 0.0) || !(p->prandtl > 0.0)) return TGKS_EINVAL;
+  if (p->tau_mode < 0 || p->tau_mode > 2) return TGKS_EINVAL;
+  if (p->tau_mode == TGKS_TAU_VISCOUS && !(p->mu > 0.0)) return TGKS_EINVAL;
+  if (p->q < 1 || p->q > 16 || !(p->eps >= 0.0)) return TGKS_EINVAL;
+  double cells = 1.0;
+  for (int d = 0; d < p->ndim; ++d) cells *= p->n[d];
+  if (cells > 4.0e9) return TGKS_EINVAL;
+  return TGKS_OK;
+}
+
+inline hipEvent_t take_event(tgks_ctx* c) {
+  if (!c->pool.empty()) {
+    hipEvent_t e = c->pool.back();
+    c->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// begin/end markers around one launch of a kernel kind
+struct Timer {
+  tgks_ctx* c;
+  int kind;
+  hipEvent_t a = nullptr;
+  Timer(tgks_ctx* c_, int k) : c(c_), kind(k) {
+    if (c->timing) {
+      a = take_event(c);
+      if (a) (void)hipEventRecord(a, c->stream);
+    }
+  }
+  ~Timer() {
+    if (c->timing && a) {
+      hipEvent_t b = take_event(c);
+      if (b) {
+        (void)hipEventRecord(b, c->stream);
+        c->ev[kind].push_back({a, b});
+      }
+    }
+  }
+};
+
+inline StageArgs stage_args(tgks_ctx* c, const double* W, int ax, const double* dt) {
+  StageArgs a;
+  a.g = c->g;
+  a.fc = c->fc;
+  a.tn = c->tn;
+  a.tt = c->tt;
+  a.W = W;
+  a.FA = c->FA[ax];
+  a.FB = c->FB[ax];
+  a.dt = dt;
+  a.fail = c->fail;
+  a.nflags = nullptr;
+  a.tflags = nullptr;
+  a.R = c->R;
+  a.Rout = c->R;
+  return a;
+}
+
+// 2-D face kernels of one direction and stage (tgks_face2d.hip)
+int launch_face2d_any(tgks_ctx* c, const StageArgs& a, int ax, int stage, bool fl);

@@ -75,11 +75,10 @@ __device__ __forceinline__ void write_combined(int STAGE, const double* Fdt, con
 // 1-D: one thread per face.
 // ---------------------------------------------------------------------------
 template <int STAGE, bool NS, bool FLAGS>
-__global__ __launch_bounds__(256) void face1d_kernel(StageArgs a) {
+__device__ __forceinline__ void face1d_body(const StageArgs& a, int f) {
   const double dt = *a.dt;
   if (!(dt > 0.0)) return;
   const int n = a.g.n[0];
-  const int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f > n) return;
   double Wl[3], Wr[3], dWl[1][3], dWr[1][3];
   const double idx = 1.0 / a.g.dx[0];  // normal slopes per unit length
@@ -111,6 +110,11 @@ __global__ __launch_bounds__(256) void face1d_kernel(StageArgs a) {
   }
 }
 
+template <int STAGE, bool NS, bool FLAGS>
+__global__ __launch_bounds__(256) void face1d_kernel(StageArgs a) {
+  face1d_body<STAGE, NS, FLAGS>(a, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // 2-D: fused face kernel.  A block owns TN faces along the normal axis AX by
 // TT rows along the tangential axis.  It stages the cells of the tile with a
@@ -125,8 +129,9 @@ constexpr int NTILE2 = 3;
 __host__ __device__ constexpr int tile2_tn(int k) { return k == 0 ? 16 : (k == 1 ? 16 : 8); }
 __host__ __device__ constexpr int tile2_tt(int k) { return k == 0 ? 8 : (k == 1 ? 16 : 16); }
 
+// (bx, by): tile index along the normal and the tangential axis
 template <int AX, int STAGE, bool NS, bool FLAGS, int TILE>
-__global__ __launch_bounds__(2 * tile2_tn(TILE) * tile2_tt(TILE), 2) void face2d_kernel(StageArgs a) {
+__device__ __forceinline__ void face2d_tile(const StageArgs& a, int bx, int by) {
   constexpr int TN = tile2_tn(TILE), TT = tile2_tt(TILE), NT = 2 * TN * TT;
   constexpr int NC = 4;
   constexpr int LN = TN + 5, LT = TT + 4, RN = TN + 1;
@@ -137,7 +142,7 @@ __global__ __launch_bounds__(2 * tile2_tn(TILE) * tile2_tt(TILE), 2) void face2d
   const Geom& g = a.g;
   const int TA = 1 - AX;  // tangential axis
   const int nN = g.n[AX], nT = g.n[TA];
-  const int f0 = blockIdx.x * TN, t0 = blockIdx.y * TT;
+  const int f0 = bx * TN, t0 = by * TT;
   const int tid = threadIdx.x;
 
   // 1. cells of the tile, ghost cells by the index map
@@ -249,6 +254,11 @@ __global__ __launch_bounds__(2 * tile2_tn(TILE) * tile2_tt(TILE), 2) void face2d
       if (STAGE == 1) a.FB[(long long)perm[q] * nf + fidx] = B[q];
     }
   }
+}
+
+template <int AX, int STAGE, bool NS, bool FLAGS, int TILE>
+__global__ __launch_bounds__(2 * tile2_tn(TILE) * tile2_tt(TILE), 2) void face2d_kernel(StageArgs a) {
+  face2d_tile<AX, STAGE, NS, FLAGS, TILE>(a, blockIdx.x, blockIdx.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -445,12 +455,12 @@ __device__ __forceinline__ double cell_dt(const double* w, double gamma, double 
   return v;
 }
 
+// cell id of this thread; the block's CFL minimum goes to *partial
 template <int D, int STAGE, bool CFL>
-__global__ __launch_bounds__(256) void update_kernel(UpdateArgs u) {
+__device__ __forceinline__ void update_body(const UpdateArgs& u, long long id, double* partial) {
   constexpr int NC = D + 2;
   __shared__ double red[4];
   const Geom& g = u.g;
-  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = id < g.ncell;
   const double dt = *u.dt;
   const bool adv = dt > 0.0;
@@ -494,17 +504,22 @@ __global__ __launch_bounds__(256) void update_kernel(UpdateArgs u) {
     // NaN (non-physical cell) wins the reduction
     const bool nan = live && !(v == v);
     v = block_min(nan ? -INFINITY : v, red);
-    if (threadIdx.x == 0) u.partial[blockIdx.x] = v == -INFINITY ? NAN : v;
+    if (threadIdx.x == 0) *partial = v == -INFINITY ? NAN : v;
   }
+}
+
+template <int D, int STAGE, bool CFL>
+__global__ __launch_bounds__(256) void update_kernel(UpdateArgs u) {
+  update_body<D, STAGE, CFL>(u, (long long)blockIdx.x * blockDim.x + threadIdx.x,
+                            CFL ? u.partial + blockIdx.x : nullptr);
 }
 
 // CFL partial minima of a state (no update)
 template <int D>
-__global__ __launch_bounds__(256) void cfl_partial_kernel(Geom g, const double* W, double gamma, double mu,
-                                                          double* partial) {
+__device__ __forceinline__ void cfl_partial_body(const Geom& g, const double* W, double gamma, double mu,
+                                                 long long id, double* partial) {
   constexpr int NC = D + 2;
   __shared__ double red[4];
-  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   double dxm = g.dx[0];
   for (int d = 1; d < D; ++d) dxm = fmin(dxm, g.dx[d]);
   double v = INFINITY;
@@ -517,15 +532,20 @@ __global__ __launch_bounds__(256) void cfl_partial_kernel(Geom g, const double* 
     nan = !(v == v);
   }
   v = block_min(nan ? -INFINITY : v, red);
-  if (threadIdx.x == 0) partial[blockIdx.x] = v == -INFINITY ? NAN : v;
+  if (threadIdx.x == 0) *partial = v == -INFINITY ? NAN : v;
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void cfl_partial_kernel(Geom g, const double* W, double gamma, double mu,
+                                                          double* partial) {
+  cfl_partial_body<D>(g, W, gamma, mu, (long long)blockIdx.x * blockDim.x + threadIdx.x, partial + blockIdx.x);
 }
 
 // Final reduction.  clock = {t, dt}.  mode 0: dt_out = cfl * min (clipped to
 // t_end - t_in); mode 1 (after a step): t += dt, then the next dt as mode 0;
 // mode 2: fixed step, t += dt only.
-__global__ __launch_bounds__(256) void cfl_finalize_kernel(const double* partial, int nblk, double cfl,
-                                                           double t_in, double t_end, double* clock,
-                                                           double* dt_out, int mode) {
+__device__ __forceinline__ void finalize_body(const double* partial, int nblk, double cfl, double t_in,
+                                              double t_end, double* clock, double* dt_out, int mode) {
   __shared__ double red[4];
   double v = INFINITY;
   bool nan = false;
@@ -558,7 +578,13 @@ __global__ __launch_bounds__(256) void cfl_finalize_kernel(const double* partial
   }
 }
 
-__global__ void set_clock_kernel(double* clock, double t, double dt) {
+static __global__ __launch_bounds__(256) void cfl_finalize_kernel(const double* partial, int nblk, double cfl,
+                                                           double t_in, double t_end, double* clock,
+                                                           double* dt_out, int mode) {
+  finalize_body(partial, nblk, cfl, t_in, t_end, clock, dt_out, mode);
+}
+
+static __global__ void set_clock_kernel(double* clock, double t, double dt) {
   clock[0] = t;
   clock[1] = dt;
 }

@@ -71,6 +71,23 @@ def lib():
     L.tgks_tune.argtypes = [vp, vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_float)]
     dp = C.POINTER(C.c_double)
     L.tgks_gp_flux_host.argtypes = [P, dp, dp, dp, dp, C.c_double, dp]
+    bp = C.POINTER(C.c_int64)
+    L.tgks_batch_create.argtypes = [P, C.c_int32, vp, C.POINTER(vp)]
+    L.tgks_batch_destroy.argtypes = [vp]
+    L.tgks_batch_set_stream.argtypes = [vp, vp]
+    L.tgks_batch_state_size.argtypes = [vp]
+    L.tgks_batch_state_size.restype = C.c_int64
+    L.tgks_batch_offsets.argtypes = [vp, bp]
+    L.tgks_batch_run.argtypes = [vp, vp, C.c_int32, C.c_double, C.c_double, vp, C.c_int32]
+    L.tgks_batch_status.argtypes = [vp, bp]
+    L.tgks_batch_steps.argtypes = [vp, bp]
+    L.tgks_batch_reset_status.argtypes = [vp]
+    L.tgks_batch_set_tile.argtypes = [vp, C.c_int32]
+    L.tgks_batch_tune.argtypes = [vp, vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_float)]
+    for f in ("tgks_batch_create", "tgks_batch_destroy", "tgks_batch_set_stream", "tgks_batch_offsets",
+              "tgks_batch_run", "tgks_batch_status", "tgks_batch_steps", "tgks_batch_reset_status",
+              "tgks_batch_set_tile", "tgks_batch_tune"):
+        getattr(L, f).restype = C.c_int
     for f in ("tgks_params_default", "tgks_create", "tgks_destroy", "tgks_set_stream", "tgks_cfl_dt", "tgks_step",
               "tgks_run", "tgks_status", "tgks_reset_status", "tgks_timing", "tgks_kernel_time",
               "tgks_flop_counts", "tgks_gp_flux_host", "tgks_set_tile", "tgks_tune"):
@@ -231,3 +248,92 @@ def tgks_tune(ctx, W, steps=3):
     ms = (C.c_float * 3)()
     _check(lib().tgks_tune(ctx, _ptr(W, n), int(steps), C.byref(ch), ms), "tgks_tune")
     return ch.value, [ms[i] for i in range(3)]
+
+
+# ---------------------------------------------------------------------------
+# batched runs
+# ---------------------------------------------------------------------------
+class _Batch:
+    """Handle of a tgks_batch with its instance count."""
+
+    def __init__(self, handle, n_inst):
+        self.handle = handle
+        self.n_inst = n_inst
+
+
+def tgks_batch_create(params_list, stream=None):
+    """Batch of len(params_list) grids (TgksParams each, same ndim)."""
+    import torch
+    n = len(params_list)
+    arr = (TgksParams * n)(*params_list)
+    s = stream if stream is not None else torch.cuda.current_stream()
+    h = C.c_void_p()
+    _check(lib().tgks_batch_create(arr, n, C.c_void_p(s.cuda_stream), C.byref(h)), "tgks_batch_create")
+    return _Batch(h.value, n)
+
+
+def tgks_batch_destroy(b):
+    _check(lib().tgks_batch_destroy(b.handle), "tgks_batch_destroy")
+
+
+def tgks_batch_set_stream(b, stream):
+    _check(lib().tgks_batch_set_stream(b.handle, C.c_void_p(stream.cuda_stream)), "tgks_batch_set_stream")
+
+
+def tgks_batch_state_size(b):
+    return int(lib().tgks_batch_state_size(b.handle))
+
+
+def tgks_batch_offsets(b):
+    """State offsets (doubles) of the instances in a packed state, n_inst + 1 entries."""
+    out = (C.c_int64 * (b.n_inst + 1))()
+    _check(lib().tgks_batch_offsets(b.handle, out), "tgks_batch_offsets")
+    return [int(x) for x in out]
+
+
+def tgks_batch_run(b, W, n_steps, cfl, t_end=0.0, time_dev=None, use_graph=False):
+    n = tgks_batch_state_size(b)
+    _check(lib().tgks_batch_run(b.handle, _ptr(W, n), int(n_steps), float(cfl), float(t_end),
+                                _ptr(time_dev, 2 * b.n_inst), int(bool(use_graph))), "tgks_batch_run")
+
+
+def tgks_batch_status(b):
+    out = (C.c_int64 * b.n_inst)()
+    _check(lib().tgks_batch_status(b.handle, out), "tgks_batch_status")
+    return [int(x) for x in out]
+
+
+def tgks_batch_steps(b):
+    """Steps each instance took in the last run."""
+    out = (C.c_int64 * b.n_inst)()
+    _check(lib().tgks_batch_steps(b.handle, out), "tgks_batch_steps")
+    return [int(x) for x in out]
+
+
+def tgks_batch_reset_status(b):
+    _check(lib().tgks_batch_reset_status(b.handle), "tgks_batch_reset_status")
+
+
+def tgks_batch_set_tile(b, tile):
+    _check(lib().tgks_batch_set_tile(b.handle, int(tile)), "tgks_batch_set_tile")
+
+
+def tgks_batch_tune(b, W, steps=2):
+    """Time every 2-D tile shape on the packed state W, keep the fastest;
+    returns (chosen index, [ms per batched step of each shape])."""
+    n = tgks_batch_state_size(b)
+    ch = C.c_int32()
+    ms = (C.c_float * 3)()
+    _check(lib().tgks_batch_tune(b.handle, _ptr(W, n), int(steps), C.byref(ch), ms), "tgks_batch_tune")
+    return ch.value, [ms[i] for i in range(3)]
+
+
+def pack(states):
+    """Concatenate instance states (numpy arrays) into one packed host array."""
+    import numpy as np
+    return np.concatenate([np.ascontiguousarray(s, dtype=np.float64).reshape(-1) for s in states])
+
+
+def unpack(packed, offsets, shapes):
+    """Views of the instances' states in a packed array (numpy or torch)."""
+    return [packed[offsets[i]:offsets[i + 1]].reshape(shapes[i]) for i in range(len(shapes))]

@@ -27,7 +27,8 @@ def lib():
 
 def test_header_declares_entry_points():
     names = declared()
-    for n in ("tgks_create", "tgks_step", "tgks_run", "tgks_cfl_dt", "tgks_status", "tgks_destroy"):
+    for n in ("tgks_create", "tgks_step", "tgks_run", "tgks_cfl_dt", "tgks_status", "tgks_destroy",
+              "tgks_batch_create", "tgks_batch_run", "tgks_batch_status", "tgks_batch_tune"):
         assert n in names
 
 

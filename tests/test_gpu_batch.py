@@ -1,0 +1,190 @@
+"""Batched runs: many uneven grids in one launch per kernel kind.
+
+A batched step of an instance must be bit-identical to the same step of that
+instance in its own context (same kernels, same per-instance CFL step), for
+eager and graph-captured runs and every tile shape; a spot sample is checked
+against the CPU oracle step by step (L1-relative 1e-10)."""
+import numpy as np
+import pytest
+
+from gpu_common import GpuProblem, assert_close, gpu_params, orc_params, problem
+from paper_2309_10534_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    return torch
+
+
+def mixed_set(dim, n_inst, seed, size_range, **ranges):
+    """Seeded Riemann instances plus a smooth periodic and a reflective grid,
+    each with its own parameters."""
+    inst, _, _ = I.riemann_instances(n_inst, dim=dim, seed=seed, size_range=size_range, **ranges)
+    probs = [(W, problem(list(W.shape[1:])[::-1], [dx] * dim)) for W, dx in inst]
+    if dim == 1:
+        W, dx = I.density_wave_1d(37)
+        probs.append((W, problem([37], [dx], bc="periodic")))
+        W, dx = I.sod(45)
+        probs.append((W, problem([45], [dx], bc=[("reflective", "transmissive")], gamma=1.6)))
+    else:
+        W, dx = I.density_wave_2d(21)
+        probs.append((W, problem([21, 21], [dx, dx], bc="periodic")))
+        W, dx, _ = I.quadrant_riemann(27, seed=3)
+        probs.append((W, problem([27, 27], [dx, dx], bc="reflective", c1=0.02)))
+    return probs
+
+
+class Batch:
+    def __init__(self, probs):
+        import torch
+        from paper_2309_10534_amd import tgks
+        self.t, self.torch = tgks, torch
+        self.probs = probs
+        self.b = tgks.tgks_batch_create([gpu_params(pr) for _, pr in probs])
+        self.off = tgks.tgks_batch_offsets(self.b)
+        self.shapes = [W.shape for W, _ in probs]
+
+    def close(self):
+        self.t.tgks_batch_destroy(self.b)
+
+    def run(self, n_steps, cfl=0.5, t_end=0.0, use_graph=False, replays=1):
+        torch = self.torch
+        W0 = torch.from_numpy(self.t.pack([W for W, _ in self.probs])).cuda()
+        td = torch.zeros(2 * len(self.probs), dtype=torch.float64, device="cuda")
+        outs = []
+        for _ in range(replays):
+            W = W0.clone()
+            self.t.tgks_batch_reset_status(self.b)
+            self.t.tgks_batch_run(self.b, W, n_steps, cfl, t_end, td, use_graph)
+            bad = self.t.tgks_batch_status(self.b)
+            self.steps = self.t.tgks_batch_steps(self.b)
+            torch.cuda.synchronize()
+            host = W.cpu().numpy()
+            outs.append((self.t.unpack(host, self.off, self.shapes), td.cpu().numpy().reshape(-1, 2), bad))
+        return outs
+
+
+def single_runs(probs, n_steps, cfl=0.5, t_end=0.0):
+    res = []
+    for W, pr in probs:
+        gp = GpuProblem(pr)
+        try:
+            res.append(gp.run(W, n_steps, cfl=cfl, t_end=t_end))
+        finally:
+            gp.close()
+    return res
+
+
+@pytest.mark.parametrize("dim,steps", [(1, 40), (2, 12)])
+def test_batch_bitwise_equals_single(torch_dev, dim, steps):
+    # 2-D: the milder state ranges of the four-quadrant workload, so that most
+    # instances run every step (the scheme has no positivity limiter)
+    mild = {} if dim == 1 else dict(rho_range=(0.1, 2.0), p_range=(0.03, 1.5), vel_range=(-1.0, 1.0))
+    probs = mixed_set(dim, 9, seed=1 if dim == 1 else 2, size_range=(16, 90) if dim == 1 else (12, 40), **mild)
+    print(f"[batch] dim={dim} instances={len(probs)} steps={steps}", flush=True)
+    ref = single_runs(probs, steps)
+    B = Batch(probs)
+    try:
+        (Wb, tb, badb), = B.run(steps)
+        # an instance stops when its CFL step turns NaN (a non-physical cell)
+        full = [i for i in range(len(probs)) if tb[i, 1] > 0]
+        assert len(full) >= len(probs) // 2
+        for i in range(len(probs)):
+            assert B.steps[i] == steps if i in full else B.steps[i] < steps
+        for tile in range(3 if dim == 2 else 1):
+            B.t.tgks_batch_set_tile(B.b, tile)
+            runs = B.run(steps, use_graph=True, replays=2)
+            for Wg, tg, badg in runs:
+                for i in range(len(probs)):
+                    assert np.array_equal(Wg[i], Wb[i], equal_nan=True), f"graph replay, tile {tile}, instance {i}"
+                assert np.array_equal(tg, tb, equal_nan=True)
+                assert badg == badb
+    finally:
+        B.close()
+    for i, (Ws, ts, bads) in enumerate(ref):
+        assert np.array_equal(Wb[i], Ws, equal_nan=True), f"instance {i} differs from its single-grid run"
+        assert np.array_equal(tb[i], ts, equal_nan=True), f"instance {i}: clock {tb[i]} vs {ts}"
+        assert badb[i] == bads
+
+
+def test_batch_t_end_clipping(torch_dev):
+    probs = mixed_set(1, 4, seed=4, size_range=(20, 60))
+    B = Batch(probs)
+    try:
+        (Wb, tb, _), = B.run(400, cfl=0.5, t_end=0.01)
+        steps = B.steps
+    finally:
+        B.close()
+    assert np.all(tb[:, 0] <= 0.01 * (1 + 1e-14))
+    for i in range(len(probs)):
+        if tb[i, 0] >= 0.01 * (1 - 1e-14):
+            assert 0 < steps[i] < 400 and tb[i, 1] == 0.0
+    ref = single_runs(probs, 400, t_end=0.01)
+    for i, (Ws, ts, _) in enumerate(ref):
+        assert np.array_equal(Wb[i], Ws, equal_nan=True)
+        assert np.array_equal(tb[i], ts, equal_nan=True)
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_batch_matches_oracle_stepwise(orc, torch_dev, dim):
+    """Spot sample: each batched step equals the oracle's step from the same
+    state with the same CFL step."""
+    probs = mixed_set(dim, 2, seed=7 if dim == 1 else 10, size_range=(24, 70) if dim == 1 else (16, 30))
+    B = Batch(probs)
+    states = [W.copy() for W, _ in probs]
+    try:
+        for s in range(3):
+            B.probs = [(states[i], pr) for i, (_, pr) in enumerate(probs)]
+            (Wb, tb, badb), = B.run(1)
+            for i, (_, pr) in enumerate(probs):
+                P = orc_params(orc, pr)
+                dt = orc.cfl_dt(P, states[i], 0.5)
+                Wo, _, _, bado = orc.step(P, states[i], dt)
+                print(f"[batch-oracle] dim={dim} step={s} instance={i} shape={pr['shape']}", flush=True)
+                assert np.all(np.isfinite(Wo))
+                assert_close(Wb[i], Wo, what=f"instance {i} step {s}")
+                assert badb[i] == bado
+                states[i] = Wb[i]
+    finally:
+        B.close()
+
+
+def test_batch_tune_and_status(torch_dev):
+    from paper_2309_10534_amd import tgks
+    probs = mixed_set(2, 5, seed=2, size_range=(20, 48))
+    B = Batch(probs)
+    try:
+        W = torch_dev.from_numpy(tgks.pack([W for W, _ in probs])).cuda()
+        chosen, ms = tgks.tgks_batch_tune(B.b, W, steps=2)
+        assert chosen in (0, 1, 2) and all(m > 0 for m in ms)
+        (Wb, _, bad), = B.run(5)
+        assert len(bad) == len(probs)
+    finally:
+        B.close()
+    ref = single_runs(probs, 5)
+    for i, (Ws, _, _) in enumerate(ref):
+        assert np.array_equal(Wb[i], Ws, equal_nan=True)
+
+
+def test_batch_invalid_args(torch_dev):
+    from paper_2309_10534_amd import tgks
+    p1 = tgks.tgks_params_default(1, [32], [1 / 32])
+    p2 = tgks.tgks_params_default(2, [16, 16], [1 / 16, 1 / 16])
+    p3 = tgks.tgks_params_default(3, [8, 8, 8], [1 / 8] * 3)
+    for bad in ([p1, p2], [p3], []):
+        with pytest.raises(tgks.TgksError):
+            tgks.tgks_batch_create(bad)
+    b = tgks.tgks_batch_create([p1, p1])
+    try:
+        W = torch_dev.zeros(tgks.tgks_batch_state_size(b) + 1, dtype=torch_dev.float64, device="cuda")
+        with pytest.raises(tgks.TgksError):
+            tgks.tgks_batch_run(b, W, 1, 0.5)
+        with pytest.raises(tgks.TgksError):
+            tgks.tgks_batch_run(b, W[:-1], 1, 0.0)
+    finally:
+        tgks.tgks_batch_destroy(b)
