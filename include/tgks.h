@@ -166,6 +166,29 @@ int tgks_gp_flux_host(const tgks_params* p, const double* Wl, const double* Wr, 
                       const double* dWr, double dt, double* F);
 
 /* ------------------------------------------------------------------------
+ * Reverse mode.  The derivative of one S2O4 step W_out = S(W_in) with the
+ * time step dt held constant and every TENO-D stencil selection (Sec. 4.2)
+ * held at the one the forward step takes on W_in; the reconstruction is then
+ * linear and S is smooth.  The collision time is differentiated through the
+ * pressures it depends on.  1-D and 2-D grids.
+ * ------------------------------------------------------------------------ */
+
+/* gW_in = (dW_out/dW_in)^T gW_out for the step from W_n with the step read
+ * from dt_dev (device).  W_n, gW_out, gW_in: device states; gW_in must not
+ * overlap gW_out.  Recomputes the step's first stage (W*) with the forward
+ * kernels.  The first call allocates the context's reverse-mode buffers.
+ * TGKS_EINVAL for 3-D contexts or invalid pointers. */
+int tgks_step_adjoint(tgks_ctx* ctx, const double* W_n, const double* dt_dev, const double* gW_out, double* gW_in);
+
+/* Host evaluation of the reverse of the Gauss-point flux (the same code the
+ * reverse kernels run), for verification.  Face frame, HOST pointers as in
+ * tgks_gp_flux_host; Fb [2][nc]: cotangents of F(dt) and F(dt/2); G receives
+ * the cotangents of Wl [nc], Wr [nc], dWl [ndim][nc], dWr [ndim][nc] in this
+ * order.  dt is a constant. */
+int tgks_gp_flux_vjp_host(const tgks_params* p, const double* Wl, const double* Wr, const double* dWl,
+                          const double* dWr, double dt, const double* Fb, double* G);
+
+/* ------------------------------------------------------------------------
  * Batched runs: many independent 1-D or 2-D grids (uneven sizes, each with
  * its own parameters, boundary kinds, CFL time step, clock and failure
  * counter) advanced together, one launch per kernel kind and stage for the

@@ -1047,6 +1047,34 @@ int orc_gp_flux(const orc_params* P, const double* Wl, const double* Wr, const d
   return bad;
 }
 
+// Directional derivative of the Gauss-point flux (forward mode, the dual
+// type above) along (tWl, tWr, tdWl, tdWr) with dt and the deltas constant:
+// F[i*5+c] and dF[i*5+c] for delta i.  Same layout as orc_gp_flux.
+int orc_gp_flux_dual(const orc_params* P, const double* Wl, const double* Wr, const double* dWl,
+                     const double* dWr, const double* tWl, const double* tWr, const double* tdWl,
+                     const double* tdWr, double dt, int ndelta, const double* delta, double* F,
+                     double* dF) {
+  if (check_params(P) || ndelta < 1 || ndelta > 2) return -1;
+  const int D = P->ndim;
+  Dual l[5], r[5], a[3][5], b[3][5], Fo[2][5], W0[5], dw[3][5];
+  for (int c = 0; c < 5; ++c) {
+    l[c] = Dual(Wl[c], tWl[c]);
+    r[c] = Dual(Wr[c], tWr[c]);
+  }
+  for (int d = 0; d < 3; ++d)
+    for (int c = 0; c < 5; ++c) {
+      a[d][c] = Dual(dWl[d * 5 + c], tdWl[d * 5 + c]);
+      b[d][c] = Dual(dWr[d * 5 + c], tdWr[d * 5 + c]);
+    }
+  const int bad = gp_flux(*P, D, l, r, a, b, dt, ndelta, delta, Fo, W0, dw);
+  for (int i = 0; i < ndelta; ++i)
+    for (int c = 0; c < D + 2; ++c) {
+      F[i * 5 + c] = Fo[i][c].v;
+      dF[i * 5 + c] = Fo[i][c].d;
+    }
+  return bad;
+}
+
 // Number of bytes of the flag buffer of one step (normal flags, then for
 // 2-D the tangential flags of both directions).
 long orc_flag_bytes(const orc_params* P) {

@@ -54,6 +54,7 @@ def lib():
         L.orc_moment_mono.argtypes = [C.c_int, C.c_double, dp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]
         L.orc_moment_mono.restype = C.c_double
         L.orc_gp_flux.argtypes = [P, dp, dp, dp, dp, C.c_double, C.c_int, dp, dp, dp, dp]
+        L.orc_gp_flux_dual.argtypes = [P, dp, dp, dp, dp, dp, dp, dp, dp, C.c_double, C.c_int, dp, dp, dp]
         L.orc_flag_bytes.argtypes = [P]
         L.orc_flag_bytes.restype = C.c_long
         L.orc_step.argtypes = [P, dp, dp, C.c_double, C.c_void_p, C.c_void_p]
@@ -206,6 +207,34 @@ def step_dual(params, W, dW, dt):
     if bad < 0:
         raise ValueError("invalid parameters or dt")
     return out, dout, bad
+
+
+def gp_flux_dual(params, Wl, Wr, dWl, dWr, tWl, tWr, tdWl, tdWr, dt, deltas):
+    """Flux at one Gauss point and its directional derivative along the
+    tangent (tWl, tWr, tdWl, tdWr), dt constant.  Returns (F, dF), each
+    (len(deltas), D+2)."""
+    D = params.ndim
+    nc = D + 2
+
+    def pad(v):
+        o = np.zeros(5)
+        o[:nc] = v
+        return o
+
+    def padd(m):
+        o = np.zeros((3, 5))
+        m = np.asarray(m, dtype=np.float64)
+        o[: m.shape[0], :nc] = m
+        return o.ravel()
+
+    deltas = np.asarray(deltas, dtype=np.float64)
+    F = np.zeros((2, 5))
+    dF = np.zeros((2, 5))
+    bad = lib().orc_gp_flux_dual(C.byref(params), pad(Wl), pad(Wr), padd(dWl), padd(dWr), pad(tWl), pad(tWr),
+                                 padd(tdWl), padd(tdWr), float(dt), len(deltas), deltas, F.ravel(), dF.ravel())
+    if bad < 0:
+        raise ValueError("invalid parameters")
+    return F[: len(deltas), :nc].copy(), dF[: len(deltas), :nc].copy()
 
 
 def cfl_dt(params, W, cfl):

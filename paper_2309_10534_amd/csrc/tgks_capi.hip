@@ -13,7 +13,7 @@ using namespace tgks;
 #define LAUNCH(kern, grid, block, args) hipLaunchKernelGGL(kern, grid, block, 0, c->stream, args)
 
 // face fluxes of one stage in every direction
-static int launch_faces(tgks_ctx* c, const double* W, const double* dt, int stage, uint8_t* flags) {
+int launch_faces(tgks_ctx* c, const double* W, const double* dt, int stage, uint8_t* flags) {
   const int D = c->g.D;
   for (int ax = 0; ax < D; ++ax) {
     StageArgs a = stage_args(c, W, ax, dt);
@@ -107,7 +107,7 @@ static UpdateArgs update_args(tgks_ctx* c, const double* W, double* o1, double* 
   return u;
 }
 
-static int launch_update(tgks_ctx* c, int stage, const double* W, double* o1, double* o2, const double* dt,
+int launch_update(tgks_ctx* c, int stage, const double* W, double* o1, double* o2, const double* dt,
                          bool cfl) {
   UpdateArgs u = update_args(c, W, o1, o2, dt, c->partial);
   dim3 grid((unsigned)c->nblk);
@@ -175,6 +175,10 @@ static void free_ctx(tgks_ctx* c) {
   (void)hipFree(c->partial);
   (void)hipFree(c->clock);
   (void)hipFree(c->fail);
+  (void)hipFree(c->aGB);
+  (void)hipFree(c->aTF);
+  (void)hipFree(c->aNRB);
+  (void)hipFree(c->aWsb);
   for (int k = 0; k < NKIND; ++k)
     for (auto& e : c->ev[k]) {
       (void)hipEventDestroy(e.a);

@@ -49,6 +49,11 @@ struct tgks_ctx {
   double g_cfl = 0, g_tend = 0, g_fixed = 0;
   double* g_W = nullptr;
   double* g_time = nullptr;
+  // reverse-mode buffers (allocated by the first tgks_step_adjoint)
+  double* aGB = nullptr;
+  uint8_t* aTF = nullptr;
+  double* aNRB = nullptr;
+  double* aWsb = nullptr;
   // timing
   bool timing = false;
   std::vector<EventPair> ev[NKIND];
@@ -138,3 +143,7 @@ inline StageArgs stage_args(tgks_ctx* c, const double* W, int ax, const double* 
 
 // 2-D face kernels of one direction and stage (tgks_face2d.hip)
 int launch_face2d_any(tgks_ctx* c, const StageArgs& a, int ax, int stage, bool fl);
+
+// forward pieces of one step (tgks_capi.hip)
+int launch_faces(tgks_ctx* c, const double* W, const double* dt, int stage, uint8_t* flags);
+int launch_update(tgks_ctx* c, int stage, const double* W, double* o1, double* o2, const double* dt, bool cfl);

@@ -145,14 +145,16 @@ def _cell_average(fun, edges, m=4):
     return np.ascontiguousarray(np.stack(acc))
 
 
-def isentropic_vortex_2d(n=512, strength=5.0, L=10.0, gamma=GAMMA, m=4):
-    """Isentropic vortex centred at (L/2, L/2) in a mean flow (1, 1) on a periodic
-    [0, L]^2; 4x4 Gauss-Legendre cell averages of the conservative variables."""
+def isentropic_vortex_2d(n=512, strength=5.0, L=10.0, gamma=GAMMA, m=4, center=None):
+    """Isentropic vortex centred at (L/2, L/2) (or `center`) in a mean flow
+    (1, 1) on a periodic [0, L]^2; 4x4 Gauss-Legendre cell averages of the
+    conservative variables."""
     e = _edges(n, 0.0, L)
     eps = strength
+    cx, cy = (0.5 * L, 0.5 * L) if center is None else center
 
     def fun(x, y):
-        xb, yb = x - 0.5 * L, y - 0.5 * L
+        xb, yb = x - cx, y - cy
         r2 = xb * xb + yb * yb
         du = eps / (2 * np.pi) * np.exp(0.5 * (1 - r2)) * (-yb)
         dv = eps / (2 * np.pi) * np.exp(0.5 * (1 - r2)) * xb

@@ -71,6 +71,10 @@ def lib():
     L.tgks_tune.argtypes = [vp, vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_float)]
     dp = C.POINTER(C.c_double)
     L.tgks_gp_flux_host.argtypes = [P, dp, dp, dp, dp, C.c_double, dp]
+    L.tgks_step_adjoint.argtypes = [vp, vp, vp, vp, vp]
+    L.tgks_step_adjoint.restype = C.c_int
+    L.tgks_gp_flux_vjp_host.argtypes = [P, dp, dp, dp, dp, C.c_double, dp, dp]
+    L.tgks_gp_flux_vjp_host.restype = C.c_int
     bp = C.POINTER(C.c_int64)
     L.tgks_batch_create.argtypes = [P, C.c_int32, vp, C.POINTER(vp)]
     L.tgks_batch_destroy.argtypes = [vp]
@@ -337,3 +341,36 @@ def pack(states):
 def unpack(packed, offsets, shapes):
     """Views of the instances' states in a packed array (numpy or torch)."""
     return [packed[offsets[i]:offsets[i + 1]].reshape(shapes[i]) for i in range(len(shapes))]
+
+
+# ---------------------------------------------------------------------------
+# reverse mode
+# ---------------------------------------------------------------------------
+def tgks_step_adjoint(ctx, W_n, dt_dev, gW_out, gW_in):
+    """gW_in = (dW_out/dW_in)^T gW_out for one step from W_n (dt and the stencil
+    selections frozen)."""
+    n = tgks_state_size(ctx)
+    _check(lib().tgks_step_adjoint(ctx, _ptr(W_n, n), _ptr(dt_dev, 1), _ptr(gW_out, n), _ptr(gW_in, n)),
+           "tgks_step_adjoint")
+
+
+def tgks_gp_flux_vjp_host(params, Wl, Wr, dWl, dWr, dt, Fb):
+    """Host reverse of the Gauss-point flux: Fb (2, nc) -> (Wl_b, Wr_b, dWl_b, dWr_b)."""
+    import numpy as np
+    D = params.ndim
+    nc = D + 2
+
+    def buf(x, n):
+        a = np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(-1))
+        assert a.size == n
+        return a
+
+    P = C.POINTER(C.c_double)
+    args = [buf(Wl, nc), buf(Wr, nc), buf(dWl, D * nc), buf(dWr, D * nc)]
+    fb = buf(Fb, 2 * nc)
+    G = np.zeros(2 * nc + 2 * D * nc)
+    rc = lib().tgks_gp_flux_vjp_host(C.byref(params), *[a.ctypes.data_as(P) for a in args], float(dt),
+                                     fb.ctypes.data_as(P), G.ctypes.data_as(P))
+    if rc < 0:
+        raise TgksError("tgks_gp_flux_vjp_host: invalid argument")
+    return G[:nc], G[nc:2 * nc], G[2 * nc:2 * nc + D * nc].reshape(D, nc), G[2 * nc + D * nc:].reshape(D, nc)
