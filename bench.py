@@ -41,6 +41,7 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched 1-D/2-D Riemann sets")
     ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--batch-instances", type=int, default=256)
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the reverse-mode vortex workload")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     return ap.parse_args()
 
@@ -142,6 +143,87 @@ def batched(dim, seed, n_inst, steps, ranges=None):
     }
 
 
+def adjoint(n=512, steps=200, every=20, fd_dirs=range(10, 15)):
+    """Reverse mode on the 2-D isentropic vortex (strength 5, mean flow (1, 1),
+    n x n periodic cells on [0, 10]^2, CFL 0.5, `steps` steps): J = dx dy
+    sum rho^2 at the final time, gradient with respect to the initial density
+    through the checkpointed rollout (every `every` steps).  Reports the time
+    of the plain forward (tgks_run), of the recording forward and of the
+    backward (recomputation + reverse steps), their ratio, and the relative
+    error against central differences of the forward along seeded smooth
+    density directions (random Fourier modes, |k| <= 8)."""
+    import numpy as np
+    import torch
+
+    from paper_2309_10534_amd import inputs as I
+    from paper_2309_10534_amd import tgks
+    from paper_2309_10534_amd.rollout import rollout, rollout_adjoint
+
+    W0, dx = I.isentropic_vortex_2d(n)
+    p = tgks.tgks_params_default(2, [n, n], [dx, dx], bc="periodic")
+    ctx = tgks.tgks_create(p)
+    W0d = torch.from_numpy(W0).cuda()
+    tile, _ = tgks.tgks_tune(ctx, W0d, steps=3)
+    # plain forward
+    W = W0d.clone()
+    tgks.tgks_run(ctx, W, 5, cfl=0.5)
+    torch.cuda.synchronize()
+    W.copy_(W0d)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tgks.tgks_run(ctx, W, steps, cfl=0.5)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    # recording forward + backward (warm-up on a short rollout first)
+    Wn, dts, ck = rollout(ctx, W0d, 4, 0.5, every=2)
+    rollout_adjoint(ctx, ck, dts, 2 * Wn * dx * dx, every=2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Wn, dts, ck = rollout(ctx, W0d, steps, 0.5, every=every)
+    torch.cuda.synchronize()
+    t_rec = time.perf_counter() - t0
+    gJ = torch.zeros_like(Wn)
+    gJ[0] = 2.0 * Wn[0] * dx * dx
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g0 = rollout_adjoint(ctx, ck, dts, gJ, every=every)
+    torch.cuda.synchronize()
+    t_bwd = time.perf_counter() - t0
+    fails = tgks.tgks_status(ctx)
+    # finite differences along seeded smooth density directions
+    x = (np.arange(n) + 0.5) / n
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    errs = []
+    for sd in fd_dirs:
+        rng = np.random.default_rng(sd)
+        v = np.zeros((n, n))
+        for kx in range(-8, 9):
+            for ky in range(0, 9):
+                if 0 < kx * kx + ky * ky <= 64:
+                    v += rng.standard_normal() * np.cos(2 * np.pi * (kx * X + ky * Y) + rng.uniform(0, 2 * np.pi))
+        vd = torch.from_numpy(v / np.abs(v).max()).cuda()
+        eps = 1e-6
+
+        def J_of(s):
+            Wp = W0d.clone()
+            Wp[0] += s * vd
+            Wf, _, _ = rollout(ctx, Wp, steps, dts=dts, every=steps + 1)
+            return float((Wf[0] ** 2).sum()) * dx * dx
+
+        fd = (J_of(eps) - J_of(-eps)) / (2 * eps)
+        ad = float((g0[0] * vd).sum())
+        errs.append(abs(ad - fd) / abs(fd))
+    tgks.tgks_destroy(ctx)
+    return {
+        "workload": f"adjoint_2d_isentropic_vortex_{n}x{n}_{steps}_steps_checkpoint{every}",
+        "objective": "dx dy sum rho^2 at the final time, gradient w.r.t. initial density",
+        "forward_ms": round(t_fwd * 1e3, 3), "recording_forward_ms": round(t_rec * 1e3, 3),
+        "backward_ms": round(t_bwd * 1e3, 3),
+        "adjoint_over_forward": round(t_bwd / t_fwd, 3),
+        "fd_rel_err": [float(f"{e:.3e}") for e in errs], "fd_eps": 1e-6, "failures": fails, "tile": tile,
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -220,6 +302,8 @@ def main():
         out["batched"] = [batched(1, 1, args.batch_instances, args.batch_steps),
                           batched(2, 2, args.batch_instances, args.batch_steps),
                           batched(2, 2, args.batch_instances, args.batch_steps, ranges=mild)]
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W0, dx, n, args.cpu_seconds)
     print(json.dumps(out), flush=True)

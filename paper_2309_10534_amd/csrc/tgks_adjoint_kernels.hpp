@@ -43,15 +43,16 @@ struct AdjArgs {
 };
 
 // extended normal-reconstruction cells: AX index in [-1, n_AX], tangential
-// index in [-2, n_T + 2) (2-D), stored [c][slot][t + 2][i + 1]
+// index in [-2, n_T + 2) (2-D), stored [c][slot][cells] with the x index
+// fastest: [t + 2][i + 1] for x faces, [i + 1][t + 2] for y faces
 __device__ __forceinline__ long long ext_count(const Geom& g, int ax) {
   const int ne = g.n[ax] + 2;
   return g.D == 1 ? (long long)ne : (long long)ne * (g.n[1 - ax] + 4);
 }
 
 __device__ __forceinline__ long long ext_index(const Geom& g, int ax, int i, int t) {
-  const int ne = g.n[ax] + 2;
-  return g.D == 1 ? (long long)(i + 1) : (long long)(t + 2) * ne + (i + 1);
+  if (g.D == 1) return (long long)(i + 1);
+  return ax == 0 ? (long long)(t + 2) * (g.n[0] + 2) + (i + 1) : (long long)(i + 1) * (g.n[0] + 4) + (t + 2);
 }
 
 // cotangent of component c of the flux on the face between cells lo and hi
@@ -259,9 +260,9 @@ __global__ __launch_bounds__(256) void adj_tan2d_kernel(AdjArgs a) {
   const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= ne * NC) return;
   const int c = (int)(id / ne);
-  const long long e = id % ne;
-  const int i = (int)(e % (nN + 2)) - 1;
-  const int r = (int)(e / (nN + 2)) - 2;
+  const long long e = id % ne;  // == ext_index(g, AX, i, r)
+  const int i = AX == 0 ? (int)(e % (nN + 2)) - 1 : (int)(e / (nT + 4)) - 1;
+  const int r = AX == 0 ? (int)(e / (nN + 2)) - 2 : (int)(e % (nT + 4)) - 2;
   const long long nf = face_count(g, AX);
   const double idn = 1.0 / g.dx[AX];
   double o[4] = {0.0, 0.0, 0.0, 0.0};
