@@ -27,6 +27,33 @@ sys.path.insert(0, ROOT)
 METRIC = "Mcell-updates/s per S2O4 step FP64 vs roofline; batched and adjoint/forward ratio"
 FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector peak (256 CU x 2.4 GHz x 128 flop/clk)
 
+# HBM traffic of the 2-D face kernel on this workload from two rocprofv3
+# --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch, mean of the stage-1
+# and stage-2 launches of each direction, tile shape 2), each scaled by what
+# the counter reads for a 32 MiB device-to-device copy (FETCH_SIZE 16401 KiB:
+# factor 32768/16401; WRITE_SIZE 32768 KiB: factor 1).  Valid only for the
+# kernel sources they were taken with (sha256 prefix of the three files
+# below); the bench reports null traffic otherwise.
+TRAFFIC_SOURCES = ("paper_2309_10534_amd/csrc/tgks_device.hpp", "paper_2309_10534_amd/csrc/tgks_kernels.hpp",
+                   "paper_2309_10534_amd/csrc/tgks_face2d.hip")
+TRAFFIC = {"sha": "a54083e9eb8b5955", "tile": 2, "fetch_factor": 32768.0 / 16401.4, "write_factor": 1.0,
+           "face_x": {"fetch_kib": 69599.1, "write_kib": 67646.0},
+           "face_y": {"fetch_kib": 59135.1, "write_kib": 49200.0}}
+
+
+def measured_traffic(kernel, tile):
+    """HBM bytes per launch of the dominant face kernel, or None when the
+    counters do not belong to the current kernel sources or tile shape."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest()[:16] != TRAFFIC["sha"] or tile != TRAFFIC["tile"] or kernel not in TRAFFIC:
+        return None
+    t = TRAFFIC[kernel]
+    return round(1024.0 * (t["fetch_kib"] * TRAFFIC["fetch_factor"] + t["write_kib"] * TRAFFIC["write_factor"]))
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -42,6 +69,8 @@ def parse():
     ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--batch-instances", type=int, default=256)
     ap.add_argument("--no-adjoint", action="store_true", help="skip the reverse-mode vortex workload")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 3-D Taylor-Green workload")
+    ap.add_argument("--no-sod", action="store_true", help="skip the 1-D Sod latency workload")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     return ap.parse_args()
 
@@ -140,6 +169,93 @@ def batched(dim, seed, n_inst, steps, ranges=None):
                          "seconds": round(t_single, 4), "graph": False},
         "speedup": round(t_single / t_batch, 3),
         "bitwise_equal_instances": same,
+    }
+
+
+def sod1d(n=400, t_end=0.2, reps=5):
+    """1-D Sod shock tube, n cells on [0, 1], CFL 0.5 to t = 0.2.  Latency
+    bound: the step count to t_end is taken from a one-instance batched run
+    (its per-instance step counter), then that many steps are timed as eager
+    launches and as a graph replay (best of `reps`)."""
+    import torch
+
+    from paper_2309_10534_amd import inputs as I
+    from paper_2309_10534_amd import tgks
+
+    W0, dx = I.sod(n)
+    p = tgks.tgks_params_default(1, [n], [dx])
+    W0d = torch.from_numpy(W0).cuda()
+    b = tgks.tgks_batch_create([p])
+    W = W0d.clone()
+    tgks.tgks_batch_run(b, W, 8 * n, 0.5, t_end)
+    steps = tgks.tgks_batch_steps(b)[0]
+    tgks.tgks_batch_destroy(b)
+    ctx = tgks.tgks_create(p)
+    td = torch.zeros(2, dtype=torch.float64, device="cuda")
+    out = {"workload": f"1d_sod_{n}_cells_cfl0.5_to_t{t_end}", "steps": steps}
+    for graph in (False, True):
+        best = None
+        for _ in range(reps):
+            W = W0d.clone()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            tgks.tgks_run(ctx, W, steps, cfl=0.5, t_end=t_end, time_dev=td, use_graph=graph)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            best = el if best is None else min(best, el)
+        key = "graph" if graph else "eager"
+        out[key + "_ms"] = round(best * 1e3, 3)
+        out[key + "_us_per_step"] = round(best * 1e6 / steps, 2)
+    out["t_reached"] = float(td[0].cpu())
+    tgks.tgks_destroy(ctx)
+    return out
+
+
+def tgv3d(n=128, steps=200, warmup=2):
+    """3-D compressible Navier-Stokes Taylor-Green vortex: n^3 periodic cells
+    on [0, 2 pi]^3, Mach 0.1, Re 1600 (mu = 1/1600 with U0 = rho0 = L = 1),
+    Pr 0.72, gamma 1.4, viscous collision time, CFL 0.4, `steps` steps from
+    t = 0 (2x2x2 Gauss-Legendre cell averages of the initial field)."""
+    import torch
+
+    from paper_2309_10534_amd import inputs as I
+    from paper_2309_10534_amd import tgks
+
+    W0, dx = I.taylor_green_3d(n, m=2)
+    p = tgks.tgks_params_default(3, [n, n, n], [dx, dx, dx], bc="periodic", mu=1.0 / 1600.0, prandtl=0.72,
+                                 tau="viscous")
+    ctx = tgks.tgks_create(p)
+    W0d = torch.from_numpy(W0).cuda()
+    W = W0d.clone()
+    tgks.tgks_run(ctx, W, warmup, cfl=0.4)
+    torch.cuda.synchronize()
+    W.copy_(W0d)
+    tgks.tgks_reset_status(ctx)
+    tgks.tgks_timing(ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tgks.tgks_run(ctx, W, steps, cfl=0.4)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    kt = {k: tgks.tgks_kernel_time(ctx, k) for k in ("face_x", "face_y", "face_z", "recon3d", "update1", "update2",
+                                                         "cfl")}
+    tgks.tgks_timing(ctx, False)
+    fails = tgks.tgks_status(ctx)
+    flops = tgks.tgks_flop_counts(p)
+    tgks.tgks_destroy(ctx)
+    ncell = n ** 3
+    nface = (n + 1) * n * n
+    ms, launches = kt["face_x"]
+    per_launch = nface * 0.5 * (flops["face"] + flops["face_stage2"])
+    achieved = per_launch / (ms / 1e3 / max(launches, 1)) / 1e12
+    return {
+        "workload": f"3d_ns_taylor_green_{n}^3_re1600_ma0.1_{steps}_steps", "cells": ncell,
+        "value": round(ncell * steps / el / 1e6, 3), "unit": "Mcell-updates/s", "ms_per_step": round(el * 1e3 / steps, 4),
+        "failures": fails,
+        "face_kernel": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "flops_per_face": flops["face"],
+                        "avg_launch_ms": round(ms / max(launches, 1), 4)},
+        "kernel_ms_per_step": {k: round(v[0] / steps, 4) for k, v in kt.items()},
     }
 
 
@@ -277,6 +393,9 @@ def main():
     # S2O4 combination only
     per_launch = nface * 0.5 * (flops["face"] + flops["face_stage2"]) + ncell * 4 * flops["normal"]
     avg_s = ms / 1e3 / max(launches, 1)
+    # algorithmic bytes of one face launch: read the state once, write the
+    # face fluxes (two arrays in stage 1, one in stage 2: mean 1.5)
+    algo_bytes = int(4 * 8 * (ncell + 1.5 * nface))
     achieved = per_launch / avg_s / 1e12
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "Mcell-updates/s", "n_gpus": 1,
@@ -289,7 +408,8 @@ def main():
                    "tile_ms_per_step": [round(x, 4) for x in tile_ms]},
         "roofline": {"bound": "alu", "kernel": f"face2d_kernel ({dom}, both stages)",
                      "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                     "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": measured_traffic(dom, tile),
+                     "traffic_unit": "bytes per launch", "algorithmic_bytes": algo_bytes,
                      "flops_per_launch": per_launch, "avg_launch_ms": round(ms / max(launches, 1), 5),
                      "launches": launches},
         "kernel_ms_per_step": {k: round(v[0] / args.steps, 5) for k, v in kt.items()},
@@ -304,6 +424,10 @@ def main():
                           batched(2, 2, args.batch_instances, args.batch_steps, ranges=mild)]
     if not args.no_adjoint:
         out["adjoint"] = adjoint()
+    if not args.no_3d:
+        out["tgv3d"] = tgv3d()
+    if not args.no_sod:
+        out["sod1d"] = sod1d()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W0, dx, n, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -607,6 +607,8 @@ TGKS_HD void gp_flux_vjp(const R* Wl, const R* Wr, const R (*dWl)[D + 2], const 
     for (int q = 0; q < NC; ++q) Xb[k][q] = R(0.0);
   R Gb[2] = {R(0.0), R(0.0)}, Hb[3] = {R(0.0), R(0.0), R(0.0)};
   R taub = R(0.0);
+  // e^{-dt/tau} = (e^{-dt/(2 tau)})^2
+  const R em = tau == 0.0 ? R(0.0) : expm1(-(0.5 * dt) / tau);
 #pragma unroll
   for (int id = 0; id < 2; ++id) {
     const R* Fb = id == 0 ? Fdtb : Fhb;
@@ -615,10 +617,12 @@ TGKS_HD void gp_flux_vjp(const R* Wl, const R* Wr, const R (*dWl)[D + 2], const 
     if (tau == 0.0) {
       e = R(0.0);
       ome = R(1.0);
+    } else if (id == 1) {
+      e = em + 1.0;
+      ome = -em;
     } else {
-      const R x = -dl / tau;
-      e = exp(x);
-      ome = -expm1(x);
+      e = (em + 1.0) * (em + 1.0);
+      ome = -em * (em + 2.0);
     }
     const R tt = (tau * tau) * ome;
     R C[6];

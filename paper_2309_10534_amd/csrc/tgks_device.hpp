@@ -201,20 +201,36 @@ struct Gas {
   bool ok;
 };
 
+// 1/sqrt(x): the device's reciprocal square root in the kernels
+template <class R>
+TGKS_HD R rsqrt_(R x) {
+  return rsqrt(x);
+}
+TGKS_HD double rsqrt_(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return rsqrt(x);
+#else
+  return 1.0 / sqrt(x);
+#endif
+}
+
+// (rho, 1/rho, U, lambda, h) of W with one division:
+// re = rho (rho E) - |rho U|^2 / 2 = rho^2 e_int, inv = 1 / (rho re)
 template <int D, class R>
 TGKS_HD void make_gas(const R* W, double N, Gas<D, R>& g) {
   g.rho = W[0];
-  g.irho = R(1.0) / g.rho;
-  R ru2 = R(0.0);
+  R m2 = R(0.0);
 #pragma unroll
-  for (int d = 0; d < D; ++d) {
-    g.U[d] = W[d + 1] * g.irho;
-    ru2 += g.U[d] * W[d + 1];
-  }
-  const R eint = W[D + 1] - 0.5 * ru2;  // rho E - rho |U|^2 / 2 = N p / 2
-  g.h = (2.0 / N) * eint * g.irho;      // p / rho = 1/(2 lambda)
-  g.lam = 0.5 / g.h;
-  g.ok = (g.rho > 0.0) && (eint > 0.0) && (g.rho < INFINITY) && (eint < INFINITY);
+  for (int d = 0; d < D; ++d) m2 += W[d + 1] * W[d + 1];
+  const R re = g.rho * W[D + 1] - 0.5 * m2;
+  const R inv = R(1.0) / (g.rho * re);
+  g.irho = re * inv;
+#pragma unroll
+  for (int d = 0; d < D; ++d) g.U[d] = W[d + 1] * g.irho;
+  const R ir2 = g.irho * g.irho;
+  g.h = ((2.0 / N) * re) * ir2;                      // p / rho = 1/(2 lambda)
+  g.lam = (0.25 * N) * ((g.rho * g.rho) * (g.rho * inv));
+  g.ok = (g.rho > 0.0) && (re > 0.0) && (g.rho < INFINITY) && (re < INFINITY);
 }
 
 template <class R>
@@ -236,9 +252,10 @@ TGKS_HD void half_table(R U, R h, R m0, R m1, R* m) {
 // first two half-space moments: sgn = +1 (u1 > 0) or -1 (u1 < 0)
 template <class R>
 TGKS_HD void half_seed(R U, R lam, double sgn, R& m0, R& m1) {
-  const R sl = sqrt(lam);
+  const R isl = rsqrt_(lam);
+  const R sl = lam * isl;
   m0 = 0.5 * erfc(-sgn * (sl * U));
-  m1 = U * m0 + (sgn * 0.5) * exp(-(lam * U) * U) / (sl * 1.7724538509055160273);
+  m1 = U * m0 + ((sgn * 0.28209479177387814347) * exp(-(lam * U) * U)) * isl;  // 1/(2 sqrt(pi))
 }
 
 template <int D, class R>
@@ -625,16 +642,26 @@ TGKS_HD bool gp_flux(const R* Wl, const R* Wr, const R (*dWl)[D + 2], const R (*
     G3 = heat_combine<D>(T3, W0t, g0.U);
   }
 
-  // collision time (Sec. 5 preamble); dt is the full step in both stages
+  // collision time (Sec. 5 preamble); dt is the full step in both stages.
+  // xh = -dt / (2 tau): e^{-dt/tau} = (e^{xh})^2, one expm1 serves both
+  // intervals.
   const R pl = gl.rho * gl.h, pr = gr.rho * gr.h;
-  const R jump = fabs(pl - pr) / (pl + pr);
-  R tau;
-  if (P.tau_mode == 2)
-    tau = R(0.0);
-  else if (P.tau_mode == 1)
-    tau = P.mu / (g0.rho * g0.h) + (P.c2 * jump) * dt;
-  else
-    tau = (P.c1 + P.c2 * jump) * dt;
+  const R S = pl + pr, A = fabs(pl - pr);
+  R tau = R(0.0), xh = R(0.0);
+  if (P.tau_mode == 1) {
+    tau = P.mu / (g0.rho * g0.h) + (P.c2 * (A / S)) * dt;
+    xh = -(0.5 * dt) / tau;
+  } else if (P.tau_mode == 0) {
+    // tau = (c1 + c2 A/S) dt = dt T/S with T = c1 S + c2 A; one division
+    const R T = P.c1 * S + P.c2 * A;
+    if (T > 0.0) {
+      const R inv = R(1.0) / (S * T);
+      tau = dt * ((T * T) * inv);
+      xh = -0.5 * ((S * S) * inv);
+    }
+  }
+  R em = R(0.0);
+  if (tau != 0.0) em = expm1(xh);
 
 #pragma unroll
   for (int id = 0; id < 2; ++id) {
@@ -643,10 +670,12 @@ TGKS_HD bool gp_flux(const R* Wl, const R* Wr, const R (*dWl)[D + 2], const R (*
     if (tau == 0.0) {
       e = R(0.0);
       ome = R(1.0);
+    } else if (id == 1) {
+      e = em + 1.0;
+      ome = -em;
     } else {
-      const R x = -dl / tau;
-      e = exp(x);
-      ome = -expm1(x);
+      e = (em + 1.0) * (em + 1.0);
+      ome = -em * (em + 2.0);
     }
     const R tt = (tau * tau) * ome;
     const R C1 = dl - tau * ome;

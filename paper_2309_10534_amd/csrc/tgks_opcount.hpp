@@ -6,8 +6,9 @@
 // carries an identity; an operation on operands already combined the same
 // way (commutative operands in either order) returns the earlier result and
 // is not counted again, as common-subexpression elimination does.  Constants
-// with equal values share one identity.  +, -, *, / and each of sqrt, exp,
-// expm1, erfc count one operation; negation, comparisons and fabs count none.
+// with equal values share one identity.  +, -, *, / and each of sqrt, rsqrt,
+// exp, expm1, erfc count one operation; negation, comparisons and fabs count
+// none.
 #pragma once
 #include <cmath>
 #include <cstdint>
@@ -61,7 +62,7 @@ struct F {
   static F input(double x) { return F(x, graph().next++); }
 };
 
-enum Op { ADD, SUB, MUL, DIV, SQRT, EXP, EXPM1, ERFC, NEG };
+enum Op { ADD, SUB, MUL, DIV, SQRT, RSQRT, EXP, EXPM1, ERFC, NEG };
 
 inline F apply(Op op, F a, F b, double v, long long* counter) {
   long long x = a.id, y = b.id;
@@ -94,6 +95,7 @@ inline F sqrt(F a) { return apply(SQRT, a, a, std::sqrt(a.v), &tally().sqrt); }
 inline F exp(F a) { return apply(EXP, a, a, std::exp(a.v), &tally().exp); }
 inline F expm1(F a) { return apply(EXPM1, a, a, std::expm1(a.v), &tally().expm1); }
 inline F erfc(F a) { return apply(ERFC, a, a, std::erfc(a.v), &tally().erfc); }
+inline F rsqrt(F a) { return apply(RSQRT, a, a, 1.0 / std::sqrt(a.v), &tally().sqrt); }
 inline F fabs(F a) { return a.v < 0 ? -a : a; }
 
 }  // namespace tgks_opcount
