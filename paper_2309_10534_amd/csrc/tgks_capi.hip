@@ -65,14 +65,16 @@ int launch_faces(tgks_ctx* c, const double* W, const double* dt, int stage, uint
       }
       {
         Timer tm(c, ax);
-        dim3 grid((unsigned)((c->nface[ax] * 4 + 255) / 256));
+        const int n1 = c->g.n[(ax + 1) % 3], n2 = c->g.n[(ax + 2) % 3];
+        dim3 grid((unsigned)(c->g.n[ax] + 1), (unsigned)((n1 + B3_1 - 1) / B3_1), (unsigned)((n2 + B3_2 - 1) / B3_2));
+        const dim3 blk3(4 * B3_1 * B3_2);
 #define F3(AXV)                                                                       \
   if (stage == 1) {                                                                   \
-    if (c->ns) LAUNCH((face3d_kernel<AXV, 1, true>), grid, dim3(256), a);             \
-    else LAUNCH((face3d_kernel<AXV, 1, false>), grid, dim3(256), a);                  \
+    if (c->ns) LAUNCH((face3d_kernel<AXV, 1, true>), grid, blk3, a);                  \
+    else LAUNCH((face3d_kernel<AXV, 1, false>), grid, blk3, a);                       \
   } else {                                                                            \
-    if (c->ns) LAUNCH((face3d_kernel<AXV, 2, true>), grid, dim3(256), a);             \
-    else LAUNCH((face3d_kernel<AXV, 2, false>), grid, dim3(256), a);                  \
+    if (c->ns) LAUNCH((face3d_kernel<AXV, 2, true>), grid, blk3, a);                  \
+    else LAUNCH((face3d_kernel<AXV, 2, false>), grid, blk3, a);                       \
   }
         if (ax == 0) {
           F3(0)
@@ -250,13 +252,15 @@ long long count_face(const tgks_ctx* c, int stage, tgks_opcount::Tally* detail) 
         for (int m = 0; m < 2; ++m) dv[m] = dv[m] * F(1.0 / c->g.dx[1]);
       }
   } else if (D == 3) {
-    // per Gauss point, side and component: five sweep-1 reconstructions of
-    // (W, W_n) along t1, then three sweep-2 reconstructions along t2
-    for (int m = 0; m < 4; ++m)
-      for (int s = 0; s < 2; ++s)
-        for (int q = 0; q < NC; ++q) {
-          F S1w[5], S1d[5], S1n[5];
-          for (int r2 = 0; r2 < 5; ++r2) {
+    // per side and component: the sweep-1 reconstruction of (W, W_n) along
+    // t1 of this face's own line (the lines of the four neighbouring faces
+    // along t2 are their work, inputs here), then per t1 Gauss point three
+    // sweep-2 reconstructions along t2
+    for (int s = 0; s < 2; ++s)
+      for (int q = 0; q < NC; ++q) {
+        F S1w[2][5], S1d[2][5], S1n[2][5];
+        for (int r2 = 0; r2 < 5; ++r2) {
+          if (r2 == 2) {
             F Qw[5], Qn[5], v[2], dv[2], vn[2], dvn[2];
             for (int r = 0; r < 5; ++r) {
               Qw[r] = smooth(q, 0.1 * r, 0.1 * r2);
@@ -264,16 +268,27 @@ long long count_face(const tgks_ctx* c, int stage, tgks_opcount::Tally* detail) 
             }
             teno_gauss(Qw, teno_flag(Qw, c->tt), v, dv);
             teno_gauss(Qn, teno_flag(Qn, c->tt), vn, dvn);
-            S1w[r2] = v[0];
-            S1d[r2] = dv[0] * F(1.0 / c->g.dx[1]);
-            S1n[r2] = vn[0];
+            for (int m1 = 0; m1 < 2; ++m1) {
+              S1w[m1][r2] = v[m1];
+              S1d[m1][r2] = dv[m1] * F(1.0 / c->g.dx[1]);
+              S1n[m1][r2] = vn[m1];
+            }
+          } else {
+            for (int m1 = 0; m1 < 2; ++m1) {
+              S1w[m1][r2] = smooth(q, 0.1 * m1, 0.1 * r2);
+              S1d[m1][r2] = F::input(0.02 * (r2 + 1) + 0.01 * m1);
+              S1n[m1][r2] = F::input(0.03 * (r2 + 1) + 0.01 * m1);
+            }
           }
-          F v[2], dv[2], x[2], dx_[2];
-          teno_gauss(S1w, teno_flag(S1w, c->tt), v, dv);
-          dv[0] = dv[0] * F(1.0 / c->g.dx[2]);
-          teno_gauss(S1d, teno_flag(S1d, c->tt), x, dx_);
-          teno_gauss(S1n, teno_flag(S1n, c->tt), x, dx_);
         }
+        for (int m1 = 0; m1 < 2; ++m1) {
+          F v[2], dv[2], x[2], dx_[2];
+          teno_gauss(S1w[m1], teno_flag(S1w[m1], c->tt), v, dv);
+          for (int m2 = 0; m2 < 2; ++m2) dv[m2] = dv[m2] * F(1.0 / c->g.dx[2]);
+          teno_gauss(S1d[m1], teno_flag(S1d[m1], c->tt), x, dx_);
+          teno_gauss(S1n[m1], teno_flag(S1n[m1], c->tt), x, dx_);
+        }
+      }
   }
   FluxCfg fc = c->fc;
   const F dt(1e-3);

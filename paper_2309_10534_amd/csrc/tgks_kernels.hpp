@@ -302,94 +302,128 @@ __global__ __launch_bounds__(256) void recon3d_kernel(StageArgs a) {
     a.nflags[((long long)AX * 5 + c) * g.ncell + ((long long)p[2] * g.n[1] + p[1]) * g.n[0] + p[0]] = (uint8_t)fl;
 }
 
-// (b) face kernel: four lanes per face, one Gauss point each.  The
-// tangential reconstruction runs along t1 and then t2 with the cyclic axis
-// order (x-faces: y, z; y-faces: z, x; z-faces: x, y).
+// (b) face kernel.  A block owns one plane of faces (fixed index along AX)
+// and a B1 x B2 tile of it along the tangential axes T1, T2 (cyclic order:
+// x-faces y, z; y-faces z, x; z-faces x, y).  It stages the normal
+// reconstruction of both sides with a halo of two in LDS (ghost positions by
+// the index map, mirrored momenta negated), reconstructs every face line of
+// the tile and its T2 halo once along T1 (sweep 1, both T1 Gauss points), and
+// then lanes 4k..4k+3 share face k: lane (m1, m2) reconstructs side m2 along
+// T2 from the sweep-1 values at Gauss point m1 (sweep 2, both T2 points),
+// hands the partner lane (m1, 1-m2) the value at the partner's Gauss point,
+// and evaluates the flux at Gauss point (m1, m2); the four lanes sum.
+constexpr int B3_1 = 4, B3_2 = 16;
+
 template <int AX, int STAGE, bool NS>
-__global__ __launch_bounds__(256) void face3d_kernel(StageArgs a) {
-  constexpr int NC = 5;
+__global__ __launch_bounds__(4 * B3_1 * B3_2) void face3d_kernel(StageArgs a) {
+  constexpr int NC = 5, B1 = B3_1, B2 = B3_2, NT = 4 * B1 * B2;
+  constexpr int L1 = B1 + 4, L2 = B2 + 4;
+  constexpr int T1 = (AX + 1) % 3, T2 = (AX + 2) % 3;
+  __shared__ double sR[2][NC][2][L2][L1];      // [side][c][value, normal slope][t2][t1]
+  __shared__ double sS[2][NC][L2][B1][6];      // sweep 1: v(m1), d_t1 v(m1), v_n(m1)
   const double dt = *a.dt;
   if (!(dt > 0.0)) return;
   const Geom& g = a.g;
-  constexpr int T1 = (AX + 1) % 3, T2 = (AX + 2) % 3;
-  const long long nf = face_count(g, AX);
-  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int gp = (int)(gid & 3);
-  const long long fid = gid >> 2;
-  const bool live = fid < nf;
-  int fp[3] = {0, 0, 0};
-  if (live) {
-    long long r = fid;
-    int nfa[3] = {g.n[0], g.n[1], g.n[2]};
-    nfa[AX] += 1;
-    fp[0] = (int)(r % nfa[0]);
-    r /= nfa[0];
-    fp[1] = (int)(r % nfa[1]);
-    fp[2] = (int)(r / nfa[1]);
-  }
-  const int m1 = gp & 1, m2 = gp >> 1;
+  const int fa = blockIdx.x;
+  const int t10 = blockIdx.y * B1, t20 = blockIdx.z * B2;
+  const int tid = threadIdx.x;
   int ext[3] = {g.n[0], g.n[1], g.n[2]};
   ext[AX] += 2;
   const long long nr = (long long)ext[0] * ext[1] * ext[2];
-  const int perm[NC] = {0, 1 + AX, 1 + T1, 1 + T2, 4};
-  const double i1 = 1.0 / g.dx[T1], i2 = 1.0 / g.dx[T2];
-  double Wg[2][NC], Dg[2][3][NC];
-  if (live) {
-#pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      const int pa = fp[AX] - 1 + side;  // cell index along AX (may be -1 or n)
-      const int vo = side == 0 ? 2 : 0;
-#pragma unroll 1
-      for (int q = 0; q < NC; ++q) {
-        const int c = perm[q];
-        double S1w[5], S1d[5], S1n[5];
-#pragma unroll
-        for (int r2 = 0; r2 < 5; ++r2) {
-          double Qw[5], Qn[5];
-#pragma unroll
-          for (int r1 = 0; r1 < 5; ++r1) {
-            int pc[3];
-            pc[AX] = pa;
-            int fl1 = 0, fl2 = 0;
-            pc[T1] = map_index(fp[T1] - 2 + r1, g.n[T1], g.bclo[T1], g.bchi[T1], fl1);
-            pc[T2] = map_index(fp[T2] - 2 + r2, g.n[T2], g.bclo[T2], g.bchi[T2], fl2);
-            int e[3] = {pc[0], pc[1], pc[2]};
-            e[AX] += 1;
-            const long long off = ((long long)e[2] * ext[1] + e[1]) * ext[0] + e[0];
-            double vw = a.R[(long long)c * 4 * nr + vo * nr + off];
-            double vn = a.R[(long long)c * 4 * nr + (vo + 1) * nr + off];
-            const bool flip = (c == 1 + T1 && fl1) ^ (c == 1 + T2 && fl2);
-            if (flip) {
-              vw = -vw;
-              vn = -vn;
-            }
-            Qw[r1] = vw;
-            Qn[r1] = vn;
-          }
-          double v[2], dv[2], vn2[2], dvn2[2];
-          teno_gauss(Qw, teno_flag(Qw, a.tt), v, dv);
-          teno_gauss(Qn, teno_flag(Qn, a.tt), vn2, dvn2);
-          S1w[r2] = v[m1];
-          S1d[r2] = dv[m1] * i1;
-          S1n[r2] = vn2[m1];
-        }
-        double v[2], dv[2], x[2], dx_[2];
-        teno_gauss(S1w, teno_flag(S1w, a.tt), v, dv);
-        Wg[side][q] = v[m2];
-        Dg[side][2][q] = dv[m2] * i2;
-        teno_gauss(S1d, teno_flag(S1d, a.tt), x, dx_);
-        Dg[side][1][q] = x[m2];
-        teno_gauss(S1n, teno_flag(S1n, a.tt), x, dx_);
-        Dg[side][0][q] = x[m2];
-      }
-    }
+
+  // 1. normal reconstruction of the two cells beside each face position
+  for (int L = tid; L < 2 * NC * 2 * L2 * L1; L += NT) {
+    const int i1 = L % L1;
+    const int i2 = (L / L1) % L2;
+    const int k = (L / (L1 * L2)) % 2;
+    const int c = (L / (2 * L1 * L2)) % NC;
+    const int s = L / (2 * NC * L1 * L2);
+    int f1 = 0, f2 = 0;
+    int e[3];
+    e[AX] = fa + s;  // cell fa - 1 + s along AX, shifted by one
+    e[T1] = map_index(t10 - 2 + i1, g.n[T1], g.bclo[T1], g.bchi[T1], f1);
+    e[T2] = map_index(t20 - 2 + i2, g.n[T2], g.bclo[T2], g.bchi[T2], f2);
+    const long long off = ((long long)e[2] * ext[1] + e[1]) * ext[0] + e[0];
+    const int vo = s == 0 ? 2 : 0;
+    double v = a.R[(long long)c * 4 * nr + (vo + k) * nr + off];
+    if ((c == 1 + T1 && f1) ^ (c == 1 + T2 && f2)) v = -v;
+    sR[s][c][k][i2][i1] = v;
   }
-  double Fdt[NC] = {0, 0, 0, 0, 0}, Fh[NC] = {0, 0, 0, 0, 0};
-  if (live) {
-    if (!gp_flux<3, NS>(Wg[0], Wg[1], Dg[0], Dg[1], a.fc, dt, Fdt, Fh)) atomicAdd(a.fail, 1ull);
+  __syncthreads();
+
+  // 2. sweep 1 along T1 of every face line of the tile and its T2 halo
+  const double i1d = 1.0 / g.dx[T1], i2d = 1.0 / g.dx[T2];
+  for (int L = tid; L < 2 * NC * L2 * B1; L += NT) {
+    const int j1 = L % B1;
+    const int i2 = (L / B1) % L2;
+    const int c = (L / (B1 * L2)) % NC;
+    const int s = L / (NC * B1 * L2);
+    double Qw[5], Qn[5];
+#pragma unroll
+    for (int r = 0; r < 5; ++r) {
+      Qw[r] = sR[s][c][0][i2][j1 + r];
+      Qn[r] = sR[s][c][1][i2][j1 + r];
+    }
+    double v[2], dv[2], vn[2], dvn[2];
+    teno_gauss(Qw, teno_flag(Qw, a.tt), v, dv);
+    teno_gauss(Qn, teno_flag(Qn, a.tt), vn, dvn);
+    double* o = sS[s][c][i2][j1];
+    o[0] = v[0];
+    o[1] = v[1];
+    o[2] = dv[0] * i1d;
+    o[3] = dv[1] * i1d;
+    o[4] = vn[0];
+    o[5] = vn[1];
+  }
+  __syncthreads();
+
+  // 3. sweep 2 along T2 and the Gauss-point fluxes
+  const int m2 = tid & 1, m1 = (tid >> 1) & 1, fi = tid >> 2;
+  const int j1 = fi % B1, j2 = fi / B1;
+  int fp[3];
+  fp[AX] = fa;
+  fp[T1] = t10 + j1;
+  fp[T2] = t20 + j2;
+  const bool live = fp[T1] < g.n[T1] && fp[T2] < g.n[T2];
+  const int perm[NC] = {0, 1 + AX, 1 + T1, 1 + T2, 4};
+  double Wg[2][NC], Dg[2][3][NC];
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+    const int c = perm[q];
+    double v[2] = {0, 0}, dv[2] = {0, 0}, x[2] = {0, 0}, y[2] = {0, 0};
+    if (live) {
+      double Qw[5], Qd[5], Qn[5], t[2];
+#pragma unroll
+      for (int r = 0; r < 5; ++r) {
+        const double* o = sS[m2][c][j2 + r][j1];
+        Qw[r] = o[m1];
+        Qd[r] = o[2 + m1];
+        Qn[r] = o[4 + m1];
+      }
+      teno_gauss(Qw, teno_flag(Qw, a.tt), v, dv);
+      teno_gauss(Qd, teno_flag(Qd, a.tt), x, t);
+      teno_gauss(Qn, teno_flag(Qn, a.tt), y, t);
+    }
+    // own side (m2) at own Gauss point; the partner's side at this point
+    // arrives from the partner
+    const double sv = m2 ? v[0] : v[1], sd = m2 ? dv[0] : dv[1], sx = m2 ? x[0] : x[1], sy = m2 ? y[0] : y[1];
+    const double rv = __shfl_xor(sv, 1), rd = __shfl_xor(sd, 1), rx = __shfl_xor(sx, 1), ry = __shfl_xor(sy, 1);
+    const double ov = m2 ? v[1] : v[0], od = m2 ? dv[1] : dv[0], ox = m2 ? x[1] : x[0], oy = m2 ? y[1] : y[0];
+    Wg[0][q] = m2 == 0 ? ov : rv;
+    Wg[1][q] = m2 == 0 ? rv : ov;
+    Dg[0][2][q] = (m2 == 0 ? od : rd) * i2d;
+    Dg[1][2][q] = (m2 == 0 ? rd : od) * i2d;
+    Dg[0][1][q] = m2 == 0 ? ox : rx;
+    Dg[1][1][q] = m2 == 0 ? rx : ox;
+    Dg[0][0][q] = m2 == 0 ? oy : ry;
+    Dg[1][0][q] = m2 == 0 ? ry : oy;
   }
   double A[NC] = {0, 0, 0, 0, 0}, B[NC] = {0, 0, 0, 0, 0};
-  write_combined<NC>(STAGE, Fdt, Fh, 0.25, A, B);
+  if (live) {
+    double Fdt[NC], Fh[NC];
+    if (!gp_flux<3, NS>(Wg[0], Wg[1], Dg[0], Dg[1], a.fc, dt, Fdt, Fh)) atomicAdd(a.fail, 1ull);
+    write_combined<NC>(STAGE, Fdt, Fh, 0.25, A, B);
+  }
   // sum over the four Gauss points held by lanes 4k..4k+3
 #pragma unroll
   for (int q = 0; q < NC; ++q) {
@@ -400,7 +434,11 @@ __global__ __launch_bounds__(256) void face3d_kernel(StageArgs a) {
       B[q] += __shfl_xor(B[q], 2);
     }
   }
-  if (live && gp == 0) {
+  if (live && (tid & 3) == 0) {
+    int nfa[3] = {g.n[0], g.n[1], g.n[2]};
+    nfa[AX] += 1;
+    const long long nf = (long long)nfa[0] * nfa[1] * nfa[2];
+    const long long fid = ((long long)fp[2] * nfa[1] + fp[1]) * nfa[0] + fp[0];
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
       a.FA[(long long)perm[q] * nf + fid] = A[q];
