@@ -324,8 +324,17 @@ __global__ __launch_bounds__(4 * B3_1 * B3_2) void face3d_kernel(StageArgs a) {
   const double dt = *a.dt;
   if (!(dt > 0.0)) return;
   const Geom& g = a.g;
-  const int fa = blockIdx.x;
-  const int t10 = blockIdx.y * B1, t20 = blockIdx.z * B2;
+  // XCD-aware order: workgroups are dealt to the 8 XCDs in turn; the
+  // logical tiles are renumbered so that each XCD walks a contiguous range
+  // with the face plane fastest, and planes that share cache lines of the
+  // normal reconstruction meet in one L2
+  const int nb1 = (g.n[T1] + B1 - 1) / B1, nb2 = (g.n[T2] + B2 - 1) / B2;
+  const int nbl = (g.n[AX] + 1) * nb1 * nb2;
+  const int per = (nbl + 7) / 8;
+  const int lb = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  if (lb >= nbl) return;
+  const int fa = lb % (g.n[AX] + 1);
+  const int t10 = ((lb / (g.n[AX] + 1)) % nb1) * B1, t20 = (lb / ((g.n[AX] + 1) * nb1)) * B2;
   const int tid = threadIdx.x;
   int ext[3] = {g.n[0], g.n[1], g.n[2]};
   ext[AX] += 2;
