@@ -473,6 +473,8 @@ struct UpdateArgs {
   double* partial;    // stage 2 with CFL: one minimum per block, or null
 };
 
+// minimum over the block (blockDim.x a multiple of 64, at most 1024);
+// valid in thread 0
 __device__ __forceinline__ double block_min(double v, double* red) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v = fmin(v, __shfl_xor(v, o));
@@ -506,7 +508,7 @@ __device__ __forceinline__ double cell_dt(const double* w, double gamma, double 
 template <int D, int STAGE, bool CFL>
 __device__ __forceinline__ void update_body(const UpdateArgs& u, long long id, double* partial) {
   constexpr int NC = D + 2;
-  __shared__ double red[4];
+  __shared__ double red[16];  // one entry per wave, up to 1024 threads
   const Geom& g = u.g;
   const bool live = id < g.ncell;
   const double dt = *u.dt;
@@ -566,7 +568,7 @@ template <int D>
 __device__ __forceinline__ void cfl_partial_body(const Geom& g, const double* W, double gamma, double mu,
                                                  long long id, double* partial) {
   constexpr int NC = D + 2;
-  __shared__ double red[4];
+  __shared__ double red[16];  // one entry per wave, up to 1024 threads
   double dxm = g.dx[0];
   for (int d = 1; d < D; ++d) dxm = fmin(dxm, g.dx[d]);
   double v = INFINITY;
@@ -593,7 +595,7 @@ __global__ __launch_bounds__(256) void cfl_partial_kernel(Geom g, const double* 
 // mode 2: fixed step, t += dt only.
 __device__ __forceinline__ void finalize_body(const double* partial, int nblk, double cfl, double t_in,
                                               double t_end, double* clock, double* dt_out, int mode) {
-  __shared__ double red[4];
+  __shared__ double red[16];  // one entry per wave, up to 1024 threads
   double v = INFINITY;
   bool nan = false;
   if (mode != 2)
