@@ -382,6 +382,7 @@ def main():
     ok = bool(torch.isfinite(W).all().item())
     flops = tgks.tgks_flop_counts(p)
     tgks.tgks_destroy(ctx)
+    meas_tflops, meas_gbps = tgks.tgks_measure_peaks()
 
     value = ncell * args.steps / el / 1e6
     # dominant kernel: face fluxes along x or y
@@ -411,7 +412,9 @@ def main():
                      "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": measured_traffic(dom, tile),
                      "traffic_unit": "bytes per launch", "algorithmic_bytes": algo_bytes,
                      "flops_per_launch": per_launch, "avg_launch_ms": round(ms / max(launches, 1), 5),
-                     "launches": launches},
+                     "launches": launches,
+                     "measured_peaks": {"fp64_fma_tflops": round(meas_tflops, 2), "copy_gbps": round(meas_gbps, 1),
+                                        "frac_of_measured_fp64": round(achieved / meas_tflops, 4)}},
         "kernel_ms_per_step": {k: round(v[0] / args.steps, 5) for k, v in kt.items()},
     }
     if not args.no_batched:

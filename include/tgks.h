@@ -156,6 +156,13 @@ int tgks_kernel_time(tgks_ctx* ctx, int32_t kind, double* ms, int64_t* launches)
  * stage-1 face; out[7]: CFL limit per cell.  nout >= 8. */
 int tgks_flop_counts(const tgks_params* p, double* out, int32_t nout);
 
+/* The roofline's two ceilings measured on the current device: FP64 FMA
+ * throughput in TFLOP/s (eight independent FMA chains per thread) and
+ * device-to-device copy bandwidth in GB/s (bytes read + written, 1 GiB
+ * each).  Allocates and frees 2 GiB of device memory; synchronises the
+ * stream (hip_stream may be NULL). */
+int tgks_measure_peaks(void* hip_stream, double* fp64_tflops, double* copy_gbps);
+
 /* Host evaluation of the device Gauss-point flux (Sec. 2.1, Eqs. 2.5-2.9,
  * kinetic weighting Eq. 2.6) for verification without a device: the same
  * code the kernels run, in double on the host.  Face frame (axis 0 normal);

@@ -70,6 +70,8 @@ def lib():
     L.tgks_set_tile.argtypes = [vp, C.c_int32]
     L.tgks_tune.argtypes = [vp, vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_float)]
     dp = C.POINTER(C.c_double)
+    L.tgks_measure_peaks.argtypes = [vp, dp, dp]
+    L.tgks_measure_peaks.restype = C.c_int
     L.tgks_gp_flux_host.argtypes = [P, dp, dp, dp, dp, C.c_double, dp]
     L.tgks_step_adjoint.argtypes = [vp, vp, vp, vp, vp]
     L.tgks_step_adjoint.restype = C.c_int
@@ -215,6 +217,15 @@ def tgks_flop_counts(params):
     _check(lib().tgks_flop_counts(C.byref(params), out, 8), "tgks_flop_counts")
     keys = ("normal", "face", "face_stage2", "update1", "update2", "face_transcendentals", "face_divisions", "cfl")
     return {k: out[i] for i, k in enumerate(keys)}
+
+
+def tgks_measure_peaks(stream=None):
+    """(FP64 FMA TFLOP/s, copy GB/s) measured on the current device."""
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    t, b = C.c_double(), C.c_double()
+    _check(lib().tgks_measure_peaks(C.c_void_p(s.cuda_stream), C.byref(t), C.byref(b)), "tgks_measure_peaks")
+    return t.value, b.value
 
 
 def tgks_gp_flux_host(params, Wl, Wr, dWl, dWr, dt):

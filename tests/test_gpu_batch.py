@@ -188,3 +188,31 @@ def test_batch_invalid_args(torch_dev):
             tgks.tgks_batch_run(b, W[:-1], 1, 0.0)
     finally:
         tgks.tgks_batch_destroy(b)
+
+
+def test_batch_full_sets_spot_oracle(orc, torch_dev):
+    """The stated batched sets at full size (256 uneven instances each, 1-D
+    seed 1 and 2-D seed 2): one batched step of the whole set, and a spot
+    sample of 16 instances (the eight smallest of each set) against the
+    oracle's step with its own CFL step."""
+    from paper_2309_10534_amd import tgks
+    torch = torch_dev
+    for dim, seed in ((1, 1), (2, 2)):
+        inst, _, _ = I.riemann_instances(256, dim=dim, seed=seed)
+        probs = [(W, problem(list(W.shape[1:])[::-1], [dx] * dim)) for W, dx in inst]
+        print(f"[batch-full] dim={dim} cells={sum(W[0].size for W, _ in probs)}", flush=True)
+        B = Batch(probs)
+        try:
+            (Wb, tb, badb), = B.run(1, use_graph=True)
+        finally:
+            B.close()
+        order = sorted(range(len(probs)), key=lambda i: probs[i][0][0].size)[:8]
+        for i in order:
+            W, pr = probs[i]
+            P = orc_params(orc, pr)
+            dt = orc.cfl_dt(P, W, 0.5)
+            Wo, _, _, bado = orc.step(P, W, dt)
+            assert tb[i, 0] == dt or abs(tb[i, 0] - dt) <= 1e-14 * dt
+            assert badb[i] == bado
+            if bado == 0 and np.all(np.isfinite(Wo)):
+                assert_close(Wb[i], Wo, what=f"dim {dim} instance {i}")
