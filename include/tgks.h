@@ -182,10 +182,12 @@ int tgks_gp_flux_host(const tgks_params* p, const double* Wl, const double* Wr, 
 
 /* gW_in = (dW_out/dW_in)^T gW_out for the step from W_n with the step read
  * from dt_dev (device).  W_n, gW_out, gW_in: device states; gW_in must not
- * overlap gW_out.  Recomputes the step's first stage (W*) with the forward
- * kernels.  The first call allocates the context's reverse-mode buffers.
- * TGKS_EINVAL for 3-D contexts or invalid pointers. */
-int tgks_step_adjoint(tgks_ctx* ctx, const double* W_n, const double* dt_dev, const double* gW_out, double* gW_in);
+ * overlap gW_out.  W_star: the step's intermediate state W* as tgks_step
+ * returned it for the same W_n and dt (device), or NULL to recompute it with
+ * the forward kernels.  The first call allocates the context's reverse-mode
+ * buffers.  TGKS_EINVAL for 3-D contexts or invalid pointers. */
+int tgks_step_adjoint(tgks_ctx* ctx, const double* W_n, const double* W_star, const double* dt_dev,
+                      const double* gW_out, double* gW_in);
 
 /* Host evaluation of the reverse of the Gauss-point flux (the same code the
  * reverse kernels run), for verification.  Face frame, HOST pointers as in

@@ -161,18 +161,23 @@ int tgks_gp_flux_vjp_host(const tgks_params* p, const double* Wl, const double* 
   return host_flux_vjp<3>(p, Wl, Wr, dWl, dWr, dt, Fb, G);
 }
 
-int tgks_step_adjoint(tgks_ctx* c, const double* W_n, const double* dt_dev, const double* gW_out, double* gW_in) {
+int tgks_step_adjoint(tgks_ctx* c, const double* W_n, const double* W_star, const double* dt_dev,
+                      const double* gW_out, double* gW_in) {
   if (!c || !W_n || !dt_dev || !gW_out || !gW_in || gW_out == gW_in) return TGKS_EINVAL;
   if (c->g.D > 2) return TGKS_EINVAL;
   int r;
   if ((r = ensure_adjoint_buffers(c))) return r;
   const int D = c->g.D;
-  // W* of the forward step (P is recomputed too, unused)
-  if ((r = launch_faces(c, W_n, dt_dev, 1, nullptr))) return r;
-  if ((r = launch_update(c, 1, W_n, c->Ws, c->P, dt_dev, false))) return r;
+  // W* of the forward step, unless the caller kept it (P is recomputed
+  // too, unused)
+  if (!W_star) {
+    if ((r = launch_faces(c, W_n, dt_dev, 1, nullptr))) return r;
+    if ((r = launch_update(c, 1, W_n, c->Ws, c->P, dt_dev, false))) return r;
+  }
+  const double* Ws = W_star ? W_star : c->Ws;
   // stage 2 at W*: G* = sum_d (dFA*_d / dW*)^T D_d^T G
   {
-    AdjArgs a = adj_args(c, c->Ws, gW_out, nullptr, 4.0 / 3.0, -8.0 / 3.0, 0.0, 0.0, dt_dev);
+    AdjArgs a = adj_args(c, Ws, gW_out, nullptr, 4.0 / 3.0, -8.0 / 3.0, 0.0, 0.0, dt_dev);
     for (int ax = 0; ax < D; ++ax)
       if ((r = reverse_direction(c, a, ax, ax == 0 ? nullptr : c->aWsb, nullptr, c->aWsb))) return r;
   }

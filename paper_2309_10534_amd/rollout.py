@@ -51,13 +51,17 @@ def rollout_adjoint(ctx, ckpt, dts, gW, every=20):
     nseg = (n_steps + every - 1) // every
     for s in reversed(range(nseg)):
         k0, k1 = s * every, min((s + 1) * every, n_steps)
-        states = [ckpt[s]]
+        # the segment's states and the intermediate states W* of its steps
+        # (the last step's W* is recomputed by the reverse step itself)
+        states, stars = [ckpt[s]], []
         for k in range(k0, k1 - 1):
-            nxt = torch.empty_like(states[-1])
-            tgks.tgks_step(ctx, states[-1], nxt, dts[k:k + 1])
+            nxt, star = torch.empty_like(states[-1]), torch.empty_like(states[-1])
+            tgks.tgks_step(ctx, states[-1], nxt, dts[k:k + 1], None, star)
             states.append(nxt)
+            stars.append(star)
+        stars.append(None)
         for k in reversed(range(k0, k1)):
-            tgks.tgks_step_adjoint(ctx, states[k - k0], dts[k:k + 1], g, g2)
+            tgks.tgks_step_adjoint(ctx, states[k - k0], dts[k:k + 1], g, g2, W_star=stars[k - k0])
             g, g2 = g2, g
     return g
 

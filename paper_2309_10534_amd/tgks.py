@@ -73,7 +73,7 @@ def lib():
     L.tgks_measure_peaks.argtypes = [vp, dp, dp]
     L.tgks_measure_peaks.restype = C.c_int
     L.tgks_gp_flux_host.argtypes = [P, dp, dp, dp, dp, C.c_double, dp]
-    L.tgks_step_adjoint.argtypes = [vp, vp, vp, vp, vp]
+    L.tgks_step_adjoint.argtypes = [vp, vp, vp, vp, vp, vp]
     L.tgks_step_adjoint.restype = C.c_int
     L.tgks_gp_flux_vjp_host.argtypes = [P, dp, dp, dp, dp, C.c_double, dp, dp]
     L.tgks_gp_flux_vjp_host.restype = C.c_int
@@ -357,12 +357,12 @@ def unpack(packed, offsets, shapes):
 # ---------------------------------------------------------------------------
 # reverse mode
 # ---------------------------------------------------------------------------
-def tgks_step_adjoint(ctx, W_n, dt_dev, gW_out, gW_in):
+def tgks_step_adjoint(ctx, W_n, dt_dev, gW_out, gW_in, W_star=None):
     """gW_in = (dW_out/dW_in)^T gW_out for one step from W_n (dt and the stencil
-    selections frozen)."""
+    selections frozen).  W_star: the step's W* from tgks_step, or None."""
     n = tgks_state_size(ctx)
-    _check(lib().tgks_step_adjoint(ctx, _ptr(W_n, n), _ptr(dt_dev, 1), _ptr(gW_out, n), _ptr(gW_in, n)),
-           "tgks_step_adjoint")
+    _check(lib().tgks_step_adjoint(ctx, _ptr(W_n, n), _ptr(W_star, n), _ptr(dt_dev, 1), _ptr(gW_out, n),
+                                   _ptr(gW_in, n)), "tgks_step_adjoint")
 
 
 def tgks_gp_flux_vjp_host(params, Wl, Wr, dWl, dWr, dt, Fb):

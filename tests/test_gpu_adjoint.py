@@ -57,6 +57,13 @@ def adjoint_vs_oracle(orc, torch, pr, W, dt, seed=0):
         tgks.tgks_step_adjoint(gp.ctx, Wd, dtd, Gd, out)
         torch.cuda.synchronize()
         Gin = out.cpu().numpy().reshape(W.shape)
+        # with the step's W* handed in: the same cotangent, bit for bit
+        Wn, Ws = torch.empty_like(Wd), torch.empty_like(Wd)
+        tgks.tgks_step(gp.ctx, Wd, Wn, dtd, None, Ws)
+        out2 = torch.empty_like(Gd)
+        tgks.tgks_step_adjoint(gp.ctx, Wd, dtd, Gd, out2, W_star=Ws)
+        torch.cuda.synchronize()
+        assert torch.equal(out, out2)
     finally:
         gp.close()
     Wo, dWo, bad = orc.step_dual(orc_params(orc, pr), W, V, dt)
