@@ -90,16 +90,16 @@ static int reverse_direction(tgks_ctx* c, AdjArgs a, int ax, const double* base0
     const dim3 gn((unsigned)((g.ncell * nc + 255) / 256));
     if (ax == 0) {
       if (c->ns)
-        ALAUNCH((adj_face2d_kernel<0, true>), grid, dim3(ATN * ATT), a);
+        ALAUNCH((adj_face2d_kernel<0, true>), grid, dim3(2 * ATN * ATT), a);
       else
-        ALAUNCH((adj_face2d_kernel<0, false>), grid, dim3(ATN * ATT), a);
+        ALAUNCH((adj_face2d_kernel<0, false>), grid, dim3(2 * ATN * ATT), a);
       ALAUNCH((adj_tan2d_kernel<0>), gt, dim3(256), a);
       ALAUNCH((adj_normal_kernel<2, 0>), gn, dim3(256), a);
     } else {
       if (c->ns)
-        ALAUNCH((adj_face2d_kernel<1, true>), grid, dim3(ATN * ATT), a);
+        ALAUNCH((adj_face2d_kernel<1, true>), grid, dim3(2 * ATN * ATT), a);
       else
-        ALAUNCH((adj_face2d_kernel<1, false>), grid, dim3(ATN * ATT), a);
+        ALAUNCH((adj_face2d_kernel<1, false>), grid, dim3(2 * ATN * ATT), a);
       ALAUNCH((adj_tan2d_kernel<1>), gt, dim3(256), a);
       ALAUNCH((adj_normal_kernel<2, 1>), gn, dim3(256), a);
     }

@@ -448,148 +448,172 @@ TGKS_HD void side_tables_bar(const Gas<D, R>& g, R m0, R m1, double K, const Mom
   half_seed_bar(g.U[0], g.lam, g.h, m0, m1, Sb.m1[0], Sb.m1[1], gb.U[0], gb.lam);
 }
 
+// Everything one side contributes, recomputed from the side's state and
+// slopes: gas state, half-space seeds and moment tables, micro slopes a_d of
+// the slopes and A of the time derivative, and Wt = sum_d J_d dW_d.
+template <int D, class R>
+struct Side {
+  Gas<D, R> g;
+  R m0, m1;
+  MomSet<D, R> S;
+  R a[D][D + 2], A[D + 2], Wt[D + 2];
+};
+
+template <int D, class R>
+TGKS_HD void side_forward(const R* Ws, const R (*dW)[D + 2], double sgn, const FluxCfg& P, Side<D, R>& sd) {
+  constexpr int NC = D + 2;
+  const double N = P.N;
+  make_gas<D>(Ws, N, sd.g);
+  half_seed(sd.g.U[0], sd.g.lam, sgn, sd.m0, sd.m1);
+  side_tables<D>(sd.g, sd.m0, sd.m1, P.K, sd.S);
+#pragma unroll
+  for (int q = 0; q < NC; ++q) sd.Wt[q] = R(0.0);
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    R b[NC];
+#pragma unroll
+    for (int q = 0; q < NC; ++q) b[q] = dW[d][q] * sd.g.irho;
+    micro_solve<D>(sd.g, N, b, sd.a[d]);
+    Prim<D, R> pd;
+    prim_dir<D>(sd.g, N, dW[d], pd);
+    R jv[NC];
+    euler_jvp<D>(sd.g, Ws[D + 1], d, dW[d], pd, jv);
+#pragma unroll
+    for (int q = 0; q < NC; ++q) sd.Wt[q] += jv[q];
+  }
+  R b[NC];
+#pragma unroll
+  for (int q = 0; q < NC; ++q) b[q] = -(sd.Wt[q] * sd.g.irho);
+  micro_solve<D>(sd.g, N, b, sd.A);
+}
+
+// the side's half-space moments of the non-equilibrium part: <u1 psi>,
+// sum_d <u1 u_d psi a_d>, <u1 psi A> (and for the heat flux <psi>,
+// sum_d <u_d psi a_d>, <psi A>)
+template <int D, bool NS, class R>
+TGKS_HD void side_moments(const Side<D, R>& sd, R* g1, R* v2, R* v3, R* f0, R* w2, R* w3) {
+  constexpr int NC = D + 2;
+  gpsi<D>(sd.S, 1, 0, 0, 0, g1);
+#pragma unroll
+  for (int q = 0; q < NC; ++q) v2[q] = R(0.0);
+  if (NS) {
+    gpsi<D>(sd.S, 0, 0, 0, 0, f0);
+#pragma unroll
+    for (int q = 0; q < NC; ++q) w2[q] = R(0.0);
+  }
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    int i, j, k;
+    unit(d, i, j, k);
+    mpsia<D, true>(sd.S, sd.a[d], 1 + i, j, k, R(1.0), v2);
+    if (NS) mpsia<D, true>(sd.S, sd.a[d], i, j, k, R(1.0), w2);
+  }
+  mpsia<D, false>(sd.S, sd.A, 1, 0, 0, R(1.0), v3);
+  if (NS) mpsia<D, false>(sd.S, sd.A, 0, 0, 0, R(1.0), w3);
+}
+
 // Reverse of gp_flux: given the cotangents Fdtb, Fhb of F(dt), F(dt/2),
-// writes the cotangents of Wl, Wr, dWl, dWr (dt is a constant).
+// writes the cotangents of Wl, Wr, dWl, dWr (dt is a constant).  The two
+// sides' data are recomputed where needed rather than kept, which keeps the
+// live state small: forward (sides, then the equilibrium part), reverse of
+// the equilibrium part, then one pass per side.
 template <int D, bool NS, class R>
 TGKS_HD void gp_flux_vjp(const R* Wl, const R* Wr, const R (*dWl)[D + 2], const R (*dWr)[D + 2], const FluxCfg& P,
                          R dt, const R* Fdtb, const R* Fhb, R* Wlb, R* Wrb, R (*dWlb)[D + 2], R (*dWrb)[D + 2]) {
   constexpr int NC = D + 2;
   const double N = P.N;
-  // ---- forward, keeping what the reverse needs ----
-  Gas<D, R> gs[2];
-  make_gas<D>(Wl, N, gs[0]);
-  make_gas<D>(Wr, N, gs[1]);
-  R h0s[2], h1s[2];
-  half_seed(gs[0].U[0], gs[0].lam, 1.0, h0s[0], h1s[0]);
-  half_seed(gs[1].U[0], gs[1].lam, -1.0, h0s[1], h1s[1]);
-  MomSet<D, R> S[2];
-  side_tables<D>(gs[0], h0s[0], h1s[0], P.K, S[0]);
-  side_tables<D>(gs[1], h0s[1], h1s[1], P.K, S[1]);
-  R W0[NC];
-  {
-    R g[NC];
-    gpsi<D>(S[0], 0, 0, 0, 0, g);
+  // ---- forward: kinetic weighting and the side terms ----
+  R W0[NC], dW0[D][NC];
+  R Cs[2][3];  // <Fb_id, S_k>, k = S1, S2, S3
+  R ps[2];     // side pressures
 #pragma unroll
-    for (int q = 0; q < NC; ++q) W0[q] = gs[0].rho * g[q];
-    gpsi<D>(S[1], 0, 0, 0, 0, g);
+  for (int q = 0; q < NC; ++q) {
+    W0[q] = R(0.0);
 #pragma unroll
-    for (int q = 0; q < NC; ++q) W0[q] += gs[1].rho * g[q];
+    for (int d = 0; d < D; ++d) dW0[d][q] = R(0.0);
   }
-  Gas<D, R> g0;
-  make_gas<D>(W0, N, g0);
-  R a[2][D][NC], Wt[2][NC], A[2][NC], dW0[D][NC];
-  R X[6][NC];  // T1, T2, T3, S1, S2, S3
-  R Hs[3] = {R(0.0), R(0.0), R(0.0)};
 #pragma unroll
-  for (int q = 0; q < NC; ++q) X[3][q] = X[4][q] = X[5][q] = R(0.0);
-#pragma unroll
-  for (int d = 0; d < D; ++d)
-#pragma unroll
-    for (int q = 0; q < NC; ++q) dW0[d][q] = R(0.0);
+  for (int id = 0; id < 2; ++id) Cs[id][0] = Cs[id][1] = Cs[id][2] = R(0.0);
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
-    const R* Ws = s == 0 ? Wl : Wr;
-    const R(*dW)[NC] = s == 0 ? dWl : dWr;
-    const Gas<D, R>& g = gs[s];
+    Side<D, R> sd;
+    side_forward<D>(s == 0 ? Wl : Wr, s == 0 ? dWl : dWr, s == 0 ? 1.0 : -1.0, P, sd);
+    const R rho = sd.g.rho;
+    ps[s] = rho * sd.g.h;
+    R g[NC];
+    gpsi<D>(sd.S, 0, 0, 0, 0, g);
 #pragma unroll
-    for (int q = 0; q < NC; ++q) Wt[s][q] = R(0.0);
+    for (int q = 0; q < NC; ++q) W0[q] += rho * g[q];
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-      R b[NC];
+    for (int d = 0; d < D; ++d) mpsia<D, true>(sd.S, sd.a[d], 0, 0, 0, rho, dW0[d]);
+    R g1[NC], v2[NC], v3[NC], f0[NC], w2[NC], w3[NC];
+    side_moments<D, false>(sd, g1, v2, v3, f0, w2, w3);
 #pragma unroll
-      for (int q = 0; q < NC; ++q) b[q] = dW[d][q] * g.irho;
-      micro_solve<D>(g, N, b, a[s][d]);
-      mpsia<D, true>(S[s], a[s][d], 0, 0, 0, g.rho, dW0[d]);
-      Prim<D, R> pd;
-      prim_dir<D>(g, N, dW[d], pd);
-      R jv[NC];
-      euler_jvp<D>(g, Ws[D + 1], d, dW[d], pd, jv);
-#pragma unroll
-      for (int q = 0; q < NC; ++q) Wt[s][q] += jv[q];
-    }
-    {
-      R b[NC];
-#pragma unroll
-      for (int q = 0; q < NC; ++q) b[q] = -(Wt[s][q] * g.irho);
-      micro_solve<D>(g, N, b, A[s]);
-    }
-    R gv[NC], v2[NC], v3[NC];
-    gpsi<D>(S[s], 1, 0, 0, 0, gv);
-#pragma unroll
-    for (int q = 0; q < NC; ++q) v2[q] = R(0.0);
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-      int i, j, k;
-      unit(d, i, j, k);
-      mpsia<D, true>(S[s], a[s][d], 1 + i, j, k, R(1.0), v2);
-    }
-    mpsia<D, false>(S[s], A[s], 1, 0, 0, R(1.0), v3);
-#pragma unroll
-    for (int q = 0; q < NC; ++q) {
-      X[3][q] += g.rho * gv[q];
-      X[4][q] += g.rho * v2[q];
-      X[5][q] += g.rho * v3[q];
-    }
-  }
-  const R p0 = g0.rho * g0.h;
-  const R E0 = W0[D + 1];
-  R W0t[NC];
-  {
-    X[0][0] = W0[1];
-#pragma unroll
-    for (int e = 0; e < D; ++e) X[0][e + 1] = W0[1] * g0.U[e] + (e == 0 ? p0 : R(0.0));
-    X[0][D + 1] = g0.U[0] * (E0 + p0);
-#pragma unroll
-    for (int q = 0; q < NC; ++q) W0t[q] = X[1][q] = R(0.0);
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-      Prim<D, R> pd;
-      prim_dir<D>(g0, N, dW0[d], pd);
-      R jv[NC], gv[NC];
-      euler_jvp<D>(g0, E0, d, dW0[d], pd, jv);
-      g1d_jvp<D>(g0, N, d, dW0[d], pd, gv);
+    for (int id = 0; id < 2; ++id) {
+      const R* Fb = id == 0 ? Fdtb : Fhb;
+      R c1 = R(0.0), c2 = R(0.0), c3 = R(0.0);
 #pragma unroll
       for (int q = 0; q < NC; ++q) {
-        W0t[q] -= jv[q];
-        X[1][q] += gv[q];
+        c1 += Fb[q] * g1[q];
+        c2 += Fb[q] * v2[q];
+        c3 += Fb[q] * v3[q];
       }
+      Cs[id][0] += rho * c1;
+      Cs[id][1] += rho * c2;
+      Cs[id][2] += rho * c3;
     }
+  }
+  // ---- forward: equilibrium part ----
+  Gas<D, R> g0;
+  make_gas<D>(W0, N, g0);
+  const R p0 = g0.rho * g0.h;
+  const R E0 = W0[D + 1];
+  R T1[NC], T2[NC], T3[NC], W0t[NC];
+  T1[0] = W0[1];
+#pragma unroll
+  for (int e = 0; e < D; ++e) T1[e + 1] = W0[1] * g0.U[e] + (e == 0 ? p0 : R(0.0));
+  T1[D + 1] = g0.U[0] * (E0 + p0);
+#pragma unroll
+  for (int q = 0; q < NC; ++q) W0t[q] = T2[q] = R(0.0);
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    Prim<D, R> pd;
+    prim_dir<D>(g0, N, dW0[d], pd);
+    R jv[NC], gv[NC];
+    euler_jvp<D>(g0, E0, d, dW0[d], pd, jv);
+    g1d_jvp<D>(g0, N, d, dW0[d], pd, gv);
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      W0t[q] -= jv[q];
+      T2[q] += gv[q];
+    }
+  }
+  {
     Prim<D, R> pt;
     prim_dir<D>(g0, N, W0t, pt);
-    euler_jvp<D>(g0, E0, 0, W0t, pt, X[2]);
+    euler_jvp<D>(g0, E0, 0, W0t, pt, T3);
   }
-  R Gq[2] = {R(0.0), R(0.0)};  // G2, G3
   R w2n[NC];
 #pragma unroll
   for (int q = 0; q < NC; ++q) w2n[q] = -W0t[q];
+  R Gq[2] = {R(0.0), R(0.0)}, Hs[3] = {R(0.0), R(0.0), R(0.0)};
   if (NS) {
-    Gq[0] = heat_combine<D>(X[1], w2n, g0.U);
-    Gq[1] = heat_combine<D>(X[2], W0t, g0.U);
-    // side heat moments
+    Gq[0] = heat_combine<D>(T2, w2n, g0.U);
+    Gq[1] = heat_combine<D>(T3, W0t, g0.U);
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-      R gv[NC], f0[NC], v2[NC], w2[NC], v3[NC], w3[NC];
-      gpsi<D>(S[s], 1, 0, 0, 0, gv);
-      gpsi<D>(S[s], 0, 0, 0, 0, f0);
-#pragma unroll
-      for (int q = 0; q < NC; ++q) v2[q] = w2[q] = R(0.0);
-#pragma unroll
-      for (int d = 0; d < D; ++d) {
-        int i, j, k;
-        unit(d, i, j, k);
-        mpsia<D, true>(S[s], a[s][d], 1 + i, j, k, R(1.0), v2);
-        mpsia<D, true>(S[s], a[s][d], i, j, k, R(1.0), w2);
-      }
-      mpsia<D, false>(S[s], A[s], 1, 0, 0, R(1.0), v3);
-      mpsia<D, false>(S[s], A[s], 0, 0, 0, R(1.0), w3);
-      Hs[0] += gs[s].rho * heat_combine<D>(gv, f0, g0.U);
-      Hs[1] += gs[s].rho * heat_combine<D>(v2, w2, g0.U);
-      Hs[2] += gs[s].rho * heat_combine<D>(v3, w3, g0.U);
+      Side<D, R> sd;
+      side_forward<D>(s == 0 ? Wl : Wr, s == 0 ? dWl : dWr, s == 0 ? 1.0 : -1.0, P, sd);
+      R g1[NC], v2[NC], v3[NC], f0[NC], w2[NC], w3[NC];
+      side_moments<D, true>(sd, g1, v2, v3, f0, w2, w3);
+      Hs[0] += sd.g.rho * heat_combine<D>(g1, f0, g0.U);
+      Hs[1] += sd.g.rho * heat_combine<D>(v2, w2, g0.U);
+      Hs[2] += sd.g.rho * heat_combine<D>(v3, w3, g0.U);
     }
   }
-  const R pl = gs[0].rho * gs[0].h, pr = gs[1].rho * gs[1].h;
-  const R jden = pl + pr;
-  const R jump = fabs(pl - pr) / jden;
+  // collision time
+  const R S_ = ps[0] + ps[1];
+  const R jump = fabs(ps[0] - ps[1]) / S_;
   R tau;
   if (P.tau_mode == 2)
     tau = R(0.0);
@@ -597,18 +621,11 @@ TGKS_HD void gp_flux_vjp(const R* Wl, const R* Wr, const R (*dWl)[D + 2], const 
     tau = P.mu / p0 + (P.c2 * jump) * dt;
   else
     tau = (P.c1 + P.c2 * jump) * dt;
-
-  // ---- reverse ----
-  // F = sum_k C_k X_k (+ NS: pr_fix q in the energy component)
-  R Xb[6][NC];
-#pragma unroll
-  for (int k = 0; k < 6; ++k)
-#pragma unroll
-    for (int q = 0; q < NC; ++q) Xb[k][q] = R(0.0);
-  R Gb[2] = {R(0.0), R(0.0)}, Hb[3] = {R(0.0), R(0.0), R(0.0)};
-  R taub = R(0.0);
-  // e^{-dt/tau} = (e^{-dt/(2 tau)})^2
+  // time coefficients, e^{-dt/tau} = (e^{-dt/(2 tau)})^2
   const R em = tau == 0.0 ? R(0.0) : expm1(-(0.5 * dt) / tau);
+  R C[2][6];
+  R taub = R(0.0);
+  R Gb[2] = {R(0.0), R(0.0)}, Hb[3] = {R(0.0), R(0.0), R(0.0)};
 #pragma unroll
   for (int id = 0; id < 2; ++id) {
     const R* Fb = id == 0 ? Fdtb : Fhb;
@@ -625,30 +642,31 @@ TGKS_HD void gp_flux_vjp(const R* Wl, const R* Wr, const R (*dWl)[D + 2], const 
       ome = -em * (em + 2.0);
     }
     const R tt = (tau * tau) * ome;
-    R C[6];
-    C[0] = dl - tau * ome;
-    C[1] = 2.0 * tt - (tau * dl) * (1.0 + e);
-    C[2] = (0.5 * dl) * dl - tau * dl + tt;
-    C[3] = tau * ome;
-    C[4] = (tau * dl) * e - 2.0 * tt;
-    C[5] = -tt;
+    C[id][0] = dl - tau * ome;
+    C[id][1] = 2.0 * tt - (tau * dl) * (1.0 + e);
+    C[id][2] = (0.5 * dl) * dl - tau * dl + tt;
+    C[id][3] = tau * ome;
+    C[id][4] = (tau * dl) * e - 2.0 * tt;
+    C[id][5] = -tt;
+    // cotangents of the coefficients: <Fb, X_k>
     R Cb[6];
+    Cb[0] = Cb[1] = Cb[2] = R(0.0);
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
-      Cb[k] = R(0.0);
-#pragma unroll
-      for (int q = 0; q < NC; ++q) {
-        Xb[k][q] += C[k] * Fb[q];
-        Cb[k] += Fb[q] * X[k][q];
-      }
+    for (int q = 0; q < NC; ++q) {
+      Cb[0] += Fb[q] * T1[q];
+      Cb[1] += Fb[q] * T2[q];
+      Cb[2] += Fb[q] * T3[q];
     }
+    Cb[3] = Cs[id][0];
+    Cb[4] = Cs[id][1];
+    Cb[5] = Cs[id][2];
     if (NS) {
       const R fe = P.pr_fix * Fb[NC - 1];
-      Gb[0] += fe * C[1];
-      Gb[1] += fe * C[2];
-      Hb[0] += fe * C[3];
-      Hb[1] += fe * C[4];
-      Hb[2] += fe * C[5];
+      Gb[0] += fe * C[id][1];
+      Gb[1] += fe * C[id][2];
+      Hb[0] += fe * C[id][3];
+      Hb[1] += fe * C[id][4];
+      Hb[2] += fe * C[id][5];
       Cb[1] += fe * Gq[0];
       Cb[2] += fe * Gq[1];
       Cb[3] += fe * Hs[0];
@@ -656,7 +674,6 @@ TGKS_HD void gp_flux_vjp(const R* Wl, const R* Wr, const R (*dWl)[D + 2], const 
       Cb[5] += fe * Hs[2];
     }
     if (tau != 0.0) {
-      // derivatives of the time coefficients with respect to tau
       const R r = dl / tau;
       const R dtt = 2.0 * tau * ome - e * dl;
       const R dC0 = e * r - ome;
@@ -668,11 +685,12 @@ TGKS_HD void gp_flux_vjp(const R* Wl, const R* Wr, const R (*dWl)[D + 2], const 
       taub += ((Cb[0] * dC0 + Cb[1] * dC1) + (Cb[2] * dC2 + Cb[3] * dC3)) + (Cb[4] * dC4 + Cb[5] * dC5);
     }
   }
-  GasBar<D, R> gb[2], g0b;
-  zero(gb[0]);
-  zero(gb[1]);
+  // cotangent of X_k: Xb_k = C_k(dt) Fdtb + C_k(dt/2) Fhb
+#define XB(k, q) (C[0][k] * Fdtb[q] + C[1][k] * Fhb[q])
+  // ---- reverse: collision time ----
+  GasBar<D, R> g0b;
   zero(g0b);
-  // collision time
+  R pb[2] = {R(0.0), R(0.0)};
   if (P.tau_mode != 2 && tau != 0.0) {
     const R jb = taub * (P.c2 * dt);
     if (P.tau_mode == 1) {
@@ -681,105 +699,54 @@ TGKS_HD void gp_flux_vjp(const R* Wl, const R* Wr, const R (*dWl)[D + 2], const 
       g0b.h += p0b * g0.rho;
     }
     // derivative of |x| taken as sign(x), +1 at x = 0 (equal pressures)
-    const R sg = pl - pr < 0.0 ? R(-1.0) : R(1.0);
-    const R plb = jb * (sg / jden - jump / jden);
-    const R prb = jb * (-sg / jden - jump / jden);
-    gb[0].rho += plb * gs[0].h;
-    gb[0].h += plb * gs[0].rho;
-    gb[1].rho += prb * gs[1].h;
-    gb[1].h += prb * gs[1].rho;
+    const R sg = ps[0] - ps[1] < 0.0 ? R(-1.0) : R(1.0);
+    pb[0] = jb * (sg / S_ - jump / S_);
+    pb[1] = jb * (-sg / S_ - jump / S_);
   }
-  // side terms: S1, S2, S3 (and the side heat moments)
-  MomSetBar<D, R> Sb[2];
-  R ab[2][D][NC], Ab[2][NC];
+  // ---- reverse: heat moments of the sides (their U0 cotangent only) ----
+  if (NS) {
 #pragma unroll
-  for (int s = 0; s < 2; ++s) {
-    zero(Sb[s]);
+    for (int s = 0; s < 2; ++s) {
+      Side<D, R> sd;
+      side_forward<D>(s == 0 ? Wl : Wr, s == 0 ? dWl : dWr, s == 0 ? 1.0 : -1.0, P, sd);
+      R g1[NC], v2[NC], v3[NC], f0[NC], w2[NC], w3[NC], t1[NC], t0[NC];
+      side_moments<D, true>(sd, g1, v2, v3, f0, w2, w3);
 #pragma unroll
-    for (int q = 0; q < NC; ++q) {
-      Ab[s][q] = R(0.0);
-#pragma unroll
-      for (int d = 0; d < D; ++d) ab[s][d][q] = R(0.0);
+      for (int q = 0; q < NC; ++q) t1[q] = t0[q] = R(0.0);
+      const R rho = sd.g.rho;
+      heat_combine_bar<D>(g1, f0, g0.U, rho * Hb[0], t1, t0, g0b.U);
+      heat_combine_bar<D>(v2, w2, g0.U, rho * Hb[1], t1, t0, g0b.U);
+      heat_combine_bar<D>(v3, w3, g0.U, rho * Hb[2], t1, t0, g0b.U);
     }
-    const R rho = gs[s].rho;
-    R gv[NC], ob[NC];
-    gpsi<D>(S[s], 1, 0, 0, 0, gv);
-    R rb = R(0.0);
-#pragma unroll
-    for (int q = 0; q < NC; ++q) {
-      rb += Xb[3][q] * gv[q];
-      ob[q] = rho * Xb[3][q];
-    }
-    gpsi_bar<D>(S[s], Sb[s], 1, 0, 0, 0, ob);
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-      int i, j, k;
-      unit(d, i, j, k);
-      rb += mpsia_bar<D>(S[s], Sb[s], a[s][d], 1 + i, j, k, rho, Xb[4], ab[s][d]);
-    }
-    rb += mpsia_bar<D>(S[s], Sb[s], A[s], 1, 0, 0, rho, Xb[5], Ab[s]);
-    if (NS) {
-      R f0[NC], v2[NC], w2[NC], v3[NC], w3[NC];
-      gpsi<D>(S[s], 0, 0, 0, 0, f0);
-#pragma unroll
-      for (int q = 0; q < NC; ++q) v2[q] = w2[q] = R(0.0);
-#pragma unroll
-      for (int d = 0; d < D; ++d) {
-        int i, j, k;
-        unit(d, i, j, k);
-        mpsia<D, true>(S[s], a[s][d], 1 + i, j, k, R(1.0), v2);
-        mpsia<D, true>(S[s], a[s][d], i, j, k, R(1.0), w2);
-      }
-      mpsia<D, false>(S[s], A[s], 1, 0, 0, R(1.0), v3);
-      mpsia<D, false>(S[s], A[s], 0, 0, 0, R(1.0), w3);
-      rb += (Hb[0] * heat_combine<D>(gv, f0, g0.U) + Hb[1] * heat_combine<D>(v2, w2, g0.U)) +
-            Hb[2] * heat_combine<D>(v3, w3, g0.U);
-      R gvb[NC], f0b[NC], v2b[NC], w2b[NC], v3b[NC], w3b[NC];
-#pragma unroll
-      for (int q = 0; q < NC; ++q) gvb[q] = f0b[q] = v2b[q] = w2b[q] = v3b[q] = w3b[q] = R(0.0);
-      heat_combine_bar<D>(gv, f0, g0.U, rho * Hb[0], gvb, f0b, g0b.U);
-      heat_combine_bar<D>(v2, w2, g0.U, rho * Hb[1], v2b, w2b, g0b.U);
-      heat_combine_bar<D>(v3, w3, g0.U, rho * Hb[2], v3b, w3b, g0b.U);
-      gpsi_bar<D>(S[s], Sb[s], 1, 0, 0, 0, gvb);
-      gpsi_bar<D>(S[s], Sb[s], 0, 0, 0, 0, f0b);
-#pragma unroll
-      for (int d = 0; d < D; ++d) {
-        int i, j, k;
-        unit(d, i, j, k);
-        (void)mpsia_bar<D>(S[s], Sb[s], a[s][d], 1 + i, j, k, R(1.0), v2b, ab[s][d]);
-        (void)mpsia_bar<D>(S[s], Sb[s], a[s][d], i, j, k, R(1.0), w2b, ab[s][d]);
-      }
-      (void)mpsia_bar<D>(S[s], Sb[s], A[s], 1, 0, 0, R(1.0), v3b, Ab[s]);
-      (void)mpsia_bar<D>(S[s], Sb[s], A[s], 0, 0, 0, R(1.0), w3b, Ab[s]);
-    }
-    gb[s].rho += rb;
   }
-  // equilibrium terms: heat moments G2 = phi(T2, -W0t), G3 = phi(T3, W0t)
-  R W0tb[NC];
+  // ---- reverse: equilibrium part ----
+  R T2b[NC], T3b[NC], W0tb[NC];
 #pragma unroll
-  for (int q = 0; q < NC; ++q) W0tb[q] = R(0.0);
+  for (int q = 0; q < NC; ++q) {
+    T2b[q] = XB(1, q);
+    T3b[q] = XB(2, q);
+    W0tb[q] = R(0.0);
+  }
   if (NS) {
     R w2b[NC];
 #pragma unroll
     for (int q = 0; q < NC; ++q) w2b[q] = R(0.0);
-    heat_combine_bar<D>(X[1], w2n, g0.U, Gb[0], Xb[1], w2b, g0b.U);
-    heat_combine_bar<D>(X[2], W0t, g0.U, Gb[1], Xb[2], W0tb, g0b.U);
+    heat_combine_bar<D>(T2, w2n, g0.U, Gb[0], T2b, w2b, g0b.U);
+    heat_combine_bar<D>(T3, W0t, g0.U, Gb[1], T3b, W0tb, g0b.U);
 #pragma unroll
     for (int q = 0; q < NC; ++q) W0tb[q] -= w2b[q];
   }
   R E0b = R(0.0);
   {
-    // T3 = J_1(W0) W0t
     Prim<D, R> pt, ptb;
     prim_dir<D>(g0, N, W0t, pt);
     zero(ptb);
-    euler_jvp_bar<D>(g0, E0, 0, W0t, pt, Xb[2], W0tb, ptb, g0b, E0b);
+    euler_jvp_bar<D>(g0, E0, 0, W0t, pt, T3b, W0tb, ptb, g0b, E0b);
     prim_dir_bar<D>(g0, N, W0t, pt, ptb, W0tb, g0b);
   }
   R dW0b[D][NC];
 #pragma unroll
   for (int d = 0; d < D; ++d) {
-    // W0t -= J_d(W0) dW0_d;  T2 += dG_1d(W0) dW0_d
 #pragma unroll
     for (int q = 0; q < NC; ++q) dW0b[d][q] = R(0.0);
     Prim<D, R> pd, pdb;
@@ -789,53 +756,120 @@ TGKS_HD void gp_flux_vjp(const R* Wl, const R* Wr, const R (*dWl)[D + 2], const 
 #pragma unroll
     for (int q = 0; q < NC; ++q) jb[q] = -W0tb[q];
     euler_jvp_bar<D>(g0, E0, d, dW0[d], pd, jb, dW0b[d], pdb, g0b, E0b);
-    g1d_jvp_bar<D>(g0, N, d, dW0[d], pd, Xb[1], dW0b[d], pdb, g0b);
+    g1d_jvp_bar<D>(g0, N, d, dW0[d], pd, T2b, dW0b[d], pdb, g0b);
     prim_dir_bar<D>(g0, N, dW0[d], pd, pdb, dW0b[d], g0b);
   }
-  // T1 = F_1(W0)
   R W0b[NC];
 #pragma unroll
   for (int q = 0; q < NC; ++q) W0b[q] = R(0.0);
   {
-    R p0b = Xb[0][1] + Xb[0][D + 1] * g0.U[0];
-    W0b[1] += Xb[0][0];
+    // T1 = F_1(W0)
+    R T1b[NC];
+#pragma unroll
+    for (int q = 0; q < NC; ++q) T1b[q] = XB(0, q);
+    const R p0b = T1b[1] + T1b[D + 1] * g0.U[0];
+    W0b[1] += T1b[0];
 #pragma unroll
     for (int e = 0; e < D; ++e) {
-      W0b[1] += Xb[0][e + 1] * g0.U[e];
-      g0b.U[e] += Xb[0][e + 1] * W0[1];
+      W0b[1] += T1b[e + 1] * g0.U[e];
+      g0b.U[e] += T1b[e + 1] * W0[1];
     }
-    g0b.U[0] += Xb[0][D + 1] * (E0 + p0);
-    E0b += Xb[0][D + 1] * g0.U[0];
+    g0b.U[0] += T1b[D + 1] * (E0 + p0);
+    E0b += T1b[D + 1] * g0.U[0];
     g0b.rho += p0b * g0.h;
     g0b.h += p0b * g0.rho;
   }
   W0b[D + 1] += E0b;
   make_gas_bar<D>(W0, N, g0, g0b, W0b);
-  // kinetic weighting: W0 = sum_s rho_s <psi>_s, dW0_d = sum_s rho_s <psi a_d>_s
-#pragma unroll
-  for (int s = 0; s < 2; ++s) {
-    const R rho = gs[s].rho;
-    R g[NC], ob[NC];
-    gpsi<D>(S[s], 0, 0, 0, 0, g);
-    R rb = R(0.0);
-#pragma unroll
-    for (int q = 0; q < NC; ++q) {
-      rb += W0b[q] * g[q];
-      ob[q] = rho * W0b[q];
-    }
-    gpsi_bar<D>(S[s], Sb[s], 0, 0, 0, 0, ob);
-#pragma unroll
-    for (int d = 0; d < D; ++d) rb += mpsia_bar<D>(S[s], Sb[s], a[s][d], 0, 0, 0, rho, dW0b[d], ab[s][d]);
-    gb[s].rho += rb;
-  }
-  // micro slopes and time derivative of each side
+  // ---- reverse: one pass per side ----
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
     const R* Ws = s == 0 ? Wl : Wr;
     const R(*dW)[NC] = s == 0 ? dWl : dWr;
     R* Wsb = s == 0 ? Wlb : Wrb;
     R(*dWb)[NC] = s == 0 ? dWlb : dWrb;
-    const Gas<D, R>& g = gs[s];
+    Side<D, R> sd;
+    side_forward<D>(Ws, dW, s == 0 ? 1.0 : -1.0, P, sd);
+    const Gas<D, R>& g = sd.g;
+    const R rho = g.rho;
+    GasBar<D, R> gb;
+    zero(gb);
+    gb.rho += pb[s] * g.h;
+    gb.h += pb[s] * rho;
+    MomSetBar<D, R> Sb;
+    zero(Sb);
+    R ab[D][NC], Ab[NC];
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      Ab[q] = R(0.0);
+#pragma unroll
+      for (int d = 0; d < D; ++d) ab[d][q] = R(0.0);
+    }
+    R rb = R(0.0);
+    {
+      // S1 += rho <u1 psi>, S2 += rho sum_d <u1 u_d psi a_d>, S3 += rho <u1 psi A>
+      R g1[NC], ob[NC], xb[NC];
+      gpsi<D>(sd.S, 1, 0, 0, 0, g1);
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        xb[q] = XB(3, q);
+        rb += xb[q] * g1[q];
+        ob[q] = rho * xb[q];
+      }
+      gpsi_bar<D>(sd.S, Sb, 1, 0, 0, 0, ob);
+#pragma unroll
+      for (int q = 0; q < NC; ++q) xb[q] = XB(4, q);
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        int i, j, k;
+        unit(d, i, j, k);
+        rb += mpsia_bar<D>(sd.S, Sb, sd.a[d], 1 + i, j, k, rho, xb, ab[d]);
+      }
+#pragma unroll
+      for (int q = 0; q < NC; ++q) xb[q] = XB(5, q);
+      rb += mpsia_bar<D>(sd.S, Sb, sd.A, 1, 0, 0, rho, xb, Ab);
+    }
+    if (NS) {
+      R g1[NC], v2[NC], v3[NC], f0[NC], w2[NC], w3[NC];
+      side_moments<D, true>(sd, g1, v2, v3, f0, w2, w3);
+      rb += (Hb[0] * heat_combine<D>(g1, f0, g0.U) + Hb[1] * heat_combine<D>(v2, w2, g0.U)) +
+            Hb[2] * heat_combine<D>(v3, w3, g0.U);
+      R g1b[NC], f0b[NC], v2b[NC], w2b[NC], v3b[NC], w3b[NC], cdump[D];
+#pragma unroll
+      for (int q = 0; q < NC; ++q) g1b[q] = f0b[q] = v2b[q] = w2b[q] = v3b[q] = w3b[q] = R(0.0);
+#pragma unroll
+      for (int d = 0; d < D; ++d) cdump[d] = R(0.0);
+      // the U0 cotangents of these terms were taken before the equilibrium
+      // reverse; here only the side moments' cotangents
+      heat_combine_bar<D>(g1, f0, g0.U, rho * Hb[0], g1b, f0b, cdump);
+      heat_combine_bar<D>(v2, w2, g0.U, rho * Hb[1], v2b, w2b, cdump);
+      heat_combine_bar<D>(v3, w3, g0.U, rho * Hb[2], v3b, w3b, cdump);
+      gpsi_bar<D>(sd.S, Sb, 1, 0, 0, 0, g1b);
+      gpsi_bar<D>(sd.S, Sb, 0, 0, 0, 0, f0b);
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        int i, j, k;
+        unit(d, i, j, k);
+        (void)mpsia_bar<D>(sd.S, Sb, sd.a[d], 1 + i, j, k, R(1.0), v2b, ab[d]);
+        (void)mpsia_bar<D>(sd.S, Sb, sd.a[d], i, j, k, R(1.0), w2b, ab[d]);
+      }
+      (void)mpsia_bar<D>(sd.S, Sb, sd.A, 1, 0, 0, R(1.0), v3b, Ab);
+      (void)mpsia_bar<D>(sd.S, Sb, sd.A, 0, 0, 0, R(1.0), w3b, Ab);
+    }
+    {
+      // kinetic weighting: W0 += rho <psi>, dW0_d += rho <psi a_d>
+      R g[NC], ob[NC];
+      gpsi<D>(sd.S, 0, 0, 0, 0, g);
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        rb += W0b[q] * g[q];
+        ob[q] = rho * W0b[q];
+      }
+      gpsi_bar<D>(sd.S, Sb, 0, 0, 0, 0, ob);
+#pragma unroll
+      for (int d = 0; d < D; ++d) rb += mpsia_bar<D>(sd.S, Sb, sd.a[d], 0, 0, 0, rho, dW0b[d], ab[d]);
+    }
+    gb.rho += rb;
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
       Wsb[q] = R(0.0);
@@ -846,14 +880,14 @@ TGKS_HD void gp_flux_vjp(const R* Wl, const R* Wr, const R (*dWl)[D + 2], const 
     R b[NC], bb[NC], Wtb[NC];
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
-      b[q] = -(Wt[s][q] * g.irho);
+      b[q] = -(sd.Wt[q] * g.irho);
       bb[q] = R(0.0);
     }
-    micro_solve_bar<D>(g, N, b, A[s], Ab[s], bb, gb[s]);
+    micro_solve_bar<D>(g, N, b, sd.A, Ab, bb, gb);
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
       Wtb[q] = -(bb[q] * g.irho);
-      gb[s].irho -= bb[q] * Wt[s][q];
+      gb.irho -= bb[q] * sd.Wt[q];
     }
     R Eb = R(0.0);
 #pragma unroll
@@ -862,25 +896,26 @@ TGKS_HD void gp_flux_vjp(const R* Wl, const R* Wr, const R (*dWl)[D + 2], const 
       Prim<D, R> pd, pdb;
       prim_dir<D>(g, N, dW[d], pd);
       zero(pdb);
-      euler_jvp_bar<D>(g, Ws[D + 1], d, dW[d], pd, Wtb, dWb[d], pdb, gb[s], Eb);
-      prim_dir_bar<D>(g, N, dW[d], pd, pdb, dWb[d], gb[s]);
+      euler_jvp_bar<D>(g, Ws[D + 1], d, dW[d], pd, Wtb, dWb[d], pdb, gb, Eb);
+      prim_dir_bar<D>(g, N, dW[d], pd, pdb, dWb[d], gb);
       // a_d = M^-1 (dW_d / rho)
 #pragma unroll
       for (int q = 0; q < NC; ++q) {
         b[q] = dW[d][q] * g.irho;
         bb[q] = R(0.0);
       }
-      micro_solve_bar<D>(g, N, b, a[s][d], ab[s][d], bb, gb[s]);
+      micro_solve_bar<D>(g, N, b, sd.a[d], ab[d], bb, gb);
 #pragma unroll
       for (int q = 0; q < NC; ++q) {
         dWb[d][q] += bb[q] * g.irho;
-        gb[s].irho += bb[q] * dW[d][q];
+        gb.irho += bb[q] * dW[d][q];
       }
     }
     Wsb[D + 1] += Eb;
-    side_tables_bar<D>(g, h0s[s], h1s[s], P.K, S[s], Sb[s], gb[s]);
-    make_gas_bar<D>(Ws, N, g, gb[s], Wsb);
+    side_tables_bar<D>(g, sd.m0, sd.m1, P.K, sd.S, Sb, gb);
+    make_gas_bar<D>(Ws, N, g, gb, Wsb);
   }
+#undef XB
 }
 
 }  // namespace tgks

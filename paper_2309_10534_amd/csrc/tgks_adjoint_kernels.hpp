@@ -124,15 +124,18 @@ __global__ __launch_bounds__(128) void adj_face1d_kernel(AdjArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// 2-D face kernel: a block owns TN x TT faces (one thread each), stages the
-// cells and their normal reconstruction in LDS as the forward kernel does,
-// and reverses the two Gauss-point fluxes of its face.
+// 2-D face kernel: a block owns TN x TT faces, stages the cells and their
+// normal reconstruction in LDS as the forward kernel does; lanes 2k and 2k+1
+// share face k: lane m reconstructs side m along the face at both Gauss
+// points (and writes that side's tangential selections), hands the partner
+// its side at the partner's Gauss point, and reverses the flux at Gauss
+// point m.
 // ---------------------------------------------------------------------------
 constexpr int ATN = 8, ATT = 16;
 
 template <int AX, bool NS>
-__global__ __launch_bounds__(ATN* ATT) void adj_face2d_kernel(AdjArgs a) {
-  constexpr int TN = ATN, TT = ATT, NT = TN * TT;
+__global__ __launch_bounds__(2 * ATN * ATT) void adj_face2d_kernel(AdjArgs a) {
+  constexpr int TN = ATN, TT = ATT, NT = 2 * TN * TT;
   constexpr int NC = 4;
   constexpr int LN = TN + 5, LT = TT + 4, RN = TN + 1;
   __shared__ double sW[NC][LT][LN];
@@ -171,33 +174,43 @@ __global__ __launch_bounds__(ATN* ATT) void adj_face2d_kernel(AdjArgs a) {
     sR[c][tl][nr][3] = o[3] * idn;
   }
   __syncthreads();
-  const int fn = tid % TN, ft = tid / TN;
+  const int m = tid & 1;
+  const int fi = tid >> 1;
+  const int fn = fi % TN, ft = fi / TN;
   const int f = f0 + fn, t = t0 + ft;
-  if (f > nN || t >= nT) return;
+  if (f > nN || t >= nT) return;  // both lanes of a face leave together
   const int perm[NC] = {0, 1 + AX, 1 + TA, 3};
   const long long nf = face_count(g, AX);
   const long long fidx = AX == 0 ? (long long)t * (g.n[0] + 1) + f : (long long)f * g.n[0] + t;
   const double idt = 1.0 / g.dx[TA];
-  // reconstruction along the face, both sides, both Gauss points
-  double vW[2][NC][2], dW[2][NC][2], vN[2][NC][2];
-#pragma unroll
-  for (int s = 0; s < 2; ++s) {
-    const int nr = s == 0 ? fn : fn + 1;
-    const int vo = s == 0 ? 2 : 0;
+  // own side m along the face; the partner's side at this Gauss point
+  double Wg[2][NC], Dg[2][2][NC];  // [side][q], [side][axis n/t][q]
+  {
+    const int nr = m == 0 ? fn : fn + 1;
+    const int vo = m == 0 ? 2 : 0;
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
       const int c = perm[q];
-      double Qw[5], Qn[5], dn[2];
+      double Qw[5], Qn[5], v[2], dv[2], vn[2], dn[2];
 #pragma unroll
       for (int r = 0; r < 5; ++r) {
         Qw[r] = sR[c][ft + r][nr][vo];
         Qn[r] = sR[c][ft + r][nr][vo + 1];
       }
       const unsigned fw = teno_flag(Qw, a.tt), fq = teno_flag(Qn, a.tt);
-      a.TF[((long long)(s * 2 + 0) * NC + c) * nf + fidx] = (uint8_t)fw;
-      a.TF[((long long)(s * 2 + 1) * NC + c) * nf + fidx] = (uint8_t)fq;
-      teno_gauss(Qw, fw, vW[s][q], dW[s][q]);
-      teno_gauss(Qn, fq, vN[s][q], dn);
+      a.TF[((long long)(m * 2 + 0) * NC + c) * nf + fidx] = (uint8_t)fw;
+      a.TF[((long long)(m * 2 + 1) * NC + c) * nf + fidx] = (uint8_t)fq;
+      teno_gauss(Qw, fw, v, dv);
+      teno_gauss(Qn, fq, vn, dn);
+      const double sv = m ? v[0] : v[1], sd = m ? dv[0] : dv[1], sn = m ? vn[0] : vn[1];
+      const double rv = __shfl_xor(sv, 1), rd = __shfl_xor(sd, 1), rn = __shfl_xor(sn, 1);
+      const double ov = m ? v[1] : v[0], od = m ? dv[1] : dv[0], on = m ? vn[1] : vn[0];
+      Wg[0][q] = m == 0 ? ov : rv;
+      Wg[1][q] = m == 0 ? rv : ov;
+      Dg[0][1][q] = (m == 0 ? od : rd) * idt;
+      Dg[1][1][q] = (m == 0 ? rd : od) * idt;
+      Dg[0][0][q] = m == 0 ? on : rn;
+      Dg[1][0][q] = m == 0 ? rn : on;
     }
   }
   // face cotangents (global components), Gauss weight 1/2
@@ -214,37 +227,25 @@ __global__ __launch_bounds__(ATN* ATT) void adj_face2d_kernel(AdjArgs a) {
       Fhb[q] = 0.5 * y;
     }
   }
-  double* GB = a.GB;
-#pragma unroll 1
-  for (int m = 0; m < 2; ++m) {
-    double Wg[2][NC], Dg[2][2][NC];
+  double Wb[2][NC], Db[2][2][NC];
+  if (dt > 0.0) {
+    gp_flux_vjp<2, NS, double>(Wg[0], Wg[1], Dg[0], Dg[1], a.fc, dt, Fdtb, Fhb, Wb[0], Wb[1], Db[0], Db[1]);
+  } else {
 #pragma unroll
     for (int s = 0; s < 2; ++s)
 #pragma unroll
-      for (int q = 0; q < NC; ++q) {
-        Wg[s][q] = vW[s][q][m];
-        Dg[s][0][q] = vN[s][q][m];
-        Dg[s][1][q] = dW[s][q][m] * idt;
-      }
-    double Wb[2][NC], Db[2][2][NC];
-    if (dt > 0.0) {
-      gp_flux_vjp<2, NS, double>(Wg[0], Wg[1], Dg[0], Dg[1], a.fc, dt, Fdtb, Fhb, Wb[0], Wb[1], Db[0], Db[1]);
-    } else {
-#pragma unroll
-      for (int s = 0; s < 2; ++s)
-#pragma unroll
-        for (int q = 0; q < NC; ++q) Wb[s][q] = Db[s][0][q] = Db[s][1][q] = 0.0;
-    }
-#pragma unroll
-    for (int s = 0; s < 2; ++s)
-#pragma unroll
-      for (int q = 0; q < NC; ++q) {
-        const long long base = ((long long)(s * NC + perm[q]) * 6) * nf + fidx;
-        GB[base + (long long)(0 + m) * nf] = Wb[s][q];
-        GB[base + (long long)(2 + m) * nf] = Db[s][1][q] * idt;
-        GB[base + (long long)(4 + m) * nf] = Db[s][0][q];
-      }
+      for (int q = 0; q < NC; ++q) Wb[s][q] = Db[s][0][q] = Db[s][1][q] = 0.0;
   }
+  double* GB = a.GB;
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      const long long base = ((long long)(s * NC + perm[q]) * 6) * nf + fidx;
+      GB[base + (long long)(0 + m) * nf] = Wb[s][q];
+      GB[base + (long long)(2 + m) * nf] = Db[s][1][q] * idt;
+      GB[base + (long long)(4 + m) * nf] = Db[s][0][q];
+    }
 }
 
 // ---------------------------------------------------------------------------
