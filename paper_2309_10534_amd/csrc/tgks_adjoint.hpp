@@ -12,6 +12,20 @@
 
 namespace tgks {
 
+// An opaque copy: the compiler cannot see that the result equals the input,
+// so a recomputation from it is not merged with the earlier one (whose
+// results would otherwise stay live in registers across the reverse pass).
+template <class R>
+TGKS_HD R opaque(R x) {
+  return x;
+}
+TGKS_HD double opaque(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile("" : "+v"(x));
+#endif
+  return x;
+}
+
 template <int D, class R>
 struct GasBar {
   R rho, irho, U[D], lam, h;
@@ -459,6 +473,17 @@ struct Side {
   R a[D][D + 2], A[D + 2], Wt[D + 2];
 };
 
+// opaque copies of one side's state and slopes (see opaque)
+template <int D, class R>
+TGKS_HD void opaque_side(const R* W, const R (*dW)[D + 2], R* Wo, R (*dWo)[D + 2]) {
+#pragma unroll
+  for (int q = 0; q < D + 2; ++q) {
+    Wo[q] = opaque(W[q]);
+#pragma unroll
+    for (int d = 0; d < D; ++d) dWo[d][q] = opaque(dW[d][q]);
+  }
+}
+
 template <int D, class R>
 TGKS_HD void side_forward(const R* Ws, const R (*dW)[D + 2], double sgn, const FluxCfg& P, Side<D, R>& sd) {
   constexpr int NC = D + 2;
@@ -602,8 +627,10 @@ TGKS_HD void gp_flux_vjp(const R* Wl, const R* Wr, const R (*dWl)[D + 2], const 
     Gq[1] = heat_combine<D>(T3, W0t, g0.U);
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
+      R Ws[NC], dW[D][NC];
+      opaque_side<D>(s == 0 ? Wl : Wr, s == 0 ? dWl : dWr, Ws, dW);
       Side<D, R> sd;
-      side_forward<D>(s == 0 ? Wl : Wr, s == 0 ? dWl : dWr, s == 0 ? 1.0 : -1.0, P, sd);
+      side_forward<D>(Ws, dW, s == 0 ? 1.0 : -1.0, P, sd);
       R g1[NC], v2[NC], v3[NC], f0[NC], w2[NC], w3[NC];
       side_moments<D, true>(sd, g1, v2, v3, f0, w2, w3);
       Hs[0] += sd.g.rho * heat_combine<D>(g1, f0, g0.U);
@@ -707,8 +734,10 @@ TGKS_HD void gp_flux_vjp(const R* Wl, const R* Wr, const R (*dWl)[D + 2], const 
   if (NS) {
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
+      R Ws[NC], dW[D][NC];
+      opaque_side<D>(s == 0 ? Wl : Wr, s == 0 ? dWl : dWr, Ws, dW);
       Side<D, R> sd;
-      side_forward<D>(s == 0 ? Wl : Wr, s == 0 ? dWl : dWr, s == 0 ? 1.0 : -1.0, P, sd);
+      side_forward<D>(Ws, dW, s == 0 ? 1.0 : -1.0, P, sd);
       R g1[NC], v2[NC], v3[NC], f0[NC], w2[NC], w3[NC], t1[NC], t0[NC];
       side_moments<D, true>(sd, g1, v2, v3, f0, w2, w3);
 #pragma unroll
@@ -784,8 +813,8 @@ TGKS_HD void gp_flux_vjp(const R* Wl, const R* Wr, const R (*dWl)[D + 2], const 
   // ---- reverse: one pass per side ----
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
-    const R* Ws = s == 0 ? Wl : Wr;
-    const R(*dW)[NC] = s == 0 ? dWl : dWr;
+    R Ws[NC], dW[D][NC];
+    opaque_side<D>(s == 0 ? Wl : Wr, s == 0 ? dWl : dWr, Ws, dW);
     R* Wsb = s == 0 ? Wlb : Wrb;
     R(*dWb)[NC] = s == 0 ? dWlb : dWrb;
     Side<D, R> sd;
