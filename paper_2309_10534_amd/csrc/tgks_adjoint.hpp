@@ -12,20 +12,6 @@
 
 namespace tgks {
 
-// An opaque copy: the compiler cannot see that the result equals the input,
-// so a recomputation from it is not merged with the earlier one (whose
-// results would otherwise stay live in registers across the reverse pass).
-template <class R>
-TGKS_HD R opaque(R x) {
-  return x;
-}
-TGKS_HD double opaque(double x) {
-#if defined(__HIP_DEVICE_COMPILE__)
-  asm volatile("" : "+v"(x));
-#endif
-  return x;
-}
-
 template <int D, class R>
 struct GasBar {
   R rho, irho, U[D], lam, h;

@@ -214,6 +214,21 @@ TGKS_HD double rsqrt_(double x) {
 #endif
 }
 
+// An opaque copy: the compiler cannot see that the result equals the input,
+// so a recomputation from it is not merged with an earlier identical one
+// (whose results would otherwise stay live in registers until the later
+// use).  The value is unchanged.
+template <class R>
+TGKS_HD R opaque(R x) {
+  return x;
+}
+TGKS_HD double opaque(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile("" : "+v"(x));
+#endif
+  return x;
+}
+
 // (rho, 1/rho, U, lambda, h) of W with one division:
 // re = rho (rho E) - |rho U|^2 / 2 = rho^2 e_int, inv = 1 / (rho re)
 template <int D, class R>
