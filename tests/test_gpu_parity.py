@@ -295,3 +295,66 @@ def test_invalid_arguments(torch_dev):
             tgks.tgks_step(ctx, W[:29], torch.empty_like(W), torch.zeros(1, dtype=torch.float64, device="cuda"))
     finally:
         tgks.tgks_destroy(ctx)
+
+
+@pytest.mark.parametrize("kind", ["rho", "p", "nan"])
+def test_fault_injection_2d(orc, torch_dev, kind):
+    """A single non-physical cell (rho < 0, p < 0 or a NaN) in a 2-D field:
+    the CFL step is NaN and the failure count of one step equals the
+    oracle's."""
+    n = 37
+    W, dx, _ = I.quadrant_riemann(n, seed=1)
+    W = W.copy()
+    rho, vel, p = I.primitive(W)
+    i, j = 17, 11
+    if kind == "rho":
+        W[0, j, i] = -0.2
+    elif kind == "p":
+        W[3, j, i] = 0.5 * (W[1, j, i] ** 2 + W[2, j, i] ** 2) / W[0, j, i] - 0.1
+    else:
+        W[1, j, i] = np.nan
+    pr = problem([n, n], [dx, dx])
+    gp = GpuProblem(pr)
+    try:
+        print(f"[parity] fault injection {kind}", flush=True)
+        # a non-physical cell has no CFL limit: the step is NaN, and a run
+        # stops there
+        assert np.isnan(gp.cfl_dt(W, 0.5))
+        dt = 1e-3
+        _, _, _, badg = gp.step(W, dt, flags=False)
+    finally:
+        gp.close()
+    _, _, _, bado = orc.step(orc_params(orc, pr), W, dt)
+    assert badg == bado and badg > 0
+
+
+def test_tile_shapes_bitwise(orc, torch_dev):
+    """Every 2-D tile shape gives the same step, W* and stencil flags, bit for
+    bit, on a ragged grid with all boundary kinds."""
+    from paper_2309_10534_amd import tgks
+    nx, ny = 45, 38
+    rng = np.random.default_rng(3)
+    x = (np.arange(nx) + 0.5) / nx
+    y = (np.arange(ny) + 0.5) / ny
+    X, Y = np.meshgrid(x, y)
+    rho = 1 + 0.3 * np.sin(2 * np.pi * X) * np.cos(2 * np.pi * Y) + 0.5 * (X + 0.7 * Y > 0.8)
+    u = 0.3 * np.cos(2 * np.pi * Y)
+    v = -0.2 * np.sin(2 * np.pi * X)
+    p = 1 + 0.2 * np.cos(2 * np.pi * (X + Y))
+    W = I.conservative(rho, [u, v], p)
+    pr = problem([nx, ny], [1 / nx, 1 / ny], bc=[("periodic", "periodic"), ("reflective", "transmissive")])
+    gp = GpuProblem(pr)
+    try:
+        dt = gp.cfl_dt(W, 0.5)
+        outs = []
+        for tile in range(3):
+            tgks.tgks_set_tile(gp.ctx, tile)
+            outs.append(gp.step(W, dt))
+    finally:
+        gp.close()
+    for o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1])
+        assert np.array_equal(o[2], outs[0][2]) and o[3] == outs[0][3]
+    Wo, fo, _, _ = orc.step(orc_params(orc, pr), W, dt, want_flags=True)
+    assert_close(outs[0][0], Wo)
+    assert np.array_equal(outs[0][2], fo)
