@@ -68,7 +68,8 @@ __global__ __launch_bounds__(2 * tile2_tn(TILE) * tile2_tt(TILE), 2) void batch_
   const BatchInst& I = b.inst[w.x];
   const StageArgs a = batch_stage(b, I, w.x, AX);
   const int nt = I.ntile[AX];
-  face2d_tile<AX, STAGE, NS, false, TILE>(a, w.y % nt, w.y / nt);
+  __shared__ double lds[tile2_lds(TILE)];
+  face2d_tile<AX, STAGE, NS, false, TILE>(a, w.y % nt, w.y / nt, lds);
 }
 
 template <int D, int STAGE, bool CFL>

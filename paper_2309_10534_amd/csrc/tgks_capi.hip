@@ -15,6 +15,24 @@ using namespace tgks;
 // face fluxes of one stage in every direction
 int launch_faces(tgks_ctx* c, const double* W, const double* dt, int stage, uint8_t* flags) {
   const int D = c->g.D;
+  if (D == 2) {
+    // both directions in one launch (timed as kind 0)
+    const bool fl = flags != nullptr && stage == 1;
+    StageArgs a[2];
+    for (int ax = 0; ax < 2; ++ax) {
+      a[ax] = stage_args(c, W, ax, dt);
+      if (fl) {
+        a[ax].nflags = flags;
+        long long off = (long long)D * c->nc * c->ncell;
+        for (int d = 0; d < ax; ++d) off += 4LL * c->nc * c->nface[d];
+        a[ax].tflags = flags + off;
+      }
+    }
+    Timer tm(c, 0);
+    launch_face2d_xy_any(c, a[0], a[1], stage, fl);
+    HIPCHK(hipGetLastError());
+    return TGKS_OK;
+  }
   for (int ax = 0; ax < D; ++ax) {
     StageArgs a = stage_args(c, W, ax, dt);
     const bool fl = flags != nullptr && stage == 1;

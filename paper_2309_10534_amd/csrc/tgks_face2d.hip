@@ -32,6 +32,44 @@ static void launch_face2d(tgks_ctx* c, const StageArgs& a, int ax, int stage, bo
 #undef F2
 }
 
+// both directions of one stage in one launch
+template <int TILE>
+static void launch_face2d_xy(tgks_ctx* c, const StageArgs& ax, const StageArgs& ay, int stage, bool fl) {
+  constexpr int TN = tile2_tn(TILE), TT = tile2_tt(TILE);
+  const int nx = c->g.n[0], ny = c->g.n[1];
+  const long long nb = (long long)((nx + 1 + TN - 1) / TN) * ((ny + TT - 1) / TT) +
+                       (long long)((ny + 1 + TN - 1) / TN) * ((nx + TT - 1) / TT);
+  const dim3 grid((unsigned)nb), block(2 * TN * TT);
+#define LXY(kern) hipLaunchKernelGGL(kern, grid, block, 0, c->stream, ax, ay)
+  if (stage == 1) {
+    if (fl) {
+      if (c->ns) LXY((face2d_xy_kernel<1, true, true, TILE>));
+      else LXY((face2d_xy_kernel<1, false, true, TILE>));
+    } else {
+      if (c->ns) LXY((face2d_xy_kernel<1, true, false, TILE>));
+      else LXY((face2d_xy_kernel<1, false, false, TILE>));
+    }
+  } else {
+    if (c->ns) LXY((face2d_xy_kernel<2, true, false, TILE>));
+    else LXY((face2d_xy_kernel<2, false, false, TILE>));
+  }
+#undef LXY
+}
+
+int launch_face2d_xy_any(tgks_ctx* c, const StageArgs& ax, const StageArgs& ay, int stage, bool fl) {
+  switch (c->tile2) {
+    case 1:
+      launch_face2d_xy<1>(c, ax, ay, stage, fl);
+      break;
+    case 2:
+      launch_face2d_xy<2>(c, ax, ay, stage, fl);
+      break;
+    default:
+      launch_face2d_xy<0>(c, ax, ay, stage, fl);
+  }
+  return TGKS_OK;
+}
+
 int launch_face2d_any(tgks_ctx* c, const StageArgs& a, int ax, int stage, bool fl) {
   const int nN = c->g.n[ax], nT = c->g.n[1 - ax];
   switch (c->tile2) {

@@ -143,6 +143,7 @@ inline StageArgs stage_args(tgks_ctx* c, const double* W, int ax, const double* 
 
 // 2-D face kernels of one direction and stage (tgks_face2d.hip)
 int launch_face2d_any(tgks_ctx* c, const StageArgs& a, int ax, int stage, bool fl);
+int launch_face2d_xy_any(tgks_ctx* c, const StageArgs& ax, const StageArgs& ay, int stage, bool fl);
 
 // forward pieces of one step (tgks_capi.hip)
 int launch_faces(tgks_ctx* c, const double* W, const double* dt, int stage, uint8_t* flags);

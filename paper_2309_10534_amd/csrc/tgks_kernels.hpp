@@ -129,14 +129,21 @@ constexpr int NTILE2 = 3;
 __host__ __device__ constexpr int tile2_tn(int k) { return k == 0 ? 16 : (k == 1 ? 16 : 8); }
 __host__ __device__ constexpr int tile2_tt(int k) { return k == 0 ? 8 : (k == 1 ? 16 : 16); }
 
-// (bx, by): tile index along the normal and the tangential axis
+// LDS doubles of one 2-D face tile: the staged cells and their normal
+// reconstruction
+__host__ __device__ constexpr int tile2_lds(int k) {
+  return 4 * (tile2_tt(k) + 4) * (tile2_tn(k) + 5) + 4 * (tile2_tt(k) + 4) * (tile2_tn(k) + 1) * 4;
+}
+
+// (bx, by): tile index along the normal and the tangential axis; lds: the
+// block's tile2_lds(TILE) doubles of shared memory
 template <int AX, int STAGE, bool NS, bool FLAGS, int TILE>
-__device__ __forceinline__ void face2d_tile(const StageArgs& a, int bx, int by) {
+__device__ __forceinline__ void face2d_tile(const StageArgs& a, int bx, int by, double* lds) {
   constexpr int TN = tile2_tn(TILE), TT = tile2_tt(TILE), NT = 2 * TN * TT;
   constexpr int NC = 4;
   constexpr int LN = TN + 5, LT = TT + 4, RN = TN + 1;
-  __shared__ double sW[NC][LT][LN];
-  __shared__ double sR[NC][LT][RN][4];
+  double(*sW)[LT][LN] = reinterpret_cast<double(*)[LT][LN]>(lds);
+  double(*sR)[LT][RN][4] = reinterpret_cast<double(*)[LT][RN][4]>(lds + NC * LT * LN);
   const double dt = *a.dt;
   if (!(dt > 0.0)) return;
   const Geom& g = a.g;
@@ -258,7 +265,27 @@ __device__ __forceinline__ void face2d_tile(const StageArgs& a, int bx, int by) 
 
 template <int AX, int STAGE, bool NS, bool FLAGS, int TILE>
 __global__ __launch_bounds__(2 * tile2_tn(TILE) * tile2_tt(TILE), 2) void face2d_kernel(StageArgs a) {
-  face2d_tile<AX, STAGE, NS, FLAGS, TILE>(a, blockIdx.x, blockIdx.y);
+  __shared__ double lds[tile2_lds(TILE)];
+  face2d_tile<AX, STAGE, NS, FLAGS, TILE>(a, blockIdx.x, blockIdx.y, lds);
+}
+
+// Both directions in one launch: the first blocks take the x-face tiles,
+// the rest the y-face tiles (one shared LDS tile), so that neither
+// direction waits for the other's tail.
+template <int STAGE, bool NS, bool FLAGS, int TILE>
+__global__ __launch_bounds__(2 * tile2_tn(TILE) * tile2_tt(TILE), 2) void face2d_xy_kernel(StageArgs ax,
+                                                                                           StageArgs ay) {
+  constexpr int TN = tile2_tn(TILE);
+  __shared__ double lds[tile2_lds(TILE)];
+  const int nbx = (ax.g.n[0] + 1 + TN - 1) / TN;          // x faces: tiles along x
+  const int nx = nbx * ((ax.g.n[1] + tile2_tt(TILE) - 1) / tile2_tt(TILE));
+  const int b = blockIdx.x;
+  if (b < nx) {
+    face2d_tile<0, STAGE, NS, FLAGS, TILE>(ax, b % nbx, b / nbx, lds);
+  } else {
+    const int nby = (ay.g.n[1] + 1 + TN - 1) / TN;        // y faces: tiles along y
+    face2d_tile<1, STAGE, NS, FLAGS, TILE>(ay, (b - nx) % nby, (b - nx) / nby, lds);
+  }
 }
 
 // ---------------------------------------------------------------------------
