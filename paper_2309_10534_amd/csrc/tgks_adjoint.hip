@@ -23,17 +23,19 @@ static int ensure_adjoint_buffers(tgks_ctx* c) {
     nf = c->nface[ax] > nf ? c->nface[ax] : nf;
   }
   bool ok = hipMalloc(&c->aNRB, (size_t)c->nc * 4 * ne * sizeof(double)) == hipSuccess &&
+            hipMalloc(&c->aNF, (size_t)c->nc * ne) == hipSuccess &&
             hipMalloc(&c->aWsb, (size_t)c->nc * c->ncell * sizeof(double)) == hipSuccess;
   if (ok && g.D == 2)
     ok = hipMalloc(&c->aGB, (size_t)2 * c->nc * 6 * nf * sizeof(double)) == hipSuccess &&
          hipMalloc(&c->aTF, (size_t)2 * 2 * c->nc * nf) == hipSuccess;
   if (!ok) {
     (void)hipFree(c->aNRB);
+    (void)hipFree(c->aNF);
     (void)hipFree(c->aWsb);
     (void)hipFree(c->aGB);
     (void)hipFree(c->aTF);
     c->aNRB = c->aWsb = c->aGB = nullptr;
-    c->aTF = nullptr;
+    c->aTF = c->aNF = nullptr;
     return TGKS_EHIP;
   }
   return TGKS_OK;
@@ -57,6 +59,7 @@ static AdjArgs adj_args(tgks_ctx* c, const double* W, const double* X, const dou
   a.GB = c->aGB;
   a.TF = c->aTF;
   a.NRB = c->aNRB;
+  a.NF = c->aNF;
   a.base0 = nullptr;
   a.base1 = nullptr;
   a.out = nullptr;
@@ -80,6 +83,8 @@ static int reverse_direction(tgks_ctx* c, AdjArgs a, int ax, const double* base0
       ALAUNCH((adj_face1d_kernel<true>), grid, dim3(128), a);
     else
       ALAUNCH((adj_face1d_kernel<false>), grid, dim3(128), a);
+    const dim3 gf((unsigned)(((g.n[0] + 2) * nc + 255) / 256));
+    ALAUNCH((adj_nflags_kernel<1, 0>), gf, dim3(256), a);
     const dim3 gn((unsigned)((g.ncell * nc + 255) / 256));
     ALAUNCH((adj_normal_kernel<1, 0>), gn, dim3(256), a);
   } else {
@@ -94,6 +99,7 @@ static int reverse_direction(tgks_ctx* c, AdjArgs a, int ax, const double* base0
       else
         ALAUNCH((adj_face2d_kernel<0, false>), grid, dim3(2 * ATN * ATT), a);
       ALAUNCH((adj_tan2d_kernel<0>), gt, dim3(256), a);
+      ALAUNCH((adj_nflags_kernel<2, 0>), gt, dim3(256), a);
       ALAUNCH((adj_normal_kernel<2, 0>), gn, dim3(256), a);
     } else {
       if (c->ns)
@@ -101,6 +107,7 @@ static int reverse_direction(tgks_ctx* c, AdjArgs a, int ax, const double* base0
       else
         ALAUNCH((adj_face2d_kernel<1, false>), grid, dim3(2 * ATN * ATT), a);
       ALAUNCH((adj_tan2d_kernel<1>), gt, dim3(256), a);
+      ALAUNCH((adj_nflags_kernel<2, 1>), gt, dim3(256), a);
       ALAUNCH((adj_normal_kernel<2, 1>), gn, dim3(256), a);
     }
   }

@@ -37,6 +37,7 @@ struct AdjArgs {
   double* GB;        // 2-D: Gauss-point cotangents [side][c][6][faces]
   uint8_t* TF;       // 2-D: tangential flags [side][W, W_n][c][faces]
   double* NRB;       // normal-reconstruction cotangents [c][4][ext cells]
+  uint8_t* NF;       // normal selections of the extended cells [c][ext cells]
   const double* base0;
   const double* base1;
   double* out;
@@ -298,6 +299,36 @@ __global__ __launch_bounds__(256) void adj_tan2d_kernel(AdjArgs a) {
   for (int k = 0; k < 4; ++k) B[k * ne] = o[k];
 }
 
+// Normal selections of every extended cell (AX index in [-1, n_AX], the
+// tangential index in [-2, n_T + 2) in 2-D), one thread per cell and
+// component: the same selection as the forward reconstruction.
+template <int D, int AX>
+__global__ __launch_bounds__(256) void adj_nflags_kernel(AdjArgs a) {
+  constexpr int NC = D + 2;
+  const Geom& g = a.g;
+  const long long ne = ext_count(g, AX);
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= ne * NC) return;
+  const int c = (int)(id / ne);
+  const long long e = id % ne;
+  const int nN = g.n[AX];
+  int i, r = 0;
+  if (D == 1) {
+    i = (int)e - 1;
+  } else {
+    const int nT = g.n[1 - AX];
+    i = AX == 0 ? (int)(e % (nN + 2)) - 1 : (int)(e / (nT + 4)) - 1;
+    r = AX == 0 ? (int)(e / (nN + 2)) - 2 : (int)(e % (nT + 4)) - 2;
+  }
+  double Q[5];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    const int pa = i - 2 + q;
+    Q[q] = D == 1 ? load_cell(g, a.W, c, pa, 0, 0) : load_cell(g, a.W, c, AX == 0 ? pa : r, AX == 0 ? r : pa, 0);
+  }
+  a.NF[(long long)c * ne + e] = (uint8_t)teno_flag(Q, a.tn);
+}
+
 // preimages of interior index x under the boundary index map among the
 // candidates x and the ghost indices -G..-1, n..n+G-1; returns the count
 template <int G>
@@ -353,18 +384,12 @@ __global__ __launch_bounds__(256) void adj_normal_kernel(AdjArgs a) {
       for (int k = 0; k < 5; ++k) {
         const int i = ip + 2 - k;  // cell whose normal stencil slot k is ip
         if (i < -1 || i > nN) continue;
-        double Q[5];
-#pragma unroll
-        for (int q = 0; q < 5; ++q) {
-          const int pa = i - 2 + q;
-          Q[q] = D == 1 ? load_cell(g, a.W, c, pa, 0, 0)
-                        : load_cell(g, a.W, c, AX == 0 ? pa : r, AX == 0 ? r : pa, 0);
-        }
-        const unsigned fl = teno_flag(Q, a.tn);
+        const long long ei = ext_index(g, AX, i, r);
+        const unsigned fl = a.NF[(long long)c * ne + ei];
         double E[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, o[4];
         E[k] = 1.0;
         teno_face(E, fl, o);
-        const double* B = a.NRB + (long long)c * 4 * ne + ext_index(g, AX, i, r);
+        const double* B = a.NRB + (long long)c * 4 * ne + ei;
         s += (o[0] * B[0] + o[1] * B[ne]) + (o[2] * B[2 * ne] + o[3] * B[3 * ne]);
       }
       acc += neg ? -s : s;

@@ -199,6 +199,7 @@ static void free_ctx(tgks_ctx* c) {
   (void)hipFree(c->aGB);
   (void)hipFree(c->aTF);
   (void)hipFree(c->aNRB);
+  (void)hipFree(c->aNF);
   (void)hipFree(c->aWsb);
   for (int k = 0; k < NKIND; ++k)
     for (auto& e : c->ev[k]) {

@@ -53,6 +53,7 @@ struct tgks_ctx {
   double* aGB = nullptr;
   uint8_t* aTF = nullptr;
   double* aNRB = nullptr;
+  uint8_t* aNF = nullptr;
   double* aWsb = nullptr;
   // timing
   bool timing = false;
