@@ -342,7 +342,7 @@ __global__ __launch_bounds__(256) void recon3d_kernel(StageArgs a) {
 constexpr int B3_1 = 4, B3_2 = 16;
 
 template <int AX, int STAGE, bool NS>
-__global__ __launch_bounds__(4 * B3_1 * B3_2) void face3d_kernel(StageArgs a) {
+__global__ __launch_bounds__(4 * B3_1 * B3_2, 2) void face3d_kernel(StageArgs a) {
   constexpr int NC = 5, B1 = B3_1, B2 = B3_2, NT = 4 * B1 * B2;
   constexpr int L1 = B1 + 4, L2 = B2 + 4;
   constexpr int T1 = (AX + 1) % 3, T2 = (AX + 2) % 3;
