@@ -343,7 +343,7 @@ def adjoint(n=512, steps=200, every=20, fd_dirs=range(10, 15)):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+        print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1 "
                           "(the multi-GPU decomposition is a design, not measured)"}))
         sys.exit(2)
     import numpy as np
