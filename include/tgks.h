@@ -133,7 +133,8 @@ int tgks_set_tile(tgks_ctx* ctx, int32_t tile);
 int tgks_tune(tgks_ctx* ctx, const double* W, int32_t steps, int32_t* chosen, float* ms_per_variant);
 
 /* Failure count since creation or the last tgks_reset_status (synchronises
- * the stream). */
+ * the stream).  tgks_reset_status enqueues a small kernel (no memset), so
+ * it may be captured into a graph. */
 int tgks_status(tgks_ctx* ctx, int64_t* failures);
 int tgks_reset_status(tgks_ctx* ctx);
 

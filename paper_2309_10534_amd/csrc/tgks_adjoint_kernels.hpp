@@ -135,7 +135,7 @@ __global__ __launch_bounds__(128) void adj_face1d_kernel(AdjArgs a) {
 constexpr int ATN = 8, ATT = 16;
 
 template <int AX, bool NS>
-__global__ __launch_bounds__(2 * ATN * ATT, 2) void adj_face2d_kernel(AdjArgs a) {
+__global__ __launch_bounds__(2 * ATN * ATT) void adj_face2d_kernel(AdjArgs a) {
   constexpr int TN = ATN, TT = ATT, NT = 2 * TN * TT;
   constexpr int NC = 4;
   constexpr int LN = TN + 5, LT = TT + 4, RN = TN + 1;

@@ -307,7 +307,11 @@ int tgks_batch_create(const tgks_params* p, int32_t n_inst, void* stream, tgks_b
     b->tile2 = -1;
     ok = tgks_batch_set_tile(b, 0) == TGKS_OK;
   }
-  if (ok) ok = hipMemsetAsync(b->fail, 0, (size_t)n_inst * sizeof(unsigned long long), b->stream) == hipSuccess;
+  if (ok) {
+    hipLaunchKernelGGL(zero_counters_kernel, dim3((unsigned)((n_inst + 255) / 256)), dim3(256), 0, b->stream, b->fail,
+                       n_inst);
+    ok = hipGetLastError() == hipSuccess;
+  }
   if (ok) ok = hipStreamSynchronize(b->stream) == hipSuccess;
   if (!ok) {
     free_batch(b);
@@ -405,7 +409,9 @@ int tgks_batch_steps(tgks_batch* b, int64_t* steps) {
 
 int tgks_batch_reset_status(tgks_batch* b) {
   if (!b) return TGKS_EINVAL;
-  HIPCHK(hipMemsetAsync(b->fail, 0, (size_t)b->ninst * sizeof(unsigned long long), b->stream));
+  hipLaunchKernelGGL(zero_counters_kernel, dim3((unsigned)((b->ninst + 255) / 256)), dim3(256), 0, b->stream, b->fail,
+                     b->ninst);
+  HIPCHK(hipGetLastError());
   return TGKS_OK;
 }
 

@@ -417,7 +417,10 @@ int tgks_create(const tgks_params* p, void* stream, tgks_ctx** out) {
     ok = hipMalloc(&c->partial, (size_t)c->nblk * sizeof(double)) == hipSuccess &&
          hipMalloc(&c->clock, 4 * sizeof(double)) == hipSuccess &&
          hipMalloc(&c->fail, sizeof(unsigned long long)) == hipSuccess;
-  if (ok) ok = hipMemsetAsync(c->fail, 0, sizeof(unsigned long long), c->stream) == hipSuccess;
+  if (ok) {
+    hipLaunchKernelGGL(zero_counters_kernel, dim3(1), dim3(256), 0, c->stream, c->fail, 1);
+    ok = hipGetLastError() == hipSuccess;
+  }
   if (ok) ok = hipStreamSynchronize(c->stream) == hipSuccess;
   if (!ok) {
     free_ctx(c);
@@ -552,7 +555,8 @@ int tgks_status(tgks_ctx* c, int64_t* failures) {
 
 int tgks_reset_status(tgks_ctx* c) {
   if (!c) return TGKS_EINVAL;
-  HIPCHK(hipMemsetAsync(c->fail, 0, sizeof(unsigned long long), c->stream));
+  hipLaunchKernelGGL(zero_counters_kernel, dim3(1), dim3(256), 0, c->stream, c->fail, 1);
+  HIPCHK(hipGetLastError());
   return TGKS_OK;
 }
 

@@ -660,6 +660,13 @@ static __global__ __launch_bounds__(256) void cfl_finalize_kernel(const double* 
   finalize_body(partial, nblk, cfl, t_in, t_end, clock, dt_out, mode);
 }
 
+// clears n counters (a kernel rather than a memset, so that a caller may
+// capture it into a graph)
+static __global__ __launch_bounds__(256) void zero_counters_kernel(unsigned long long* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
 static __global__ void set_clock_kernel(double* clock, double t, double dt) {
   clock[0] = t;
   clock[1] = dt;
