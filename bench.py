@@ -29,16 +29,15 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector peak (256 CU x 2.4 GHz x 128 flop/
 
 # HBM traffic of the 2-D face kernel on this workload from two rocprofv3
 # --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch, mean of the stage-1
-# and stage-2 launches of each direction, tile shape 2), each scaled by what
-# the counter reads for a 32 MiB device-to-device copy (FETCH_SIZE 16401 KiB:
-# factor 32768/16401; WRITE_SIZE 32768 KiB: factor 1).  Valid only for the
-# kernel sources they were taken with (sha256 prefix of the three files
-# below); the bench reports null traffic otherwise.
+# and stage-2 launches of the merged x/y face kernel, tile shape 2), each
+# scaled by what the counter reads for a 32 MiB device-to-device copy
+# (FETCH_SIZE 16398 KiB: factor 32768/16398; WRITE_SIZE 32768 KiB: factor 1).
+# Valid only for the kernel sources they were taken with (sha256 prefix of
+# the three files below); the bench reports null traffic otherwise.
 TRAFFIC_SOURCES = ("paper_2309_10534_amd/csrc/tgks_device.hpp", "paper_2309_10534_amd/csrc/tgks_kernels.hpp",
                    "paper_2309_10534_amd/csrc/tgks_face2d.hip")
-TRAFFIC = {"sha": "a54083e9eb8b5955", "tile": 2, "fetch_factor": 32768.0 / 16401.4, "write_factor": 1.0,
-           "face_x": {"fetch_kib": 69599.1, "write_kib": 67646.0},
-           "face_y": {"fetch_kib": 59135.1, "write_kib": 49200.0}}
+TRAFFIC = {"sha": "bb30be67847aeef2", "tile": 2, "fetch_factor": 32768.0 / 16397.9, "write_factor": 1.0,
+           "face_xy": {"fetch_kib": 128507.8, "write_kib": 116854.8}}
 
 
 def measured_traffic(kernel, tile):
