@@ -69,6 +69,7 @@ def parse():
     ap.add_argument("--batch-instances", type=int, default=256)
     ap.add_argument("--no-adjoint", action="store_true", help="skip the reverse-mode vortex workload")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3-D Taylor-Green workload")
+    ap.add_argument("--tgv-steps", type=int, default=200, help="timed steps of the 3-D Taylor-Green workload")
     ap.add_argument("--no-sod", action="store_true", help="skip the 1-D Sod latency workload")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     return ap.parse_args()
@@ -438,7 +439,7 @@ def main():
     if not args.no_adjoint:
         out["adjoint"] = adjoint()
     if not args.no_3d:
-        out["tgv3d"] = tgv3d()
+        out["tgv3d"] = tgv3d(steps=args.tgv_steps)
     if not args.no_sod:
         out["sod1d"] = sod1d()
     if not args.no_cpu_baseline:
