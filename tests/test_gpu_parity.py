@@ -117,6 +117,28 @@ def test_step_2d_navier_stokes(orc, torch_dev):
     compare_step(orc, pr, W, orc.cfl_dt(orc_params(orc, pr), W, 0.5))
 
 
+@pytest.mark.parametrize("ct1,ct2", [(0.25, 1e-5), (0.5, 1.0 / 3.0)])
+def test_cutoff_ties(orc, torch_dev, ct1, ct2):
+    """Cut-off comparisons at exact and near ties, normal and tangential.
+    Constant regions give four equal weights, so C_T1 = 1/4 puts the
+    large-stencil cut-off exactly at its threshold; linear ramps give four
+    weights equal up to rounding, so C_T1 = 1/2 rejects the large stencil and
+    C_T2 = 1/3 puts each small-stencil cut-off within a few ulps of its
+    threshold.  The kernels decide such cases with correctly rounded weights;
+    the flags must equal the oracle's bit for bit."""
+    n = 40
+    x = (np.arange(n) + 0.5) / n
+    X, Y = np.meshgrid(x, x)
+    left = X < 0.5
+    rho = np.where(left, 1.0 + 0.3 * X + 0.2 * Y, 0.8)
+    u = np.where(left, 0.1, -0.2)
+    v = np.where(Y < 0.5, 0.05, -0.1)
+    p = np.where(left, 1.0 + 0.1 * Y, 0.9)
+    W = I.conservative(rho, [u, v], p)
+    pr = problem([n, n], [1.0 / n, 1.0 / n], ct1=ct1, ct2=ct2, ct1_tan=ct1, ct2_tan=ct2)
+    compare_step(orc, pr, W, orc.cfl_dt(orc_params(orc, pr), W, 0.5))
+
+
 def test_step_2d_tau_zero_density_wave(orc, torch_dev):
     W, dx = I.density_wave_2d(20)
     pr = problem([20, 20], [dx, dx], bc="periodic", tau="zero")
