@@ -171,6 +171,22 @@ def test_step_3d_ragged_euler(orc, torch_dev):
     compare_step(orc, pr, W, orc.cfl_dt(orc_params(orc, pr), W, 0.5))
 
 
+@pytest.mark.parametrize("shape", [[3], [3, 3], [3, 11], [11, 3], [3, 3, 3], [3, 4, 5]])
+@pytest.mark.parametrize("bc", ["periodic", "reflective", "transmissive"])
+def test_minimum_grids(orc, torch_dev, shape, bc):
+    """The smallest grids the library accepts (three cells along an axis):
+    every stencil reaches past both boundaries, so ghost cells come from the
+    index map on both sides at once."""
+    rng = np.random.default_rng(len(shape) * 100 + sum(shape))
+    sh = tuple(reversed(shape))
+    rho = np.exp(rng.uniform(np.log(0.7), np.log(1.4), sh))
+    p = np.exp(rng.uniform(np.log(0.7), np.log(1.4), sh))
+    vel = [rng.uniform(-0.3, 0.3, sh) for _ in shape]
+    W = I.conservative(rho, vel, p)
+    pr = problem(shape, [1.0 / n for n in shape], bc=bc)
+    compare_step(orc, pr, W, 0.2 * orc.cfl_dt(orc_params(orc, pr), W, 0.5))
+
+
 def test_cfl_dt(orc, torch_dev):
     W = smooth_2d(40, 30)
     pr = problem([40, 30], [1 / 40, 1 / 30], mu=1e-3, tau="viscous")
@@ -304,9 +320,11 @@ def test_failure_count_matches_oracle(orc, torch_dev):
 def test_invalid_arguments(torch_dev):
     import torch
     from paper_2309_10534_amd import tgks
-    p = tgks.tgks_params_default(2, [2, 10], [0.1, 0.1])
-    with pytest.raises(tgks.TgksError):
-        tgks.tgks_create(p)
+    # fewer than three cells along an axis (empty grids included)
+    for nd, shape in ((2, [2, 10]), (1, [0]), (1, [1]), (2, [10, 0]), (3, [3, 3, 2])):
+        p = tgks.tgks_params_default(nd, shape, [0.1] * nd)
+        with pytest.raises(tgks.TgksError):
+            tgks.tgks_create(p)
     p = tgks.tgks_params_default(1, [10], [0.1])
     ctx = tgks.tgks_create(p)
     try:
