@@ -31,7 +31,7 @@
 //    d_tF*, the combined flux and the final update, in the paper's order.
 //  * Collision time and CFL step (Sec. 5 preamble).
 //
-// Readings where the paper is silent or garbled (each is listed in the design doc):
+// Readings where the paper is silent or garbled:
 //  * Eq. 2.5 pairs g_r with H(u); the upwind reading g_l H(u), g_r (1-H(u)) is
 //    used, consistent with Eq. 2.6.  Eqs. 3.25-3.26 integrate g^r over u<0.
 //  * Reconstruction acts component-wise on the conservative variables.

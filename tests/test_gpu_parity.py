@@ -1,6 +1,6 @@
 """GPU parity: the HIP path (through the C ABI) against the CPU oracle.
 
-Bar (spec tolerance): L1-relative difference <= 1e-10 per component;
+Bar: L1-relative difference <= 1e-10 per component;
 stage-1 stencil-selection flags bit-identical on identical input.  Sizes span
 several 16x16 tiles with ragged tails; the full-size workloads are checked on
 sampled cells against the oracle run on a local patch that contains every

@@ -7,7 +7,7 @@ equilibrium state (Eq. 2.6), the tau = 0 flux with its time derivative
 (Eqs. 2.5-2.9), the S2O4 update (Sec. 2.2), the tangential Gauss-point
 reconstruction (Sec. 3.2 Steps 1-3) and the CFL step (Sec. 5).
 
-Readings fixed by these tables (see DESIGN.md):
+Readings fixed by these tables:
   * 1-D: the table is reproduced with CFL 0.5 time steps; the fixed
     dt = 0.2 dx printed in the caption gives errors 0.65 % higher.
   * 1-D "mesh length" is the cell width (n = 2/h); 2-D "mesh length" is 1/n.
