@@ -86,7 +86,7 @@ int launch_faces(tgks_ctx* c, const double* W, const double* dt, int stage, uint
         const int n1 = c->g.n[(ax + 1) % 3], n2 = c->g.n[(ax + 2) % 3];
         const long long nbl = (long long)(c->g.n[ax] + 1) * ((n1 + B3_1 - 1) / B3_1) * ((n2 + B3_2 - 1) / B3_2);
         dim3 grid((unsigned)(8 * ((nbl + 7) / 8)));
-        const dim3 blk3(4 * B3_1 * B3_2);
+        const dim3 blk3(L3 * B3_1 * B3_2);
 #define F3(AXV)                                                                       \
   if (stage == 1) {                                                                   \
     if (c->ns) LAUNCH((face3d_kernel<AXV, 1, true>), grid, blk3, a);                  \

@@ -483,135 +483,127 @@ TGKS_HD void g1d_jvp(const Gas<D, R>& g, double N, int d, const R* dW, const Pri
   out[D + 1] = 0.5 * vE;
 }
 
-// Time-integrated flux F(dt) and F(dt/2) at one Gauss point.
-// Wl, Wr: states; dWl[d], dWr[d]: derivatives along frame axis d.
-// Returns false when a state is non-physical.
+// ---------------------------------------------------------------------------
+// The Gauss-point flux in three pieces, for kernels that give the two sides
+// of a Gauss point to two lanes: each lane evaluates its side's share of the
+// equilibrium state (side_w0) and, once W0 is known, its side's shares of
+// the slopes of W0 and of the non-equilibrium moments (side_part); the two
+// shares are summed left + right and flux_combine adds the equilibrium part
+// and the time integration.  gp_flux below evaluates the same arithmetic in
+// one lane.
+// ---------------------------------------------------------------------------
+template <int D, class R>
+struct SidePart {
+  R dW0[D][D + 2];          // rho_s <psi a_d>_s: share of the slopes of W0 (Eq. 2.6)
+  R S1[D + 2], S2[D + 2], S3[D + 2];  // rho_s <u1 psi>, sum_d <u1 u_d psi a_d>, <u1 psi A> over the half space
+  R H1, H2, H3;             // their heat-flux moments (Navier-Stokes)
+};
+
+// gas state, half-space seeds and the side's share rho_s <psi>_s of W0;
+// sgn = +1 for the left side (u1 > 0), -1 for the right side
+template <int D, class R>
+TGKS_HD void side_w0(const R* Ws, const FluxCfg& P, double sgn, Gas<D, R>& gs, R& h0, R& h1, R* w0) {
+  constexpr int NC = D + 2;
+  make_gas<D>(Ws, P.N, gs);
+  half_seed(gs.U[0], gs.lam, sgn, h0, h1);
+  MomSet<D, R> S;
+  half_table(gs.U[0], gs.h, h0, h1, S.m1);
+  tangential_tables<D>(gs, S);
+  xi_moments<D>(gs, P.K, S);
+  R g[NC];
+  gpsi<D>(S, 0, 0, 0, 0, g);
+#pragma unroll
+  for (int q = 0; q < NC; ++q) w0[q] = gs.rho * g[q];
+}
+
 template <int D, bool NS, class R>
-TGKS_HD bool gp_flux(const R* Wl, const R* Wr, const R (*dWl)[D + 2], const R (*dWr)[D + 2], const FluxCfg& P,
-                     R dt, R* Fdt, R* Fh) {
+TGKS_HD void side_part(const Gas<D, R>& gs, R h0, R h1, const R* Ws, const R (*dW)[D + 2], const FluxCfg& P,
+                       const Gas<D, R>& g0, SidePart<D, R>& o) {
   constexpr int NC = D + 2;
   const double N = P.N;
-  Gas<D, R> gl, gr;
-  make_gas<D>(Wl, N, gl);
-  make_gas<D>(Wr, N, gr);
-  R hl0, hl1, hr0, hr1;
-  half_seed(gl.U[0], gl.lam, 1.0, hl0, hl1);
-  half_seed(gr.U[0], gr.lam, -1.0, hr0, hr1);
-
-  // equilibrium state by kinetic weighting (Eq. 2.6): rho_l <psi>_{>0} + rho_r <psi>_{<0}
-  R W0[NC];
-  {
-    MomSet<D, R> S;
-    half_table(gl.U[0], gl.h, hl0, hl1, S.m1);
-    tangential_tables<D>(gl, S);
-    xi_moments<D>(gl, P.K, S);
-    R g[NC];
-    gpsi<D>(S, 0, 0, 0, 0, g);
+  MomSet<D, R> Sh;
+  half_table(gs.U[0], gs.h, h0, h1, Sh.m1);
+  tangential_tables<D>(gs, Sh);
+  xi_moments<D>(gs, P.K, Sh);
+  R a[D][NC];
+  R Wt[NC];  // rho <(sum_d u_d a_d) psi> = sum_d J_d dW_d; A^s solves <A psi> = -that / rho
 #pragma unroll
-    for (int q = 0; q < NC; ++q) W0[q] = gl.rho * g[q];
-    half_table(gr.U[0], gr.h, hr0, hr1, S.m1);
-    tangential_tables<D>(gr, S);
-    xi_moments<D>(gr, P.K, S);
-    gpsi<D>(S, 0, 0, 0, 0, g);
+  for (int d = 0; d < D; ++d) {
+    R b[NC];
 #pragma unroll
-    for (int q = 0; q < NC; ++q) W0[q] += gr.rho * g[q];
-  }
-  Gas<D, R> g0;
-  make_gas<D>(W0, N, g0);
-
-  // side contributions: dW0 (Eq. 2.6), A^s (Eq. 2.7), and the moments of the
-  // non-equilibrium part of Eq. 2.5 over the half space
-  R dW0[D][NC], S1[NC], S2[NC], S3[NC];
-  R H1 = R(0.0), H2 = R(0.0), H3 = R(0.0);  // heat-flux moments (NS)
+    for (int q = 0; q < NC; ++q) b[q] = dW[d][q] * gs.irho;
+    micro_solve<D>(gs, N, b, a[d]);
+    mpsia<D, false>(Sh, a[d], 0, 0, 0, gs.rho, o.dW0[d]);
+    Prim<D, R> pd;
+    prim_dir<D>(gs, N, dW[d], pd);
+    R jv[NC];
+    euler_jvp<D>(gs, Ws[D + 1], d, dW[d], pd, jv);
 #pragma unroll
-  for (int side = 0; side < 2; ++side) {
-    const Gas<D, R>& gs = side == 0 ? gl : gr;
-    const R* Ws = side == 0 ? Wl : Wr;
-    const R(*dW)[NC] = side == 0 ? dWl : dWr;
-    MomSet<D, R> Sh;
-    if (side == 0)
-      half_table(gs.U[0], gs.h, hl0, hl1, Sh.m1);
-    else
-      half_table(gs.U[0], gs.h, hr0, hr1, Sh.m1);
-    tangential_tables<D>(gs, Sh);
-    xi_moments<D>(gs, P.K, Sh);
-    R a[D][NC];
-    R Wt[NC];  // rho <(sum_d u_d a_d) psi> = sum_d J_d dW_d; A^s solves <A psi> = -that / rho
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-      R b[NC];
-#pragma unroll
-      for (int q = 0; q < NC; ++q) b[q] = dW[d][q] * gs.irho;
-      micro_solve<D>(gs, N, b, a[d]);
-      if (side == 0)
-        mpsia<D, false>(Sh, a[d], 0, 0, 0, gs.rho, dW0[d]);
+    for (int q = 0; q < NC; ++q) {
+      if (d == 0)
+        Wt[q] = jv[q];
       else
-        mpsia<D, true>(Sh, a[d], 0, 0, 0, gs.rho, dW0[d]);
-      Prim<D, R> pd;
-      prim_dir<D>(gs, N, dW[d], pd);
-      R jv[NC];
-      euler_jvp<D>(gs, Ws[D + 1], d, dW[d], pd, jv);
-#pragma unroll
-      for (int q = 0; q < NC; ++q) {
-        if (d == 0)
-          Wt[q] = jv[q];
-        else
-          Wt[q] += jv[q];
-      }
+        Wt[q] += jv[q];
     }
-    R A[NC];
-    {
-      R b[NC];
+  }
+  R A[NC];
+  {
+    R b[NC];
 #pragma unroll
-      for (int q = 0; q < NC; ++q) b[q] = -(Wt[q] * gs.irho);
-      micro_solve<D>(gs, N, b, A);
-    }
-    // <u1 psi>, sum_d <u1 u_d psi a_d>, <u1 psi A> over the half space
-    R g[NC];
-    gpsi<D>(Sh, 1, 0, 0, 0, g);
-    R v2[NC];
+    for (int q = 0; q < NC; ++q) b[q] = -(Wt[q] * gs.irho);
+    micro_solve<D>(gs, N, b, A);
+  }
+  R g[NC];
+  gpsi<D>(Sh, 1, 0, 0, 0, g);
+  R v2[NC];
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    int i, j, k;
+    unit(d, i, j, k);
+    if (d == 0)
+      mpsia<D, false>(Sh, a[d], 1 + i, j, k, R(1.0), v2);
+    else
+      mpsia<D, true>(Sh, a[d], 1 + i, j, k, R(1.0), v2);
+  }
+  R v3[NC];
+  mpsia<D, false>(Sh, A, 1, 0, 0, R(1.0), v3);
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+    o.S1[q] = gs.rho * g[q];
+    o.S2[q] = gs.rho * v2[q];
+    o.S3[q] = gs.rho * v3[q];
+  }
+  o.H1 = o.H2 = o.H3 = R(0.0);
+  if (NS) {
+    R f0[NC], w2[NC], w3[NC];
+    gpsi<D>(Sh, 0, 0, 0, 0, f0);
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       int i, j, k;
       unit(d, i, j, k);
       if (d == 0)
-        mpsia<D, false>(Sh, a[d], 1 + i, j, k, R(1.0), v2);
+        mpsia<D, false>(Sh, a[d], i, j, k, R(1.0), w2);
       else
-        mpsia<D, true>(Sh, a[d], 1 + i, j, k, R(1.0), v2);
+        mpsia<D, true>(Sh, a[d], i, j, k, R(1.0), w2);
     }
-    R v3[NC];
-    mpsia<D, false>(Sh, A, 1, 0, 0, R(1.0), v3);
-#pragma unroll
-    for (int q = 0; q < NC; ++q) {
-      if (side == 0) {
-        S1[q] = gs.rho * g[q];
-        S2[q] = gs.rho * v2[q];
-        S3[q] = gs.rho * v3[q];
-      } else {
-        S1[q] += gs.rho * g[q];
-        S2[q] += gs.rho * v2[q];
-        S3[q] += gs.rho * v3[q];
-      }
-    }
-    if (NS) {
-      R f0[NC], w2[NC], w3[NC];
-      gpsi<D>(Sh, 0, 0, 0, 0, f0);
-#pragma unroll
-      for (int d = 0; d < D; ++d) {
-        int i, j, k;
-        unit(d, i, j, k);
-        if (d == 0)
-          mpsia<D, false>(Sh, a[d], i, j, k, R(1.0), w2);
-        else
-          mpsia<D, true>(Sh, a[d], i, j, k, R(1.0), w2);
-      }
-      mpsia<D, false>(Sh, A, 0, 0, 0, R(1.0), w3);
-      H1 += gs.rho * heat_combine<D>(g, f0, g0.U);
-      H2 += gs.rho * heat_combine<D>(v2, w2, g0.U);
-      H3 += gs.rho * heat_combine<D>(v3, w3, g0.U);
-    }
+    mpsia<D, false>(Sh, A, 0, 0, 0, R(1.0), w3);
+    o.H1 = gs.rho * heat_combine<D>(g, f0, g0.U);
+    o.H2 = gs.rho * heat_combine<D>(v2, w2, g0.U);
+    o.H3 = gs.rho * heat_combine<D>(v3, w3, g0.U);
   }
+}
 
+// Equilibrium part of Eq. 2.5 and the time integration over dt and dt/2,
+// given W0, its gas state g0, the two sides' shares summed left + right
+// (dW0, S1..S3, H1..H3) and the side pressures pl, pr (collision time).
+template <int D, bool NS, class R>
+TGKS_HD void flux_combine(const R* W0, const Gas<D, R>& g0, const SidePart<D, R>& T, R pl, R pr,
+                          const FluxCfg& P, R dt, R* Fdt, R* Fh) {
+  constexpr int NC = D + 2;
+  const double N = P.N;
+  const R(*dW0)[NC] = T.dW0;
+  const R *S1 = T.S1, *S2 = T.S2, *S3 = T.S3;
+  const R H1 = T.H1, H2 = T.H2, H3 = T.H3;
   // equilibrium part of Eq. 2.5, rho0-weighted moments in closed form:
   //   T1 = rho0 <u1 psi>_0 = F_1(W0)
   //   W0t = -sum_d J_d(W0) dW0_d = rho0 <Abar psi>_0 (compatibility, Eq. 2.7)
@@ -660,7 +652,6 @@ TGKS_HD bool gp_flux(const R* Wl, const R* Wr, const R (*dWl)[D + 2], const R (*
   // collision time (Sec. 5 preamble); dt is the full step in both stages.
   // xh = -dt / (2 tau): e^{-dt/tau} = (e^{xh})^2, one expm1 serves both
   // intervals.
-  const R pl = gl.rho * gl.h, pr = gr.rho * gr.h;
   const R S = pl + pr, A = fabs(pl - pr);
   R tau = R(0.0), xh = R(0.0);
   if (P.tau_mode == 1) {
@@ -708,6 +699,47 @@ TGKS_HD bool gp_flux(const R* Wl, const R* Wr, const R (*dWl)[D + 2], const R (*
       F[NC - 1] += P.pr_fix * q;
     }
   }
+}
+
+// left + right sum of the two sides' shares, in that order
+template <int D, class R>
+TGKS_HD void side_sum(const SidePart<D, R>& l, const SidePart<D, R>& r, SidePart<D, R>& o) {
+  constexpr int NC = D + 2;
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) o.dW0[d][q] = l.dW0[d][q] + r.dW0[d][q];
+    o.S1[q] = l.S1[q] + r.S1[q];
+    o.S2[q] = l.S2[q] + r.S2[q];
+    o.S3[q] = l.S3[q] + r.S3[q];
+  }
+  o.H1 = l.H1 + r.H1;
+  o.H2 = l.H2 + r.H2;
+  o.H3 = l.H3 + r.H3;
+}
+
+// Time-integrated flux F(dt) and F(dt/2) at one Gauss point.
+// Wl, Wr: states; dWl[d], dWr[d]: derivatives along frame axis d.
+// Returns false when a state is non-physical.
+template <int D, bool NS, class R>
+TGKS_HD bool gp_flux(const R* Wl, const R* Wr, const R (*dWl)[D + 2], const R (*dWr)[D + 2], const FluxCfg& P,
+                     R dt, R* Fdt, R* Fh) {
+  constexpr int NC = D + 2;
+  Gas<D, R> gl, gr, g0;
+  R hl0, hl1, hr0, hr1, wl[NC], wr[NC], W0[NC];
+  // equilibrium state by kinetic weighting (Eq. 2.6): rho_l <psi>_{>0} + rho_r <psi>_{<0}
+  side_w0<D>(Wl, P, 1.0, gl, hl0, hl1, wl);
+  side_w0<D>(Wr, P, -1.0, gr, hr0, hr1, wr);
+#pragma unroll
+  for (int q = 0; q < NC; ++q) W0[q] = wl[q] + wr[q];
+  make_gas<D>(W0, P.N, g0);
+  // side contributions: dW0 (Eq. 2.6), A^s (Eq. 2.7), and the moments of the
+  // non-equilibrium part of Eq. 2.5 over the half space
+  SidePart<D, R> L, Rt, T;
+  side_part<D, NS>(gl, hl0, hl1, Wl, dWl, P, g0, L);
+  side_part<D, NS>(gr, hr0, hr1, Wr, dWr, P, g0, Rt);
+  side_sum<D>(L, Rt, T);
+  flux_combine<D, NS>(W0, g0, T, gl.rho * gl.h, gr.rho * gr.h, P, dt, Fdt, Fh);
   return gl.ok && gr.ok && g0.ok;
 }
 

@@ -332,18 +332,26 @@ __global__ __launch_bounds__(256) void recon3d_kernel(StageArgs a) {
 // (b) face kernel.  A block owns one plane of faces (fixed index along AX)
 // and a B1 x B2 tile of it along the tangential axes T1, T2 (cyclic order:
 // x-faces y, z; y-faces z, x; z-faces x, y).  It stages the normal
-// reconstruction of both sides with a halo of two in LDS (ghost positions by
-// the index map, mirrored momenta negated), reconstructs every face line of
-// the tile and its T2 halo once along T1 (sweep 1, both T1 Gauss points), and
-// then lanes 4k..4k+3 share face k: lane (m1, m2) reconstructs side m2 along
-// T2 from the sweep-1 values at Gauss point m1 (sweep 2, both T2 points),
-// hands the partner lane (m1, 1-m2) the value at the partner's Gauss point,
-// and evaluates the flux at Gauss point (m1, m2); the four lanes sum.
-constexpr int B3_1 = 4, B3_2 = 16;
+// reconstruction of both sides (from recon3d_kernel) with a halo of two in
+// LDS (ghost positions by the index map, mirrored momenta negated),
+// reconstructs every face line of the tile and its T2 halo once along T1
+// (sweep 1, both T1 Gauss points), and then eight lanes share a face: lane
+// (m1, m3, m2) owns side m2 at Gauss point (m1, m3).
+//   * Sweep 2: the pair (m3 = 0, 1) of a side and T1 point splits the
+//     fifteen T2 reconstructions of that side (five components of the value,
+//     its T1 derivative and its normal slope) and swaps the results at each
+//     other's T2 point.
+//   * Flux: each lane evaluates its side's share of the equilibrium state
+//     and of the non-equilibrium moments (side_w0, side_part); the pair
+//     (m2 = 0, 1) adds the shares (a + b is exact-order independent), and
+//     both lanes evaluate the equilibrium part (flux_combine).  One side per
+//     lane keeps the flux within the register budget of two waves per SIMD.
+// Tiles are dealt to the 8 XCDs in contiguous ranges.
+constexpr int B3_1 = 2, B3_2 = 16, L3 = 8;
 
 template <int AX, int STAGE, bool NS>
-__global__ __launch_bounds__(4 * B3_1 * B3_2, 2) void face3d_kernel(StageArgs a) {
-  constexpr int NC = 5, B1 = B3_1, B2 = B3_2, NT = 4 * B1 * B2;
+__global__ __launch_bounds__(L3 * B3_1 * B3_2, 2) void face3d_kernel(StageArgs a) {
+  constexpr int NC = 5, B1 = B3_1, B2 = B3_2, NT = L3 * B1 * B2;
   constexpr int L1 = B1 + 4, L2 = B2 + 4;
   constexpr int T1 = (AX + 1) % 3, T2 = (AX + 2) % 3;
   __shared__ double sR[2][NC][2][L2][L1];      // [side][c][value, normal slope][t2][t1]
@@ -413,8 +421,11 @@ __global__ __launch_bounds__(4 * B3_1 * B3_2, 2) void face3d_kernel(StageArgs a)
   }
   __syncthreads();
 
-  // 3. sweep 2 along T2 and the Gauss-point fluxes
-  const int m2 = tid & 1, m1 = (tid >> 1) & 1, fi = tid >> 2;
+  // 3. sweep 2 along T2, split over the pair m3 = 0, 1.  Item it = 3 q + kind
+  //    (kind 0: value, 1: T1 derivative, 2: normal slope of component perm[q]);
+  //    in round r lane m3 reconstructs item 2 r + m3 at both T2 points and
+  //    hands its partner the value (and T2 derivative) at the partner's point.
+  const int m2 = tid & 1, m3 = (tid >> 1) & 1, m1 = (tid >> 2) & 1, fi = tid >> 3;
   const int j1 = fi % B1, j2 = fi / B1;
   int fp[3];
   fp[AX] = fa;
@@ -422,55 +433,97 @@ __global__ __launch_bounds__(4 * B3_1 * B3_2, 2) void face3d_kernel(StageArgs a)
   fp[T2] = t20 + j2;
   const bool live = fp[T1] < g.n[T1] && fp[T2] < g.n[T2];
   const int perm[NC] = {0, 1 + AX, 1 + T1, 1 + T2, 4};
-  double Wg[2][NC], Dg[2][3][NC];
+  double item[15], item_d[15];  // at this lane's T2 point: value, T2 derivative (cell units)
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const int it = 2 * r + m3;
+    double v[2] = {0.0, 0.0}, d[2] = {0.0, 0.0};
+    if (live && it < 15) {
+      const int q = it / 3, kind = it - 3 * q;
+      const int c = q == 0 ? perm[0] : q == 1 ? perm[1] : q == 2 ? perm[2] : q == 3 ? perm[3] : perm[4];
+      double Q[5];
+#pragma unroll
+      for (int k = 0; k < 5; ++k) Q[k] = sS[m2][c][j2 + k][j1][2 * kind + m1];
+      teno_gauss(Q, teno_flag(Q, a.tt), v, d);
+    }
+    const double own = m3 ? v[1] : v[0], own_d = m3 ? d[1] : d[0];
+    const double rcv = __shfl_xor(m3 ? v[0] : v[1], 2), rcv_d = __shfl_xor(m3 ? d[0] : d[1], 2);
+    // item 2 r is lane m3 = 0's, item 2 r + 1 lane m3 = 1's
+    item[2 * r] = m3 ? rcv : own;
+    item_d[2 * r] = m3 ? rcv_d : own_d;
+    if (2 * r + 1 < 15) {
+      item[2 * r + 1] = m3 ? own : rcv;
+      item_d[2 * r + 1] = m3 ? own_d : rcv_d;
+    }
+  }
+  double Ws[NC], dWs[3][NC];  // this lane's side at its Gauss point, face frame
 #pragma unroll
   for (int q = 0; q < NC; ++q) {
-    const int c = perm[q];
-    double v[2] = {0, 0}, dv[2] = {0, 0}, x[2] = {0, 0}, y[2] = {0, 0};
-    if (live) {
-      double Qw[5], Qd[5], Qn[5], t[2];
-#pragma unroll
-      for (int r = 0; r < 5; ++r) {
-        const double* o = sS[m2][c][j2 + r][j1];
-        Qw[r] = o[m1];
-        Qd[r] = o[2 + m1];
-        Qn[r] = o[4 + m1];
-      }
-      teno_gauss(Qw, teno_flag(Qw, a.tt), v, dv);
-      teno_gauss(Qd, teno_flag(Qd, a.tt), x, t);
-      teno_gauss(Qn, teno_flag(Qn, a.tt), y, t);
-    }
-    // own side (m2) at own Gauss point; the partner's side at this point
-    // arrives from the partner
-    const double sv = m2 ? v[0] : v[1], sd = m2 ? dv[0] : dv[1], sx = m2 ? x[0] : x[1], sy = m2 ? y[0] : y[1];
-    const double rv = __shfl_xor(sv, 1), rd = __shfl_xor(sd, 1), rx = __shfl_xor(sx, 1), ry = __shfl_xor(sy, 1);
-    const double ov = m2 ? v[1] : v[0], od = m2 ? dv[1] : dv[0], ox = m2 ? x[1] : x[0], oy = m2 ? y[1] : y[0];
-    Wg[0][q] = m2 == 0 ? ov : rv;
-    Wg[1][q] = m2 == 0 ? rv : ov;
-    Dg[0][2][q] = (m2 == 0 ? od : rd) * i2d;
-    Dg[1][2][q] = (m2 == 0 ? rd : od) * i2d;
-    Dg[0][1][q] = m2 == 0 ? ox : rx;
-    Dg[1][1][q] = m2 == 0 ? rx : ox;
-    Dg[0][0][q] = m2 == 0 ? oy : ry;
-    Dg[1][0][q] = m2 == 0 ? ry : oy;
+    Ws[q] = item[3 * q];
+    dWs[2][q] = item_d[3 * q] * i2d;
+    dWs[1][q] = item[3 * q + 1];
+    dWs[0][q] = item[3 * q + 2];
   }
+
+  // 4. the Gauss-point flux, one side per lane
+  Gas<3, double> gs, g0;
+  double h0 = 0.0, h1 = 0.0, w0[NC] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (live) side_w0<3>(Ws, a.fc, m2 ? -1.0 : 1.0, gs, h0, h1, w0);
+  double W0[NC];
+#pragma unroll
+  for (int q = 0; q < NC; ++q) W0[q] = w0[q] + __shfl_xor(w0[q], 1);
+  SidePart<3, double> P, T;
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) P.dW0[d][q] = 0.0;
+    P.S1[q] = P.S2[q] = P.S3[q] = 0.0;
+  }
+  P.H1 = P.H2 = P.H3 = 0.0;
+  bool ok = true;
+  double ps = 0.0;
+  if (live) {
+    make_gas<3>(W0, a.fc.N, g0);
+    side_part<3, NS>(gs, h0, h1, Ws, dWs, a.fc, g0, P);
+    ok = gs.ok && g0.ok;
+    ps = gs.rho * gs.h;
+  }
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) T.dW0[d][q] = P.dW0[d][q] + __shfl_xor(P.dW0[d][q], 1);
+    T.S1[q] = P.S1[q] + __shfl_xor(P.S1[q], 1);
+    T.S2[q] = P.S2[q] + __shfl_xor(P.S2[q], 1);
+    T.S3[q] = P.S3[q] + __shfl_xor(P.S3[q], 1);
+  }
+  if (NS) {
+    T.H1 = P.H1 + __shfl_xor(P.H1, 1);
+    T.H2 = P.H2 + __shfl_xor(P.H2, 1);
+    T.H3 = P.H3 + __shfl_xor(P.H3, 1);
+  } else {
+    T.H1 = T.H2 = T.H3 = 0.0;
+  }
+  const double pp = __shfl_xor(ps, 1);
+  ok = ok && (__shfl_xor((int)ok, 1) != 0);
   double A[NC] = {0, 0, 0, 0, 0}, B[NC] = {0, 0, 0, 0, 0};
   if (live) {
     double Fdt[NC], Fh[NC];
-    if (!gp_flux<3, NS>(Wg[0], Wg[1], Dg[0], Dg[1], a.fc, dt, Fdt, Fh)) atomicAdd(a.fail, 1ull);
+    flux_combine<3, NS>(W0, g0, T, m2 ? pp : ps, m2 ? ps : pp, a.fc, dt, Fdt, Fh);
+    if (!ok && m2 == 0) atomicAdd(a.fail, 1ull);
     write_combined<NC>(STAGE, Fdt, Fh, 0.25, A, B);
   }
-  // sum over the four Gauss points held by lanes 4k..4k+3
+  // sum over the four Gauss points (m3, m1); both lanes of a pair hold the
+  // same flux
 #pragma unroll
   for (int q = 0; q < NC; ++q) {
-    A[q] += __shfl_xor(A[q], 1);
     A[q] += __shfl_xor(A[q], 2);
+    A[q] += __shfl_xor(A[q], 4);
     if (STAGE == 1) {
-      B[q] += __shfl_xor(B[q], 1);
       B[q] += __shfl_xor(B[q], 2);
+      B[q] += __shfl_xor(B[q], 4);
     }
   }
-  if (live && (tid & 3) == 0) {
+  if (live && (tid & 7) == 0) {
     int nfa[3] = {g.n[0], g.n[1], g.n[2]};
     nfa[AX] += 1;
     const long long nf = (long long)nfa[0] * nfa[1] * nfa[2];
