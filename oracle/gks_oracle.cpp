@@ -107,6 +107,7 @@ typedef struct {
   double ct1, ct2, ct1_tan, ct2_tan;
   double eps;
   int q;
+  int recon;               // 0 conservative variables, 1 characteristic variables (1-D, 2-D)
 } orc_params;
 }
 
@@ -680,6 +681,167 @@ static uint8_t normal_recon(const orc_params& P, const Grid& g, const T* W, int 
   return f;
 }
 
+// ---------------------------------------------------------------------------
+// Characteristic-variable reconstruction (an option; the paper reconstructs
+// the conservative variables).  At a face the reference state is the mean of
+// the conservative states of the two adjacent cells; the characteristic
+// fields are the eigenvectors of the Euler flux Jacobian dF_a/dW along frame
+// axis a at that state (a = 0: the face normal, for the normal
+// reconstruction; a = 1: along the face, for the tangential one).  Fields,
+// in order: u_a - c, entropy, one shear wave per other axis (increasing
+// axis), u_a + c.  With u = m / rho, q2 = |u|^2, p = (gamma-1)(E - rho q2/2),
+// c^2 = gamma p / rho, H = (E + p) / rho, b1 = (gamma-1)/c^2, b2 = b1 q2 / 2:
+//   l(u_a -+ c) = ((b2 +- u_a/c)/2, -(b1 u + -+ e_a / c)/2 ..., b1/2)
+//   l(entropy)  = (1 - b2, b1 u, -b1),   l(shear s) = (-u_s, e_s, 0)
+//   r(u_a -+ c) = (1, u -+ c e_a, H -+ u_a c), r(entropy) = (1, u, q2/2),
+//   r(shear s)  = (0, e_s, u_s).
+// Every entry, projection and back-projection follows one fixed operation
+// order (dense left-to-right sums over all components), so that identical
+// inputs give identical characteristic values and stencil flags.  A
+// non-physical reference state (rho <= 0, p <= 0, not finite) falls back to
+// the identity (component-wise reconstruction) for that face.
+// ---------------------------------------------------------------------------
+template <class T>
+static bool char_basis(int D, double gamma, const T* Wb, int a, T L[5][5], T R[5][5]) {
+  const int nc = D + 2;
+  const T rho = Wb[0];
+  const T irho = 1.0 / rho;
+  T u[3] = {T(0.0), T(0.0), T(0.0)};
+  for (int e = 0; e < D; ++e) u[e] = Wb[1 + e] * irho;
+  T q2 = u[0] * u[0];
+  for (int e = 1; e < D; ++e) q2 = q2 + u[e] * u[e];
+  const T E = Wb[D + 1];
+  const T p = (gamma - 1.0) * (E - 0.5 * (rho * q2));
+  const T c2 = (gamma * p) * irho;
+  const bool ok = val(rho) > 0.0 && val(p) > 0.0 && std::isfinite(val(c2)) && std::isfinite(val(E));
+  if (!ok) {
+    for (int i = 0; i < nc; ++i)
+      for (int j = 0; j < nc; ++j) L[i][j] = R[i][j] = T(i == j ? 1.0 : 0.0);
+    return false;
+  }
+  const T c = sqrt(c2);
+  const T ic = 1.0 / c;
+  const T H = (E + p) * irho;
+  const T b1 = (gamma - 1.0) / c2;
+  const T b2 = 0.5 * (b1 * q2);
+  const T un = u[a];
+  const T uc = un * c;
+  for (int i = 0; i < nc; ++i)
+    for (int j = 0; j < nc; ++j) L[i][j] = R[i][j] = T(0.0);
+  const int kp = D + 1;  // field u_a + c
+  // acoustic rows
+  L[0][0] = 0.5 * (b2 + un * ic);
+  L[kp][0] = 0.5 * (b2 - un * ic);
+  for (int e = 0; e < D; ++e) {
+    if (e == a) {
+      L[0][1 + e] = 0.5 * (-(b1 * un) - ic);
+      L[kp][1 + e] = 0.5 * (ic - b1 * un);
+    } else {
+      L[0][1 + e] = 0.5 * (-(b1 * u[e]));
+      L[kp][1 + e] = 0.5 * (-(b1 * u[e]));
+    }
+  }
+  L[0][D + 1] = 0.5 * b1;
+  L[kp][D + 1] = 0.5 * b1;
+  // entropy row
+  L[1][0] = 1.0 - b2;
+  for (int e = 0; e < D; ++e) L[1][1 + e] = b1 * u[e];
+  L[1][D + 1] = -b1;
+  // shear rows
+  int k = 2;
+  for (int s = 0; s < D; ++s) {
+    if (s == a) continue;
+    L[k][0] = -u[s];
+    L[k][1 + s] = T(1.0);
+    R[1 + s][k] = T(1.0);
+    R[D + 1][k] = u[s];
+    ++k;
+  }
+  // right eigenvectors (columns)
+  R[0][0] = T(1.0);
+  R[0][1] = T(1.0);
+  R[0][kp] = T(1.0);
+  for (int e = 0; e < D; ++e) {
+    R[1 + e][0] = e == a ? un - c : u[e];
+    R[1 + e][1] = u[e];
+    R[1 + e][kp] = e == a ? un + c : u[e];
+  }
+  R[D + 1][0] = H - uc;
+  R[D + 1][1] = 0.5 * q2;
+  R[D + 1][kp] = H + uc;
+  return true;
+}
+
+// y = M x, dense left-to-right sums
+template <class T>
+static void matvec(int nc, const T M[5][5], const T* x, T* y) {
+  for (int i = 0; i < nc; ++i) {
+    T v = M[i][0] * x[0];
+    for (int j = 1; j < nc; ++j) v = v + M[i][j] * x[j];
+    y[i] = v;
+  }
+}
+
+// conservative state of a cell in frame order
+template <class T>
+static void cell_frame(const Grid& g, const T* W, const int* perm, const long idx[3], T* out) {
+  for (int a = 0; a < g.nc; ++a) out[a] = cell(g, W, perm[a], idx);
+}
+
+// Normal reconstruction of both sides of a face in characteristic
+// variables from the six frame-ordered cells C[0..5] = cells f-3 .. f+2
+// along the normal: values and slopes (per unit length, idn = 1/dx) in frame
+// order; fr = flags of the right side (cell f at its low face).
+template <class T>
+static void char_recon_cells(const orc_params& P, int D, const T C[6][5], double idn, T vl[5], T sl[5],
+                             T vr[5], T sr[5], uint8_t fr[5]) {
+  const int nc = D + 2;
+  T Wb[5], L[5][5], R[5][5];
+  for (int a = 0; a < nc; ++a) Wb[a] = 0.5 * (C[2][a] + C[3][a]);
+  char_basis(D, P.gamma, Wb, 0, L, R);
+  T V[6][5];
+  for (int r = 0; r < 6; ++r) matvec(nc, L, C[r], V[r]);
+  T ol[5][4], orr[5][4];
+  for (int k = 0; k < nc; ++k) {
+    T Ql[5], Qr[5];
+    for (int r = 0; r < 5; ++r) {
+      Ql[r] = V[r][k];
+      Qr[r] = V[r + 1][k];
+    }
+    const uint8_t f0 = select_T(Ql, P.ct1, P.ct2, P.eps, P.q);
+    const uint8_t f1 = select_T(Qr, P.ct1, P.ct2, P.eps, P.q);
+    teno_face_values(Ql, f0, ol[k]);
+    teno_face_values(Qr, f1, orr[k]);
+    fr[k] = f1;
+  }
+  T a[5] = {T(0.0), T(0.0), T(0.0), T(0.0), T(0.0)};
+  for (int k = 0; k < nc; ++k) a[k] = ol[k][2];
+  matvec(nc, R, a, vl);
+  for (int k = 0; k < nc; ++k) a[k] = ol[k][3];
+  matvec(nc, R, a, sl);
+  for (int k = 0; k < nc; ++k) a[k] = orr[k][0];
+  matvec(nc, R, a, vr);
+  for (int k = 0; k < nc; ++k) a[k] = orr[k][1];
+  matvec(nc, R, a, sr);
+  for (int q = 0; q < nc; ++q) {
+    sl[q] = sl[q] * idn;
+    sr[q] = sr[q] * idn;
+  }
+}
+
+// the same for the face at fpos of direction d of the grid
+template <class T>
+static void char_normal_face(const orc_params& P, const Grid& g, const T* W, int d, const int* perm,
+                             const long fpos[3], T vl[5], T sl[5], T vr[5], T sr[5], uint8_t fr[5]) {
+  T C[6][5];
+  for (int r = 0; r < 6; ++r) {
+    long j[3] = {fpos[0], fpos[1], fpos[2]};
+    j[d] += r - 3;
+    cell_frame(g, W, perm, j, C[r]);
+  }
+  char_recon_cells(P, g.D, C, 1.0 / g.dx[d], vl, sl, vr, sr, fr);
+}
+
 // Face-averaged fluxes over every face of direction d for the intervals
 // dt and dt/2, global component order, layout [nc][faces] with faces indexed
 // with the direction-d face index in place of the cell index.
@@ -721,7 +883,73 @@ static long face_fluxes(const orc_params& P, const Grid& g, const T* W, int d, d
     const double wgp = 1.0 / (ngp1 * ngp2);
     // per Gauss point, per side: W, dW/dn, dW/dt1, dW/dt2 in frame order
     T Wg[2][2][2][5], Dg[2][2][2][3][5];
-    for (int side = 0; side < 2; ++side) {
+    if (P.recon == 1) {
+      if (D == 1) {
+        T vl[5], sl[5], vr[5], sr[5];
+        uint8_t fr[5];
+        char_normal_face(P, g, W, d, perm, fpos, vl, sl, vr, sr, fr);
+        if (nflags && fpos[d] < g.n[d])
+          for (int k = 0; k < nc; ++k) nflags[(long)d * nc * g.ncell + (long)k * g.ncell + g.lin(fpos[0], fpos[1], fpos[2])] = fr[k];
+        for (int a = 0; a < nc; ++a) {
+          Wg[0][0][0][a] = vl[a];
+          Dg[0][0][0][0][a] = sl[a];
+          Wg[0][0][1][a] = vr[a];
+          Dg[0][0][1][0][a] = sr[a];
+        }
+      } else {
+        // normal reconstruction (each face of the tangential stencil in its
+        // own normal basis), then the tangential one in the basis along the
+        // face at this face's reference state
+        T X[2][5][5], Xn[2][5][5];  // [side][r][frame component]
+        for (int r = -2; r <= 2; ++r) {
+          long j[3] = {fpos[0], fpos[1], fpos[2]};
+          j[t1] += r;
+          T vl[5], sl[5], vr[5], sr[5];
+          uint8_t fr[5];
+          char_normal_face(P, g, W, d, perm, j, vl, sl, vr, sr, fr);
+          if (r == 0 && nflags && fpos[d] < g.n[d])
+            for (int k = 0; k < nc; ++k) nflags[(long)d * nc * g.ncell + (long)k * g.ncell + g.lin(fpos[0], fpos[1], fpos[2])] = fr[k];
+          for (int a = 0; a < nc; ++a) {
+            X[0][r + 2][a] = vl[a];
+            Xn[0][r + 2][a] = sl[a];
+            X[1][r + 2][a] = vr[a];
+            Xn[1][r + 2][a] = sr[a];
+          }
+        }
+        T Cl[5], Cr[5], Wb[5], L[5][5], R[5][5];
+        cell_frame(g, W, perm, cl, Cl);
+        cell_frame(g, W, perm, cr, Cr);
+        for (int a = 0; a < nc; ++a) Wb[a] = 0.5 * (Cl[a] + Cr[a]);
+        char_basis(D, P.gamma, Wb, 1, L, R);
+        for (int side = 0; side < 2; ++side) {
+          T ow[5][4], on[5][4];
+          for (int qn = 0; qn < 2; ++qn) {
+            T Vr[5][5];  // [r][field]
+            for (int r = 0; r < 5; ++r) matvec(nc, L, qn == 0 ? X[side][r] : Xn[side][r], Vr[r]);
+            for (int k = 0; k < nc; ++k) {
+              T Q[5];
+              for (int r = 0; r < 5; ++r) Q[r] = Vr[r][k];
+              const uint8_t f = select_T(Q, P.ct1_tan, P.ct2_tan, P.eps, P.q);
+              if (tflags) tflags[(((long)qn * 2 + side) * nc + k) * nface + fidx] = f;
+              teno_gauss_values(Q, f, qn == 0 ? ow[k] : on[k]);
+            }
+          }
+          for (int m = 0; m < 2; ++m) {
+            T a[5], b[5];
+            for (int k = 0; k < nc; ++k) a[k] = ow[k][2 * m];
+            matvec(nc, R, a, b);
+            for (int q = 0; q < nc; ++q) Wg[m][0][side][q] = b[q];
+            for (int k = 0; k < nc; ++k) a[k] = ow[k][2 * m + 1];
+            matvec(nc, R, a, b);
+            for (int q = 0; q < nc; ++q) Dg[m][0][side][1][q] = b[q] / dt1;
+            for (int k = 0; k < nc; ++k) a[k] = on[k][2 * m];
+            matvec(nc, R, a, b);
+            for (int q = 0; q < nc; ++q) Dg[m][0][side][0][q] = b[q];
+          }
+        }
+      }
+    }
+    for (int side = 0; side < 2 && P.recon != 1; ++side) {
       const long* cc = side == 0 ? cl : cr;
       const int vo = side == 0 ? 2 : 0;  // +1/2 values of the left cell, -1/2 of the right
       for (int a = 0; a < nc; ++a) {
@@ -950,6 +1178,7 @@ static int check_params(const orc_params* P) {
     if ((P->bc_lo[d] == 0) != (P->bc_hi[d] == 0)) return -1;
   }
   if (!(P->gamma > 1.0)) return -1;
+  if (P->recon < 0 || P->recon > 1 || (P->recon == 1 && P->ndim > 2)) return -1;
   return 0;
 }
 
@@ -1077,6 +1306,40 @@ int orc_gp_flux_dual(const orc_params* P, const double* Wl, const double* Wr, co
 
 // Number of bytes of the flag buffer of one step (normal flags, then for
 // 2-D the tangential flags of both directions).
+// Characteristic basis along frame axis a at the frame-ordered state Wb:
+// L (rows) and R (columns), row-major nc x nc.  Returns 1 for a physical
+// state, 0 when the identity was returned.
+int orc_char_basis(int D, double gamma, const double* Wb, int a, double* L, double* R) {
+  if (D < 1 || D > 3 || a < 0 || a >= D) return -1;
+  double l[5][5], r[5][5];
+  const bool ok = char_basis(D, gamma, Wb, a, l, r);
+  for (int i = 0; i < D + 2; ++i)
+    for (int j = 0; j < D + 2; ++j) {
+      L[i * (D + 2) + j] = l[i][j];
+      R[i * (D + 2) + j] = r[i][j];
+    }
+  return ok ? 1 : 0;
+}
+
+// Characteristic normal reconstruction of one face from six frame-ordered
+// cells C (6 x nc) with cell width dx: out = {vl, sl, vr, sr} (4 x nc).
+int orc_char_recon(const orc_params* P, const double* C, double dx, double* out, uint8_t* fr) {
+  if (!P || P->ndim < 1 || P->ndim > 3) return -1;
+  const int nc = P->ndim + 2;
+  double c[6][5];
+  for (int r = 0; r < 6; ++r)
+    for (int a = 0; a < nc; ++a) c[r][a] = C[r * nc + a];
+  double vl[5], sl[5], vr[5], sr[5];
+  char_recon_cells(*P, P->ndim, c, 1.0 / dx, vl, sl, vr, sr, fr);
+  for (int a = 0; a < nc; ++a) {
+    out[a] = vl[a];
+    out[nc + a] = sl[a];
+    out[2 * nc + a] = vr[a];
+    out[3 * nc + a] = sr[a];
+  }
+  return 0;
+}
+
 long orc_flag_bytes(const orc_params* P) {
   if (check_params(P)) return -1;
   const Grid g(*P);

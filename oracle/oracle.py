@@ -26,7 +26,7 @@ class OrcParams(C.Structure):
         ("gamma", C.c_double), ("mu", C.c_double), ("prandtl", C.c_double),
         ("tau_mode", C.c_int), ("c1", C.c_double), ("c2", C.c_double),
         ("ct1", C.c_double), ("ct2", C.c_double), ("ct1_tan", C.c_double), ("ct2_tan", C.c_double),
-        ("eps", C.c_double), ("q", C.c_int),
+        ("eps", C.c_double), ("q", C.c_int), ("recon", C.c_int),
     ]
 
 
@@ -55,6 +55,8 @@ def lib():
         L.orc_moment_mono.restype = C.c_double
         L.orc_gp_flux.argtypes = [P, dp, dp, dp, dp, C.c_double, C.c_int, dp, dp, dp, dp]
         L.orc_gp_flux_dual.argtypes = [P, dp, dp, dp, dp, dp, dp, dp, dp, C.c_double, C.c_int, dp, dp, dp]
+        L.orc_char_basis.argtypes = [C.c_int, C.c_double, dp, C.c_int, dp, dp]
+        L.orc_char_recon.argtypes = [P, dp, C.c_double, dp, C.c_void_p]
         L.orc_flag_bytes.argtypes = [P]
         L.orc_flag_bytes.restype = C.c_long
         L.orc_step.argtypes = [P, dp, dp, C.c_double, C.c_void_p, C.c_void_p]
@@ -75,9 +77,11 @@ def set_threads(n: int) -> int:
 
 
 def make_params(shape, dx, bc="transmissive", gamma=1.4, mu=0.0, prandtl=1.0, tau="inviscid",
-                c1=0.01, c2=1.0, ct1=1e-7, ct2=1e-5, ct1_tan=None, ct2_tan=None, eps=1e-40, q=7):
+                c1=0.01, c2=1.0, ct1=1e-7, ct2=1e-5, ct1_tan=None, ct2_tan=None, eps=1e-40, q=7,
+                recon=0):
     """shape: cells per axis (x, y, z) truncated to D; bc: one name or a list of
-    (lo, hi) names per axis."""
+    (lo, hi) names per axis; recon: 0 conservative, 1 characteristic variables
+    (1-D, 2-D)."""
     p = OrcParams()
     D = len(shape)
     p.ndim = D
@@ -97,6 +101,7 @@ def make_params(shape, dx, bc="transmissive", gamma=1.4, mu=0.0, prandtl=1.0, ta
     p.ct1_tan = ct1 if ct1_tan is None else ct1_tan
     p.ct2_tan = ct2 if ct2_tan is None else ct2_tan
     p.eps, p.q = eps, q
+    p.recon = int(recon)
     return p
 
 
@@ -124,6 +129,29 @@ def teno_eval(Q, flag, gauss=False):
 
 def teno_select(Q, ct1=1e-7, ct2=1e-5, eps=1e-40, q=7):
     return lib().orc_teno_select(_arr(Q), ct1, ct2, eps, q)
+
+
+def char_basis(D, gamma, Wb, a):
+    """(L, R, ok): left eigenvectors (rows) and right eigenvectors (columns)
+    of the Euler flux Jacobian along frame axis a at the frame-ordered state
+    Wb; the identity and ok = False for a non-physical state."""
+    nc = D + 2
+    L, R = np.zeros((nc, nc)), np.zeros((nc, nc))
+    ok = lib().orc_char_basis(int(D), float(gamma), _arr(Wb), int(a), L.reshape(-1), R.reshape(-1))
+    if ok < 0:
+        raise ValueError("bad arguments")
+    return L, R, bool(ok)
+
+
+def char_recon(P, cells, dx):
+    """Characteristic normal reconstruction of one face from six frame-ordered
+    cells (6 x nc): ({vl, sl, vr, sr} as a 4 x nc array, right-side flags)."""
+    cells = _arr(cells)
+    nc = cells.shape[1]
+    out = np.zeros((4, nc))
+    fr = np.zeros(5, dtype=np.uint8)
+    lib().orc_char_recon(P, cells.reshape(-1), float(dx), out.reshape(-1), fr.ctypes.data)
+    return out, fr[:nc]
 
 
 def beta(Q):
