@@ -56,6 +56,13 @@ extern "C" {
 #define TGKS_TAU_VISCOUS 1
 #define TGKS_TAU_ZERO 2
 
+/* Reconstruction variables: the conservative variables component by
+ * component (the paper's scheme), or the characteristic fields of the
+ * Euler flux Jacobian at the mean of the two cells beside each face
+ * (normal and tangential reconstruction; 1-D and 2-D single grids). */
+#define TGKS_RECON_CONSERVATIVE 0
+#define TGKS_RECON_CHARACTERISTIC 1
+
 typedef struct tgks_params {
   int32_t ndim;      /* 1, 2 or 3 */
   int32_t n[3];      /* cells per axis, >= 3 on every used axis (1 on unused ones) */
@@ -71,6 +78,7 @@ typedef struct tgks_params {
   double ct1_tan, ct2_tan; /* cut-offs of the tangential reconstruction */
   double eps;        /* epsilon of Eq. 4.5 (1e-40) */
   int32_t q;         /* power of Eq. 4.5 (7) */
+  int32_t recon;     /* TGKS_RECON_*; characteristic only with ndim 1 or 2 (default conservative) */
 } tgks_params;
 
 typedef struct tgks_ctx tgks_ctx;
@@ -122,14 +130,16 @@ int tgks_run(tgks_ctx* ctx, double* W, int32_t n_steps, double cfl, double t_end
 
 /* Tile shape of the 2-D face kernel (faces along the normal x along the
  * face, two lanes per face): 0 = 16 x 8, 1 = 16 x 16, 2 = 8 x 16; -1 selects
- * the default (0).  Other dimensions ignore it. */
+ * the default (0).  Other dimensions ignore it; with characteristic
+ * variables the 2-D shape is always 2. */
 int tgks_set_tile(tgks_ctx* ctx, int32_t tile);
 
 /* Autotuner: time every tile shape over `steps` S2O4 steps of the state W
  * (device; not modified) with HIP events, select the fastest and return its
  * index in *chosen (host, may be NULL); ms_per_variant (host, 3 floats, or
- * NULL) receives the milliseconds per step of each shape.  Synchronises the
- * stream. */
+ * NULL) receives the milliseconds per step of each shape (0 for shapes not
+ * timed: with characteristic variables only shape 2 exists).  Synchronises
+ * the stream. */
 int tgks_tune(tgks_ctx* ctx, const double* W, int32_t steps, int32_t* chosen, float* ms_per_variant);
 
 /* Failure count since creation or the last tgks_reset_status (synchronises
@@ -154,7 +164,9 @@ int tgks_kernel_time(tgks_ctx* ctx, int32_t kind, double* ms, int64_t* launches)
  * face beyond the normal reconstruction (tangential reconstruction, the
  * Gauss-point fluxes, the S2O4 combination); out[3], out[4]: stage-1 /
  * stage-2 update per cell; out[5]: transcendentals and out[6]: divisions per
- * stage-1 face; out[7]: CFL limit per cell.  nout >= 8. */
+ * stage-1 face; out[7]: CFL limit per cell.  With characteristic variables
+ * the normal reconstruction is per face: out[0] is 0 and out[1], out[2]
+ * include it.  nout >= 8. */
 int tgks_flop_counts(const tgks_params* p, double* out, int32_t nout);
 
 /* The roofline's two ceilings measured on the current device: FP64 FMA
@@ -186,7 +198,8 @@ int tgks_gp_flux_host(const tgks_params* p, const double* Wl, const double* Wr, 
  * overlap gW_out.  W_star: the step's intermediate state W* as tgks_step
  * returned it for the same W_n and dt (device), or NULL to recompute it with
  * the forward kernels.  The first call allocates the context's reverse-mode
- * buffers.  TGKS_EINVAL for 3-D contexts or invalid pointers. */
+ * buffers.  TGKS_EINVAL for 3-D contexts, characteristic variables or
+ * invalid pointers. */
 int tgks_step_adjoint(tgks_ctx* ctx, const double* W_n, const double* W_star, const double* dt_dev,
                       const double* gW_out, double* gW_in);
 
@@ -212,8 +225,8 @@ int tgks_gp_flux_vjp_host(const tgks_params* p, const double* Wl, const double* 
 typedef struct tgks_batch tgks_batch;
 
 /* per_instance: host array of n_inst parameter sets, all with the same ndim
- * (1 or 2) and all Euler or all Navier-Stokes with a Prandtl correction.
- * Allocates the batch's work buffers (about three packed states plus face
+ * (1 or 2), conservative reconstruction variables, and all Euler or all
+ * Navier-Stokes with a Prandtl correction.  Allocates the batch's work buffers (about three packed states plus face
  * fluxes).  TGKS_EINVAL for invalid or mixed parameters. */
 int tgks_batch_create(const tgks_params* per_instance, int32_t n_inst, void* hip_stream, tgks_batch** out);
 int tgks_batch_destroy(tgks_batch* b);

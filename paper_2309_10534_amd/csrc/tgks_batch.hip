@@ -213,7 +213,7 @@ int tgks_batch_create(const tgks_params* p, int32_t n_inst, void* stream, tgks_b
   if (D != 1 && D != 2) return TGKS_EINVAL;
   const bool ns = p[0].mu > 0.0 && p[0].prandtl != 1.0;
   for (int i = 0; i < n_inst; ++i) {
-    if (check_params(&p[i]) || p[i].ndim != D) return TGKS_EINVAL;
+    if (check_params(&p[i]) || p[i].ndim != D || p[i].recon != TGKS_RECON_CONSERVATIVE) return TGKS_EINVAL;
     if ((p[i].mu > 0.0 && p[i].prandtl != 1.0) != ns) return TGKS_EINVAL;
   }
   tgks_batch* b = new (std::nothrow) tgks_batch();

@@ -47,18 +47,25 @@ int launch_faces(tgks_ctx* c, const double* W, const double* dt, int stage, uint
     if (D == 1) {
       Timer tm(c, 0);
       dim3 grid((unsigned)((c->g.n[0] + 1 + 255) / 256));
-      if (stage == 1) {
-        if (fl) {
-          if (c->ns) LAUNCH((face1d_kernel<1, true, true>), grid, dim3(256), a);
-          else LAUNCH((face1d_kernel<1, false, true>), grid, dim3(256), a);
-        } else {
-          if (c->ns) LAUNCH((face1d_kernel<1, true, false>), grid, dim3(256), a);
-          else LAUNCH((face1d_kernel<1, false, false>), grid, dim3(256), a);
-        }
+#define F1(CH)                                                                  \
+  if (stage == 1) {                                                             \
+    if (fl) {                                                                   \
+      if (c->ns) LAUNCH((face1d_kernel<1, true, true, CH>), grid, dim3(256), a);  \
+      else LAUNCH((face1d_kernel<1, false, true, CH>), grid, dim3(256), a);       \
+    } else {                                                                    \
+      if (c->ns) LAUNCH((face1d_kernel<1, true, false, CH>), grid, dim3(256), a); \
+      else LAUNCH((face1d_kernel<1, false, false, CH>), grid, dim3(256), a);      \
+    }                                                                           \
+  } else {                                                                      \
+    if (c->ns) LAUNCH((face1d_kernel<2, true, false, CH>), grid, dim3(256), a);   \
+    else LAUNCH((face1d_kernel<2, false, false, CH>), grid, dim3(256), a);        \
+  }
+      if (c->p.recon == TGKS_RECON_CHARACTERISTIC) {
+        F1(true)
       } else {
-        if (c->ns) LAUNCH((face1d_kernel<2, true, false>), grid, dim3(256), a);
-        else LAUNCH((face1d_kernel<2, false, false>), grid, dim3(256), a);
+        F1(false)
       }
+#undef F1
     } else if (D == 2) {
       Timer tm(c, ax);
       launch_face2d_any(c, a, ax, stage, fl);
@@ -331,8 +338,93 @@ long long count_face(const tgks_ctx* c, int stage, tgks_opcount::Tally* detail) 
   return tgks_opcount::tally().total();
 }
 
+// Characteristic variables: the face's own normal reconstruction (basis at
+// the face mean state, projection of the six cells, both sides' selections,
+// back-projection) belongs to the face; in 2-D the faces of the tangential
+// stencil are their own work (inputs here), followed by the tangential
+// basis, projections, selections and back-projections of both sides and the
+// two Gauss-point fluxes.
+template <int D, bool NS>
+long long count_face_char(const tgks_ctx* c, int stage, tgks_opcount::Tally* detail) {
+  constexpr int NC = D + 2;
+  constexpr int NG = D == 1 ? 1 : 2;
+  tgks_opcount::graph().reset();
+  F C[6][NC];
+  for (int r = 0; r < 6; ++r)
+    for (int q = 0; q < NC; ++q) C[r][q] = smooth(q < D + 1 ? q : 4, 0.1 * r, 0.0);
+  F vl[NC], sl[NC], vr[NC], sr[NC];
+  unsigned fr[NC];
+  char_recon_face<D>(c->p.gamma, C, c->tn, 1.0 / c->g.dx[0], vl, sl, vr, sr, fr);
+  F Wg[2][2][NC], Dg[2][2][D][NC];
+  if (D == 1) {
+    for (int q = 0; q < NC; ++q) {
+      Wg[0][0][q] = vl[q];
+      Wg[0][1][q] = vr[q];
+      Dg[0][0][0][q] = sl[q];
+      Dg[0][1][0][q] = sr[q];
+    }
+  } else {
+    F Wb[NC], L[NC][NC], R[NC][NC];
+    for (int q = 0; q < NC; ++q) Wb[q] = F(0.5) * (C[2][q] + C[3][q]);
+    char_basis<D, D - 1>(c->p.gamma, Wb, L, R);
+    for (int s = 0; s < 2; ++s) {
+      F X[5][NC], Xn[5][NC];
+      for (int r = 0; r < 5; ++r)
+        for (int q = 0; q < NC; ++q) {
+          X[r][q] = r == 2 ? (s == 0 ? vl[q] : vr[q]) : smooth(q < D + 1 ? q : 4, 0.1 * r, 0.05 * s);
+          Xn[r][q] = r == 2 ? (s == 0 ? sl[q] : sr[q]) : F::input(0.01 * (r + 1) * (q + 1));
+        }
+      F aV[NC][2], aD[NC][2], aN[NC][2];
+      for (int k = 0; k < NC; ++k) {
+        F Qw[5], Qn[5], v[2], dv[2], vn[2], dvn[2];
+        for (int r = 0; r < 5; ++r) {
+          Qw[r] = char_dot<NC>(L[k], X[r]);
+          Qn[r] = char_dot<NC>(L[k], Xn[r]);
+        }
+        teno_gauss(Qw, teno_flag(Qw, c->tt), v, dv);
+        teno_gauss(Qn, teno_flag(Qn, c->tt), vn, dvn);
+        for (int q = 0; q < NC; ++q)
+          for (int g = 0; g < 2; ++g) {
+            aV[q][g] = k == 0 ? R[q][k] * v[g] : aV[q][g] + R[q][k] * v[g];
+            aD[q][g] = k == 0 ? R[q][k] * dv[g] : aD[q][g] + R[q][k] * dv[g];
+            aN[q][g] = k == 0 ? R[q][k] * vn[g] : aN[q][g] + R[q][k] * vn[g];
+          }
+      }
+      for (int g = 0; g < 2; ++g)
+        for (int q = 0; q < NC; ++q) {
+          Wg[g][s][q] = aV[q][g];
+          Dg[g][s][0][q] = aN[q][g];
+          Dg[g][s][D - 1][q] = aD[q][g] * F(1.0 / c->g.dx[1]);
+        }
+    }
+  }
+  FluxCfg fc = c->fc;
+  const F dt(1e-3);
+  F A[NC], B[NC];
+  for (int q = 0; q < NC; ++q) A[q] = B[q] = F(0.0);
+  const double w = 1.0 / NG;
+  for (int m = 0; m < NG; ++m) {
+    F Fdt[NC], Fh[NC];
+    gp_flux<D, NS>(Wg[m][0], Wg[m][1], Dg[m][0], Dg[m][1], fc, dt, Fdt, Fh);
+    for (int q = 0; q < NC; ++q) {
+      if (stage == 1) {
+        A[q] += F(w) * Fh[q];
+        B[q] += F(w) * (F(8.0 / 3.0) * Fh[q] - F(1.0 / 3.0) * Fdt[q]);
+      } else {
+        A[q] += F(w) * (F(4.0 / 3.0) * Fdt[q] - F(8.0 / 3.0) * Fh[q]);
+      }
+    }
+  }
+  if (detail) *detail = tgks_opcount::tally();
+  return tgks_opcount::tally().total();
+}
+
 template <int D>
 long long count_face_dispatch(const tgks_ctx* c, int stage, tgks_opcount::Tally* t) {
+  if constexpr (D <= 2) {
+    if (c->p.recon == TGKS_RECON_CHARACTERISTIC)
+      return c->ns ? count_face_char<D, true>(c, stage, t) : count_face_char<D, false>(c, stage, t);
+  }
   return c->ns ? count_face<D, true>(c, stage, t) : count_face<D, false>(c, stage, t);
 }
 
@@ -623,7 +715,8 @@ int tgks_flop_counts(const tgks_params* p, double* out, int32_t nout) {
     f1 = count_face_dispatch<3>(&c, 1, &t1);
     f2 = count_face_dispatch<3>(&c, 2, nullptr);
   }
-  const long long nr = count_normal(&c);
+  // characteristic variables: the normal reconstruction is part of the face work
+  const long long nr = p->recon == TGKS_RECON_CHARACTERISTIC ? 0 : count_normal(&c);
   const int nc = D + 2;
   out[0] = (double)nr;                       // normal reconstruction, per cell, direction and component
   out[1] = (double)f1;                       // stage-1 face work beyond the normal reconstruction, per face
@@ -683,7 +776,8 @@ int tgks_gp_flux_host(const tgks_params* p, const double* Wl, const double* Wr, 
 
 int tgks_set_tile(tgks_ctx* c, int32_t tile) {
   if (!c || tile < -1 || tile >= NTILE2) return TGKS_EINVAL;
-  const int t = tile < 0 ? 0 : tile;
+  int t = tile < 0 ? 0 : tile;
+  if (c->g.D == 2 && c->p.recon == TGKS_RECON_CHARACTERISTIC) t = CHAR_TILE2;
   if (t != c->tile2 && c->gexec) {
     (void)hipGraphExecDestroy(c->gexec);
     (void)hipGraphDestroy(c->graph);
@@ -710,7 +804,13 @@ int tgks_tune(tgks_ctx* c, const double* W, int32_t steps, int32_t* chosen, floa
   int best = 0;
   float best_ms = 0.f;
   const int old = c->tile2;
+  const bool char2 = c->g.D == 2 && c->p.recon == TGKS_RECON_CHARACTERISTIC;
+  bool first = true;
   for (int k = 0; k < nvar; ++k) {
+    if (char2 && k != CHAR_TILE2) {  // one tile shape on the characteristic path
+      if (ms_per_variant) ms_per_variant[k] = 0.f;
+      continue;
+    }
     c->tile2 = k;
     if ((r = do_step(c, W, c->W2, c->clock + 1, nullptr, false))) break;  // warm-up
     HIPCHK(hipEventRecord(e0, c->stream));
@@ -720,9 +820,10 @@ int tgks_tune(tgks_ctx* c, const double* W, int32_t steps, int32_t* chosen, floa
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, e0, e1));
     if (ms_per_variant) ms_per_variant[k] = ms / steps;
-    if (k == 0 || ms < best_ms) {
+    if (first || ms < best_ms) {
       best = k;
       best_ms = ms;
+      first = false;
     }
   }
   (void)hipEventDestroy(e0);

@@ -182,6 +182,164 @@ TGKS_HD void teno_gauss_at(const R* Q, unsigned flag, int m, R& val, R& der) {
 }
 
 // ---------------------------------------------------------------------------
+// Characteristic variables: an optional choice of reconstruction variables
+// (the paper reconstructs the conservative ones).  At a face the reference
+// state Wb is the mean of the conservative states of the two adjacent cells
+// (frame order: rho, m_0..m_{D-1}, E); the fields are the eigenvectors of the
+// Euler flux Jacobian along frame axis A at Wb (A = 0 normal, A = 1 along
+// the face), ordered u_A - c, entropy, shear waves of the other axes in
+// increasing order, u_A + c.  L holds the left eigenvectors as rows, Rm the
+// right ones as columns (Rm L = I).  Entries, projections and
+// back-projections follow one fixed operation order without contraction
+// (dense left-to-right sums over all components), so that the projected
+// values, and the stencil selections made on them, are a deterministic
+// function of the input bits.  A non-physical Wb gives the identity.
+// ---------------------------------------------------------------------------
+template <int D, int A, class R>
+TGKS_HD bool char_basis(double gamma, const R* Wb, R (*L)[D + 2], R (*Rm)[D + 2]) {
+#pragma clang fp contract(off)
+  constexpr int NC = D + 2, KP = D + 1;
+  const R rho = Wb[0];
+  const R irho = R(1.0) / rho;
+  R u[D];
+#pragma unroll
+  for (int e = 0; e < D; ++e) u[e] = Wb[1 + e] * irho;
+  R q2 = u[0] * u[0];
+#pragma unroll
+  for (int e = 1; e < D; ++e) q2 = q2 + u[e] * u[e];
+  const R E = Wb[D + 1];
+  const R p = (gamma - 1.0) * (E - 0.5 * (rho * q2));
+  const R c2 = (gamma * p) * irho;
+  const bool ok = (rho > 0.0) && (p > 0.0) && (c2 < INFINITY) && (E < INFINITY) && (E > -INFINITY);
+#pragma unroll
+  for (int i = 0; i < NC; ++i)
+#pragma unroll
+    for (int j = 0; j < NC; ++j) L[i][j] = Rm[i][j] = R(0.0);
+  if (!ok) {
+#pragma unroll
+    for (int i = 0; i < NC; ++i) L[i][i] = Rm[i][i] = R(1.0);
+    return false;
+  }
+  const R c = sqrt(c2);
+  const R ic = R(1.0) / c;
+  const R H = (E + p) * irho;
+  const R b1 = (gamma - 1.0) / c2;
+  const R b2 = 0.5 * (b1 * q2);
+  const R un = u[A];
+  const R uc = un * c;
+  L[0][0] = 0.5 * (b2 + un * ic);
+  L[KP][0] = 0.5 * (b2 - un * ic);
+  L[1][0] = 1.0 - b2;
+#pragma unroll
+  for (int e = 0; e < D; ++e) {
+    if (e == A) {
+      L[0][1 + e] = 0.5 * (-(b1 * un) - ic);
+      L[KP][1 + e] = 0.5 * (ic - b1 * un);
+    } else {
+      L[0][1 + e] = 0.5 * (-(b1 * u[e]));
+      L[KP][1 + e] = 0.5 * (-(b1 * u[e]));
+    }
+    L[1][1 + e] = b1 * u[e];
+  }
+  L[0][D + 1] = 0.5 * b1;
+  L[KP][D + 1] = 0.5 * b1;
+  L[1][D + 1] = -b1;
+  int k = 2;
+#pragma unroll
+  for (int s = 0; s < D; ++s) {
+    if (s == A) continue;
+    L[k][0] = -u[s];
+    L[k][1 + s] = R(1.0);
+    Rm[1 + s][k] = R(1.0);
+    Rm[D + 1][k] = u[s];
+    ++k;
+  }
+  Rm[0][0] = R(1.0);
+  Rm[0][1] = R(1.0);
+  Rm[0][KP] = R(1.0);
+#pragma unroll
+  for (int e = 0; e < D; ++e) {
+    Rm[1 + e][0] = e == A ? un - c : u[e];
+    Rm[1 + e][1] = u[e];
+    Rm[1 + e][KP] = e == A ? un + c : u[e];
+  }
+  Rm[D + 1][0] = H - uc;
+  Rm[D + 1][1] = 0.5 * q2;
+  Rm[D + 1][KP] = H + uc;
+  return true;
+}
+
+// y = M x with dense left-to-right sums, no contraction
+template <int NC, class R>
+TGKS_HD void char_mv(const R (*M)[NC], const R* x, R* y) {
+#pragma clang fp contract(off)
+#pragma unroll
+  for (int i = 0; i < NC; ++i) {
+    R v = M[i][0] * x[0];
+#pragma unroll
+    for (int j = 1; j < NC; ++j) v = v + M[i][j] * x[j];
+    y[i] = v;
+  }
+}
+
+// one row: l . x
+template <int NC, class R>
+TGKS_HD R char_dot(const R* l, const R* x) {
+#pragma clang fp contract(off)
+  R v = l[0] * x[0];
+#pragma unroll
+  for (int j = 1; j < NC; ++j) v = v + l[j] * x[j];
+  return v;
+}
+
+// Normal reconstruction of both sides of one face in characteristic
+// variables, from the six frame-ordered cells C[0..5] = f-3 .. f+2 along the
+// normal: values and slopes (slopes per unit length, idn = 1/dx) in frame
+// order; fr = selection flags of the right side (cell f at its low face).
+template <int D, class R>
+TGKS_HD void char_recon_face(double gamma, const R (*C)[D + 2], const TenoCfg& tn, double idn, R* vl, R* sl,
+                             R* vr, R* sr, unsigned* fr) {
+  constexpr int NC = D + 2;
+  R Wb[NC], L[NC][NC], Rm[NC][NC];
+  {
+#pragma clang fp contract(off)
+#pragma unroll
+    for (int q = 0; q < NC; ++q) Wb[q] = 0.5 * (C[2][q] + C[3][q]);
+  }
+  char_basis<D, 0>(gamma, Wb, L, Rm);
+  R ol[NC][4], orr[NC][4];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    R V[6];
+#pragma unroll
+    for (int r = 0; r < 6; ++r) V[r] = char_dot<NC>(L[k], C[r]);
+    const unsigned f0 = teno_flag(V, tn);
+    const unsigned f1 = teno_flag(V + 1, tn);
+    teno_face(V, f0, ol[k]);
+    teno_face(V + 1, f1, orr[k]);
+    fr[k] = f1;
+  }
+  R a[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) a[k] = ol[k][2];
+  char_mv<NC>(Rm, a, vl);
+#pragma unroll
+  for (int k = 0; k < NC; ++k) a[k] = ol[k][3];
+  char_mv<NC>(Rm, a, sl);
+#pragma unroll
+  for (int k = 0; k < NC; ++k) a[k] = orr[k][0];
+  char_mv<NC>(Rm, a, vr);
+#pragma unroll
+  for (int k = 0; k < NC; ++k) a[k] = orr[k][1];
+  char_mv<NC>(Rm, a, sr);
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+    sl[q] = sl[q] * idn;
+    sr[q] = sr[q] * idn;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Gas-kinetic flux at one Gauss point (Sec. 2.1), face frame: u1 is normal.
 // ---------------------------------------------------------------------------
 struct FluxCfg {

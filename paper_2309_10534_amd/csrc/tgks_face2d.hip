@@ -56,7 +56,35 @@ static void launch_face2d_xy(tgks_ctx* c, const StageArgs& ax, const StageArgs& 
 #undef LXY
 }
 
+// characteristic variables: one tile shape
+static void launch_face2d_xy_char(tgks_ctx* c, const StageArgs& ax, const StageArgs& ay, int stage, bool fl) {
+  constexpr int TILE = CHAR_TILE2;
+  constexpr int TN = tile2_tn(TILE), TT = tile2_tt(TILE);
+  const int nx = c->g.n[0], ny = c->g.n[1];
+  const long long nb = (long long)((nx + 1 + TN - 1) / TN) * ((ny + TT - 1) / TT) +
+                       (long long)((ny + 1 + TN - 1) / TN) * ((nx + TT - 1) / TT);
+  const dim3 grid((unsigned)nb), block(2 * TN * TT);
+#define LXY(kern) hipLaunchKernelGGL(kern, grid, block, 0, c->stream, ax, ay)
+  if (stage == 1) {
+    if (fl) {
+      if (c->ns) LXY((face2d_xy_kernel<1, true, true, TILE, true>));
+      else LXY((face2d_xy_kernel<1, false, true, TILE, true>));
+    } else {
+      if (c->ns) LXY((face2d_xy_kernel<1, true, false, TILE, true>));
+      else LXY((face2d_xy_kernel<1, false, false, TILE, true>));
+    }
+  } else {
+    if (c->ns) LXY((face2d_xy_kernel<2, true, false, TILE, true>));
+    else LXY((face2d_xy_kernel<2, false, false, TILE, true>));
+  }
+#undef LXY
+}
+
 int launch_face2d_xy_any(tgks_ctx* c, const StageArgs& ax, const StageArgs& ay, int stage, bool fl) {
+  if (c->p.recon == TGKS_RECON_CHARACTERISTIC) {
+    launch_face2d_xy_char(c, ax, ay, stage, fl);
+    return TGKS_OK;
+  }
   switch (c->tile2) {
     case 1:
       launch_face2d_xy<1>(c, ax, ay, stage, fl);

@@ -85,6 +85,8 @@ inline int check_params(const tgks_params* p) {
   if (p->tau_mode < 0 || p->tau_mode > 2) return TGKS_EINVAL;
   if (p->tau_mode == TGKS_TAU_VISCOUS && !(p->mu > 0.0)) return TGKS_EINVAL;
   if (p->q < 1 || p->q > 16 || !(p->eps >= 0.0)) return TGKS_EINVAL;
+  if (p->recon != TGKS_RECON_CONSERVATIVE && p->recon != TGKS_RECON_CHARACTERISTIC) return TGKS_EINVAL;
+  if (p->recon == TGKS_RECON_CHARACTERISTIC && p->ndim > 2) return TGKS_EINVAL;
   double cells = 1.0;
   for (int d = 0; d < p->ndim; ++d) cells *= p->n[d];
   if (cells > 4.0e9) return TGKS_EINVAL;
@@ -139,6 +141,7 @@ inline StageArgs stage_args(tgks_ctx* c, const double* W, int ax, const double* 
   a.tflags = nullptr;
   a.R = c->R;
   a.Rout = c->R;
+  a.gamma = c->p.gamma;
   return a;
 }
 

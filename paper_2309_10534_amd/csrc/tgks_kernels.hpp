@@ -36,6 +36,7 @@ struct StageArgs {
   uint8_t* tflags;  // tangential flags of this direction or null
   const double* R;  // 3-D: normal reconstruction of this direction
   double* Rout;
+  double gamma;     // ratio of specific heats (characteristic variables)
 };
 
 __device__ __forceinline__ long long face_count(const Geom& g, int ax) {
@@ -74,7 +75,7 @@ __device__ __forceinline__ void write_combined(int STAGE, const double* Fdt, con
 // ---------------------------------------------------------------------------
 // 1-D: one thread per face.
 // ---------------------------------------------------------------------------
-template <int STAGE, bool NS, bool FLAGS>
+template <int STAGE, bool NS, bool FLAGS, bool CHAR = false>
 __device__ __forceinline__ void face1d_body(const StageArgs& a, int f) {
   const double dt = *a.dt;
   if (!(dt > 0.0)) return;
@@ -82,21 +83,34 @@ __device__ __forceinline__ void face1d_body(const StageArgs& a, int f) {
   if (f > n) return;
   double Wl[3], Wr[3], dWl[1][3], dWr[1][3];
   const double idx = 1.0 / a.g.dx[0];  // normal slopes per unit length
+  if (CHAR) {
+    double C[6][3];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    double Q[6];
+    for (int r = 0; r < 6; ++r)
 #pragma unroll
-    for (int r = 0; r < 6; ++r) Q[r] = load_cell(a.g, a.W, c, f - 3 + r, 0, 0);
-    double o[4];
-    const unsigned fl = teno_flag(Q, a.tn);
-    teno_face(Q, fl, o);
-    Wl[c] = o[2];
-    dWl[0][c] = o[3] * idx;
-    const unsigned fr = teno_flag(Q + 1, a.tn);
-    teno_face(Q + 1, fr, o);
-    Wr[c] = o[0];
-    dWr[0][c] = o[1] * idx;
-    if (FLAGS && f < n) a.nflags[(long long)c * n + f] = (uint8_t)fr;
+      for (int c = 0; c < 3; ++c) C[r][c] = load_cell(a.g, a.W, c, f - 3 + r, 0, 0);
+    unsigned fr[3];
+    char_recon_face<1>(a.gamma, C, a.tn, idx, Wl, dWl[0], Wr, dWr[0], fr);
+    if (FLAGS && f < n)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) a.nflags[(long long)k * n + f] = (uint8_t)fr[k];
+  } else {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      double Q[6];
+#pragma unroll
+      for (int r = 0; r < 6; ++r) Q[r] = load_cell(a.g, a.W, c, f - 3 + r, 0, 0);
+      double o[4];
+      const unsigned fl = teno_flag(Q, a.tn);
+      teno_face(Q, fl, o);
+      Wl[c] = o[2];
+      dWl[0][c] = o[3] * idx;
+      const unsigned fr = teno_flag(Q + 1, a.tn);
+      teno_face(Q + 1, fr, o);
+      Wr[c] = o[0];
+      dWr[0][c] = o[1] * idx;
+      if (FLAGS && f < n) a.nflags[(long long)c * n + f] = (uint8_t)fr;
+    }
   }
   double Fdt[3], Fh[3], A[3] = {0, 0, 0}, B[3] = {0, 0, 0};
   const bool ok = gp_flux<1, NS>(Wl, Wr, dWl, dWr, a.fc, dt, Fdt, Fh);
@@ -110,9 +124,9 @@ __device__ __forceinline__ void face1d_body(const StageArgs& a, int f) {
   }
 }
 
-template <int STAGE, bool NS, bool FLAGS>
+template <int STAGE, bool NS, bool FLAGS, bool CHAR = false>
 __global__ __launch_bounds__(256) void face1d_kernel(StageArgs a) {
-  face1d_body<STAGE, NS, FLAGS>(a, blockIdx.x * blockDim.x + threadIdx.x);
+  face1d_body<STAGE, NS, FLAGS, CHAR>(a, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -126,6 +140,7 @@ __global__ __launch_bounds__(256) void face1d_kernel(StageArgs a) {
 // Tile shapes (faces along the normal x faces along the tangential axis),
 // two lanes per face; chosen per grid by the autotuner.
 constexpr int NTILE2 = 3;
+constexpr int CHAR_TILE2 = 2;  // the one tile shape of the characteristic path
 __host__ __device__ constexpr int tile2_tn(int k) { return k == 0 ? 16 : (k == 1 ? 16 : 8); }
 __host__ __device__ constexpr int tile2_tt(int k) { return k == 0 ? 8 : (k == 1 ? 16 : 16); }
 
@@ -135,9 +150,17 @@ __host__ __device__ constexpr int tile2_lds(int k) {
   return 4 * (tile2_tt(k) + 4) * (tile2_tn(k) + 5) + 4 * (tile2_tt(k) + 4) * (tile2_tn(k) + 1) * 4;
 }
 
+// ... plus, with characteristic variables, the per-face field values of both
+// sides and the right eigenvectors of every staged face row
+__host__ __device__ constexpr int tile2_lds_char(int k) {
+  return tile2_lds(k) + 4 * (tile2_tt(k) + 4) * tile2_tn(k) * 4 + (tile2_tt(k) + 4) * tile2_tn(k) * 16;
+}
+
 // (bx, by): tile index along the normal and the tangential axis; lds: the
-// block's tile2_lds(TILE) doubles of shared memory
-template <int AX, int STAGE, bool NS, bool FLAGS, int TILE>
+// block's tile2_lds(TILE) (CHAR: tile2_lds_char(TILE)) doubles of shared
+// memory.  CHAR: reconstruction in characteristic variables (steps 2 and 3
+// below project onto the fields of each face and back).
+template <int AX, int STAGE, bool NS, bool FLAGS, int TILE, bool CHAR = false>
 __device__ __forceinline__ void face2d_tile(const StageArgs& a, int bx, int by, double* lds) {
   constexpr int TN = tile2_tn(TILE), TT = tile2_tt(TILE), NT = 2 * TN * TT;
   constexpr int NC = 4;
@@ -171,23 +194,98 @@ __device__ __forceinline__ void face2d_tile(const StageArgs& a, int bx, int by, 
 
   // 2. normal reconstruction of cells f0-1 .. f0+TN-1 on every staged row
   const double idn = 1.0 / g.dx[AX];  // normal slopes per unit length
-  for (int L = tid; L < NC * LT * RN; L += NT) {
-    const int nr = L % RN;
-    const int tl = (L / RN) % LT;
-    const int c = L / (RN * LT);
-    const double* Q = &sW[c][tl][nr];
-    const unsigned fl = teno_flag(Q, a.tn);
-    double o[4];
-    teno_face(Q, fl, o);
-    sR[c][tl][nr][0] = o[0];
-    sR[c][tl][nr][1] = o[1] * idn;
-    sR[c][tl][nr][2] = o[2];
-    sR[c][tl][nr][3] = o[3] * idn;
-    if (FLAGS) {
-      const int cell = f0 - 1 + nr, row = t0 - 2 + tl;
-      if (nr >= 1 && cell < nN && tl >= 2 && tl < TT + 2 && row < nT) {
-        const long long lin = AX == 0 ? (long long)row * g.n[0] + cell : (long long)cell * g.n[0] + row;
-        a.nflags[((long long)AX * NC + c) * g.ncell + lin] = (uint8_t)fl;
+  const int perm[NC] = {0, 1 + AX, 1 + TA, 3};
+  if (CHAR) {
+    // per face and row: the fields of the face's normal basis.  (a) one
+    // thread per (side, row, face) projects the side's five cells, selects
+    // and reconstructs every field; the left-side thread also keeps the
+    // right eigenvectors.  (b) one thread per (component, row, face) projects
+    // back.  Same slots of sR as the conservative path: face fn's left state
+    // in cell slot fn (high face), its right state in slot fn + 1 (low face).
+    double(*sV)[LT][TN][4] = reinterpret_cast<double(*)[LT][TN][4]>(lds + tile2_lds(TILE));
+    double(*sM)[TN][16] = reinterpret_cast<double(*)[TN][16]>(lds + tile2_lds(TILE) + NC * LT * TN * 4);
+    for (int L = tid; L < 2 * LT * TN; L += NT) {
+      const int fn = L % TN;
+      const int tl = (L / TN) % LT;
+      const int sd = L / (TN * LT);
+      double C[6][NC];
+#pragma unroll
+      for (int r = 0; r < 6; ++r)
+#pragma unroll
+        for (int q = 0; q < NC; ++q) C[r][q] = sW[perm[q]][tl][fn + r];
+      double Wb[NC], Lm[NC][NC], Rm[NC][NC];
+      {
+#pragma clang fp contract(off)
+#pragma unroll
+        for (int q = 0; q < NC; ++q) Wb[q] = 0.5 * (C[2][q] + C[3][q]);
+      }
+      char_basis<2, 0>(a.gamma, Wb, Lm, Rm);
+#pragma unroll
+      for (int k = 0; k < NC; ++k) {
+        double V[5];
+#pragma unroll
+        for (int r = 0; r < 5; ++r) V[r] = char_dot<NC>(Lm[k], sd == 0 ? C[r] : C[r + 1]);
+        const unsigned fl = teno_flag(V, a.tn);
+        double o[4];
+        teno_face(V, fl, o);
+        if (sd == 0) {
+          sV[k][tl][fn][0] = o[2];
+          sV[k][tl][fn][1] = o[3];
+        } else {
+          sV[k][tl][fn][2] = o[0];
+          sV[k][tl][fn][3] = o[1];
+          if (FLAGS) {
+            const int cell = f0 + fn, row = t0 - 2 + tl;
+            if (cell < nN && tl >= 2 && tl < TT + 2 && row < nT) {
+              const long long lin = AX == 0 ? (long long)row * g.n[0] + cell : (long long)cell * g.n[0] + row;
+              a.nflags[((long long)AX * NC + k) * g.ncell + lin] = (uint8_t)fl;
+            }
+          }
+        }
+      }
+      if (sd == 0)
+#pragma unroll
+        for (int q = 0; q < NC; ++q)
+#pragma unroll
+          for (int k = 0; k < NC; ++k) sM[tl][fn][q * NC + k] = Rm[q][k];
+    }
+    __syncthreads();
+    for (int L = tid; L < NC * LT * TN; L += NT) {
+      const int fn = L % TN;
+      const int tl = (L / TN) % LT;
+      const int q = L / (TN * LT);
+      const double* rq = &sM[tl][fn][q * NC];
+      double x[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const double v[NC] = {sV[0][tl][fn][j], sV[1][tl][fn][j], sV[2][tl][fn][j], sV[3][tl][fn][j]};
+        x[j] = char_dot<NC>(rq, v);
+      }
+      const int c = q == 0 ? perm[0] : (q == 1 ? perm[1] : (q == 2 ? perm[2] : perm[3]));
+      sR[c][tl][fn][2] = x[0];
+      sR[c][tl][fn][3] = x[1] * idn;
+      sR[c][tl][fn + 1][0] = x[2];
+      sR[c][tl][fn + 1][1] = x[3] * idn;
+    }
+  } else {
+    for (int L = tid; L < NC * LT * RN; L += NT) {
+      const int nr = L % RN;
+      const int tl = (L / RN) % LT;
+      const int c = L / (RN * LT);
+      const double* Q = &sW[c][tl][nr];
+      const unsigned fl = teno_flag(Q, a.tn);
+      double o[4];
+      teno_face(Q, fl, o);
+      sR[c][tl][nr][0] = o[0];
+      sR[c][tl][nr][1] = o[1] * idn;
+      sR[c][tl][nr][2] = o[2];
+      sR[c][tl][nr][3] = o[3] * idn;
+      if (FLAGS) {
+        const int cell = f0 - 1 + nr, row = t0 - 2 + tl;
+        if (nr >= 1 && cell < nN && tl >= 2 && tl < TT + 2 && row < nT) {
+          const long long lin = AX == 0 ? (long long)row * g.n[0] + cell : (long long)cell * g.n[0] + row;
+          a.nflags[((long long)AX * NC + c) * g.ncell + lin] = (uint8_t)fl;
+        }
       }
     }
   }
@@ -202,14 +300,73 @@ __device__ __forceinline__ void face2d_tile(const StageArgs& a, int bx, int by, 
   const int fn = fi % TN, ft = fi / TN;
   const int f = f0 + fn, t = t0 + ft;
   const bool live = f <= nN && t < nT;
-  const int perm[NC] = {0, 1 + AX, 1 + TA, 3};
   const long long nf = face_count(g, AX);
   const long long fidx = AX == 0 ? (long long)t * (g.n[0] + 1) + f : (long long)f * g.n[0] + t;
   const double idt = 1.0 / g.dx[TA];
   double Wg[2][NC], Dg[2][2][NC];  // [side][q], [side][axis n/t][q]
-  {
-    const int nr = m == 0 ? fn : fn + 1;
-    const int vo = m == 0 ? 2 : 0;
+  const int nr = m == 0 ? fn : fn + 1;
+  const int vo = m == 0 ? 2 : 0;
+  if (CHAR) {
+    // fields of the basis along the face at this face's reference state
+    // (cells f-1 and f of row t); each field of W and of W_n is selected and
+    // evaluated at both Gauss points, then projected back
+    double aV[NC][2], aD[NC][2], aN[NC][2];
+#pragma unroll
+    for (int q = 0; q < NC; ++q) aV[q][0] = aV[q][1] = aD[q][0] = aD[q][1] = aN[q][0] = aN[q][1] = 0.0;
+    if (live) {
+      double Wb[NC], Lt[NC][NC], Rt[NC][NC];
+      {
+#pragma clang fp contract(off)
+#pragma unroll
+        for (int q = 0; q < NC; ++q) Wb[q] = 0.5 * (sW[perm[q]][ft + 2][fn + 2] + sW[perm[q]][ft + 2][fn + 3]);
+      }
+      char_basis<2, 1>(a.gamma, Wb, Lt, Rt);
+#pragma unroll
+      for (int k = 0; k < NC; ++k) {
+        double Qw[5], Qn[5];
+#pragma unroll
+        for (int r = 0; r < 5; ++r) {
+          double xw[NC], xn[NC];
+#pragma unroll
+          for (int q = 0; q < NC; ++q) {
+            xw[q] = sR[perm[q]][ft + r][nr][vo];
+            xn[q] = sR[perm[q]][ft + r][nr][vo + 1];
+          }
+          Qw[r] = char_dot<NC>(Lt[k], xw);
+          Qn[r] = char_dot<NC>(Lt[k], xn);
+        }
+        const unsigned fw = teno_flag(Qw, a.tt);
+        const unsigned fq = teno_flag(Qn, a.tt);
+        if (FLAGS) {
+          a.tflags[((long long)(0 * 2 + m) * NC + k) * nf + fidx] = (uint8_t)fw;
+          a.tflags[((long long)(1 * 2 + m) * NC + k) * nf + fidx] = (uint8_t)fq;
+        }
+        double v[2], dv[2], vn[2], dvn[2];
+        teno_gauss(Qw, fw, v, dv);
+        teno_gauss(Qn, fq, vn, dvn);
+#pragma unroll
+        for (int q = 0; q < NC; ++q)
+#pragma unroll
+          for (int gp = 0; gp < 2; ++gp) {
+            aV[q][gp] = aV[q][gp] + Rt[q][k] * v[gp];
+            aD[q][gp] = aD[q][gp] + Rt[q][k] * dv[gp];
+            aN[q][gp] = aN[q][gp] + Rt[q][k] * vn[gp];
+          }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      const double sv = aV[q][1 - m], sd = aD[q][1 - m], sn = aN[q][1 - m];
+      const double rv = __shfl_xor(sv, 1), rd = __shfl_xor(sd, 1), rn = __shfl_xor(sn, 1);
+      const double ov = aV[q][m], od = aD[q][m], on = aN[q][m];
+      Wg[0][q] = m == 0 ? ov : rv;
+      Wg[1][q] = m == 0 ? rv : ov;
+      Dg[0][1][q] = (m == 0 ? od : rd) * idt;
+      Dg[1][1][q] = (m == 0 ? rd : od) * idt;
+      Dg[0][0][q] = m == 0 ? on : rn;
+      Dg[1][0][q] = m == 0 ? rn : on;
+    }
+  } else {
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
       const int c = perm[q];
@@ -272,19 +429,19 @@ __global__ __launch_bounds__(2 * tile2_tn(TILE) * tile2_tt(TILE), 2) void face2d
 // Both directions in one launch: the first blocks take the x-face tiles,
 // the rest the y-face tiles (one shared LDS tile), so that neither
 // direction waits for the other's tail.
-template <int STAGE, bool NS, bool FLAGS, int TILE>
+template <int STAGE, bool NS, bool FLAGS, int TILE, bool CHAR = false>
 __global__ __launch_bounds__(2 * tile2_tn(TILE) * tile2_tt(TILE), 2) void face2d_xy_kernel(StageArgs ax,
                                                                                            StageArgs ay) {
   constexpr int TN = tile2_tn(TILE);
-  __shared__ double lds[tile2_lds(TILE)];
+  __shared__ double lds[CHAR ? tile2_lds_char(TILE) : tile2_lds(TILE)];
   const int nbx = (ax.g.n[0] + 1 + TN - 1) / TN;          // x faces: tiles along x
   const int nx = nbx * ((ax.g.n[1] + tile2_tt(TILE) - 1) / tile2_tt(TILE));
   const int b = blockIdx.x;
   if (b < nx) {
-    face2d_tile<0, STAGE, NS, FLAGS, TILE>(ax, b % nbx, b / nbx, lds);
+    face2d_tile<0, STAGE, NS, FLAGS, TILE, CHAR>(ax, b % nbx, b / nbx, lds);
   } else {
     const int nby = (ay.g.n[1] + 1 + TN - 1) / TN;        // y faces: tiles along y
-    face2d_tile<1, STAGE, NS, FLAGS, TILE>(ay, (b - nx) % nby, (b - nx) / nby, lds);
+    face2d_tile<1, STAGE, NS, FLAGS, TILE, CHAR>(ay, (b - nx) % nby, (b - nx) / nby, lds);
   }
 }
 

@@ -30,7 +30,7 @@ class TgksParams(C.Structure):
         ("gamma", C.c_double), ("mu", C.c_double), ("prandtl", C.c_double),
         ("tau_mode", C.c_int32), ("c1", C.c_double), ("c2", C.c_double),
         ("ct1", C.c_double), ("ct2", C.c_double), ("ct1_tan", C.c_double), ("ct2_tan", C.c_double),
-        ("eps", C.c_double), ("q", C.c_int32),
+        ("eps", C.c_double), ("q", C.c_int32), ("recon", C.c_int32),
     ]
 
 
@@ -125,7 +125,8 @@ def _ptr(t, numel=None, dtype=None):
 
 def tgks_params_default(ndim, shape=None, dx=None, bc="transmissive", **kw):
     """tgks_params filled with the paper's constants; shape / dx / bc / keyword
-    fields (gamma, mu, prandtl, tau, c1, c2, ct1, ct2, ct1_tan, ct2_tan, eps, q)
+    fields (gamma, mu, prandtl, tau, c1, c2, ct1, ct2, ct1_tan, ct2_tan, eps, q,
+    recon: 0 conservative, 1 characteristic variables)
     override them."""
     p = TgksParams()
     _check(lib().tgks_params_default(C.byref(p), int(ndim)), "tgks_params_default")

@@ -60,3 +60,19 @@ def test_create_rejects_invalid_parameters_without_device(lib):
     p = tgks.tgks_params_default(1, [10], [0.1])
     p.bc_lo[0], p.bc_hi[0] = tgks.BC_PERIODIC, tgks.BC_TRANSMISSIVE
     assert lib.tgks_create(ctypes.byref(p), None, ctypes.byref(h)) == -1
+
+
+def test_reconstruction_variables_option(lib):
+    """Characteristic variables: accepted in 1-D and 2-D, rejected in 3-D
+    and for unknown values (before any device work); the operation counts
+    move the normal reconstruction into the per-face work."""
+    from paper_2309_10534_amd import tgks
+    h = ctypes.c_void_p()
+    for nd, recon in ((3, 1), (2, 2), (1, -1)):
+        p = tgks.tgks_params_default(nd, [8] * nd, [0.1] * nd, recon=recon)
+        assert lib.tgks_create(ctypes.byref(p), None, ctypes.byref(h)) == -1
+    for nd in (1, 2):
+        cons = tgks.tgks_flop_counts(tgks.tgks_params_default(nd, [8] * nd, [0.1] * nd))
+        char = tgks.tgks_flop_counts(tgks.tgks_params_default(nd, [8] * nd, [0.1] * nd, recon=1))
+        assert char["normal"] == 0.0 and cons["normal"] > 0.0
+        assert char["face"] > cons["face"] + 2 * (nd + 2) * cons["normal"]

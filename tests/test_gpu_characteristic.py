@@ -1,0 +1,130 @@
+"""GPU parity of the characteristic-variable reconstruction option against
+the oracle (1-D and 2-D): one step on identical input, L1-relative <= 1e-10
+per component, stage-1 selection flags (per characteristic field) bit for
+bit; rejection where the option does not exist (3-D, batched runs, reverse
+mode)."""
+import numpy as np
+import pytest
+
+from gpu_common import GpuProblem, assert_close, orc_params, problem
+from paper_2309_10534_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    return torch
+
+
+def compare_step(orc, pr, W, dt, tol=1e-10):
+    gp = GpuProblem(pr)
+    try:
+        print(f"[char] step shape={pr['shape']} bc={pr['bc']} tau={pr['tau']}", flush=True)
+        Wg, Wsg, fg, badg = gp.step(W, dt, flags=True)
+    finally:
+        gp.close()
+    Wo, fo, Wso, bado = orc.step(orc_params(orc, pr), W, dt, want_flags=True, want_wstar=True)
+    assert np.all(np.isfinite(Wo)), "test input drives the oracle to a non-physical state"
+    assert_close(Wsg, Wso, tol, "W*")
+    assert_close(Wg, Wo, tol, "W^{n+1}")
+    assert badg == bado
+    mism = np.flatnonzero(fg != fo)
+    assert mism.size == 0, f"{mism.size} flag mismatches, first at {mism[:10]}"
+
+
+def test_sod(orc, torch_dev):
+    W, dx = I.sod(400)
+    pr = problem([400], [dx], recon=1)
+    compare_step(orc, pr, W, orc.cfl_dt(orc_params(orc, pr), W, 0.5))
+
+
+@pytest.mark.parametrize("bc", ["periodic", "reflective", "transmissive"])
+def test_1d_ragged_random(orc, torch_dev, bc):
+    rng = np.random.default_rng(3)
+    n = 301
+    rho = np.exp(rng.uniform(np.log(0.5), np.log(2.0), n))
+    u = rng.uniform(-0.5, 0.5, n)
+    p = np.exp(rng.uniform(np.log(0.5), np.log(2.0), n))
+    W = I.conservative(rho, [u], p)
+    pr = problem([n], [1.0 / n], bc=bc, recon=1)
+    compare_step(orc, pr, W, 0.2 * orc.cfl_dt(orc_params(orc, pr), W, 0.5))
+
+
+def test_1d_navier_stokes(orc, torch_dev):
+    W, dx = I.riemann_1d(97, (1.0, 0.2, 1.0), (0.5, -0.1, 0.6))
+    pr = problem([97], [dx], tau="viscous", mu=2e-3, prandtl=0.72, recon=1)
+    compare_step(orc, pr, W, 0.3 * orc.cfl_dt(orc_params(orc, pr), W, 0.5))
+
+
+QUAD = [(0.9, 0.3, -0.2, 1.0), (0.4, -0.5, 0.1, 0.3), (1.7, 0.2, 0.6, 1.2), (0.6, 0.9, -0.7, 0.5)]
+
+
+@pytest.mark.parametrize("nx,ny", [(70, 45), (33, 17)])
+def test_2d_quadrants(orc, torch_dev, nx, ny):
+    W = I.quadrant_field(nx, ny, QUAD)
+    pr = problem([nx, ny], [1.0 / nx, 1.0 / ny], recon=1)
+    compare_step(orc, pr, W, orc.cfl_dt(orc_params(orc, pr), W, 0.5))
+
+
+def test_2d_seeded_riemann(orc, torch_dev):
+    W, dx, _ = I.quadrant_riemann(48, seed=1)
+    pr = problem([48, 48], [dx, dx], recon=1)
+    compare_step(orc, pr, W, orc.cfl_dt(orc_params(orc, pr), W, 0.5))
+
+
+def smooth_2d(nx, ny, seed=0):
+    rng = np.random.default_rng(seed)
+    x = (np.arange(nx) + 0.5) / nx
+    y = (np.arange(ny) + 0.5) / ny
+    X, Y = np.meshgrid(x, y)
+    rho = 1.0 + 0.3 * np.sin(2 * np.pi * (X + 2 * Y)) + 0.02 * rng.normal(size=X.shape)
+    u = 0.4 * np.cos(2 * np.pi * Y)
+    v = -0.3 + 0.2 * np.sin(2 * np.pi * X)
+    p = 1.0 + 0.2 * np.cos(2 * np.pi * (X - Y))
+    return I.conservative(rho, [u, v], p)
+
+
+@pytest.mark.parametrize("bc", ["periodic", [("reflective", "transmissive"), ("periodic", "periodic")]])
+def test_2d_boundaries(orc, torch_dev, bc):
+    W = smooth_2d(37, 29)
+    pr = problem([37, 29], [1 / 37, 1 / 29], bc=bc, recon=1)
+    compare_step(orc, pr, W, 0.5 * orc.cfl_dt(orc_params(orc, pr), W, 0.5))
+
+
+def test_2d_navier_stokes(orc, torch_dev):
+    W = smooth_2d(35, 19, seed=2)
+    pr = problem([35, 19], [1 / 35, 1 / 19], bc="periodic", tau="viscous", mu=5e-3, prandtl=0.72, recon=1)
+    compare_step(orc, pr, W, orc.cfl_dt(orc_params(orc, pr), W, 0.5))
+
+
+def test_2d_minimum_grid(orc, torch_dev):
+    rng = np.random.default_rng(5)
+    rho = np.exp(rng.uniform(np.log(0.7), np.log(1.4), (3, 3)))
+    p = np.exp(rng.uniform(np.log(0.7), np.log(1.4), (3, 3)))
+    W = I.conservative(rho, [rng.uniform(-0.3, 0.3, (3, 3)) for _ in range(2)], p)
+    pr = problem([3, 3], [1 / 3, 1 / 3], bc="reflective", recon=1)
+    compare_step(orc, pr, W, 0.2 * orc.cfl_dt(orc_params(orc, pr), W, 0.5))
+
+
+def test_rejected_where_absent(torch_dev):
+    import torch
+    from paper_2309_10534_amd import tgks
+    with pytest.raises(tgks.TgksError):
+        tgks.tgks_create(tgks.tgks_params_default(3, [8, 8, 8], [0.1] * 3, bc="periodic", recon=1))
+    p = tgks.tgks_params_default(1, [32], [1 / 32], recon=1)
+    with pytest.raises(tgks.TgksError):
+        tgks.tgks_batch_create([p, p])
+    ctx = tgks.tgks_create(p)
+    try:
+        W0, dx = I.sod(32)
+        W = torch.from_numpy(W0).cuda()
+        g = torch.ones_like(W)
+        dt = torch.full((1,), 1e-3, dtype=torch.float64, device="cuda")
+        with pytest.raises(tgks.TgksError):
+            tgks.tgks_step_adjoint(ctx, W, dt, g, torch.empty_like(g))
+    finally:
+        tgks.tgks_destroy(ctx)
