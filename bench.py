@@ -17,6 +17,7 @@ region) and the CPU oracle timed on a bounded sample on the host cores.
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -36,8 +37,8 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector peak (256 CU x 2.4 GHz x 128 flop/
 # the three files below); the bench reports null traffic otherwise.
 TRAFFIC_SOURCES = ("paper_2309_10534_amd/csrc/tgks_device.hpp", "paper_2309_10534_amd/csrc/tgks_kernels.hpp",
                    "paper_2309_10534_amd/csrc/tgks_face2d.hip")
-TRAFFIC = {"sha": "be651f0cbd9456d2", "tile": 2, "fetch_factor": 32768.0 / 16397.8, "write_factor": 1.0,
-           "face_xy": {"fetch_kib": 128489.4, "write_kib": 116847.0}}
+TRAFFIC = {"sha": "0ec44377f4cc61aa", "tile": 2, "fetch_factor": 32768.0 / 16397.6, "write_factor": 1.0,
+           "face_xy": {"fetch_kib": 128471.5, "write_kib": 116854.5}}
 
 
 def measured_traffic(kernel, tile):
@@ -71,6 +72,7 @@ def parse():
     ap.add_argument("--no-3d", action="store_true", help="skip the 3-D Taylor-Green workload")
     ap.add_argument("--tgv-steps", type=int, default=200, help="timed steps of the 3-D Taylor-Green workload")
     ap.add_argument("--no-sod", action="store_true", help="skip the 1-D Sod latency workload")
+    ap.add_argument("--no-char", action="store_true", help="skip the characteristic-variable workload")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     return ap.parse_args()
 
@@ -170,6 +172,82 @@ def batched(dim, seed, n_inst, steps, ranges=None):
         "speedup": round(t_single / t_batch, 3),
         "bitwise_equal_instances": same,
     }
+
+
+def characteristic(n=1024, seed=1, steps=100, n_inst=256):
+    """Characteristic-variable reconstruction (option): the 2-D
+    four-quadrant workload (n^2, `seed`, CFL 0.5, `steps` steps from t = 0)
+    timed with characteristic and with conservative variables, the face
+    kernel's roofline with characteristic variables, and the instances of
+    the seeded batched Riemann sets (1-D seed 1, 2-D seed 2, the stated
+    ranges) that run `steps` single-grid steps without a non-physical state
+    under each choice."""
+    import numpy as np
+    import torch
+
+    from paper_2309_10534_amd import inputs as I
+    from paper_2309_10534_amd import tgks
+
+    W0, dx, _ = I.quadrant_riemann(n, seed=seed)
+    W0d = torch.from_numpy(W0).cuda()
+    out = {"workload": f"2d_euler_four_quadrant_riemann_{n}x{n}_seed{seed}_{steps}_steps"}
+    for recon in (1, 0):
+        p = tgks.tgks_params_default(2, [n, n], [dx, dx], recon=recon)
+        ctx = tgks.tgks_create(p)
+        W = W0d.clone()
+        tgks.tgks_run(ctx, W, 2, cfl=0.5)  # warm-up
+        torch.cuda.synchronize()
+        W.copy_(W0d)
+        tgks.tgks_reset_status(ctx)
+        tgks.tgks_timing(ctx, recon == 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tgks.tgks_run(ctx, W, steps, cfl=0.5)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        fails = tgks.tgks_status(ctx)
+        if recon == 1:
+            ms, launches = tgks.tgks_kernel_time(ctx, "face_x")
+            tgks.tgks_timing(ctx, False)
+            fl = tgks.tgks_flop_counts(p)
+            per_launch = 2 * (n + 1) * n * 0.5 * (fl["face"] + fl["face_stage2"])
+            avg_s = ms / 1e3 / max(launches, 1)
+            out.update({"value": round(n * n * steps / el / 1e6, 3), "unit": "Mcell-updates/s",
+                        "ms_per_step": round(el * 1e3 / steps, 4), "failures": fails,
+                        "finite": bool(torch.isfinite(W).all().item()),
+                        "face_kernel": {"bound": "alu", "achieved": round(per_launch / avg_s / 1e12, 3),
+                                        "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                        "frac": round(per_launch / avg_s / 1e12 / FP64_PEAK_TFLOPS, 4),
+                                        "flops_per_face": fl["face"], "flops_per_launch": per_launch,
+                                        "avg_launch_ms": round(ms / max(launches, 1), 5)}})
+        else:
+            out["conservative_value"] = round(n * n * steps / el / 1e6, 3)
+        tgks.tgks_destroy(ctx)
+    out["cost_ratio"] = round(out["conservative_value"] / out["value"], 3)
+
+    free = {}
+    for dim, iseed in ((1, 1), (2, 2)):
+        inst, _, _ = I.riemann_instances(n_inst, dim=dim, seed=iseed)
+        counts = {}
+        for recon, name in ((0, "conservative"), (1, "characteristic")):
+            ok = 0
+            td = torch.zeros(2, dtype=torch.float64, device="cuda")
+            for Wi, dxi in inst:
+                p = tgks.tgks_params_default(dim, list(Wi.shape[1:])[::-1], [dxi] * dim, recon=recon)
+                ctx = tgks.tgks_create(p)
+                W = torch.from_numpy(np.ascontiguousarray(Wi)).cuda()
+                td.zero_()
+                tgks.tgks_run(ctx, W, steps, cfl=0.5, time_dev=td)
+                # every step taken (a non-physical cell makes dt NaN and
+                # stops the clock), no failing Gauss point, finite state
+                last_dt = float(td[1].cpu())
+                ok += int(tgks.tgks_status(ctx) == 0 and last_dt > 0.0 and math.isfinite(last_dt)
+                          and bool(torch.isfinite(W).all().item()))
+                tgks.tgks_destroy(ctx)
+            counts[name] = ok
+        free[f"{dim}d_riemann_{n_inst}_instances_seed{iseed}_{steps}_steps"] = counts
+    out["instances_failure_free"] = free
+    return out
 
 
 def sod1d(n=400, t_end=0.2, reps=5):
@@ -442,6 +520,8 @@ def main():
         out["tgv3d"] = tgv3d(steps=args.tgv_steps)
     if not args.no_sod:
         out["sod1d"] = sod1d()
+    if not args.no_char:
+        out["characteristic"] = characteristic()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W0, dx, n, args.cpu_seconds)
     print(json.dumps(out), flush=True)
