@@ -34,7 +34,8 @@
 // Readings where the paper is silent or garbled:
 //  * Eq. 2.5 pairs g_r with H(u); the upwind reading g_l H(u), g_r (1-H(u)) is
 //    used, consistent with Eq. 2.6.  Eqs. 3.25-3.26 integrate g^r over u<0.
-//  * Reconstruction acts component-wise on the conservative variables.
+//  * Reconstruction acts component-wise on the conservative variables (an
+//    option reconstructs characteristic fields instead, see below).
 //  * Cut-off "0 if chi < C_T, 1 otherwise" is evaluated as
 //    !(gamma_k < C_T * sum gamma) (no division, ties keep the stencil).
 //  * The smoothness quantities and the candidate values are evaluated with a
