@@ -47,6 +47,13 @@
 //    (1/Pr - 1) * q with q the time-integrated heat flux of f about U0.
 //  * A reconstructed or equilibrium state with rho <= 0, p <= 0 or a
 //    non-finite value at a Gauss point is counted as a failure.
+//  * The no-slip adiabatic wall of the viscous shock tube (Sec. 5.8): ghost
+//    cells mirror the interior with every momentum component negated (zero
+//    velocity and zero normal temperature gradient at the wall), and the
+//    mass and energy fluxes through the wall faces are zero (impermeable;
+//    at rest it does no work, adiabatic it conducts no heat); the momentum
+//    flux is the flux of the mirrored states.  The symmetry condition there
+//    is the reflective kind.
 
 #include <algorithm>
 #include <cmath>
@@ -101,7 +108,7 @@ typedef struct {
   int ndim;
   int n[3];
   double dx[3];
-  int bc_lo[3], bc_hi[3];  // 0 periodic, 1 transmissive, 2 reflective
+  int bc_lo[3], bc_hi[3];  // 0 periodic, 1 transmissive, 2 reflective, 3 no-slip adiabatic wall
   double gamma, mu, prandtl;
   int tau_mode;            // 0 inviscid c1 dt + c2 |dp|/(sum p) dt, 1 viscous mu/p0 + ..., 2 zero
   double c1, c2;
@@ -642,8 +649,9 @@ struct Grid {
       ncell *= n[d];
     }
   }
-  // map index i along axis d into the interior; *flip set when the normal
-  // momentum of axis d changes sign (reflective wall).
+  // map index i along axis d into the interior; *flip = 1 behind a
+  // reflective wall (the momentum normal to it changes sign), 2 behind a
+  // no-slip adiabatic wall (every momentum component changes sign).
   long map(int d, long i, int* flip) const {
     const long N = n[d];
     if (d >= D) return 0;
@@ -651,7 +659,7 @@ struct Grid {
     const int bc = i < 0 ? bclo[d] : bchi[d];
     if (bc == 0) return ((i % N) + N) % N;
     if (bc == 1) return i < 0 ? 0 : N - 1;
-    *flip ^= 1;
+    *flip ^= bc == 3 ? 2 : 1;
     return i < 0 ? -1 - i : 2 * N - 1 - i;
   }
   long lin(long i, long j, long k) const { return (k * n[1] + j) * n[0] + i; }
@@ -663,7 +671,11 @@ static T cell(const Grid& g, const T* W, int c, const long idx[3]) {
   long m[3];
   for (int d = 0; d < 3; ++d) m[d] = g.map(d, idx[d], &fl[d]);
   T v = W[c * g.ncell + g.lin(m[0], m[1], m[2])];
-  if (c >= 1 && c <= g.D && fl[c - 1]) v = -v;
+  if (c >= 1 && c <= g.D) {
+    bool neg = fl[c - 1] == 1;
+    for (int d = 0; d < g.D; ++d) neg ^= fl[d] == 2;
+    if (neg) v = -v;
+  }
   return v;
 }
 
@@ -1046,6 +1058,11 @@ static long face_fluxes(const orc_params& P, const Grid& g, const T* W, int d, d
         for (int i = 0; i < 2; ++i)
           for (int a = 0; a < nc; ++a) acc[i][a] += wgp * F[i][a];
       }
+    // a no-slip adiabatic wall is impermeable and, at rest, does no work
+    // and conducts no heat: no mass or energy crosses it
+    const bool wall = (fpos[d] == 0 && g.bclo[d] == 3) || (fpos[d] == g.n[d] && g.bchi[d] == 3);
+    if (wall)
+      for (int i = 0; i < 2; ++i) acc[i][0] = acc[i][nc - 1] = T(0.0);
     for (int a = 0; a < nc; ++a) {
       Fdt[(size_t)perm[a] * nface + fidx] = acc[0][a];
       Fh[(size_t)perm[a] * nface + fidx] = acc[1][a];
@@ -1175,7 +1192,7 @@ static int check_params(const orc_params* P) {
   if (!P || P->ndim < 1 || P->ndim > 3) return -1;
   for (int d = 0; d < P->ndim; ++d) {
     if (P->n[d] < 3 || !(P->dx[d] > 0)) return -1;
-    if (P->bc_lo[d] < 0 || P->bc_lo[d] > 2 || P->bc_hi[d] < 0 || P->bc_hi[d] > 2) return -1;
+    if (P->bc_lo[d] < 0 || P->bc_lo[d] > 3 || P->bc_hi[d] < 0 || P->bc_hi[d] > 3) return -1;
     if ((P->bc_lo[d] == 0) != (P->bc_hi[d] == 0)) return -1;
   }
   if (!(P->gamma > 1.0)) return -1;

@@ -15,7 +15,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 
-BC = {"periodic": 0, "transmissive": 1, "reflective": 2}
+BC = {"periodic": 0, "transmissive": 1, "reflective": 2, "noslip": 3}
 TAU = {"inviscid": 0, "viscous": 1, "zero": 2}
 
 
