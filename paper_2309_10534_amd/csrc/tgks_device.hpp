@@ -903,8 +903,12 @@ TGKS_HD bool gp_flux(const R* Wl, const R* Wr, const R (*dWl)[D + 2], const R (*
 
 // ---------------------------------------------------------------------------
 // Boundary index map (ghost cells): periodic, transmissive (copy of the
-// nearest cell) or reflective (mirror image, normal momentum negated).
+// nearest cell), reflective (mirror image; flip = 1: the momentum normal to
+// the wall changes sign) or a no-slip adiabatic wall (mirror image; flip =
+// 2: every momentum component changes sign).
 // ---------------------------------------------------------------------------
+constexpr int BC_NOSLIP = 3;  // boundary kind of the no-slip adiabatic wall
+
 TGKS_HD int map_index(int i, int n, int bclo, int bchi, int& flip) {
   if (i >= 0 && i < n) return i;
   const int bc = i < 0 ? bclo : bchi;
@@ -913,7 +917,7 @@ TGKS_HD int map_index(int i, int n, int bclo, int bchi, int& flip) {
     return r < 0 ? r + n : r;
   }
   if (bc == 1) return i < 0 ? 0 : n - 1;
-  flip ^= 1;
+  flip ^= bc == BC_NOSLIP ? 2 : 1;
   // mirror image; cells farther than n outside are never used by a face and
   // are clamped into the domain so that every load stays in bounds
   const int r = i < 0 ? -1 - i : 2 * n - 1 - i;

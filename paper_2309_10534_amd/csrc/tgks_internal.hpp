@@ -75,7 +75,7 @@ inline int check_params(const tgks_params* p) {
   for (int d = 0; d < 3; ++d) {
     if (d < p->ndim) {
       if (p->n[d] < 3 || !(p->dx[d] > 0.0)) return TGKS_EINVAL;
-      if (p->bc_lo[d] < 0 || p->bc_lo[d] > 2 || p->bc_hi[d] < 0 || p->bc_hi[d] > 2) return TGKS_EINVAL;
+      if (p->bc_lo[d] < 0 || p->bc_lo[d] > 3 || p->bc_hi[d] < 0 || p->bc_hi[d] > 3) return TGKS_EINVAL;
       if ((p->bc_lo[d] == TGKS_BC_PERIODIC) != (p->bc_hi[d] == TGKS_BC_PERIODIC)) return TGKS_EINVAL;
     } else if (p->n[d] != 1) {
       return TGKS_EINVAL;

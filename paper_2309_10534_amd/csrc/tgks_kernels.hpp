@@ -53,8 +53,12 @@ __device__ __forceinline__ double load_cell(const Geom& g, const double* W, int 
   const int jj = g.D >= 2 ? map_index(j, g.n[1], g.bclo[1], g.bchi[1], f1) : 0;
   const int kk = g.D >= 3 ? map_index(k, g.n[2], g.bclo[2], g.bchi[2], f2) : 0;
   double v = W[(long long)c * g.ncell + ((long long)kk * g.n[1] + jj) * g.n[0] + ii];
-  const int fl = c == 1 ? f0 : c == 2 ? f1 : c == 3 ? f2 : 0;
-  if (c >= 1 && c <= g.D && fl) v = -v;
+  if (c >= 1 && c <= g.D) {
+    // a reflective wall negates the momentum normal to it, a no-slip wall
+    // every momentum component
+    const int fo = c == 1 ? f0 : (c == 2 ? f1 : f2);
+    if ((fo == 1) ^ (f0 == 2) ^ (f1 == 2) ^ (f2 == 2)) v = -v;
+  }
   return v;
 }
 
@@ -69,6 +73,17 @@ __device__ __forceinline__ void write_combined(int STAGE, const double* Fdt, con
     } else {
       accA[q] += w * ((4.0 / 3.0) * Fdt[q] - (8.0 / 3.0) * Fh[q]);
     }
+  }
+}
+
+// A no-slip adiabatic wall is impermeable and, at rest, does no work and
+// conducts no heat: the mass and energy fluxes of its faces are zero (frame
+// components 0 and NC-1); f: face index along the normal axis ax.
+template <int NC>
+__device__ __forceinline__ void wall_fluxes(const Geom& g, int ax, int f, double* accA, double* accB) {
+  if ((f == 0 && g.bclo[ax] == BC_NOSLIP) || (f == g.n[ax] && g.bchi[ax] == BC_NOSLIP)) {
+    accA[0] = accA[NC - 1] = 0.0;
+    accB[0] = accB[NC - 1] = 0.0;
   }
 }
 
@@ -116,6 +131,7 @@ __device__ __forceinline__ void face1d_body(const StageArgs& a, int f) {
   const bool ok = gp_flux<1, NS>(Wl, Wr, dWl, dWr, a.fc, dt, Fdt, Fh);
   if (!ok) atomicAdd(a.fail, 1ull);
   write_combined<3>(STAGE, Fdt, Fh, 1.0, A, B);
+  wall_fluxes<3>(a.g, 0, f, A, B);
   const long long nf = n + 1;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
@@ -411,6 +427,7 @@ __device__ __forceinline__ void face2d_tile(const StageArgs& a, int bx, int by, 
     A[q] += __shfl_xor(A[q], 1);
     if (STAGE == 1) B[q] += __shfl_xor(B[q], 1);
   }
+  wall_fluxes<NC>(g, AX, f, A, B);
   if (live && m == 0) {
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
@@ -547,7 +564,8 @@ __global__ __launch_bounds__(L3 * B3_1 * B3_2, 2) void face3d_kernel(StageArgs a
     const long long off = ((long long)e[2] * ext[1] + e[1]) * ext[0] + e[0];
     const int vo = s == 0 ? 2 : 0;
     double v = a.R[(long long)c * 4 * nr + (vo + k) * nr + off];
-    if ((c == 1 + T1 && f1) ^ (c == 1 + T2 && f2)) v = -v;
+    const bool mom = c >= 1 && c <= 3;
+    if ((c == 1 + T1 && f1 == 1) ^ (c == 1 + T2 && f2 == 1) ^ (mom && f1 == 2) ^ (mom && f2 == 2)) v = -v;
     sR[s][c][k][i2][i1] = v;
   }
   __syncthreads();
@@ -680,6 +698,7 @@ __global__ __launch_bounds__(L3 * B3_1 * B3_2, 2) void face3d_kernel(StageArgs a
       B[q] += __shfl_xor(B[q], 4);
     }
   }
+  wall_fluxes<NC>(g, AX, fa, A, B);
   if (live && (tid & 7) == 0) {
     int nfa[3] = {g.n[0], g.n[1], g.n[2]};
     nfa[AX] += 1;

@@ -84,6 +84,19 @@ def riemann_1d(n, left, right, x0=0.5, gamma=GAMMA):
     return np.ascontiguousarray(W), 1.0 / n
 
 
+def viscous_shock_tube(nx, ny, gamma=GAMMA):
+    """Viscous shock tube (Sec. 5.8): [0, 1] x [0, 1/2], nx x ny cells,
+    (rho, U, p) = (120, 0, 120/gamma) for x < 1/2 and (1.2, 0, 1.2/gamma) for
+    x > 1/2 (area-weighted across the membrane).  Returns (W [4][ny][nx],
+    dx); square cells need ny = nx / 2."""
+    W1, dx = riemann_1d(nx, (120.0, 0.0, 120.0 / gamma), (1.2, 0.0, 1.2 / gamma), gamma=gamma)
+    W = np.zeros((4, ny, nx))
+    W[0] = W1[0][None, :]
+    W[1] = W1[1][None, :]
+    W[3] = W1[2][None, :]
+    return W, dx
+
+
 def quadrant_states(rng, rho_range=(0.1, 2.0), vel_range=(-1.0, 1.0), p_range=(0.03, 1.5)):
     """Four (rho, u, v, p) states drawn in quadrant order (x<1/2,y<1/2), (>=,<),
     (>=,>=), (<,>=); rho and p log-uniform, velocities uniform."""

@@ -14,9 +14,9 @@ import os
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libtgks.so")
 
-BC_PERIODIC, BC_TRANSMISSIVE, BC_REFLECTIVE = 0, 1, 2
+BC_PERIODIC, BC_TRANSMISSIVE, BC_REFLECTIVE, BC_NOSLIP = 0, 1, 2, 3
 TAU_INVISCID, TAU_VISCOUS, TAU_ZERO = 0, 1, 2
-_BC = {"periodic": 0, "transmissive": 1, "reflective": 2}
+_BC = {"periodic": 0, "transmissive": 1, "reflective": 2, "noslip": 3}
 _TAU = {"inviscid": 0, "viscous": 1, "zero": 2}
 
 KERNEL_KINDS = {"face_x": 0, "face_y": 1, "face_z": 2, "recon3d": 3, "update1": 4, "update2": 5, "cfl": 6}
