@@ -73,6 +73,7 @@ def parse():
     ap.add_argument("--tgv-steps", type=int, default=200, help="timed steps of the 3-D Taylor-Green workload")
     ap.add_argument("--no-sod", action="store_true", help="skip the 1-D Sod latency workload")
     ap.add_argument("--no-char", action="store_true", help="skip the characteristic-variable workload")
+    ap.add_argument("--no-vst", action="store_true", help="skip the viscous shock tube")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     return ap.parse_args()
 
@@ -247,6 +248,63 @@ def characteristic(n=1024, seed=1, steps=100, n_inst=256):
             counts[name] = ok
         free[f"{dim}d_riemann_{n_inst}_instances_seed{iseed}_{steps}_steps"] = counts
     out["instances_failure_free"] = free
+    return out
+
+
+def viscous_shock_tube(nx=500, re=200.0, t_end=1.0, cfl=0.2, chunk=200):
+    """Viscous shock tube (Sec. 5.8): [0, 1] x [0, 1/2], nx x nx/2 cells,
+    Re 200 (mu = 1/Re), Pr 0.73, no-slip adiabatic walls left, right and at
+    the bottom, symmetry at the top, CFL 0.2 to t = 1, with conservative and
+    with characteristic reconstruction variables: time reached, failures,
+    steps and throughput; the density along the bottom wall at t = 1 is
+    summarised (the paper shows it only as a figure)."""
+    import numpy as np
+    import torch
+
+    from paper_2309_10534_amd import inputs as I
+    from paper_2309_10534_amd import tgks
+
+    ny = nx // 2
+    W0, dx = I.viscous_shock_tube(nx, ny)
+    bc = [("noslip", "noslip"), ("noslip", "reflective")]
+    out = {"workload": f"2d_ns_viscous_shock_tube_{nx}x{ny}_re{re:g}_pr0.73_cfl{cfl:g}_to_t{t_end:g}"}
+    td = torch.zeros(2, dtype=torch.float64, device="cuda")
+    xc = (np.arange(nx) + 0.5) * dx
+    for recon, name in ((0, "conservative"), (1, "characteristic")):
+        p = tgks.tgks_params_default(2, [nx, ny], [dx, dx], bc=bc, mu=1.0 / re, prandtl=0.73, tau="viscous",
+                                     recon=recon)
+        ctx = tgks.tgks_create(p)
+        W = torch.from_numpy(W0).cuda()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        # chunks of steps (every tgks_run starts its clock at 0, so each
+        # chunk is clipped to the time still to go), single steps near the
+        # end so that the step count is exact; a non-physical state stops
+        # the clock (dt NaN) and ends the run
+        t_done, steps, last_dt = 0.0, 0, None
+        while t_end - t_done > 1e-14 * t_end and steps < 200000:
+            rest = t_end - t_done
+            n = chunk if last_dt is None or rest > (chunk + 5) * last_dt else 1
+            td.zero_()
+            tgks.tgks_run(ctx, W, n, cfl=cfl, t_end=rest, time_dev=td)
+            adv, last_dt = float(td[0].cpu()), float(td[1].cpu())
+            if not (adv > 0.0) or not math.isfinite(adv) or not math.isfinite(last_dt):
+                break
+            t_done += adv
+            steps += n
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        fails = tgks.tgks_status(ctx)
+        tgks.tgks_destroy(ctx)
+        rho = W[0].cpu().numpy()
+        wall = rho[0]
+        out[name] = {"t_reached": t_done, "failures": fails, "finite": bool(torch.isfinite(W).all().item()),
+                     "steps": steps, "seconds": round(el, 3),
+                     "value": round(nx * ny * steps / el / 1e6, 3), "unit": "Mcell-updates/s",
+                     "rho_bottom_wall": {"max": round(float(wall.max()), 4),
+                                         "x_at_max": round(float(xc[wall.argmax()]), 4),
+                                         "min": round(float(wall.min()), 4)},
+                     "rho_domain": {"max": round(float(rho.max()), 4), "min": round(float(rho.min()), 4)}}
     return out
 
 
@@ -522,6 +580,8 @@ def main():
         out["sod1d"] = sod1d()
     if not args.no_char:
         out["characteristic"] = characteristic()
+    if not args.no_vst:
+        out["viscous_shock_tube"] = viscous_shock_tube()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W0, dx, n, args.cpu_seconds)
     print(json.dumps(out), flush=True)
