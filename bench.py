@@ -37,8 +37,8 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector peak (256 CU x 2.4 GHz x 128 flop/
 # the three files below); the bench reports null traffic otherwise.
 TRAFFIC_SOURCES = ("paper_2309_10534_amd/csrc/tgks_device.hpp", "paper_2309_10534_amd/csrc/tgks_kernels.hpp",
                    "paper_2309_10534_amd/csrc/tgks_face2d.hip")
-TRAFFIC = {"sha": "0ec44377f4cc61aa", "tile": 2, "fetch_factor": 32768.0 / 16397.6, "write_factor": 1.0,
-           "face_xy": {"fetch_kib": 128471.5, "write_kib": 116854.5}}
+TRAFFIC = {"sha": "2d64fef0c7f65e5e", "tile": 2, "fetch_factor": 32768.0 / 16397.7, "write_factor": 1.0,
+           "face_xy": {"fetch_kib": 128489.6, "write_kib": 116845.4}}
 
 
 def measured_traffic(kernel, tile):
@@ -53,6 +53,18 @@ def measured_traffic(kernel, tile):
         return None
     t = TRAFFIC[kernel]
     return round(1024.0 * (t["fetch_kib"] * TRAFFIC["fetch_factor"] + t["write_kib"] * TRAFFIC["write_factor"]))
+
+
+def strict_json(x):
+    """The same structure with every non-finite float replaced by None (the
+    line must be strict JSON)."""
+    if isinstance(x, dict):
+        return {k: strict_json(v) for k, v in x.items()}
+    if isinstance(x, (list, tuple)):
+        return [strict_json(v) for v in x]
+    if isinstance(x, float) and not math.isfinite(x):
+        return None
+    return x
 
 
 def parse():
@@ -296,15 +308,17 @@ def viscous_shock_tube(nx=500, re=200.0, t_end=1.0, cfl=0.2, chunk=200):
         el = time.perf_counter() - t0
         fails = tgks.tgks_status(ctx)
         tgks.tgks_destroy(ctx)
-        rho = W[0].cpu().numpy()
-        wall = rho[0]
-        out[name] = {"t_reached": t_done, "failures": fails, "finite": bool(torch.isfinite(W).all().item()),
+        finite = bool(torch.isfinite(W).all().item())
+        out[name] = {"t_reached": t_done, "failures": fails, "finite": finite,
                      "steps": steps, "seconds": round(el, 3),
-                     "value": round(nx * ny * steps / el / 1e6, 3), "unit": "Mcell-updates/s",
-                     "rho_bottom_wall": {"max": round(float(wall.max()), 4),
-                                         "x_at_max": round(float(xc[wall.argmax()]), 4),
-                                         "min": round(float(wall.min()), 4)},
-                     "rho_domain": {"max": round(float(rho.max()), 4), "min": round(float(rho.min()), 4)}}
+                     "value": round(nx * ny * steps / el / 1e6, 3), "unit": "Mcell-updates/s"}
+        if finite and fails == 0:
+            rho = W[0].cpu().numpy()
+            wall = rho[0]
+            out[name]["rho_bottom_wall"] = {"max": round(float(wall.max()), 4),
+                                            "x_at_max": round(float(xc[wall.argmax()]), 4),
+                                            "min": round(float(wall.min()), 4)}
+            out[name]["rho_domain"] = {"max": round(float(rho.max()), 4), "min": round(float(rho.min()), 4)}
     return out
 
 
@@ -584,7 +598,7 @@ def main():
         out["viscous_shock_tube"] = viscous_shock_tube()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W0, dx, n, args.cpu_seconds)
-    print(json.dumps(out), flush=True)
+    print(json.dumps(strict_json(out), allow_nan=False), flush=True)
 
 
 if __name__ == "__main__":
