@@ -115,7 +115,7 @@ def cpu_baseline(W0, dx, n, target_s):
                       f"of the same initial field, {el:.1f} s"}
 
 
-def batched(dim, seed, n_inst, steps, ranges=None):
+def batched(dim, seed, n_inst, steps, ranges=None, recon=0):
     """Batched set of seeded uneven Riemann instances (1-D: N ~ U{64..1024};
     2-D: N x N, N ~ U{64..512}; rho log-uniform [0.1, 10], p log-uniform
     [0.01, 1000], velocities uniform [-2, 2]; transmissive, CFL 0.5): one
@@ -132,7 +132,7 @@ def batched(dim, seed, n_inst, steps, ranges=None):
 
     inst, rej, _ = I.riemann_instances(n_inst, dim=dim, seed=seed, **(ranges or {}))
     shapes = [W.shape for W, _ in inst]
-    params = [tgks.tgks_params_default(dim, list(W.shape[1:])[::-1], [dx] * dim) for W, dx in inst]
+    params = [tgks.tgks_params_default(dim, list(W.shape[1:])[::-1], [dx] * dim, recon=recon) for W, dx in inst]
     cells = np.array([W[0].size for W, _ in inst], dtype=np.int64)
     b = tgks.tgks_batch_create(params)
     W0 = torch.from_numpy(tgks.pack([W for W, _ in inst])).cuda()
@@ -173,7 +173,8 @@ def batched(dim, seed, n_inst, steps, ranges=None):
     updates = int((cells * taken).sum())
     return {
         "workload": f"batched_{dim}d_riemann_{n_inst}_instances_seed{seed}_{steps}_steps"
-                    + ("" if ranges is None else "_" + "_".join(f"{k}{v[0]}-{v[1]}" for k, v in ranges.items())),
+                    + ("" if ranges is None else "_" + "_".join(f"{k}{v[0]}-{v[1]}" for k, v in ranges.items()))
+                    + ("_characteristic" if recon else ""),
         "cells": int(cells.sum()), "cell_updates": updates,
         "instances_failure_free": int(sum(1 for f, k in zip(fails, taken) if f == 0 and k == steps)),
         "rejected_draws": rej,
@@ -260,6 +261,8 @@ def characteristic(n=1024, seed=1, steps=100, n_inst=256):
             counts[name] = ok
         free[f"{dim}d_riemann_{n_inst}_instances_seed{iseed}_{steps}_steps"] = counts
     out["instances_failure_free"] = free
+    # the 2-D set as one batch with characteristic variables
+    out["batched_2d"] = batched(2, 2, n_inst, steps, recon=1)
     return out
 
 

@@ -63,7 +63,7 @@ extern "C" {
 /* Reconstruction variables: the conservative variables component by
  * component (the paper's scheme), or the characteristic fields of the
  * Euler flux Jacobian at the mean of the two cells beside each face
- * (normal and tangential reconstruction; 1-D and 2-D single grids). */
+ * (normal and tangential reconstruction; 1-D and 2-D grids and batches). */
 #define TGKS_RECON_CONSERVATIVE 0
 #define TGKS_RECON_CHARACTERISTIC 1
 
@@ -229,8 +229,9 @@ int tgks_gp_flux_vjp_host(const tgks_params* p, const double* Wl, const double* 
 typedef struct tgks_batch tgks_batch;
 
 /* per_instance: host array of n_inst parameter sets, all with the same ndim
- * (1 or 2), conservative reconstruction variables, and all Euler or all
- * Navier-Stokes with a Prandtl correction.  Allocates the batch's work buffers (about three packed states plus face
+ * (1 or 2), the same reconstruction variables, and all Euler or all
+ * Navier-Stokes with a Prandtl correction (characteristic variables: one
+ * 2-D tile shape, 2).  Allocates the batch's work buffers (about three packed states plus face
  * fluxes).  TGKS_EINVAL for invalid or mixed parameters. */
 int tgks_batch_create(const tgks_params* per_instance, int32_t n_inst, void* hip_stream, tgks_batch** out);
 int tgks_batch_destroy(tgks_batch* b);

@@ -13,6 +13,7 @@ using namespace tgks;
 struct tgks_batch {
   int D = 0, nc = 0, ninst = 0;
   bool ns = false;
+  bool chr = false;  // characteristic reconstruction variables
   int tile2 = 0;
   hipStream_t stream = nullptr;
   std::vector<BatchInst> host;   // per instance (offsets in doubles)
@@ -97,19 +98,19 @@ static BatchArgs batch_args(tgks_batch* b, const double* W, double* o1, double* 
 
 #define BLAUNCH(kern, nblk, threads, args) hipLaunchKernelGGL(kern, dim3((unsigned)(nblk)), dim3(threads), 0, b->stream, args)
 
-template <int TILE>
+template <int TILE, bool CHAR = false>
 static void batch_face2d(tgks_batch* b, const double* W, int ax, int stage) {
   constexpr int NT = 2 * tile2_tn(TILE) * tile2_tt(TILE);
   const int nw = b->nwface[TILE][ax];
   if (nw == 0) return;
   BatchArgs a = batch_args(b, W, nullptr, nullptr, b->wface[TILE][ax]);
-#define BF2(AXV)                                                                            \
-  if (stage == 1) {                                                                         \
-    if (b->ns) BLAUNCH((batch_face2d_kernel<AXV, 1, true, TILE>), nw, NT, a);               \
-    else BLAUNCH((batch_face2d_kernel<AXV, 1, false, TILE>), nw, NT, a);                    \
-  } else {                                                                                  \
-    if (b->ns) BLAUNCH((batch_face2d_kernel<AXV, 2, true, TILE>), nw, NT, a);               \
-    else BLAUNCH((batch_face2d_kernel<AXV, 2, false, TILE>), nw, NT, a);                    \
+#define BF2(AXV)                                                                                  \
+  if (stage == 1) {                                                                               \
+    if (b->ns) BLAUNCH((batch_face2d_kernel<AXV, 1, true, TILE, CHAR>), nw, NT, a);               \
+    else BLAUNCH((batch_face2d_kernel<AXV, 1, false, TILE, CHAR>), nw, NT, a);                    \
+  } else {                                                                                        \
+    if (b->ns) BLAUNCH((batch_face2d_kernel<AXV, 2, true, TILE, CHAR>), nw, NT, a);               \
+    else BLAUNCH((batch_face2d_kernel<AXV, 2, false, TILE, CHAR>), nw, NT, a);                    \
   }
   if (ax == 0) {
     BF2(0)
@@ -122,15 +123,26 @@ static void batch_face2d(tgks_batch* b, const double* W, int ax, int stage) {
 static int batch_faces(tgks_batch* b, const double* W, int stage) {
   if (b->D == 1) {
     BatchArgs a = batch_args(b, W, nullptr, nullptr, b->wface1);
-    if (stage == 1) {
-      if (b->ns) BLAUNCH((batch_face1d_kernel<1, true>), b->nwface1, 256, a);
-      else BLAUNCH((batch_face1d_kernel<1, false>), b->nwface1, 256, a);
+#define BF1(CH)                                                                     \
+  if (stage == 1) {                                                                 \
+    if (b->ns) BLAUNCH((batch_face1d_kernel<1, true, CH>), b->nwface1, 256, a);     \
+    else BLAUNCH((batch_face1d_kernel<1, false, CH>), b->nwface1, 256, a);          \
+  } else {                                                                          \
+    if (b->ns) BLAUNCH((batch_face1d_kernel<2, true, CH>), b->nwface1, 256, a);     \
+    else BLAUNCH((batch_face1d_kernel<2, false, CH>), b->nwface1, 256, a);          \
+  }
+    if (b->chr) {
+      BF1(true)
     } else {
-      if (b->ns) BLAUNCH((batch_face1d_kernel<2, true>), b->nwface1, 256, a);
-      else BLAUNCH((batch_face1d_kernel<2, false>), b->nwface1, 256, a);
+      BF1(false)
     }
+#undef BF1
   } else {
     for (int ax = 0; ax < 2; ++ax) {
+      if (b->chr) {  // one tile shape on the characteristic path
+        batch_face2d<CHAR_TILE2, true>(b, W, ax, stage);
+        continue;
+      }
       switch (b->tile2) {
         case 1:
           batch_face2d<1>(b, W, ax, stage);
@@ -213,7 +225,7 @@ int tgks_batch_create(const tgks_params* p, int32_t n_inst, void* stream, tgks_b
   if (D != 1 && D != 2) return TGKS_EINVAL;
   const bool ns = p[0].mu > 0.0 && p[0].prandtl != 1.0;
   for (int i = 0; i < n_inst; ++i) {
-    if (check_params(&p[i]) || p[i].ndim != D || p[i].recon != TGKS_RECON_CONSERVATIVE) return TGKS_EINVAL;
+    if (check_params(&p[i]) || p[i].ndim != D || p[i].recon != p[0].recon) return TGKS_EINVAL;
     if ((p[i].mu > 0.0 && p[i].prandtl != 1.0) != ns) return TGKS_EINVAL;
   }
   tgks_batch* b = new (std::nothrow) tgks_batch();
@@ -222,6 +234,7 @@ int tgks_batch_create(const tgks_params* p, int32_t n_inst, void* stream, tgks_b
   b->nc = D + 2;
   b->ninst = n_inst;
   b->ns = ns;
+  b->chr = p[0].recon == TGKS_RECON_CHARACTERISTIC;
   b->stream = (hipStream_t)stream;
   std::vector<int2> wcell, wface1, wface[NTILE2][2];
   long long woff = 0, foff[2] = {0, 0};
@@ -345,7 +358,7 @@ int tgks_batch_offsets(const tgks_batch* b, int64_t* offsets) {
 
 int tgks_batch_set_tile(tgks_batch* b, int32_t tile) {
   if (!b || tile < -1 || tile >= NTILE2) return TGKS_EINVAL;
-  const int t = tile < 0 ? 0 : tile;
+  const int t = b->chr ? CHAR_TILE2 : (tile < 0 ? 0 : tile);  // one shape with characteristic variables
   if (t == b->tile2) return TGKS_OK;
   drop_graph(b);
   // tiles along the normal axis of each direction for this shape
@@ -424,9 +437,14 @@ int tgks_batch_tune(tgks_batch* b, const double* W, int32_t steps, int32_t* chos
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   const int old = b->tile2;
-  int best = 0;
+  int best = b->chr ? CHAR_TILE2 : 0;
   float best_ms = 0.f;
+  bool first = true;
   for (int k = 0; k < nvar && !r; ++k) {
+    if (b->chr && k != CHAR_TILE2) {  // one tile shape on the characteristic path
+      if (ms_per_variant) ms_per_variant[k] = 0.f;
+      continue;
+    }
     if ((r = tgks_batch_set_tile(b, k))) break;
     if ((r = batch_step(b, W, b->W2))) break;  // warm-up
     if (hipEventRecord(e0, b->stream) != hipSuccess) r = TGKS_EHIP;
@@ -437,9 +455,10 @@ int tgks_batch_tune(tgks_batch* b, const double* W, int32_t steps, int32_t* chos
     if (!r && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) r = TGKS_EHIP;
     if (r) break;
     if (ms_per_variant) ms_per_variant[k] = ms / steps;
-    if (k == 0 || ms < best_ms) {
+    if (first || ms < best_ms) {
       best = k;
       best_ms = ms;
+      first = false;
     }
   }
   (void)hipEventDestroy(e0);

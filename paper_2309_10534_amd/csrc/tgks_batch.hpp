@@ -52,24 +52,25 @@ __device__ __forceinline__ StageArgs batch_stage(const BatchArgs& b, const Batch
   a.tflags = nullptr;
   a.R = nullptr;
   a.Rout = nullptr;
+  a.gamma = I.gamma;
   return a;
 }
 
-template <int STAGE, bool NS>
+template <int STAGE, bool NS, bool CHAR = false>
 __global__ __launch_bounds__(256) void batch_face1d_kernel(BatchArgs b) {
   const int2 w = b.work[blockIdx.x];
   const StageArgs a = batch_stage(b, b.inst[w.x], w.x, 0);
-  face1d_body<STAGE, NS, false>(a, w.y * 256 + (int)threadIdx.x);
+  face1d_body<STAGE, NS, false, CHAR>(a, w.y * 256 + (int)threadIdx.x);
 }
 
-template <int AX, int STAGE, bool NS, int TILE>
+template <int AX, int STAGE, bool NS, int TILE, bool CHAR = false>
 __global__ __launch_bounds__(2 * tile2_tn(TILE) * tile2_tt(TILE), 2) void batch_face2d_kernel(BatchArgs b) {
   const int2 w = b.work[blockIdx.x];
   const BatchInst& I = b.inst[w.x];
   const StageArgs a = batch_stage(b, I, w.x, AX);
   const int nt = I.ntile[AX];
-  __shared__ double lds[tile2_lds(TILE)];
-  face2d_tile<AX, STAGE, NS, false, TILE>(a, w.y % nt, w.y / nt, lds);
+  __shared__ double lds[CHAR ? tile2_lds_char(TILE) : tile2_lds(TILE)];
+  face2d_tile<AX, STAGE, NS, false, TILE, CHAR>(a, w.y % nt, w.y / nt, lds);
 }
 
 template <int D, int STAGE, bool CFL>

@@ -112,6 +112,29 @@ def test_batch_bitwise_equals_single(torch_dev, dim, steps):
         assert badb[i] == bads
 
 
+@pytest.mark.parametrize("dim,steps", [(1, 30), (2, 10)])
+def test_batch_characteristic_bitwise_equals_single(torch_dev, dim, steps):
+    """Characteristic reconstruction variables in a batch: every instance
+    bit-identical to its single-grid run, eager and graph-captured."""
+    mild = {} if dim == 1 else dict(rho_range=(0.1, 2.0), p_range=(0.03, 1.5), vel_range=(-1.0, 1.0))
+    probs = mixed_set(dim, 7, seed=5, size_range=(16, 90) if dim == 1 else (12, 40), **mild)
+    probs = [(W, dict(pr, recon=1)) for W, pr in probs]
+    print(f"[batch-char] dim={dim} instances={len(probs)} steps={steps}", flush=True)
+    ref = single_runs(probs, steps)
+    B = Batch(probs)
+    try:
+        (Wb, tb, badb), = B.run(steps)
+        (Wg, tg, badg), = B.run(steps, use_graph=True)
+    finally:
+        B.close()
+    assert sum(1 for i in range(len(probs)) if tb[i, 1] > 0) >= len(probs) // 2
+    for i, (Ws, ts, bads) in enumerate(ref):
+        assert np.array_equal(Wb[i], Ws, equal_nan=True), f"instance {i} differs from its single-grid run"
+        assert np.array_equal(Wg[i], Wb[i], equal_nan=True), f"instance {i}: graph replay differs"
+        assert np.array_equal(tb[i], ts, equal_nan=True)
+        assert badb[i] == bads
+
+
 def test_batch_t_end_clipping(torch_dev):
     probs = mixed_set(1, 4, seed=4, size_range=(20, 60))
     B = Batch(probs)

@@ -1,8 +1,8 @@
 """GPU parity of the characteristic-variable reconstruction option against
 the oracle (1-D and 2-D): one step on identical input, L1-relative <= 1e-10
 per component, stage-1 selection flags (per characteristic field) bit for
-bit; rejection where the option does not exist (3-D, batched runs, reverse
-mode)."""
+bit; rejection where the option does not exist (3-D, reverse mode) and of
+batches that mix the two choices."""
 import numpy as np
 import pytest
 
@@ -116,8 +116,8 @@ def test_rejected_where_absent(torch_dev):
     with pytest.raises(tgks.TgksError):
         tgks.tgks_create(tgks.tgks_params_default(3, [8, 8, 8], [0.1] * 3, bc="periodic", recon=1))
     p = tgks.tgks_params_default(1, [32], [1 / 32], recon=1)
-    with pytest.raises(tgks.TgksError):
-        tgks.tgks_batch_create([p, p])
+    with pytest.raises(tgks.TgksError):  # mixed reconstruction variables
+        tgks.tgks_batch_create([p, tgks.tgks_params_default(1, [32], [1 / 32])])
     ctx = tgks.tgks_create(p)
     try:
         W0, dx = I.sod(32)
