@@ -43,8 +43,8 @@ extern "C" {
  * zero-gradient condition (ghost cells copy the nearest interior cell);
  * reflective = mirror image with the wall-normal momentum negated (also the
  * symmetry condition of Sec. 5.8); no-slip = the adiabatic no-slip wall of
- * Sec. 5.8, mirror image with every momentum component negated (not in the
- * reverse mode). */
+ * Sec. 5.8, mirror image with every momentum component negated, and no mass
+ * or energy flux through the wall faces. */
 #define TGKS_BC_PERIODIC 0
 #define TGKS_BC_TRANSMISSIVE 1
 #define TGKS_BC_REFLECTIVE 2
@@ -202,8 +202,8 @@ int tgks_gp_flux_host(const tgks_params* p, const double* Wl, const double* Wr, 
  * overlap gW_out.  W_star: the step's intermediate state W* as tgks_step
  * returned it for the same W_n and dt (device), or NULL to recompute it with
  * the forward kernels.  The first call allocates the context's reverse-mode
- * buffers.  TGKS_EINVAL for 3-D contexts, characteristic variables,
- * no-slip walls or invalid pointers. */
+ * buffers.  TGKS_EINVAL for 3-D contexts, characteristic variables or
+ * invalid pointers. */
 int tgks_step_adjoint(tgks_ctx* ctx, const double* W_n, const double* W_star, const double* dt_dev,
                       const double* gW_out, double* gW_in);
 

@@ -172,8 +172,6 @@ int tgks_step_adjoint(tgks_ctx* c, const double* W_n, const double* W_star, cons
                       const double* gW_out, double* gW_in) {
   if (!c || !W_n || !dt_dev || !gW_out || !gW_in || gW_out == gW_in) return TGKS_EINVAL;
   if (c->g.D > 2 || c->p.recon != TGKS_RECON_CONSERVATIVE) return TGKS_EINVAL;
-  for (int d = 0; d < c->g.D; ++d)
-    if (c->p.bc_lo[d] == TGKS_BC_NOSLIP || c->p.bc_hi[d] == TGKS_BC_NOSLIP) return TGKS_EINVAL;
   int r;
   if ((r = ensure_adjoint_buffers(c))) return r;
   const int D = c->g.D;

@@ -102,6 +102,7 @@ __global__ __launch_bounds__(128) void adj_face1d_kernel(AdjArgs a) {
 #pragma unroll
   for (int c = 0; c < 3; ++c)
     face_cot(a, c, f >= 1 ? f - 1 : -1, f < n ? f : -1, idx, Fdtb[c], Fhb[c]);
+  wall_fluxes<3>(a.g, 0, f, Fdtb, Fhb);  // transpose of the zero wall fluxes
   double Wlb[3], Wrb[3], dWlb[1][3], dWrb[1][3];
   if (dt > 0.0) {
     gp_flux_vjp<1, NS, double>(Wl, Wr, dWl, dWr, a.fc, dt, Fdtb, Fhb, Wlb, Wrb, dWlb, dWrb);
@@ -227,6 +228,7 @@ __global__ __launch_bounds__(2 * ATN * ATT) void adj_face2d_kernel(AdjArgs a) {
       Fdtb[q] = 0.5 * x;
       Fhb[q] = 0.5 * y;
     }
+    wall_fluxes<NC>(g, AX, f, Fdtb, Fhb);  // transpose of the zero wall fluxes
   }
   double Wb[2][NC], Db[2][2][NC];
   if (dt > 0.0) {
@@ -376,10 +378,11 @@ __global__ __launch_bounds__(256) void adj_normal_kernel(AdjArgs a) {
     const int r = pt[u];
     for (int w = 0; w < cn; ++w) {
       const int ip = pn[w];
-      // sign of the image: momentum normal to a mirror
-      bool neg = false;
-      if (c == 1 + AX && fn_[w]) neg = !neg;
-      if (D == 2 && c == 1 + TA && ft_[u]) neg = !neg;
+      // sign of the image: the momentum normal to a reflective wall, every
+      // momentum component behind a no-slip wall
+      const bool mom = c >= 1 && c <= D;
+      bool neg = (c == 1 + AX && fn_[w] == 1) ^ (mom && fn_[w] == 2);
+      if (D == 2) neg ^= (c == 1 + TA && ft_[u] == 1) ^ (mom && ft_[u] == 2);
       double s = 0.0;
       for (int k = 0; k < 5; ++k) {
         const int i = ip + 2 - k;  // cell whose normal stencil slot k is ip

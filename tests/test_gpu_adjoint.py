@@ -75,7 +75,8 @@ def adjoint_vs_oracle(orc, torch, pr, W, dt, seed=0):
     return Gin
 
 
-@pytest.mark.parametrize("bc", ["periodic", "transmissive", "reflective"])
+@pytest.mark.parametrize("bc", ["periodic", "transmissive", "reflective", "noslip",
+                                [("noslip", "noslip"), ("noslip", "reflective")]])
 def test_step_adjoint_2d_smooth_ragged(orc, torch_dev, bc):
     shape = [37, 29]  # several 8 x 16 face tiles with ragged tails
     W = smooth_field(shape, seed=3)
@@ -125,7 +126,7 @@ def test_step_adjoint_2d_vortex(orc, torch_dev):
     adjoint_vs_oracle(orc, torch_dev, pr, W, dt, seed=4)
 
 
-@pytest.mark.parametrize("case", ["sod", "wave", "reflective", "viscous"])
+@pytest.mark.parametrize("case", ["sod", "wave", "reflective", "viscous", "noslip"])
 def test_step_adjoint_1d(orc, torch_dev, case):
     if case == "sod":
         # Sod's states with a smooth modulation (no exactly constant region)
@@ -147,6 +148,10 @@ def test_step_adjoint_1d(orc, torch_dev, case):
         W = smooth_field([90], seed=8)
         dx = 1 / 90
         pr = problem([90], [dx], bc=[("reflective", "reflective")])
+    elif case == "noslip":
+        W = smooth_field([90], seed=9)
+        dx = 1 / 90
+        pr = problem([90], [dx], bc=[("noslip", "transmissive")], tau="viscous", mu=2e-3, prandtl=0.72)
     else:
         W = smooth_field([64], seed=9)
         pr = problem([64], [1 / 64], bc="periodic", tau="viscous", mu=1e-3, prandtl=0.72)
