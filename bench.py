@@ -86,6 +86,8 @@ def parse():
     ap.add_argument("--no-sod", action="store_true", help="skip the 1-D Sod latency workload")
     ap.add_argument("--no-char", action="store_true", help="skip the characteristic-variable workload")
     ap.add_argument("--no-vst", action="store_true", help="skip the viscous shock tube")
+    ap.add_argument("--vst-nx", type=int, default=500, help="viscous shock tube cells along x (nx x nx/2)")
+    ap.add_argument("--vst-re", type=float, default=200.0, help="viscous shock tube Reynolds number")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     return ap.parse_args()
 
@@ -598,7 +600,7 @@ def main():
     if not args.no_char:
         out["characteristic"] = characteristic()
     if not args.no_vst:
-        out["viscous_shock_tube"] = viscous_shock_tube()
+        out["viscous_shock_tube"] = viscous_shock_tube(nx=args.vst_nx, re=args.vst_re)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W0, dx, n, args.cpu_seconds)
     print(json.dumps(strict_json(out), allow_nan=False), flush=True)
