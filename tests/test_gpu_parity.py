@@ -63,6 +63,19 @@ def test_step_1d_ragged_random(orc, torch_dev, bc):
     compare_step(orc, pr, W, dt)
 
 
+def test_step_1d_large_grid(orc, torch_dev):
+    """A 1-D grid of 10,007 cells (40 blocks of faces, ragged tail)."""
+    rng = np.random.default_rng(11)
+    n = 10007
+    x = (np.arange(n) + 0.5) / n
+    rho = 1.0 + 0.3 * np.sin(6 * np.pi * x) + 0.05 * rng.uniform(-1, 1, n)
+    u = 0.3 * np.cos(4 * np.pi * x)
+    p = 1.0 + 0.2 * (x > 0.6)
+    W = I.conservative(rho, [u], p)
+    pr = problem([n], [1.0 / n])
+    compare_step(orc, pr, W, 0.5 * orc.cfl_dt(orc_params(orc, pr), W, 0.5))
+
+
 def test_step_1d_density_wave_tau_zero(orc, torch_dev):
     W, dx = I.density_wave_1d(40)
     pr = problem([40], [dx], bc="periodic", tau="zero")
