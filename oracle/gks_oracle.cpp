@@ -54,6 +54,17 @@
 //    at rest it does no work, adiabatic it conducts no heat); the momentum
 //    flux is the flux of the mirrored states.  The symmetry condition there
 //    is the reflective kind.
+//  * Prescribed (Dirichlet) sides, for the inflow, the post-shock part of
+//    the bottom and the moving-shock top of the double Mach reflection
+//    (Sec. 5.7), 1-D and 2-D grids: a ghost cell holds the point value of a
+//    given state at its centre.  With s the centre's coordinate along the
+//    other axis (0 on a 1-D grid), r its coordinate along the side's own
+//    axis (both from the domain origin, so r < 0 below a low side) and t the
+//    time, it holds state A where s < (s0 + s_n r) + s_t t, otherwise what
+//    the side's far kind gives: state B, or the transmissive or reflective
+//    image.  The time of stage 1 is t^n, that of stage 2 t^n + dt/2 (W* is
+//    the state at the half step).  A corner ghost cell is decided by the
+//    x side first when that side is prescribed and gives a state.
 
 #include <algorithm>
 #include <cmath>
@@ -108,7 +119,8 @@ typedef struct {
   int ndim;
   int n[3];
   double dx[3];
-  int bc_lo[3], bc_hi[3];  // 0 periodic, 1 transmissive, 2 reflective, 3 no-slip adiabatic wall
+  int bc_lo[3], bc_hi[3];  // 0 periodic, 1 transmissive, 2 reflective, 3 no-slip adiabatic wall,
+                           // 4 prescribed (1-D, 2-D)
   double gamma, mu, prandtl;
   int tau_mode;            // 0 inviscid c1 dt + c2 |dp|/(sum p) dt, 1 viscous mu/p0 + ..., 2 zero
   double c1, c2;
@@ -116,6 +128,9 @@ typedef struct {
   double eps;
   int q;
   int recon;               // 0 conservative variables, 1 characteristic variables (1-D, 2-D)
+  double bc_state[2][5];   // prescribed states A and B (rho, m_0 .. m_{D-1}, E)
+  double bc_line[3][2][3]; // per axis and end: (s0, s_n, s_t) of the line bounding state A
+  int bc_far[3][2];        // per axis and end: kind beyond the line (1, 2, or 4 = state B)
 } orc_params;
 }
 
@@ -637,39 +652,57 @@ struct Grid {
   long ncell;
   double dx[3];
   int bclo[3], bchi[3];
-  explicit Grid(const orc_params& P) {
-    D = P.ndim;
+  const orc_params* P;
+  double time;  // time of the prescribed boundary states
+  explicit Grid(const orc_params& Pin, double t = 0.0) : P(&Pin), time(t) {
+    D = Pin.ndim;
     nc = D + 2;
     ncell = 1;
     for (int d = 0; d < 3; ++d) {
-      n[d] = d < D ? P.n[d] : 1;
-      dx[d] = d < D ? P.dx[d] : 1.0;
-      bclo[d] = P.bc_lo[d];
-      bchi[d] = P.bc_hi[d];
+      n[d] = d < D ? Pin.n[d] : 1;
+      dx[d] = d < D ? Pin.dx[d] : 1.0;
+      bclo[d] = Pin.bc_lo[d];
+      bchi[d] = Pin.bc_hi[d];
       ncell *= n[d];
     }
   }
-  // map index i along axis d into the interior; *flip = 1 behind a
-  // reflective wall (the momentum normal to it changes sign), 2 behind a
-  // no-slip adiabatic wall (every momentum component changes sign).
-  long map(int d, long i, int* flip) const {
+  // map index i along axis d into the interior with the boundary kinds
+  // (lo, hi); *flip = 1 behind a reflective wall (the momentum normal to it
+  // changes sign), 2 behind a no-slip adiabatic wall (every momentum
+  // component changes sign).
+  long map(int d, long i, int* flip, int lo, int hi) const {
     const long N = n[d];
     if (d >= D) return 0;
     if (i >= 0 && i < N) return i;
-    const int bc = i < 0 ? bclo[d] : bchi[d];
+    const int bc = i < 0 ? lo : hi;
     if (bc == 0) return ((i % N) + N) % N;
     if (bc == 1) return i < 0 ? 0 : N - 1;
     *flip ^= bc == 3 ? 2 : 1;
     return i < 0 ? -1 - i : 2 * N - 1 - i;
   }
+  long map(int d, long i, int* flip) const { return map(d, i, flip, bclo[d], bchi[d]); }
   long lin(long i, long j, long k) const { return (k * n[1] + j) * n[0] + i; }
 };
 
 template <class T>
 static T cell(const Grid& g, const T* W, int c, const long idx[3]) {
+  int lo[3] = {g.bclo[0], g.bclo[1], g.bclo[2]};
+  int hi[3] = {g.bchi[0], g.bchi[1], g.bchi[2]};
+  // prescribed sides: the state at the ghost cell's centre
+  for (int d = 0; d < g.D && g.D <= 2; ++d) {
+    const int e = idx[d] < 0 ? 0 : (idx[d] >= g.n[d] ? 1 : -1);
+    if (e < 0 || (e == 0 ? lo[d] : hi[d]) != 4) continue;
+    const double s = g.D == 2 ? ((double)idx[1 - d] + 0.5) * g.dx[1 - d] : 0.0;
+    const double r = ((double)idx[d] + 0.5) * g.dx[d];
+    const double* L = g.P->bc_line[d][e];
+    if (s < (L[0] + L[1] * r) + L[2] * g.time) return T(g.P->bc_state[0][c]);
+    const int far = g.P->bc_far[d][e];
+    if (far == 4) return T(g.P->bc_state[1][c]);
+    (e == 0 ? lo[d] : hi[d]) = far;
+  }
   int fl[3] = {0, 0, 0};
   long m[3];
-  for (int d = 0; d < 3; ++d) m[d] = g.map(d, idx[d], &fl[d]);
+  for (int d = 0; d < 3; ++d) m[d] = g.map(d, idx[d], &fl[d], lo[d], hi[d]);
   T v = W[c * g.ncell + g.lin(m[0], m[1], m[2])];
   if (c >= 1 && c <= g.D) {
     bool neg = fl[c - 1] == 1;
@@ -1083,8 +1116,9 @@ static inline long face_index(const Grid& g, int d, long i, long j, long k, int 
 // One S2O4 step (Sec. 2.2).
 template <class T>
 static long s2o4_step(const orc_params& P, const T* Wn, T* Wout, double dt, uint8_t* flags,
-                      T* Wstar_out) {
-  const Grid g(P);
+                      T* Wstar_out, double t = 0.0) {
+  const Grid g(P, t);
+  const Grid gs(P, t + 0.5 * dt);  // stage 2: W* is the state at the half step
   const int D = g.D, nc = g.nc;
   const long N = g.ncell;
   long nbad = 0;
@@ -1133,7 +1167,7 @@ static long s2o4_step(const orc_params& P, const T* Wn, T* Wout, double dt, uint
       }
   if (Wstar_out)
     for (size_t i = 0; i < Ws.size(); ++i) Wstar_out[i] = Ws[i];
-  for (int d = 0; d < D; ++d) nbad += face_fluxes(P, g, Ws.data(), d, dt, Gdt[d], Gh[d], (uint8_t*)nullptr, (uint8_t*)nullptr);
+  for (int d = 0; d < D; ++d) nbad += face_fluxes(P, gs, Ws.data(), d, dt, Gdt[d], Gh[d], (uint8_t*)nullptr, (uint8_t*)nullptr);
   // combined flux F^n + dt/6 (d_tF^n + 2 d_tF*), then the final update
   std::vector<T> Fc[3];
   for (int d = 0; d < D; ++d) {
@@ -1192,8 +1226,14 @@ static int check_params(const orc_params* P) {
   if (!P || P->ndim < 1 || P->ndim > 3) return -1;
   for (int d = 0; d < P->ndim; ++d) {
     if (P->n[d] < 3 || !(P->dx[d] > 0)) return -1;
-    if (P->bc_lo[d] < 0 || P->bc_lo[d] > 3 || P->bc_hi[d] < 0 || P->bc_hi[d] > 3) return -1;
+    if (P->bc_lo[d] < 0 || P->bc_lo[d] > 4 || P->bc_hi[d] < 0 || P->bc_hi[d] > 4) return -1;
     if ((P->bc_lo[d] == 0) != (P->bc_hi[d] == 0)) return -1;
+    for (int e = 0; e < 2; ++e) {
+      if ((e == 0 ? P->bc_lo[d] : P->bc_hi[d]) != 4) continue;
+      if (P->ndim > 2) return -1;
+      const int far = P->bc_far[d][e];
+      if (far != 1 && far != 2 && far != 4) return -1;
+    }
   }
   if (!(P->gamma > 1.0)) return -1;
   if (P->recon < 0 || P->recon > 1 || (P->recon == 1 && P->ndim > 2)) return -1;
@@ -1372,10 +1412,11 @@ long orc_flag_bytes(const orc_params* P) {
 }
 
 // One S2O4 step; returns the number of failing Gauss-point evaluations, or -1.
+// t: time of W (prescribed boundary states).
 long orc_step(const orc_params* P, const double* W, double* Wout, double dt, uint8_t* flags,
-              double* Wstar) {
+              double* Wstar, double t) {
   if (check_params(P) || !(dt > 0)) return -1;
-  return s2o4_step<double>(*P, W, Wout, dt, flags, Wstar);
+  return s2o4_step<double>(*P, W, Wout, dt, flags, Wstar, t);
 }
 
 // Same step carrying one tangent direction (forward mode).
@@ -1402,9 +1443,11 @@ int orc_cfl_dt(const orc_params* P, const double* W, double cfl, double* dt) {
 
 // Advance W in place.  fixed_dt > 0: constant step; otherwise CFL steps,
 // the last one clipped to t_end when t_end > 0.  Stops after max_steps steps
-// or at t_end.  Returns the number of failing Gauss-point evaluations.
+// or at t_end.  The time t runs from 0; the prescribed boundary states are
+// those of time t0 + t.  Returns the number of failing Gauss-point
+// evaluations.
 long orc_run(const orc_params* P, double* W, int max_steps, double cfl, double t_end,
-             double fixed_dt, double* t_out, int* steps_out) {
+             double fixed_dt, double* t_out, int* steps_out, double t0) {
   if (check_params(P)) return -1;
   const Grid g(*P);
   std::vector<double> tmp((size_t)g.nc * g.ncell);
@@ -1416,7 +1459,7 @@ long orc_run(const orc_params* P, double* W, int max_steps, double cfl, double t
     double dt = fixed_dt > 0.0 ? fixed_dt : cfl_dt(*P, W, cfl);
     if (t_end > 0.0 && t + dt > t_end) dt = t_end - t;
     if (!(dt > 0.0)) return -2;
-    bad += s2o4_step<double>(*P, W, tmp.data(), dt, nullptr, nullptr);
+    bad += s2o4_step<double>(*P, W, tmp.data(), dt, nullptr, nullptr, t0 + t);
     std::copy(tmp.begin(), tmp.end(), W);
     t += dt;
     ++s;

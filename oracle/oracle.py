@@ -15,7 +15,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 
-BC = {"periodic": 0, "transmissive": 1, "reflective": 2, "noslip": 3}
+BC = {"periodic": 0, "transmissive": 1, "reflective": 2, "noslip": 3, "prescribed": 4}
+FAR = {"transmissive": 1, "reflective": 2, "state_b": 4}
 TAU = {"inviscid": 0, "viscous": 1, "zero": 2}
 
 
@@ -27,6 +28,8 @@ class OrcParams(C.Structure):
         ("tau_mode", C.c_int), ("c1", C.c_double), ("c2", C.c_double),
         ("ct1", C.c_double), ("ct2", C.c_double), ("ct1_tan", C.c_double), ("ct2_tan", C.c_double),
         ("eps", C.c_double), ("q", C.c_int), ("recon", C.c_int),
+        ("bc_state", (C.c_double * 5) * 2), ("bc_line", ((C.c_double * 3) * 2) * 3),
+        ("bc_far", (C.c_int * 2) * 3),
     ]
 
 
@@ -59,13 +62,13 @@ def lib():
         L.orc_char_recon.argtypes = [P, dp, C.c_double, dp, C.c_void_p]
         L.orc_flag_bytes.argtypes = [P]
         L.orc_flag_bytes.restype = C.c_long
-        L.orc_step.argtypes = [P, dp, dp, C.c_double, C.c_void_p, C.c_void_p]
+        L.orc_step.argtypes = [P, dp, dp, C.c_double, C.c_void_p, C.c_void_p, C.c_double]
         L.orc_step.restype = C.c_long
         L.orc_step_dual.argtypes = [P, dp, dp, dp, dp, C.c_double]
         L.orc_step_dual.restype = C.c_long
         L.orc_cfl_dt.argtypes = [P, dp, C.c_double, C.POINTER(C.c_double)]
         L.orc_run.argtypes = [P, dp, C.c_int, C.c_double, C.c_double, C.c_double,
-                              C.POINTER(C.c_double), C.POINTER(C.c_int)]
+                              C.POINTER(C.c_double), C.POINTER(C.c_int), C.c_double]
         L.orc_run.restype = C.c_long
         _ = u8
         _lib = L
@@ -78,10 +81,14 @@ def set_threads(n: int) -> int:
 
 def make_params(shape, dx, bc="transmissive", gamma=1.4, mu=0.0, prandtl=1.0, tau="inviscid",
                 c1=0.01, c2=1.0, ct1=1e-7, ct2=1e-5, ct1_tan=None, ct2_tan=None, eps=1e-40, q=7,
-                recon=0):
+                recon=0, states=None, lines=None, far=None):
     """shape: cells per axis (x, y, z) truncated to D; bc: one name or a list of
     (lo, hi) names per axis; recon: 0 conservative, 1 characteristic variables
-    (1-D, 2-D)."""
+    (1-D, 2-D).  Prescribed sides ("prescribed", 1-D and 2-D): states = (A, B)
+    conservative states; lines = {(axis, end): (s0, s_n, s_t)}; far =
+    {(axis, end): "transmissive" | "reflective" | "state_b"}: the ghost cell
+    centred at (s, r) holds A where s < (s0 + s_n r) + s_t t, else what far
+    gives."""
     p = OrcParams()
     D = len(shape)
     p.ndim = D
@@ -102,6 +109,18 @@ def make_params(shape, dx, bc="transmissive", gamma=1.4, mu=0.0, prandtl=1.0, ta
     p.ct2_tan = ct2 if ct2_tan is None else ct2_tan
     p.eps, p.q = eps, q
     p.recon = int(recon)
+    if states is not None:
+        for k in range(2):
+            for c, v in enumerate(states[k]):
+                p.bc_state[k][c] = float(v)
+    for (d, e), ln in (lines or {}).items():
+        for k in range(3):
+            p.bc_line[d][e][k] = float(ln[k])
+    for d in range(3):
+        for e in range(2):
+            p.bc_far[d][e] = FAR["state_b"]
+    for (d, e), name in (far or {}).items():
+        p.bc_far[d][e] = FAR[name]
     return p
 
 
@@ -213,14 +232,15 @@ def flag_bytes(params):
     return lib().orc_flag_bytes(C.byref(params))
 
 
-def step(params, W, dt, want_flags=False, want_wstar=False):
+def step(params, W, dt, want_flags=False, want_wstar=False, t=0.0):
+    """One step of W, the state at time t (prescribed boundary states)."""
     W = _arr(W)
     out = np.empty_like(W)
     flags = np.zeros(flag_bytes(params), dtype=np.uint8) if want_flags else None
     ws = np.empty_like(W) if want_wstar else None
     bad = lib().orc_step(C.byref(params), W, out, float(dt),
                          flags.ctypes.data if flags is not None else None,
-                         ws.ctypes.data if ws is not None else None)
+                         ws.ctypes.data if ws is not None else None, float(t))
     if bad < 0:
         raise ValueError("invalid parameters or dt")
     return out, flags, ws, bad
@@ -272,13 +292,14 @@ def cfl_dt(params, W, cfl):
     return dt.value
 
 
-def run(params, W, max_steps, cfl=0.5, t_end=0.0, fixed_dt=0.0):
-    """Advance a copy of W; returns (W, t, steps, failures)."""
+def run(params, W, max_steps, cfl=0.5, t_end=0.0, fixed_dt=0.0, t0=0.0):
+    """Advance a copy of W; returns (W, t, steps, failures).  t counts from 0;
+    the prescribed boundary states are those of time t0 + t."""
     W = _arr(W).copy()
     t = C.c_double()
     s = C.c_int()
     bad = lib().orc_run(C.byref(params), W, int(max_steps), float(cfl), float(t_end),
-                        float(fixed_dt), C.byref(t), C.byref(s))
+                        float(fixed_dt), C.byref(t), C.byref(s), float(t0))
     if bad < 0:
         raise ValueError("invalid parameters or non-positive dt")
     return W, t.value, s.value, bad

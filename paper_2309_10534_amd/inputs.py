@@ -97,6 +97,69 @@ def viscous_shock_tube(nx, ny, gamma=GAMMA):
     return W, dx
 
 
+def _left_of_line_fraction(x0, x1, y0, y1, a, b):
+    """Exact fraction of the cell [x0, x1] x [y0, y1] with x < a + b y
+    (b >= 0): the mean over y of clip((a + b y - x0) / (x1 - x0), 0, 1),
+    integrated piecewise between the kinks."""
+    w = x1 - x0
+
+    def prim(y):  # antiderivative of the unclipped fraction
+        return ((a - x0) * y + 0.5 * b * y * y) / w
+
+    if b == 0.0:
+        return np.clip((a - x0) / w, 0.0, 1.0) * np.ones_like(y0)
+    ya = (x0 - a) / b  # fraction 0 here
+    yb = (x1 - a) / b  # fraction 1 here
+    lo = np.clip(ya, y0, y1)
+    hi = np.clip(yb, y0, y1)
+    return ((prim(hi) - prim(lo)) + (y1 - hi)) / (y1 - y0)
+
+
+DMR_POST = (8.0, 4.125 * np.sqrt(3.0), -4.125, 116.5)
+DMR_PRE = (1.4, 0.0, 0.0, 1.0)
+
+
+def oblique_shock(nx, ny, post, pre, Lx=4.0, Ly=1.0, x0=1.0 / 6.0, gamma=GAMMA):
+    """A straight shock at 60 degrees to the x axis through (x0, 0), the line
+    x = x0 + y / sqrt 3, with the primitive state post = (rho, U, V, p) on
+    its left and pre on its right, on [0, Lx] x [0, Ly]; cells cut by the
+    line hold area-weighted averages.  Returns (W [4][ny][nx], (dx, dy), A,
+    B) with A, B the conservative states."""
+    ex = np.linspace(0.0, Lx, nx + 1)
+    ey = np.linspace(0.0, Ly, ny + 1)
+    X0, Y0 = np.meshgrid(ex[:-1], ey[:-1])
+    X1, Y1 = np.meshgrid(ex[1:], ey[1:])
+    f = _left_of_line_fraction(X0, X1, Y0, Y1, x0, 1.0 / np.sqrt(3.0))
+
+    def cons(st):
+        return conservative(np.array(st[0]), [np.array(st[1]), np.array(st[2])], np.array(st[3]), gamma)
+
+    A, B = cons(post), cons(pre)
+    W = f[None] * A[:, None, None] + (1.0 - f[None]) * B[:, None, None]
+    return np.ascontiguousarray(W), (Lx / nx, Ly / ny), A, B
+
+
+def double_mach(nx=960, ny=240, gamma=GAMMA):
+    """Double Mach reflection (Sec. 5.7) on [0, 4] x [0, 1]: a Mach 10 shock
+    at 60 degrees to the x axis through (1/6, 0) separates the post-shock
+    state (rho, U, V, p) = (8, 4.125 sqrt 3, -4.125, 116.5) (left) from
+    (1.4, 0, 0, 1); its line moves as x = 1/6 + (y + 20 t) / sqrt 3.  Returns
+    (W [4][ny][nx], (dx, dy), boundary description): the left side takes
+    the post-shock state, the right side is transmissive, the bottom takes
+    the post-shock state for x < 1/6 and is a slip (reflective) wall beyond,
+    the top follows the exact moving shock."""
+    W, dxy, A, B = oblique_shock(nx, ny, DMR_POST, DMR_PRE, gamma=gamma)
+    s3 = np.sqrt(3.0)
+    spec = {
+        "bc": [("prescribed", "transmissive"), ("prescribed", "prescribed")],
+        "states": (A.tolist(), B.tolist()),
+        "lines": {(0, 0): (np.inf, 0.0, 0.0), (1, 0): (1.0 / 6.0, 0.0, 0.0),
+                  (1, 1): (1.0 / 6.0, 1.0 / s3, 20.0 / s3)},
+        "far": {(1, 0): "reflective", (1, 1): "state_b"},
+    }
+    return W, dxy, spec
+
+
 def quadrant_states(rng, rho_range=(0.1, 2.0), vel_range=(-1.0, 1.0), p_range=(0.03, 1.5)):
     """Four (rho, u, v, p) states drawn in quadrant order (x<1/2,y<1/2), (>=,<),
     (>=,>=), (<,>=); rho and p log-uniform, velocities uniform."""

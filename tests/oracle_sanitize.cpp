@@ -26,6 +26,23 @@ static orc_params params(int D, int n, int bc, int tau, double mu) {
   p.ct2 = p.ct2_tan = 1e-5;
   p.eps = 1e-40;
   p.q = 7;
+  // prescribed sides: states A, B and a moving line on every side, each far
+  // kind once
+  const double A[5] = {2.0, 0.4, -0.2, 0.1, 6.0}, B[5] = {1.0, 0.0, 0.1, 0.0, 2.5};
+  for (int c = 0; c < D + 1; ++c) {
+    p.bc_state[0][c] = A[c];
+    p.bc_state[1][c] = B[c];
+  }
+  p.bc_state[0][D + 1] = A[4];
+  p.bc_state[1][D + 1] = B[4];
+  const int far[4] = {2, 1, 4, 2};
+  for (int d = 0; d < 2; ++d)
+    for (int e = 0; e < 2; ++e) {
+      p.bc_line[d][e][0] = 0.3 + 0.1 * e;
+      p.bc_line[d][e][1] = 0.5;
+      p.bc_line[d][e][2] = 1.0;
+      p.bc_far[d][e] = far[2 * d + e];
+    }
   return p;
 }
 
@@ -57,8 +74,9 @@ static std::vector<double> field(const orc_params& p, int jump) {
 int main() {
   int cases = 0;
   for (int D = 1; D <= 3; ++D)
-    for (int bc = 0; bc <= 2; ++bc)
+    for (int bc = 0; bc <= 4; ++bc)
       for (int tau = 0; tau <= 1; ++tau) {
+        if (bc == 4 && D == 3) continue;  // prescribed sides: 1-D and 2-D grids
         const int n = D == 3 ? 3 : (D == 2 ? 7 : 13);
         orc_params p = params(D, n, bc, tau, tau == 1 ? 1e-3 : 0.0);
         std::vector<double> W = field(p, bc != 0), Wo(W.size()), Wo2(W.size()), Ws(W.size()), dW(W.size()),
@@ -67,12 +85,12 @@ int main() {
         std::vector<uint8_t> flags(orc_flag_bytes(&p));
         double dt = 0.0;
         if (orc_cfl_dt(&p, W.data(), 0.5, &dt) != 0) return 2;
-        if (orc_step(&p, W.data(), Wo.data(), dt, flags.data(), Ws.data()) < 0) return 3;
+        if (orc_step(&p, W.data(), Wo.data(), dt, flags.data(), Ws.data(), 0.1) < 0) return 3;
         if (orc_step_dual(&p, W.data(), dW.data(), Wo2.data(), dWo.data(), dt) < 0) return 4;
         std::vector<double> Wr(W);
         double t = 0.0;
         int steps = 0;
-        if (orc_run(&p, Wr.data(), 2, 0.5, 0.0, 0.0, &t, &steps) < 0) return 5;
+        if (orc_run(&p, Wr.data(), 2, 0.5, 0.0, 0.0, &t, &steps, 0.05) < 0) return 5;
         // one Gauss-point flux and its derivative in the face frame
         double Wl[5] = {1.0, 0.1, 0.05, 0.02, 2.6}, Wrr[5] = {0.9, -0.1, 0.0, 0.01, 2.4};
         double dWl[15], dWr[15], tW[5], tdW[15], F[10], dF[10], W0[5], dW0[15];
