@@ -65,6 +65,12 @@
 //    image.  The time of stage 1 is t^n, that of stage 2 t^n + dt/2 (W* is
 //    the state at the half step).  A corner ghost cell is decided by the
 //    x side first when that side is prescribed and gives a state.
+//  * Optional first-order fallback (not in the paper, off by default; 1-D
+//    and 2-D): a Gauss-point state of one side whose density or pressure is
+//    not positive or not finite is replaced by the average of that side's
+//    cell at the face, with zero slopes, before the flux is evaluated.  The
+//    pressure of the test is (gamma - 1) (E - (0.5 sum_a m_a^2) / rho), the
+//    sum taken over the momenta in order.
 
 #include <algorithm>
 #include <cmath>
@@ -131,6 +137,7 @@ typedef struct {
   double bc_state[2][5];   // prescribed states A and B (rho, m_0 .. m_{D-1}, E)
   double bc_line[3][2][3]; // per axis and end: (s0, s_n, s_t) of the line bounding state A
   int bc_far[3][2];        // per axis and end: kind beyond the line (1, 2, or 4 = state B)
+  int fallback;            // 1: first-order fallback at non-physical Gauss-point states (1-D, 2-D)
 } orc_params;
 }
 
@@ -828,6 +835,16 @@ static void matvec(int nc, const T M[5][5], const T* x, T* y) {
   }
 }
 
+// density and pressure of a frame-ordered state positive and finite (the
+// test of the first-order fallback, in one fixed operation order)
+template <class T>
+static bool physical_state(int D, double gamma, const T* w) {
+  T ke = T(0.0);
+  for (int a = 1; a <= D; ++a) ke = ke + w[a] * w[a];
+  const T pr = (gamma - 1.0) * (w[D + 1] - 0.5 * ke / w[0]);
+  return val(w[0]) > 0.0 && val(pr) > 0.0 && std::isfinite(val(w[0])) && std::isfinite(val(pr));
+}
+
 // conservative state of a cell in frame order
 template <class T>
 static void cell_frame(const Grid& g, const T* W, const int* perm, const long idx[3], T* out) {
@@ -1083,6 +1100,23 @@ static long face_fluxes(const orc_params& P, const Grid& g, const T* W, int d, d
     T acc[2][5];
     for (int i = 0; i < 2; ++i)
       for (int a = 0; a < 5; ++a) acc[i][a] = T(0.0);
+    if (P.fallback) {
+      // first-order fallback: a non-physical side state at a Gauss point
+      // becomes the side's cell average with zero slopes
+      T C[2][5];
+      cell_frame(g, W, perm, cl, C[0]);
+      cell_frame(g, W, perm, cr, C[1]);
+      for (int m1 = 0; m1 < ngp1; ++m1)
+        for (int m2 = 0; m2 < ngp2; ++m2)
+          for (int side = 0; side < 2; ++side) {
+            T* w = Wg[m1][m2][side];
+            if (physical_state(D, P.gamma, w)) continue;
+            for (int a = 0; a < nc; ++a) {
+              w[a] = C[side][a];
+              for (int q = 0; q < 3; ++q) Dg[m1][m2][side][q][a] = T(0.0);
+            }
+          }
+    }
     for (int m1 = 0; m1 < ngp1; ++m1)
       for (int m2 = 0; m2 < ngp2; ++m2) {
         T F[2][5];
@@ -1237,6 +1271,7 @@ static int check_params(const orc_params* P) {
   }
   if (!(P->gamma > 1.0)) return -1;
   if (P->recon < 0 || P->recon > 1 || (P->recon == 1 && P->ndim > 2)) return -1;
+  if (P->fallback < 0 || P->fallback > 1 || (P->fallback == 1 && P->ndim > 2)) return -1;
   return 0;
 }
 

@@ -29,7 +29,7 @@ class OrcParams(C.Structure):
         ("ct1", C.c_double), ("ct2", C.c_double), ("ct1_tan", C.c_double), ("ct2_tan", C.c_double),
         ("eps", C.c_double), ("q", C.c_int), ("recon", C.c_int),
         ("bc_state", (C.c_double * 5) * 2), ("bc_line", ((C.c_double * 3) * 2) * 3),
-        ("bc_far", (C.c_int * 2) * 3),
+        ("bc_far", (C.c_int * 2) * 3), ("fallback", C.c_int),
     ]
 
 
@@ -81,14 +81,15 @@ def set_threads(n: int) -> int:
 
 def make_params(shape, dx, bc="transmissive", gamma=1.4, mu=0.0, prandtl=1.0, tau="inviscid",
                 c1=0.01, c2=1.0, ct1=1e-7, ct2=1e-5, ct1_tan=None, ct2_tan=None, eps=1e-40, q=7,
-                recon=0, states=None, lines=None, far=None):
+                recon=0, states=None, lines=None, far=None, fallback=0):
     """shape: cells per axis (x, y, z) truncated to D; bc: one name or a list of
     (lo, hi) names per axis; recon: 0 conservative, 1 characteristic variables
     (1-D, 2-D).  Prescribed sides ("prescribed", 1-D and 2-D): states = (A, B)
     conservative states; lines = {(axis, end): (s0, s_n, s_t)}; far =
     {(axis, end): "transmissive" | "reflective" | "state_b"}: the ghost cell
     centred at (s, r) holds A where s < (s0 + s_n r) + s_t t, else what far
-    gives."""
+    gives.  fallback = 1: first-order fallback at non-physical Gauss-point
+    states (1-D, 2-D; not in the paper)."""
     p = OrcParams()
     D = len(shape)
     p.ndim = D
@@ -109,6 +110,7 @@ def make_params(shape, dx, bc="transmissive", gamma=1.4, mu=0.0, prandtl=1.0, ta
     p.ct2_tan = ct2 if ct2_tan is None else ct2_tan
     p.eps, p.q = eps, q
     p.recon = int(recon)
+    p.fallback = int(fallback)
     if states is not None:
         for k in range(2):
             for c, v in enumerate(states[k]):
