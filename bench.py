@@ -37,8 +37,8 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector peak (256 CU x 2.4 GHz x 128 flop/
 # the three files below); the bench reports null traffic otherwise.
 TRAFFIC_SOURCES = ("paper_2309_10534_amd/csrc/tgks_device.hpp", "paper_2309_10534_amd/csrc/tgks_kernels.hpp",
                    "paper_2309_10534_amd/csrc/tgks_face2d.hip")
-TRAFFIC = {"sha": "2d64fef0c7f65e5e", "tile": 2, "fetch_factor": 32768.0 / 16397.7, "write_factor": 1.0,
-           "face_xy": {"fetch_kib": 128489.6, "write_kib": 116845.4}}
+TRAFFIC = {"sha": "a4c601441b0a53af", "tile": 2, "fetch_factor": 32768.0 / 16397.5, "write_factor": 1.0,
+           "face_xy": {"fetch_kib": 128515.0, "write_kib": 116847.6}}
 
 
 def measured_traffic(kernel, tile):
@@ -86,6 +86,7 @@ def parse():
     ap.add_argument("--no-sod", action="store_true", help="skip the 1-D Sod latency workload")
     ap.add_argument("--no-char", action="store_true", help="skip the characteristic-variable workload")
     ap.add_argument("--no-vst", action="store_true", help="skip the viscous shock tube")
+    ap.add_argument("--no-dmr", action="store_true", help="skip the double Mach reflection")
     ap.add_argument("--vst-nx", type=int, default=500, help="viscous shock tube cells along x (nx x nx/2)")
     ap.add_argument("--vst-re", type=float, default=200.0, help="viscous shock tube Reynolds number")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
@@ -273,8 +274,9 @@ def viscous_shock_tube(nx=500, re=200.0, t_end=1.0, cfl=0.2, chunk=200):
     Re 200 (mu = 1/Re), Pr 0.73, no-slip adiabatic walls left, right and at
     the bottom, symmetry at the top, CFL 0.2 to t = 1, with conservative and
     with characteristic reconstruction variables: time reached, failures,
-    steps and throughput; the density along the bottom wall at t = 1 is
-    summarised (the paper shows it only as a figure)."""
+    steps and throughput, without and with the first-order fallback at
+    non-physical Gauss-point states; the density along the bottom wall at
+    t = 1 is summarised (the paper shows it only as a figure)."""
     import numpy as np
     import torch
 
@@ -287,9 +289,10 @@ def viscous_shock_tube(nx=500, re=200.0, t_end=1.0, cfl=0.2, chunk=200):
     out = {"workload": f"2d_ns_viscous_shock_tube_{nx}x{ny}_re{re:g}_pr0.73_cfl{cfl:g}_to_t{t_end:g}"}
     td = torch.zeros(2, dtype=torch.float64, device="cuda")
     xc = (np.arange(nx) + 0.5) * dx
-    for recon, name in ((0, "conservative"), (1, "characteristic")):
+    for recon, fb, name in ((0, 0, "conservative"), (1, 0, "characteristic"),
+                            (0, 1, "conservative_fallback"), (1, 1, "characteristic_fallback")):
         p = tgks.tgks_params_default(2, [nx, ny], [dx, dx], bc=bc, mu=1.0 / re, prandtl=0.73, tau="viscous",
-                                     recon=recon)
+                                     recon=recon, fallback=fb)
         ctx = tgks.tgks_create(p)
         W = torch.from_numpy(W0).cuda()
         torch.cuda.synchronize()
@@ -324,6 +327,56 @@ def viscous_shock_tube(nx=500, re=200.0, t_end=1.0, cfl=0.2, chunk=200):
                                             "x_at_max": round(float(xc[wall.argmax()]), 4),
                                             "min": round(float(wall.min()), 4)}
             out[name]["rho_domain"] = {"max": round(float(rho.max()), 4), "min": round(float(rho.min()), 4)}
+    return out
+
+
+def double_mach(nx=960, ny=240, t_end=0.2, cfl=0.5, chunk=100):
+    """Double Mach reflection (Sec. 5.7): [0, 4] x [0, 1], nx x ny cells,
+    Mach 10 shock, post-shock inflow on the left and on the bottom for
+    x < 1/6, slip wall beyond, the exact moving shock at the top, CFL 0.5 to
+    t = 0.2, with conservative and with characteristic reconstruction
+    variables: time reached, failures (non-physical Gauss-point states),
+    steps and throughput, without and with the first-order fallback at
+    non-physical Gauss-point states."""
+    import torch
+
+    from paper_2309_10534_amd import inputs as I
+    from paper_2309_10534_amd import tgks
+
+    W0, (dx, dy), spec = I.double_mach(nx, ny)
+    out = {"workload": f"2d_euler_double_mach_reflection_{nx}x{ny}_cfl{cfl:g}_to_t{t_end:g}"}
+    td = torch.zeros(2, dtype=torch.float64, device="cuda")
+    for recon, fb, name in ((0, 0, "conservative"), (1, 0, "characteristic"),
+                            (0, 1, "conservative_fallback"), (1, 1, "characteristic_fallback")):
+        p = tgks.tgks_params_default(2, [nx, ny], [dx, dy], bc=spec["bc"], states=spec["states"],
+                                     lines=spec["lines"], far=spec["far"], recon=recon, fallback=fb)
+        ctx = tgks.tgks_create(p)
+        W = torch.from_numpy(W0).cuda()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        # chunks as in the viscous shock tube; the boundary's time origin
+        # moves to the start of every chunk
+        t_done, steps, last_dt = 0.0, 0, None
+        while t_end - t_done > 1e-14 * t_end and steps < 100000:
+            rest = t_end - t_done
+            n = chunk if last_dt is None or rest > (chunk + 5) * last_dt else 1
+            tgks.tgks_set_time(ctx, t_done)
+            td.zero_()
+            tgks.tgks_run(ctx, W, n, cfl=cfl, t_end=rest, time_dev=td)
+            adv, last_dt = float(td[0].cpu()), float(td[1].cpu())
+            if not (adv > 0.0) or not math.isfinite(adv) or not math.isfinite(last_dt):
+                break
+            t_done += adv
+            steps += n
+            if tgks.tgks_status(ctx):
+                break
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        fails = tgks.tgks_status(ctx)
+        tgks.tgks_destroy(ctx)
+        out[name] = {"t_reached": t_done, "failures": fails, "finite": bool(torch.isfinite(W).all().item()),
+                     "steps": steps, "seconds": round(el, 3),
+                     "value": round(nx * ny * steps / el / 1e6, 3) if steps else None, "unit": "Mcell-updates/s"}
     return out
 
 
@@ -601,6 +654,8 @@ def main():
         out["characteristic"] = characteristic()
     if not args.no_vst:
         out["viscous_shock_tube"] = viscous_shock_tube(nx=args.vst_nx, re=args.vst_re)
+    if not args.no_dmr:
+        out["double_mach"] = double_mach()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W0, dx, n, args.cpu_seconds)
     print(json.dumps(strict_json(out), allow_nan=False), flush=True)

@@ -44,11 +44,23 @@ extern "C" {
  * reflective = mirror image with the wall-normal momentum negated (also the
  * symmetry condition of Sec. 5.8); no-slip = the adiabatic no-slip wall of
  * Sec. 5.8, mirror image with every momentum component negated, and no mass
- * or energy flux through the wall faces. */
+ * or energy flux through the wall faces; prescribed = given states (the
+ * inflow, post-shock bottom and moving-shock top of the double Mach
+ * reflection, Sec. 5.7; 1-D and 2-D contexts only): a ghost cell of such a
+ * side, centred at coordinate s along the other axis of a 2-D grid (s = 0
+ * on a 1-D grid) and r along the side's own axis (both measured from the
+ * domain origin, r < 0 beyond a low side), holds at time t the state
+ * bc_state[0] where s < (s0 + s_n r) + s_t t, (s0, s_n, s_t) =
+ * bc_line[axis][end], and beyond that line what bc_far[axis][end] gives:
+ * TGKS_BC_TRANSMISSIVE or TGKS_BC_REFLECTIVE images, or TGKS_BC_PRESCRIBED
+ * for the state bc_state[1].  Stage 1 of a step from t uses time t, stage 2
+ * time t + dt/2.  A ghost cell outside both axes is decided by the x side
+ * first when that side is prescribed and gives a state. */
 #define TGKS_BC_PERIODIC 0
 #define TGKS_BC_TRANSMISSIVE 1
 #define TGKS_BC_REFLECTIVE 2
 #define TGKS_BC_NOSLIP 3
+#define TGKS_BC_PRESCRIBED 4
 
 /* collision time (Sec. 5 preamble):
  * INVISCID: tau = c1 dt + c2 |p_l - p_r| / (p_l + p_r) dt
@@ -83,6 +95,18 @@ typedef struct tgks_params {
   double eps;        /* epsilon of Eq. 4.5 (1e-40) */
   int32_t q;         /* power of Eq. 4.5 (7) */
   int32_t recon;     /* TGKS_RECON_*; characteristic only with ndim 1 or 2 (default conservative) */
+  /* prescribed sides (TGKS_BC_PRESCRIBED), ignored otherwise: */
+  double bc_state[2][5];   /* states A and B, conservative, (rho, m_0 .. m_{ndim-1}, E) */
+  double bc_line[3][2][3]; /* per axis and end (0 low, 1 high): (s0, s_n, s_t) */
+  int32_t bc_far[3][2];    /* per axis and end: kind beyond the line */
+  /* first-order fallback (not in the paper; 1-D and 2-D contexts; default
+   * 0): 1 replaces a reconstructed Gauss-point state of one side whose
+   * density or pressure, (gamma-1) (E - (0.5 sum_a m_a^2) / rho) evaluated in
+   * that order, is not positive or not finite by the average of that side's
+   * cell at the face, with zero slopes, before the flux is evaluated.  It is
+   * not a positivity-preserving limiter: cell averages can still become
+   * non-physical. */
+  int32_t fallback;
 } tgks_params;
 
 typedef struct tgks_ctx tgks_ctx;
@@ -131,6 +155,12 @@ int tgks_step(tgks_ctx* ctx, const double* W_in, double* W_out, const double* dt
  * captures the n_steps loop into a HIP graph on first use and replays it. */
 int tgks_run(tgks_ctx* ctx, double* W, int32_t n_steps, double cfl, double t_end, double fixed_dt,
              double* time_dev, int32_t use_graph);
+
+/* Time of the prescribed boundary states (TGKS_BC_PRESCRIBED): tgks_step
+ * advances a state of time t0, tgks_run a state of time t0 + its clock (the
+ * clock starts at 0 in every call).  Default 0; does not touch the device
+ * and affects later calls only. */
+int tgks_set_time(tgks_ctx* ctx, double t0);
 
 /* Tile shape of the 2-D face kernel (faces along the normal x along the
  * face, two lanes per face): 0 = 16 x 8, 1 = 16 x 16, 2 = 8 x 16; -1 selects
@@ -202,8 +232,8 @@ int tgks_gp_flux_host(const tgks_params* p, const double* Wl, const double* Wr, 
  * overlap gW_out.  W_star: the step's intermediate state W* as tgks_step
  * returned it for the same W_n and dt (device), or NULL to recompute it with
  * the forward kernels.  The first call allocates the context's reverse-mode
- * buffers.  TGKS_EINVAL for 3-D contexts, characteristic variables or
- * invalid pointers. */
+ * buffers.  TGKS_EINVAL for 3-D contexts, characteristic variables,
+ * prescribed sides, the first-order fallback or invalid pointers. */
 int tgks_step_adjoint(tgks_ctx* ctx, const double* W_n, const double* W_star, const double* dt_dev,
                       const double* gW_out, double* gW_in);
 
@@ -232,7 +262,8 @@ typedef struct tgks_batch tgks_batch;
  * (1 or 2), the same reconstruction variables, and all Euler or all
  * Navier-Stokes with a Prandtl correction (characteristic variables: one
  * 2-D tile shape, 2).  Allocates the batch's work buffers (about three packed states plus face
- * fluxes).  TGKS_EINVAL for invalid or mixed parameters. */
+ * fluxes).  TGKS_EINVAL for invalid or mixed parameters, prescribed sides
+ * and the first-order fallback. */
 int tgks_batch_create(const tgks_params* per_instance, int32_t n_inst, void* hip_stream, tgks_batch** out);
 int tgks_batch_destroy(tgks_batch* b);
 int tgks_batch_set_stream(tgks_batch* b, void* hip_stream);

@@ -93,6 +93,7 @@ static BatchArgs batch_args(tgks_batch* b, const double* W, double* o1, double* 
   a.clock = b->clock;
   a.partial = b->partial;
   a.fail = b->fail;
+  a.fallback = 0;
   return a;
 }
 
@@ -226,6 +227,7 @@ int tgks_batch_create(const tgks_params* p, int32_t n_inst, void* stream, tgks_b
   const bool ns = p[0].mu > 0.0 && p[0].prandtl != 1.0;
   for (int i = 0; i < n_inst; ++i) {
     if (check_params(&p[i]) || p[i].ndim != D || p[i].recon != p[0].recon) return TGKS_EINVAL;
+    if (has_prescribed(&p[i]) || p[i].fallback) return TGKS_EINVAL;
     if ((p[i].mu > 0.0 && p[i].prandtl != 1.0) != ns) return TGKS_EINVAL;
   }
   tgks_batch* b = new (std::nothrow) tgks_batch();

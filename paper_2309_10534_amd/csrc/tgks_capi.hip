@@ -460,6 +460,7 @@ int tgks_create(const tgks_params* p, void* stream, tgks_ctx** out) {
   tgks_ctx* c = new (std::nothrow) tgks_ctx();
   if (!c) return TGKS_EHIP;
   c->p = *p;
+  c->pb = prescribed_of(p);
   c->stream = (hipStream_t)stream;
   const int D = p->ndim;
   c->nc = D + 2;
@@ -571,7 +572,7 @@ int tgks_step(tgks_ctx* c, const double* W_in, double* W_out, const double* dt_d
 
 static int enqueue_run(tgks_ctx* c, double* W, int n_steps, double cfl, double t_end, double fixed_dt,
                        double* time_dev) {
-  int r;
+  int r = 0;
   const bool use_cfl = cfl > 0.0;
   if (use_cfl) {
     if ((r = launch_cfl_partial(c, W))) return r;
@@ -582,13 +583,16 @@ static int enqueue_run(tgks_ctx* c, double* W, int n_steps, double cfl, double t
   }
   double* src = W;
   double* dst = c->W2;
+  c->tclk = c->clock;  // the state of each step is that of time t0 + clock[0]
   for (int s = 0; s < n_steps; ++s) {
-    if ((r = do_step(c, src, dst, c->clock + 1, nullptr, use_cfl))) return r;
-    if ((r = launch_finalize(c, cfl, 0.0, t_end, c->clock, nullptr, use_cfl ? 1 : 2))) return r;
+    if ((r = do_step(c, src, dst, c->clock + 1, nullptr, use_cfl))) break;
+    if ((r = launch_finalize(c, cfl, 0.0, t_end, c->clock, nullptr, use_cfl ? 1 : 2))) break;
     double* t = src;
     src = dst;
     dst = t;
   }
+  c->tclk = nullptr;
+  if (r) return r;
   if (src != W)
     HIPCHK(hipMemcpyAsync(W, src, (size_t)c->nc * c->ncell * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   if (time_dev)
@@ -602,7 +606,8 @@ int tgks_run(tgks_ctx* c, double* W, int32_t n_steps, double cfl, double t_end, 
   if (!(cfl > 0.0) && !(fixed_dt > 0.0)) return TGKS_EINVAL;
   if (!use_graph || c->timing) return enqueue_run(c, W, n_steps, cfl, t_end, fixed_dt, time_dev);
   const bool same = c->gexec && c->g_steps == n_steps && c->g_cfl == cfl && c->g_tend == t_end &&
-                    c->g_fixed == fixed_dt && c->g_W == W && c->g_time == time_dev;
+                    c->g_fixed == fixed_dt && c->g_W == W && c->g_time == time_dev &&
+                    (!c->pb.on || c->g_t0 == c->t0);
   if (!same) {
     if (c->gexec) {
       (void)hipGraphExecDestroy(c->gexec);
@@ -631,8 +636,15 @@ int tgks_run(tgks_ctx* c, double* W, int32_t n_steps, double cfl, double t_end, 
     c->g_fixed = fixed_dt;
     c->g_W = W;
     c->g_time = time_dev;
+    c->g_t0 = c->t0;
   }
   HIPCHK(hipGraphLaunch(c->gexec, c->stream));
+  return TGKS_OK;
+}
+
+int tgks_set_time(tgks_ctx* c, double t0) {
+  if (!c || !std::isfinite(t0)) return TGKS_EINVAL;
+  c->t0 = t0;
   return TGKS_OK;
 }
 

@@ -908,6 +908,7 @@ TGKS_HD bool gp_flux(const R* Wl, const R* Wr, const R (*dWl)[D + 2], const R (*
 // 2: every momentum component changes sign).
 // ---------------------------------------------------------------------------
 constexpr int BC_NOSLIP = 3;  // boundary kind of the no-slip adiabatic wall
+constexpr int BC_PRESCRIBED = 4;  // boundary kind of given states (resolved before the map)
 
 TGKS_HD int map_index(int i, int n, int bclo, int bchi, int& flip) {
   if (i >= 0 && i < n) return i;

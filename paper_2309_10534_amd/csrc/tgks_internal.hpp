@@ -42,11 +42,16 @@ struct tgks_ctx {
   int nblk = 0;
   double* clock = nullptr;
   unsigned long long* fail = nullptr;
+  // prescribed sides: states, lines, and the time of the state being stepped
+  // (t0 + *tclk; tclk is the run clock inside tgks_run, null otherwise)
+  Prescribed pb{};
+  double t0 = 0.0;
+  const double* tclk = nullptr;
   // graph cache of tgks_run
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
   int g_steps = -1;
-  double g_cfl = 0, g_tend = 0, g_fixed = 0;
+  double g_cfl = 0, g_tend = 0, g_fixed = 0, g_t0 = 0;
   double* g_W = nullptr;
   double* g_time = nullptr;
   // reverse-mode buffers (allocated by the first tgks_step_adjoint)
@@ -75,8 +80,17 @@ inline int check_params(const tgks_params* p) {
   for (int d = 0; d < 3; ++d) {
     if (d < p->ndim) {
       if (p->n[d] < 3 || !(p->dx[d] > 0.0)) return TGKS_EINVAL;
-      if (p->bc_lo[d] < 0 || p->bc_lo[d] > 3 || p->bc_hi[d] < 0 || p->bc_hi[d] > 3) return TGKS_EINVAL;
+      if (p->bc_lo[d] < 0 || p->bc_lo[d] > 4 || p->bc_hi[d] < 0 || p->bc_hi[d] > 4) return TGKS_EINVAL;
       if ((p->bc_lo[d] == TGKS_BC_PERIODIC) != (p->bc_hi[d] == TGKS_BC_PERIODIC)) return TGKS_EINVAL;
+      for (int e = 0; e < 2; ++e) {
+        if ((e == 0 ? p->bc_lo[d] : p->bc_hi[d]) != TGKS_BC_PRESCRIBED) continue;
+        if (p->ndim > 2) return TGKS_EINVAL;
+        const int far = p->bc_far[d][e];
+        if (far != TGKS_BC_TRANSMISSIVE && far != TGKS_BC_REFLECTIVE && far != TGKS_BC_PRESCRIBED)
+          return TGKS_EINVAL;
+        for (int k = 0; k < 3; ++k)
+          if (std::isnan(p->bc_line[d][e][k])) return TGKS_EINVAL;
+      }
     } else if (p->n[d] != 1) {
       return TGKS_EINVAL;
     }
@@ -87,10 +101,34 @@ inline int check_params(const tgks_params* p) {
   if (p->q < 1 || p->q > 16 || !(p->eps >= 0.0)) return TGKS_EINVAL;
   if (p->recon != TGKS_RECON_CONSERVATIVE && p->recon != TGKS_RECON_CHARACTERISTIC) return TGKS_EINVAL;
   if (p->recon == TGKS_RECON_CHARACTERISTIC && p->ndim > 2) return TGKS_EINVAL;
+  if (p->fallback != 0 && p->fallback != 1) return TGKS_EINVAL;
+  if (p->fallback == 1 && p->ndim > 2) return TGKS_EINVAL;
   double cells = 1.0;
   for (int d = 0; d < p->ndim; ++d) cells *= p->n[d];
   if (cells > 4.0e9) return TGKS_EINVAL;
   return TGKS_OK;
+}
+
+inline bool has_prescribed(const tgks_params* p) {
+  for (int d = 0; d < p->ndim; ++d)
+    if (p->bc_lo[d] == TGKS_BC_PRESCRIBED || p->bc_hi[d] == TGKS_BC_PRESCRIBED) return true;
+  return false;
+}
+
+// kernel form of the prescribed sides (1-D and 2-D)
+inline Prescribed prescribed_of(const tgks_params* p) {
+  Prescribed b{};
+  b.on = has_prescribed(p) ? 1 : 0;
+  for (int d = 0; d < 2; ++d)
+    for (int e = 0; e < 2; ++e) {
+      b.far[d][e] = p->bc_far[d][e];
+      for (int k = 0; k < 3; ++k) b.line[d][e][k] = p->bc_line[d][e][k];
+    }
+  for (int c = 0; c < 4; ++c) {
+    b.A[c] = p->bc_state[0][c];
+    b.B[c] = p->bc_state[1][c];
+  }
+  return b;
 }
 
 inline hipEvent_t take_event(tgks_ctx* c) {
@@ -142,6 +180,10 @@ inline StageArgs stage_args(tgks_ctx* c, const double* W, int ax, const double* 
   a.R = c->R;
   a.Rout = c->R;
   a.gamma = c->p.gamma;
+  a.pb = c->pb;
+  a.t0 = c->t0;
+  a.tclk = c->tclk;
+  a.fallback = c->p.fallback;
   return a;
 }
 

@@ -22,6 +22,17 @@ struct Geom {
   long long ncell;
 };
 
+// Prescribed sides of 1-D and 2-D grids: a ghost cell centred at s along
+// the other axis (0 in 1-D) and r along the side's axis holds A where
+// s < (s0 + s_n r) + s_t t, beyond the line B (far == BC_PRESCRIBED) or the
+// transmissive / reflective image (far == 1 / 2).
+struct Prescribed {
+  int on;               // some side is prescribed
+  int far[2][2];        // [axis][end]
+  double A[4], B[4];    // global component order
+  double line[2][2][3]; // [axis][end]: s0, s_n, s_t
+};
+
 struct StageArgs {
   Geom g;
   FluxCfg fc;
@@ -37,6 +48,10 @@ struct StageArgs {
   const double* R;  // 3-D: normal reconstruction of this direction
   double* Rout;
   double gamma;     // ratio of specific heats (characteristic variables)
+  Prescribed pb;    // prescribed sides
+  double t0;        // time of W (prescribed states) is t0 + *tclk (tclk may be null)
+  const double* tclk;
+  int fallback;     // 1: first-order fallback at non-physical Gauss-point states
 };
 
 __device__ __forceinline__ long long face_count(const Geom& g, int ax) {
@@ -60,6 +75,79 @@ __device__ __forceinline__ double load_cell(const Geom& g, const double* W, int 
     if ((fo == 1) ^ (f0 == 2) ^ (f1 == 2) ^ (f2 == 2)) v = -v;
   }
   return v;
+}
+
+// time of the prescribed states in stage STAGE of a step of length dt
+// (stage 2 works on W*, the state at the half step)
+__device__ __forceinline__ double boundary_time(const StageArgs& a, int stage, double dt) {
+#pragma clang fp contract(off)
+  if (!a.pb.on) return 0.0;
+  const double t = a.t0 + (a.tclk ? *a.tclk : 0.0);
+  return stage == 2 ? t + 0.5 * dt : t;
+}
+
+// load_cell with prescribed sides resolved first (x side, then y side): the
+// given state at the ghost cell's centre, or the far kind's image
+__device__ __forceinline__ double cell_value(const Geom& g, const Prescribed& pb, const double* W, int c, int i,
+                                             int j, double tb) {
+#pragma clang fp contract(off)
+  if (!pb.on) return load_cell(g, W, c, i, j, 0);
+  int lo0 = g.bclo[0], hi0 = g.bchi[0], lo1 = g.bclo[1], hi1 = g.bchi[1];
+#pragma unroll
+  for (int d = 0; d < 2; ++d) {
+    if (d >= g.D) break;
+    const int id = d == 0 ? i : j;
+    const int n = g.n[d];
+    if (id >= 0 && id < n) continue;
+    const bool low = id < 0;
+    const int kind = d == 0 ? (low ? lo0 : hi0) : (low ? lo1 : hi1);
+    if (kind != BC_PRESCRIBED) continue;
+    const double s = g.D == 2 ? ((double)(d == 0 ? j : i) + 0.5) * g.dx[1 - d] : 0.0;
+    const double r = ((double)id + 0.5) * g.dx[d];
+    const double* L = low ? pb.line[d][0] : pb.line[d][1];
+    if (s < (L[0] + L[1] * r) + L[2] * tb) return pb.A[c];
+    const int far = low ? pb.far[d][0] : pb.far[d][1];
+    if (far == BC_PRESCRIBED) return pb.B[c];
+    if (d == 0) {
+      if (low) lo0 = far; else hi0 = far;
+    } else {
+      if (low) lo1 = far; else hi1 = far;
+    }
+  }
+  int f0 = 0, f1 = 0;
+  const int ii = map_index(i, g.n[0], lo0, hi0, f0);
+  const int jj = g.D >= 2 ? map_index(j, g.n[1], lo1, hi1, f1) : 0;
+  double v = W[(long long)c * g.ncell + (long long)jj * g.n[0] + ii];
+  if (c >= 1 && c <= g.D) {
+    const int fo = c == 1 ? f0 : f1;
+    if ((fo == 1) ^ (f0 == 2) ^ (f1 == 2)) v = -v;
+  }
+  return v;
+}
+
+// density and pressure of a frame-ordered Gauss-point state positive and
+// finite, in one fixed operation order (the fallback's test)
+template <int NC>
+__device__ __forceinline__ bool physical_state(const double* w, double gamma) {
+#pragma clang fp contract(off)
+  double ke = 0.0;
+#pragma unroll
+  for (int q = 1; q < NC - 1; ++q) ke = ke + w[q] * w[q];
+  const double pr = (gamma - 1.0) * (w[NC - 1] - 0.5 * ke / w[0]);
+  return w[0] > 0.0 && pr > 0.0 && isfinite(w[0]) && isfinite(pr);
+}
+
+// first-order fallback: a non-physical side state becomes the side's cell
+// average C with zero slopes
+template <int NC, int ND>
+__device__ __forceinline__ void fallback_side(double* w, double (*dw)[NC], const double* C, double gamma) {
+  if (physical_state<NC>(w, gamma)) return;
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+    w[q] = C[q];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) dw[d][q] = 0.0;
+  }
 }
 
 template <int NC>
@@ -98,12 +186,13 @@ __device__ __forceinline__ void face1d_body(const StageArgs& a, int f) {
   if (f > n) return;
   double Wl[3], Wr[3], dWl[1][3], dWr[1][3];
   const double idx = 1.0 / a.g.dx[0];  // normal slopes per unit length
+  const double tb = boundary_time(a, STAGE, dt);
   if (CHAR) {
     double C[6][3];
 #pragma unroll
     for (int r = 0; r < 6; ++r)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) C[r][c] = load_cell(a.g, a.W, c, f - 3 + r, 0, 0);
+      for (int c = 0; c < 3; ++c) C[r][c] = cell_value(a.g, a.pb, a.W, c, f - 3 + r, 0, tb);
     unsigned fr[3];
     char_recon_face<1>(a.gamma, C, a.tn, idx, Wl, dWl[0], Wr, dWr[0], fr);
     if (FLAGS && f < n)
@@ -114,7 +203,7 @@ __device__ __forceinline__ void face1d_body(const StageArgs& a, int f) {
     for (int c = 0; c < 3; ++c) {
       double Q[6];
 #pragma unroll
-      for (int r = 0; r < 6; ++r) Q[r] = load_cell(a.g, a.W, c, f - 3 + r, 0, 0);
+      for (int r = 0; r < 6; ++r) Q[r] = cell_value(a.g, a.pb, a.W, c, f - 3 + r, 0, tb);
       double o[4];
       const unsigned fl = teno_flag(Q, a.tn);
       teno_face(Q, fl, o);
@@ -126,6 +215,16 @@ __device__ __forceinline__ void face1d_body(const StageArgs& a, int f) {
       dWr[0][c] = o[1] * idx;
       if (FLAGS && f < n) a.nflags[(long long)c * n + f] = (uint8_t)fr;
     }
+  }
+  if (a.fallback) {
+    double Cl[3], Cr[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      Cl[c] = cell_value(a.g, a.pb, a.W, c, f - 1, 0, tb);
+      Cr[c] = cell_value(a.g, a.pb, a.W, c, f, 0, tb);
+    }
+    fallback_side<3, 1>(Wl, dWl, Cl, a.gamma);
+    fallback_side<3, 1>(Wr, dWr, Cr, a.gamma);
   }
   double Fdt[3], Fh[3], A[3] = {0, 0, 0}, B[3] = {0, 0, 0};
   const bool ok = gp_flux<1, NS>(Wl, Wr, dWl, dWr, a.fc, dt, Fdt, Fh);
@@ -190,8 +289,9 @@ __device__ __forceinline__ void face2d_tile(const StageArgs& a, int bx, int by, 
   const int nN = g.n[AX], nT = g.n[TA];
   const int f0 = bx * TN, t0 = by * TT;
   const int tid = threadIdx.x;
+  const double tb = boundary_time(a, STAGE, dt);
 
-  // 1. cells of the tile, ghost cells by the index map
+  // 1. cells of the tile, ghost cells by the index map or prescribed states
   for (int L = tid; L < NC * LN * LT; L += NT) {
     int nl, tl;
     if (AX == 0) {
@@ -204,7 +304,7 @@ __device__ __forceinline__ void face2d_tile(const StageArgs& a, int bx, int by, 
     const int c = L / (LN * LT);
     const int pn = f0 - 3 + nl, pt = t0 - 2 + tl;
     const int x = AX == 0 ? pn : pt, y = AX == 0 ? pt : pn;
-    sW[c][tl][nl] = load_cell(g, a.W, c, x, y, 0);
+    sW[c][tl][nl] = cell_value(g, a.pb, a.W, c, x, y, tb);
   }
   __syncthreads();
 
@@ -360,14 +460,18 @@ __device__ __forceinline__ void face2d_tile(const StageArgs& a, int bx, int by, 
         double v[2], dv[2], vn[2], dvn[2];
         teno_gauss(Qw, fw, v, dv);
         teno_gauss(Qn, fq, vn, dvn);
+        {
+          // back-projection: dense sums in field order, no contraction
+#pragma clang fp contract(off)
 #pragma unroll
-        for (int q = 0; q < NC; ++q)
+          for (int q = 0; q < NC; ++q)
 #pragma unroll
-          for (int gp = 0; gp < 2; ++gp) {
-            aV[q][gp] = aV[q][gp] + Rt[q][k] * v[gp];
-            aD[q][gp] = aD[q][gp] + Rt[q][k] * dv[gp];
-            aN[q][gp] = aN[q][gp] + Rt[q][k] * vn[gp];
-          }
+            for (int gp = 0; gp < 2; ++gp) {
+              aV[q][gp] = aV[q][gp] + Rt[q][k] * v[gp];
+              aD[q][gp] = aD[q][gp] + Rt[q][k] * dv[gp];
+              aN[q][gp] = aN[q][gp] + Rt[q][k] * vn[gp];
+            }
+        }
       }
     }
 #pragma unroll
@@ -417,6 +521,16 @@ __device__ __forceinline__ void face2d_tile(const StageArgs& a, int bx, int by, 
     }
   }
   double A[NC] = {0, 0, 0, 0}, B[NC] = {0, 0, 0, 0};
+  if (live && a.fallback) {
+    double Cl[NC], Cr[NC];
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      Cl[q] = sW[perm[q]][ft + 2][fn + 2];
+      Cr[q] = sW[perm[q]][ft + 2][fn + 3];
+    }
+    fallback_side<NC, 2>(Wg[0], Dg[0], Cl, a.gamma);
+    fallback_side<NC, 2>(Wg[1], Dg[1], Cr, a.gamma);
+  }
   if (live) {
     double Fdt[NC], Fh[NC];
     if (!gp_flux<2, NS>(Wg[0], Wg[1], Dg[0], Dg[1], a.fc, dt, Fdt, Fh)) atomicAdd(a.fail, 1ull);

@@ -14,9 +14,10 @@ import os
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libtgks.so")
 
-BC_PERIODIC, BC_TRANSMISSIVE, BC_REFLECTIVE, BC_NOSLIP = 0, 1, 2, 3
+BC_PERIODIC, BC_TRANSMISSIVE, BC_REFLECTIVE, BC_NOSLIP, BC_PRESCRIBED = 0, 1, 2, 3, 4
 TAU_INVISCID, TAU_VISCOUS, TAU_ZERO = 0, 1, 2
-_BC = {"periodic": 0, "transmissive": 1, "reflective": 2, "noslip": 3}
+_BC = {"periodic": 0, "transmissive": 1, "reflective": 2, "noslip": 3, "prescribed": 4}
+_FAR = {"transmissive": 1, "reflective": 2, "state_b": 4}
 _TAU = {"inviscid": 0, "viscous": 1, "zero": 2}
 
 KERNEL_KINDS = {"face_x": 0, "face_y": 1, "face_z": 2, "recon3d": 3, "update1": 4, "update2": 5, "cfl": 6}
@@ -31,6 +32,8 @@ class TgksParams(C.Structure):
         ("tau_mode", C.c_int32), ("c1", C.c_double), ("c2", C.c_double),
         ("ct1", C.c_double), ("ct2", C.c_double), ("ct1_tan", C.c_double), ("ct2_tan", C.c_double),
         ("eps", C.c_double), ("q", C.c_int32), ("recon", C.c_int32),
+        ("bc_state", (C.c_double * 5) * 2), ("bc_line", ((C.c_double * 3) * 2) * 3),
+        ("bc_far", (C.c_int32 * 2) * 3), ("fallback", C.c_int32),
     ]
 
 
@@ -62,6 +65,7 @@ def lib():
     L.tgks_cfl_dt.argtypes = [vp, vp, C.c_double, C.c_double, C.c_double, vp]
     L.tgks_step.argtypes = [vp, vp, vp, vp, vp, vp]
     L.tgks_run.argtypes = [vp, vp, C.c_int32, C.c_double, C.c_double, C.c_double, vp, C.c_int32]
+    L.tgks_set_time.argtypes = [vp, C.c_double]
     L.tgks_status.argtypes = [vp, C.POINTER(C.c_int64)]
     L.tgks_reset_status.argtypes = [vp]
     L.tgks_timing.argtypes = [vp, C.c_int32]
@@ -96,7 +100,7 @@ def lib():
         getattr(L, f).restype = C.c_int
     for f in ("tgks_params_default", "tgks_create", "tgks_destroy", "tgks_set_stream", "tgks_cfl_dt", "tgks_step",
               "tgks_run", "tgks_status", "tgks_reset_status", "tgks_timing", "tgks_kernel_time",
-              "tgks_flop_counts", "tgks_gp_flux_host", "tgks_set_tile", "tgks_tune"):
+              "tgks_flop_counts", "tgks_gp_flux_host", "tgks_set_tile", "tgks_tune", "tgks_set_time"):
         getattr(L, f).restype = C.c_int
     _lib = L
     return L
@@ -126,8 +130,11 @@ def _ptr(t, numel=None, dtype=None):
 def tgks_params_default(ndim, shape=None, dx=None, bc="transmissive", **kw):
     """tgks_params filled with the paper's constants; shape / dx / bc / keyword
     fields (gamma, mu, prandtl, tau, c1, c2, ct1, ct2, ct1_tan, ct2_tan, eps, q,
-    recon: 0 conservative, 1 characteristic variables)
-    override them."""
+    recon: 0 conservative, 1 characteristic variables, fallback: 1 first-order
+    fallback at non-physical Gauss-point states) override them.  Prescribed
+    sides (bc name "prescribed"): states = (A, B), lines = {(axis, end):
+    (s0, s_n, s_t)}, far = {(axis, end): "transmissive" | "reflective" |
+    "state_b"} (see tgks.h)."""
     p = TgksParams()
     _check(lib().tgks_params_default(C.byref(p), int(ndim)), "tgks_params_default")
     if shape is not None:
@@ -141,6 +148,19 @@ def tgks_params_default(ndim, shape=None, dx=None, bc="transmissive", **kw):
         p.bc_lo[d], p.bc_hi[d] = _BC[lo], _BC[hi]
     if "tau" in kw:
         p.tau_mode = _TAU[kw.pop("tau")]
+    states, lines, far = kw.pop("states", None), kw.pop("lines", None), kw.pop("far", None)
+    if states is not None:
+        for k in range(2):
+            for c, v in enumerate(states[k]):
+                p.bc_state[k][c] = float(v)
+    for (d, e), ln in (lines or {}).items():
+        for k in range(3):
+            p.bc_line[d][e][k] = float(ln[k])
+    for d in range(3):
+        for e in range(2):
+            p.bc_far[d][e] = _FAR["state_b"]
+    for (d, e), name in (far or {}).items():
+        p.bc_far[d][e] = _FAR[name]
     for k, v in kw.items():
         setattr(p, k, v)
     return p
@@ -187,6 +207,12 @@ def tgks_run(ctx, W, n_steps, cfl=0.0, t_end=0.0, fixed_dt=0.0, time_dev=None, u
     n = tgks_state_size(ctx)
     _check(lib().tgks_run(ctx, _ptr(W, n), int(n_steps), float(cfl), float(t_end), float(fixed_dt),
                           _ptr(time_dev, 2), int(bool(use_graph))), "tgks_run")
+
+
+def tgks_set_time(ctx, t0):
+    """Time of the state that the next tgks_step / tgks_run advances (the
+    prescribed boundary states depend on it)."""
+    _check(lib().tgks_set_time(ctx, float(t0)), "tgks_set_time")
 
 
 def tgks_status(ctx):

@@ -43,8 +43,10 @@ class GpuProblem:
     def dev(self, W):
         return self.torch.from_numpy(np.ascontiguousarray(W, dtype=np.float64)).cuda()
 
-    def step(self, W, dt, flags=True):
+    def step(self, W, dt, flags=True, t0=None):
         torch = self.torch
+        if t0 is not None:
+            self.t.tgks_set_time(self.ctx, t0)
         Win = self.dev(W)
         Wout = torch.empty_like(Win)
         Ws = torch.empty_like(Win)
@@ -63,8 +65,10 @@ class GpuProblem:
         self.t.tgks_cfl_dt(self.ctx, self.dev(W), cfl, t, t_end, dtd)
         return float(dtd.cpu()[0])
 
-    def run(self, W, n_steps, cfl=0.0, t_end=0.0, fixed_dt=0.0, use_graph=False):
+    def run(self, W, n_steps, cfl=0.0, t_end=0.0, fixed_dt=0.0, use_graph=False, t0=None):
         torch = self.torch
+        if t0 is not None:
+            self.t.tgks_set_time(self.ctx, t0)
         Wd = self.dev(W)
         td = torch.zeros(2, dtype=torch.float64, device="cuda")
         self.t.tgks_reset_status(self.ctx)
