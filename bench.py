@@ -37,8 +37,8 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector peak (256 CU x 2.4 GHz x 128 flop/
 # the three files below); the bench reports null traffic otherwise.
 TRAFFIC_SOURCES = ("paper_2309_10534_amd/csrc/tgks_device.hpp", "paper_2309_10534_amd/csrc/tgks_kernels.hpp",
                    "paper_2309_10534_amd/csrc/tgks_face2d.hip")
-TRAFFIC = {"sha": "a4c601441b0a53af", "tile": 2, "fetch_factor": 32768.0 / 16397.5, "write_factor": 1.0,
-           "face_xy": {"fetch_kib": 128515.0, "write_kib": 116847.6}}
+TRAFFIC = {"sha": "75b974f933da5506", "tile": 2, "fetch_factor": 32768.0 / 16397.9, "write_factor": 1.0,
+           "face_xy": {"fetch_kib": 128495.8, "write_kib": 116857.9}}
 
 
 def measured_traffic(kernel, tile):
@@ -269,6 +269,15 @@ def characteristic(n=1024, seed=1, steps=100, n_inst=256):
     return out
 
 
+def stop_reason(t_done, t_end, fails):
+    """Why a run to t_end ended: reached it, a non-physical Gauss-point state
+    (counted by the flux), or a non-physical cell average (no finite CFL
+    step; the first-order fallback does not prevent these)."""
+    if t_end - t_done <= 1e-12 * t_end:
+        return "t_end"
+    return "non-physical Gauss-point state" if fails else "non-physical cell (no finite CFL step)"
+
+
 def viscous_shock_tube(nx=500, re=200.0, t_end=1.0, cfl=0.2, chunk=200):
     """Viscous shock tube (Sec. 5.8): [0, 1] x [0, 1/2], nx x nx/2 cells,
     Re 200 (mu = 1/Re), Pr 0.73, no-slip adiabatic walls left, right and at
@@ -318,6 +327,7 @@ def viscous_shock_tube(nx=500, re=200.0, t_end=1.0, cfl=0.2, chunk=200):
         tgks.tgks_destroy(ctx)
         finite = bool(torch.isfinite(W).all().item())
         out[name] = {"t_reached": t_done, "failures": fails, "finite": finite,
+                     "stopped": stop_reason(t_done, t_end, fails),
                      "steps": steps, "seconds": round(el, 3),
                      "value": round(nx * ny * steps / el / 1e6, 3), "unit": "Mcell-updates/s"}
         if finite and fails == 0:
@@ -375,7 +385,7 @@ def double_mach(nx=960, ny=240, t_end=0.2, cfl=0.5, chunk=100):
         fails = tgks.tgks_status(ctx)
         tgks.tgks_destroy(ctx)
         out[name] = {"t_reached": t_done, "failures": fails, "finite": bool(torch.isfinite(W).all().item()),
-                     "steps": steps, "seconds": round(el, 3),
+                     "stopped": stop_reason(t_done, t_end, fails), "steps": steps, "seconds": round(el, 3),
                      "value": round(nx * ny * steps / el / 1e6, 3) if steps else None, "unit": "Mcell-updates/s"}
     return out
 

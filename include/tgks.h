@@ -165,14 +165,16 @@ int tgks_set_time(tgks_ctx* ctx, double t0);
 /* Tile shape of the 2-D face kernel (faces along the normal x along the
  * face, two lanes per face): 0 = 16 x 8, 1 = 16 x 16, 2 = 8 x 16; -1 selects
  * the default (0).  Other dimensions ignore it; with characteristic
- * variables the 2-D shape is always 2. */
+ * variables, prescribed sides or the first-order fallback the 2-D shape is
+ * always 2. */
 int tgks_set_tile(tgks_ctx* ctx, int32_t tile);
 
 /* Autotuner: time every tile shape over `steps` S2O4 steps of the state W
  * (device; not modified) with HIP events, select the fastest and return its
  * index in *chosen (host, may be NULL); ms_per_variant (host, 3 floats, or
  * NULL) receives the milliseconds per step of each shape (0 for shapes not
- * timed: with characteristic variables only shape 2 exists).  Synchronises
+ * timed: with characteristic variables, prescribed sides or the fallback
+ * only shape 2 exists).  Synchronises
  * the stream. */
 int tgks_tune(tgks_ctx* ctx, const double* W, int32_t steps, int32_t* chosen, float* ms_per_variant);
 

@@ -93,7 +93,6 @@ static BatchArgs batch_args(tgks_batch* b, const double* W, double* o1, double* 
   a.clock = b->clock;
   a.partial = b->partial;
   a.fail = b->fail;
-  a.fallback = 0;
   return a;
 }
 

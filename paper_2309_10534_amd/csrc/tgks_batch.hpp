@@ -35,10 +35,6 @@ struct BatchArgs {
   double* clock;     // [instance][t, dt]
   double* partial;   // per cell block
   unsigned long long* fail;  // per instance
-  // first-order fallback flag, always 0 (batches reject it); passed at run
-  // time so that the batched face code compiles exactly as the single-grid
-  // one does and stays bit-identical to it
-  int fallback;
 };
 
 __device__ __forceinline__ StageArgs batch_stage(const BatchArgs& b, const BatchInst& I, int inst, int ax) {
@@ -57,8 +53,8 @@ __device__ __forceinline__ StageArgs batch_stage(const BatchArgs& b, const Batch
   a.R = nullptr;
   a.Rout = nullptr;
   a.gamma = I.gamma;
-  a.pb.on = 0;  // batches have no prescribed sides
-  a.fallback = b.fallback;
+  a.pb.on = 0;  // batches have neither prescribed sides nor the fallback
+  a.fallback = 0;  // (and run the face bodies without them, EX = false)
   a.t0 = 0.0;
   a.tclk = nullptr;
   return a;

@@ -47,23 +47,28 @@ int launch_faces(tgks_ctx* c, const double* W, const double* dt, int stage, uint
     if (D == 1) {
       Timer tm(c, 0);
       dim3 grid((unsigned)((c->g.n[0] + 1 + 255) / 256));
-#define F1(CH)                                                                  \
-  if (stage == 1) {                                                             \
-    if (fl) {                                                                   \
-      if (c->ns) LAUNCH((face1d_kernel<1, true, true, CH>), grid, dim3(256), a);  \
-      else LAUNCH((face1d_kernel<1, false, true, CH>), grid, dim3(256), a);       \
-    } else {                                                                    \
-      if (c->ns) LAUNCH((face1d_kernel<1, true, false, CH>), grid, dim3(256), a); \
-      else LAUNCH((face1d_kernel<1, false, false, CH>), grid, dim3(256), a);      \
-    }                                                                           \
-  } else {                                                                      \
-    if (c->ns) LAUNCH((face1d_kernel<2, true, false, CH>), grid, dim3(256), a);   \
-    else LAUNCH((face1d_kernel<2, false, false, CH>), grid, dim3(256), a);        \
+#define F1(CH, EX)                                                                  \
+  if (stage == 1) {                                                                 \
+    if (fl) {                                                                       \
+      if (c->ns) LAUNCH((face1d_kernel<1, true, true, CH, EX>), grid, dim3(256), a);  \
+      else LAUNCH((face1d_kernel<1, false, true, CH, EX>), grid, dim3(256), a);       \
+    } else {                                                                        \
+      if (c->ns) LAUNCH((face1d_kernel<1, true, false, CH, EX>), grid, dim3(256), a); \
+      else LAUNCH((face1d_kernel<1, false, false, CH, EX>), grid, dim3(256), a);      \
+    }                                                                               \
+  } else {                                                                          \
+    if (c->ns) LAUNCH((face1d_kernel<2, true, false, CH, EX>), grid, dim3(256), a);   \
+    else LAUNCH((face1d_kernel<2, false, false, CH, EX>), grid, dim3(256), a);        \
   }
-      if (c->p.recon == TGKS_RECON_CHARACTERISTIC) {
-        F1(true)
+      const bool ch = c->p.recon == TGKS_RECON_CHARACTERISTIC;
+      if (ch && c->ex) {
+        F1(true, true)
+      } else if (ch) {
+        F1(true, false)
+      } else if (c->ex) {
+        F1(false, true)
       } else {
-        F1(false)
+        F1(false, false)
       }
 #undef F1
     } else if (D == 2) {
@@ -461,6 +466,7 @@ int tgks_create(const tgks_params* p, void* stream, tgks_ctx** out) {
   if (!c) return TGKS_EHIP;
   c->p = *p;
   c->pb = prescribed_of(p);
+  c->ex = c->pb.on || p->fallback;
   c->stream = (hipStream_t)stream;
   const int D = p->ndim;
   c->nc = D + 2;
@@ -789,7 +795,7 @@ int tgks_gp_flux_host(const tgks_params* p, const double* Wl, const double* Wr, 
 int tgks_set_tile(tgks_ctx* c, int32_t tile) {
   if (!c || tile < -1 || tile >= NTILE2) return TGKS_EINVAL;
   int t = tile < 0 ? 0 : tile;
-  if (c->g.D == 2 && c->p.recon == TGKS_RECON_CHARACTERISTIC) t = CHAR_TILE2;
+  if (c->g.D == 2 && (c->p.recon == TGKS_RECON_CHARACTERISTIC || c->ex)) t = CHAR_TILE2;
   if (t != c->tile2 && c->gexec) {
     (void)hipGraphExecDestroy(c->gexec);
     (void)hipGraphDestroy(c->graph);
@@ -816,10 +822,10 @@ int tgks_tune(tgks_ctx* c, const double* W, int32_t steps, int32_t* chosen, floa
   int best = 0;
   float best_ms = 0.f;
   const int old = c->tile2;
-  const bool char2 = c->g.D == 2 && c->p.recon == TGKS_RECON_CHARACTERISTIC;
+  const bool char2 = c->g.D == 2 && (c->p.recon == TGKS_RECON_CHARACTERISTIC || c->ex);
   bool first = true;
   for (int k = 0; k < nvar; ++k) {
-    if (char2 && k != CHAR_TILE2) {  // one tile shape on the characteristic path
+    if (char2 && k != CHAR_TILE2) {  // one tile shape on the characteristic / extras path
       if (ms_per_variant) ms_per_variant[k] = 0.f;
       continue;
     }

@@ -56,8 +56,9 @@ static void launch_face2d_xy(tgks_ctx* c, const StageArgs& ax, const StageArgs& 
 #undef LXY
 }
 
-// characteristic variables: one tile shape
-static void launch_face2d_xy_char(tgks_ctx* c, const StageArgs& ax, const StageArgs& ay, int stage, bool fl) {
+// characteristic variables, prescribed sides or the fallback: one tile shape
+template <bool CH, bool EX>
+static void launch_face2d_xy_one(tgks_ctx* c, const StageArgs& ax, const StageArgs& ay, int stage, bool fl) {
   constexpr int TILE = CHAR_TILE2;
   constexpr int TN = tile2_tn(TILE), TT = tile2_tt(TILE);
   const int nx = c->g.n[0], ny = c->g.n[1];
@@ -67,22 +68,25 @@ static void launch_face2d_xy_char(tgks_ctx* c, const StageArgs& ax, const StageA
 #define LXY(kern) hipLaunchKernelGGL(kern, grid, block, 0, c->stream, ax, ay)
   if (stage == 1) {
     if (fl) {
-      if (c->ns) LXY((face2d_xy_kernel<1, true, true, TILE, true>));
-      else LXY((face2d_xy_kernel<1, false, true, TILE, true>));
+      if (c->ns) LXY((face2d_xy_kernel<1, true, true, TILE, CH, EX>));
+      else LXY((face2d_xy_kernel<1, false, true, TILE, CH, EX>));
     } else {
-      if (c->ns) LXY((face2d_xy_kernel<1, true, false, TILE, true>));
-      else LXY((face2d_xy_kernel<1, false, false, TILE, true>));
+      if (c->ns) LXY((face2d_xy_kernel<1, true, false, TILE, CH, EX>));
+      else LXY((face2d_xy_kernel<1, false, false, TILE, CH, EX>));
     }
   } else {
-    if (c->ns) LXY((face2d_xy_kernel<2, true, false, TILE, true>));
-    else LXY((face2d_xy_kernel<2, false, false, TILE, true>));
+    if (c->ns) LXY((face2d_xy_kernel<2, true, false, TILE, CH, EX>));
+    else LXY((face2d_xy_kernel<2, false, false, TILE, CH, EX>));
   }
 #undef LXY
 }
 
 int launch_face2d_xy_any(tgks_ctx* c, const StageArgs& ax, const StageArgs& ay, int stage, bool fl) {
-  if (c->p.recon == TGKS_RECON_CHARACTERISTIC) {
-    launch_face2d_xy_char(c, ax, ay, stage, fl);
+  const bool ch = c->p.recon == TGKS_RECON_CHARACTERISTIC, ex = c->ex;
+  if (ch || ex) {
+    if (ch && ex) launch_face2d_xy_one<true, true>(c, ax, ay, stage, fl);
+    else if (ch) launch_face2d_xy_one<true, false>(c, ax, ay, stage, fl);
+    else launch_face2d_xy_one<false, true>(c, ax, ay, stage, fl);
     return TGKS_OK;
   }
   switch (c->tile2) {
@@ -99,6 +103,7 @@ int launch_face2d_xy_any(tgks_ctx* c, const StageArgs& ax, const StageArgs& ay, 
 }
 
 int launch_face2d_any(tgks_ctx* c, const StageArgs& a, int ax, int stage, bool fl) {
+  if (c->ex || c->p.recon == TGKS_RECON_CHARACTERISTIC) return TGKS_EINVAL;  // merged launch only
   const int nN = c->g.n[ax], nT = c->g.n[1 - ax];
   switch (c->tile2) {
     case 1:

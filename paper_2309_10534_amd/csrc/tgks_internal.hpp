@@ -47,6 +47,7 @@ struct tgks_ctx {
   Prescribed pb{};
   double t0 = 0.0;
   const double* tclk = nullptr;
+  bool ex = false;  // prescribed sides or the first-order fallback: the EX face kernels
   // graph cache of tgks_run
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;

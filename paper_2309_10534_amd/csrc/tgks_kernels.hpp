@@ -178,7 +178,9 @@ __device__ __forceinline__ void wall_fluxes(const Geom& g, int ax, int f, double
 // ---------------------------------------------------------------------------
 // 1-D: one thread per face.
 // ---------------------------------------------------------------------------
-template <int STAGE, bool NS, bool FLAGS, bool CHAR = false>
+// EX: prescribed sides or the first-order fallback may be on (a separate
+// instantiation, so that grids without them run the plain code)
+template <int STAGE, bool NS, bool FLAGS, bool CHAR = false, bool EX = false>
 __device__ __forceinline__ void face1d_body(const StageArgs& a, int f) {
   const double dt = *a.dt;
   if (!(dt > 0.0)) return;
@@ -186,13 +188,14 @@ __device__ __forceinline__ void face1d_body(const StageArgs& a, int f) {
   if (f > n) return;
   double Wl[3], Wr[3], dWl[1][3], dWr[1][3];
   const double idx = 1.0 / a.g.dx[0];  // normal slopes per unit length
-  const double tb = boundary_time(a, STAGE, dt);
+  const double tb = EX ? boundary_time(a, STAGE, dt) : 0.0;
   if (CHAR) {
     double C[6][3];
 #pragma unroll
     for (int r = 0; r < 6; ++r)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) C[r][c] = cell_value(a.g, a.pb, a.W, c, f - 3 + r, 0, tb);
+      for (int c = 0; c < 3; ++c)
+        C[r][c] = EX ? cell_value(a.g, a.pb, a.W, c, f - 3 + r, 0, tb) : load_cell(a.g, a.W, c, f - 3 + r, 0, 0);
     unsigned fr[3];
     char_recon_face<1>(a.gamma, C, a.tn, idx, Wl, dWl[0], Wr, dWr[0], fr);
     if (FLAGS && f < n)
@@ -203,7 +206,8 @@ __device__ __forceinline__ void face1d_body(const StageArgs& a, int f) {
     for (int c = 0; c < 3; ++c) {
       double Q[6];
 #pragma unroll
-      for (int r = 0; r < 6; ++r) Q[r] = cell_value(a.g, a.pb, a.W, c, f - 3 + r, 0, tb);
+      for (int r = 0; r < 6; ++r)
+        Q[r] = EX ? cell_value(a.g, a.pb, a.W, c, f - 3 + r, 0, tb) : load_cell(a.g, a.W, c, f - 3 + r, 0, 0);
       double o[4];
       const unsigned fl = teno_flag(Q, a.tn);
       teno_face(Q, fl, o);
@@ -216,7 +220,7 @@ __device__ __forceinline__ void face1d_body(const StageArgs& a, int f) {
       if (FLAGS && f < n) a.nflags[(long long)c * n + f] = (uint8_t)fr;
     }
   }
-  if (a.fallback) {
+  if (EX && a.fallback) {
     double Cl[3], Cr[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -239,9 +243,9 @@ __device__ __forceinline__ void face1d_body(const StageArgs& a, int f) {
   }
 }
 
-template <int STAGE, bool NS, bool FLAGS, bool CHAR = false>
+template <int STAGE, bool NS, bool FLAGS, bool CHAR = false, bool EX = false>
 __global__ __launch_bounds__(256) void face1d_kernel(StageArgs a) {
-  face1d_body<STAGE, NS, FLAGS, CHAR>(a, blockIdx.x * blockDim.x + threadIdx.x);
+  face1d_body<STAGE, NS, FLAGS, CHAR, EX>(a, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -275,7 +279,7 @@ __host__ __device__ constexpr int tile2_lds_char(int k) {
 // block's tile2_lds(TILE) (CHAR: tile2_lds_char(TILE)) doubles of shared
 // memory.  CHAR: reconstruction in characteristic variables (steps 2 and 3
 // below project onto the fields of each face and back).
-template <int AX, int STAGE, bool NS, bool FLAGS, int TILE, bool CHAR = false>
+template <int AX, int STAGE, bool NS, bool FLAGS, int TILE, bool CHAR = false, bool EX = false>
 __device__ __forceinline__ void face2d_tile(const StageArgs& a, int bx, int by, double* lds) {
   constexpr int TN = tile2_tn(TILE), TT = tile2_tt(TILE), NT = 2 * TN * TT;
   constexpr int NC = 4;
@@ -289,7 +293,7 @@ __device__ __forceinline__ void face2d_tile(const StageArgs& a, int bx, int by, 
   const int nN = g.n[AX], nT = g.n[TA];
   const int f0 = bx * TN, t0 = by * TT;
   const int tid = threadIdx.x;
-  const double tb = boundary_time(a, STAGE, dt);
+  const double tb = EX ? boundary_time(a, STAGE, dt) : 0.0;
 
   // 1. cells of the tile, ghost cells by the index map or prescribed states
   for (int L = tid; L < NC * LN * LT; L += NT) {
@@ -304,7 +308,7 @@ __device__ __forceinline__ void face2d_tile(const StageArgs& a, int bx, int by, 
     const int c = L / (LN * LT);
     const int pn = f0 - 3 + nl, pt = t0 - 2 + tl;
     const int x = AX == 0 ? pn : pt, y = AX == 0 ? pt : pn;
-    sW[c][tl][nl] = cell_value(g, a.pb, a.W, c, x, y, tb);
+    sW[c][tl][nl] = EX ? cell_value(g, a.pb, a.W, c, x, y, tb) : load_cell(g, a.W, c, x, y, 0);
   }
   __syncthreads();
 
@@ -521,7 +525,7 @@ __device__ __forceinline__ void face2d_tile(const StageArgs& a, int bx, int by, 
     }
   }
   double A[NC] = {0, 0, 0, 0}, B[NC] = {0, 0, 0, 0};
-  if (live && a.fallback) {
+  if (EX && live && a.fallback) {
     double Cl[NC], Cr[NC];
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
@@ -560,7 +564,7 @@ __global__ __launch_bounds__(2 * tile2_tn(TILE) * tile2_tt(TILE), 2) void face2d
 // Both directions in one launch: the first blocks take the x-face tiles,
 // the rest the y-face tiles (one shared LDS tile), so that neither
 // direction waits for the other's tail.
-template <int STAGE, bool NS, bool FLAGS, int TILE, bool CHAR = false>
+template <int STAGE, bool NS, bool FLAGS, int TILE, bool CHAR = false, bool EX = false>
 __global__ __launch_bounds__(2 * tile2_tn(TILE) * tile2_tt(TILE), 2) void face2d_xy_kernel(StageArgs ax,
                                                                                            StageArgs ay) {
   constexpr int TN = tile2_tn(TILE);
@@ -569,10 +573,10 @@ __global__ __launch_bounds__(2 * tile2_tn(TILE) * tile2_tt(TILE), 2) void face2d
   const int nx = nbx * ((ax.g.n[1] + tile2_tt(TILE) - 1) / tile2_tt(TILE));
   const int b = blockIdx.x;
   if (b < nx) {
-    face2d_tile<0, STAGE, NS, FLAGS, TILE, CHAR>(ax, b % nbx, b / nbx, lds);
+    face2d_tile<0, STAGE, NS, FLAGS, TILE, CHAR, EX>(ax, b % nbx, b / nbx, lds);
   } else {
     const int nby = (ay.g.n[1] + 1 + TN - 1) / TN;        // y faces: tiles along y
-    face2d_tile<1, STAGE, NS, FLAGS, TILE, CHAR>(ay, (b - nx) % nby, (b - nx) / nby, lds);
+    face2d_tile<1, STAGE, NS, FLAGS, TILE, CHAR, EX>(ay, (b - nx) % nby, (b - nx) / nby, lds);
   }
 }
 
