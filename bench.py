@@ -198,7 +198,7 @@ def characteristic(n=1024, seed=1, steps=100, n_inst=256):
     kernel's roofline with characteristic variables, and the instances of
     the seeded batched Riemann sets (1-D seed 1, 2-D seed 2, the stated
     ranges) that run `steps` single-grid steps without a non-physical state
-    under each choice."""
+    under each choice, without and with the first-order fallback."""
     import numpy as np
     import torch
 
@@ -246,11 +246,13 @@ def characteristic(n=1024, seed=1, steps=100, n_inst=256):
     for dim, iseed in ((1, 1), (2, 2)):
         inst, _, _ = I.riemann_instances(n_inst, dim=dim, seed=iseed)
         counts = {}
-        for recon, name in ((0, "conservative"), (1, "characteristic")):
+        for recon, fb, name in ((0, 0, "conservative"), (1, 0, "characteristic"),
+                                (0, 1, "conservative_fallback"), (1, 1, "characteristic_fallback")):
             ok = 0
             td = torch.zeros(2, dtype=torch.float64, device="cuda")
             for Wi, dxi in inst:
-                p = tgks.tgks_params_default(dim, list(Wi.shape[1:])[::-1], [dxi] * dim, recon=recon)
+                p = tgks.tgks_params_default(dim, list(Wi.shape[1:])[::-1], [dxi] * dim, recon=recon,
+                                             fallback=fb)
                 ctx = tgks.tgks_create(p)
                 W = torch.from_numpy(np.ascontiguousarray(Wi)).cuda()
                 td.zero_()
