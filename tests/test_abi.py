@@ -76,3 +76,58 @@ def test_reconstruction_variables_option(lib):
         char = tgks.tgks_flop_counts(tgks.tgks_params_default(nd, [8] * nd, [0.1] * nd, recon=1))
         assert char["normal"] == 0.0 and cons["normal"] > 0.0
         assert char["face"] > cons["face"] + 2 * (nd + 2) * cons["normal"]
+
+
+def _c_layout(src, struct, fields, tmp_path):
+    """sizeof and offsetof of a C struct, from a program compiled with gcc."""
+    import subprocess
+    prog = tmp_path / "layout.c"
+    body = "".join(f'  printf("%zu\\n", offsetof({struct}, {f}));\n' for f in fields)
+    prog.write_text(f'#include <stdio.h>\n#include <stddef.h>\n{src}\nint main(void) {{\n'
+                    f'  printf("%zu\\n", sizeof({struct}));\n{body}  return 0;\n}}\n')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-o", str(exe), str(prog)], check=True, capture_output=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    return int(out[0]), [int(x) for x in out[1:]]
+
+
+def test_params_layout_matches_header(tmp_path):
+    """The ctypes mirror of tgks_params has the C struct's size and field
+    offsets (a mismatch would let tgks_params_default write past it)."""
+    from paper_2309_10534_amd import tgks
+    fields = [f for f, _ in tgks.TgksParams._fields_]
+    size, offs = _c_layout(f'#include "{HEADER}"', "tgks_params", fields, tmp_path)
+    assert size == ctypes.sizeof(tgks.TgksParams)
+    assert offs == [getattr(tgks.TgksParams, f).offset for f in fields]
+
+
+def test_oracle_params_layout(tmp_path):
+    """Same for the oracle's parameter structure and its ctypes mirror."""
+    from oracle import oracle as orc
+    src = open(os.path.join(ROOT, "oracle", "gks_oracle.cpp")).read()
+    start = src.index("typedef struct {", src.index('extern "C" {'))
+    decl = src[start:src.index("} orc_params;", start) + len("} orc_params;")]
+    decl = re.sub(r"//[^\n]*", "", decl)
+    fields = [f for f, _ in orc.OrcParams._fields_]
+    size, offs = _c_layout(decl, "orc_params", fields, tmp_path)
+    assert size == ctypes.sizeof(orc.OrcParams)
+    assert offs == [getattr(orc.OrcParams, f).offset for f in fields]
+
+
+def test_prescribed_and_fallback_checks_without_device(lib):
+    """Prescribed sides and the fallback: 3-D grids, far kinds other than
+    transmissive / reflective / state B, a NaN line and unknown fallback
+    values are rejected before any device work."""
+    from paper_2309_10534_amd import tgks
+    h = ctypes.c_void_p()
+    bad = [tgks.tgks_params_default(3, [8] * 3, [0.1] * 3, bc=[("prescribed", "transmissive")] * 3),
+           tgks.tgks_params_default(3, [8] * 3, [0.1] * 3, fallback=1),
+           tgks.tgks_params_default(2, [8, 8], [0.1, 0.1], fallback=2)]
+    p = tgks.tgks_params_default(2, [8, 8], [0.1, 0.1], bc=[("prescribed", "transmissive")] * 2)
+    p.bc_far[0][0] = tgks.BC_NOSLIP
+    bad.append(p)
+    p = tgks.tgks_params_default(2, [8, 8], [0.1, 0.1], bc=[("prescribed", "transmissive")] * 2)
+    p.bc_line[0][0][1] = float("nan")
+    bad.append(p)
+    for q in bad:
+        assert lib.tgks_create(ctypes.byref(q), None, ctypes.byref(h)) == -1
