@@ -37,8 +37,8 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector peak (256 CU x 2.4 GHz x 128 flop/
 # the three files below); the bench reports null traffic otherwise.
 TRAFFIC_SOURCES = ("paper_2309_10534_amd/csrc/tgks_device.hpp", "paper_2309_10534_amd/csrc/tgks_kernels.hpp",
                    "paper_2309_10534_amd/csrc/tgks_face2d.hip")
-TRAFFIC = {"sha": "75b974f933da5506", "tile": 2, "fetch_factor": 32768.0 / 16397.9, "write_factor": 1.0,
-           "face_xy": {"fetch_kib": 128495.8, "write_kib": 116857.9}}
+TRAFFIC = {"sha": "7ce67e175a16f25f", "tile": 2, "fetch_factor": 32768.0 / 16397.6, "write_factor": 1.0,
+           "face_xy": {"fetch_kib": 128474.9, "write_kib": 116846.4}}
 
 
 def measured_traffic(kernel, tile):
@@ -326,10 +326,11 @@ def viscous_shock_tube(nx=500, re=200.0, t_end=1.0, cfl=0.2, chunk=200):
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         fails = tgks.tgks_status(ctx)
+        nfb = tgks.tgks_fallback_count(ctx)
         tgks.tgks_destroy(ctx)
         finite = bool(torch.isfinite(W).all().item())
         out[name] = {"t_reached": t_done, "failures": fails, "finite": finite,
-                     "stopped": stop_reason(t_done, t_end, fails),
+                     "stopped": stop_reason(t_done, t_end, fails), "fallbacks": nfb,
                      "steps": steps, "seconds": round(el, 3),
                      "value": round(nx * ny * steps / el / 1e6, 3), "unit": "Mcell-updates/s"}
         if finite and fails == 0:
@@ -385,9 +386,11 @@ def double_mach(nx=960, ny=240, t_end=0.2, cfl=0.5, chunk=100):
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         fails = tgks.tgks_status(ctx)
+        nfb = tgks.tgks_fallback_count(ctx)
         tgks.tgks_destroy(ctx)
         out[name] = {"t_reached": t_done, "failures": fails, "finite": bool(torch.isfinite(W).all().item()),
-                     "stopped": stop_reason(t_done, t_end, fails), "steps": steps, "seconds": round(el, 3),
+                     "stopped": stop_reason(t_done, t_end, fails), "fallbacks": nfb, "steps": steps,
+                     "seconds": round(el, 3),
                      "value": round(nx * ny * steps / el / 1e6, 3) if steps else None, "unit": "Mcell-updates/s"}
     return out
 

@@ -184,6 +184,11 @@ int tgks_tune(tgks_ctx* ctx, const double* W, int32_t steps, int32_t* chosen, fl
 int tgks_status(tgks_ctx* ctx, int64_t* failures);
 int tgks_reset_status(tgks_ctx* ctx);
 
+/* Number of Gauss-point side states the first-order fallback replaced
+ * (fallback = 1; both stages of every step) since the context was created
+ * or tgks_reset_status last ran; synchronises the stream. */
+int tgks_fallback_count(tgks_ctx* ctx, int64_t* count);
+
 /* Per-kernel timing with HIP events recorded on the context's stream around
  * every launch while enabled.  kind: 0 face fluxes along x, 1 along y, 2
  * along z, 3 normal reconstruction (3-D), 4 stage-1 update, 5 stage-2

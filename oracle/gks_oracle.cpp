@@ -911,7 +911,7 @@ static void char_normal_face(const orc_params& P, const Grid& g, const T* W, int
 template <class T>
 static long face_fluxes(const orc_params& P, const Grid& g, const T* W, int d, double dt,
                         std::vector<T>& Fdt, std::vector<T>& Fh, uint8_t* nflags,
-                        uint8_t* tflags) {
+                        uint8_t* tflags, long* nfallback = nullptr) {
   const int D = g.D, nc = g.nc;
   long nf[3] = {g.n[0], g.n[1], g.n[2]};
   nf[d] += 1;
@@ -931,9 +931,9 @@ static long face_fluxes(const orc_params& P, const Grid& g, const T* W, int d, d
   const double idn = 1.0 / dn;  // normal slopes per unit length
   const double dt1 = t1 >= 0 ? g.dx[t1] : 1.0, dt2 = t2 >= 0 ? g.dx[t2] : 1.0;
   const double deltas[2] = {dt, 0.5 * dt};
-  long nbad = 0;
+  long nbad = 0, nfb = 0;
 
-#pragma omp parallel for schedule(dynamic, 16) reduction(+ : nbad)
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : nbad, nfb)
   for (long fidx = 0; fidx < nface; ++fidx) {
     long fpos[3];
     fpos[0] = fidx % nf[0];
@@ -1111,6 +1111,7 @@ static long face_fluxes(const orc_params& P, const Grid& g, const T* W, int d, d
           for (int side = 0; side < 2; ++side) {
             T* w = Wg[m1][m2][side];
             if (physical_state(D, P.gamma, w)) continue;
+            ++nfb;
             for (int a = 0; a < nc; ++a) {
               w[a] = C[side][a];
               for (int q = 0; q < 3; ++q) Dg[m1][m2][side][q][a] = T(0.0);
@@ -1135,6 +1136,7 @@ static long face_fluxes(const orc_params& P, const Grid& g, const T* W, int d, d
       Fh[(size_t)perm[a] * nface + fidx] = acc[1][a];
     }
   }
+  if (nfallback) *nfallback += nfb;
   return nbad;
 }
 
@@ -1150,7 +1152,7 @@ static inline long face_index(const Grid& g, int d, long i, long j, long k, int 
 // One S2O4 step (Sec. 2.2).
 template <class T>
 static long s2o4_step(const orc_params& P, const T* Wn, T* Wout, double dt, uint8_t* flags,
-                      T* Wstar_out, double t = 0.0) {
+                      T* Wstar_out, double t = 0.0, long* nfallback = nullptr) {
   const Grid g(P, t);
   const Grid gs(P, t + 0.5 * dt);  // stage 2: W* is the state at the half step
   const int D = g.D, nc = g.nc;
@@ -1168,7 +1170,7 @@ static long s2o4_step(const orc_params& P, const T* Wn, T* Wout, double dt, uint
       off += 4L * nc * nf[0] * nf[1] * nf[2];
     }
   }
-  for (int d = 0; d < D; ++d) nbad += face_fluxes(P, g, Wn, d, dt, Fdt[d], Fh[d], flags, tfl[d]);
+  for (int d = 0; d < D; ++d) nbad += face_fluxes(P, g, Wn, d, dt, Fdt[d], Fh[d], flags, tfl[d], nfallback);
   // F^n = (4 F(dt/2) - F(dt)) / dt,  d_t F^n = 4 (F(dt) - 2 F(dt/2)) / dt^2
   std::vector<T> Fn[3], dFn[3];
   for (int d = 0; d < D; ++d) {
@@ -1201,7 +1203,8 @@ static long s2o4_step(const orc_params& P, const T* Wn, T* Wout, double dt, uint
       }
   if (Wstar_out)
     for (size_t i = 0; i < Ws.size(); ++i) Wstar_out[i] = Ws[i];
-  for (int d = 0; d < D; ++d) nbad += face_fluxes(P, gs, Ws.data(), d, dt, Gdt[d], Gh[d], (uint8_t*)nullptr, (uint8_t*)nullptr);
+  for (int d = 0; d < D; ++d)
+    nbad += face_fluxes(P, gs, Ws.data(), d, dt, Gdt[d], Gh[d], (uint8_t*)nullptr, (uint8_t*)nullptr, nfallback);
   // combined flux F^n + dt/6 (d_tF^n + 2 d_tF*), then the final update
   std::vector<T> Fc[3];
   for (int d = 0; d < D; ++d) {
@@ -1447,11 +1450,16 @@ long orc_flag_bytes(const orc_params* P) {
 }
 
 // One S2O4 step; returns the number of failing Gauss-point evaluations, or -1.
-// t: time of W (prescribed boundary states).
+// t: time of W (prescribed boundary states); fallbacks (or null) receives the
+// number of Gauss-point side states the first-order fallback replaced, both
+// stages.
 long orc_step(const orc_params* P, const double* W, double* Wout, double dt, uint8_t* flags,
-              double* Wstar, double t) {
+              double* Wstar, double t, long* fallbacks) {
   if (check_params(P) || !(dt > 0)) return -1;
-  return s2o4_step<double>(*P, W, Wout, dt, flags, Wstar, t);
+  long nfb = 0;
+  const long bad = s2o4_step<double>(*P, W, Wout, dt, flags, Wstar, t, &nfb);
+  if (fallbacks) *fallbacks = nfb;
+  return bad;
 }
 
 // Same step carrying one tangent direction (forward mode).

@@ -62,7 +62,7 @@ def lib():
         L.orc_char_recon.argtypes = [P, dp, C.c_double, dp, C.c_void_p]
         L.orc_flag_bytes.argtypes = [P]
         L.orc_flag_bytes.restype = C.c_long
-        L.orc_step.argtypes = [P, dp, dp, C.c_double, C.c_void_p, C.c_void_p, C.c_double]
+        L.orc_step.argtypes = [P, dp, dp, C.c_double, C.c_void_p, C.c_void_p, C.c_double, C.POINTER(C.c_long)]
         L.orc_step.restype = C.c_long
         L.orc_step_dual.argtypes = [P, dp, dp, dp, dp, C.c_double]
         L.orc_step_dual.restype = C.c_long
@@ -234,17 +234,22 @@ def flag_bytes(params):
     return lib().orc_flag_bytes(C.byref(params))
 
 
-def step(params, W, dt, want_flags=False, want_wstar=False, t=0.0):
-    """One step of W, the state at time t (prescribed boundary states)."""
+def step(params, W, dt, want_flags=False, want_wstar=False, t=0.0, fallbacks=None):
+    """One step of W, the state at time t (prescribed boundary states).
+    fallbacks: a one-element list that receives the number of Gauss-point
+    side states the first-order fallback replaced."""
     W = _arr(W)
     out = np.empty_like(W)
     flags = np.zeros(flag_bytes(params), dtype=np.uint8) if want_flags else None
     ws = np.empty_like(W) if want_wstar else None
+    nfb = C.c_long(0)
     bad = lib().orc_step(C.byref(params), W, out, float(dt),
                          flags.ctypes.data if flags is not None else None,
-                         ws.ctypes.data if ws is not None else None, float(t))
+                         ws.ctypes.data if ws is not None else None, float(t), C.byref(nfb))
     if bad < 0:
         raise ValueError("invalid parameters or dt")
+    if fallbacks is not None:
+        fallbacks[:] = [nfb.value]
     return out, flags, ws, bad
 
 

@@ -515,9 +515,9 @@ int tgks_create(const tgks_params* p, void* stream, tgks_ctx** out) {
   if (ok)
     ok = hipMalloc(&c->partial, (size_t)c->nblk * sizeof(double)) == hipSuccess &&
          hipMalloc(&c->clock, 4 * sizeof(double)) == hipSuccess &&
-         hipMalloc(&c->fail, sizeof(unsigned long long)) == hipSuccess;
+         hipMalloc(&c->fail, 2 * sizeof(unsigned long long)) == hipSuccess;
   if (ok) {
-    hipLaunchKernelGGL(zero_counters_kernel, dim3(1), dim3(256), 0, c->stream, c->fail, 1);
+    hipLaunchKernelGGL(zero_counters_kernel, dim3(1), dim3(256), 0, c->stream, c->fail, 2);
     ok = hipGetLastError() == hipSuccess;
   }
   if (ok) ok = hipStreamSynchronize(c->stream) == hipSuccess;
@@ -648,6 +648,15 @@ int tgks_run(tgks_ctx* c, double* W, int32_t n_steps, double cfl, double t_end, 
   return TGKS_OK;
 }
 
+int tgks_fallback_count(tgks_ctx* c, int64_t* count) {
+  if (!c || !count) return TGKS_EINVAL;
+  unsigned long long h = 0;
+  HIPCHK(hipMemcpyAsync(&h, c->fail + 1, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  *count = (int64_t)h;
+  return TGKS_OK;
+}
+
 int tgks_set_time(tgks_ctx* c, double t0) {
   if (!c || !std::isfinite(t0)) return TGKS_EINVAL;
   c->t0 = t0;
@@ -665,7 +674,7 @@ int tgks_status(tgks_ctx* c, int64_t* failures) {
 
 int tgks_reset_status(tgks_ctx* c) {
   if (!c) return TGKS_EINVAL;
-  hipLaunchKernelGGL(zero_counters_kernel, dim3(1), dim3(256), 0, c->stream, c->fail, 1);
+  hipLaunchKernelGGL(zero_counters_kernel, dim3(1), dim3(256), 0, c->stream, c->fail, 2);
   HIPCHK(hipGetLastError());
   return TGKS_OK;
 }

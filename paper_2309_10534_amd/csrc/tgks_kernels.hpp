@@ -42,7 +42,7 @@ struct StageArgs {
   double* FA;
   double* FB;
   const double* dt;
-  unsigned long long* fail;
+  unsigned long long* fail;  // [0] failing Gauss points; [1] fallbacks (contexts with the fallback)
   uint8_t* nflags;  // normal flags [D][nc][cells] or null
   uint8_t* tflags;  // tangential flags of this direction or null
   const double* R;  // 3-D: normal reconstruction of this direction
@@ -138,16 +138,17 @@ __device__ __forceinline__ bool physical_state(const double* w, double gamma) {
 }
 
 // first-order fallback: a non-physical side state becomes the side's cell
-// average C with zero slopes
+// average C with zero slopes; returns 1 if it did
 template <int NC, int ND>
-__device__ __forceinline__ void fallback_side(double* w, double (*dw)[NC], const double* C, double gamma) {
-  if (physical_state<NC>(w, gamma)) return;
+__device__ __forceinline__ int fallback_side(double* w, double (*dw)[NC], const double* C, double gamma) {
+  if (physical_state<NC>(w, gamma)) return 0;
 #pragma unroll
   for (int q = 0; q < NC; ++q) {
     w[q] = C[q];
 #pragma unroll
     for (int d = 0; d < ND; ++d) dw[d][q] = 0.0;
   }
+  return 1;
 }
 
 template <int NC>
@@ -227,8 +228,8 @@ __device__ __forceinline__ void face1d_body(const StageArgs& a, int f) {
       Cl[c] = cell_value(a.g, a.pb, a.W, c, f - 1, 0, tb);
       Cr[c] = cell_value(a.g, a.pb, a.W, c, f, 0, tb);
     }
-    fallback_side<3, 1>(Wl, dWl, Cl, a.gamma);
-    fallback_side<3, 1>(Wr, dWr, Cr, a.gamma);
+    const int nfb = fallback_side<3, 1>(Wl, dWl, Cl, a.gamma) + fallback_side<3, 1>(Wr, dWr, Cr, a.gamma);
+    if (nfb) atomicAdd(a.fail + 1, (unsigned long long)nfb);  // second counter: fallbacks
   }
   double Fdt[3], Fh[3], A[3] = {0, 0, 0}, B[3] = {0, 0, 0};
   const bool ok = gp_flux<1, NS>(Wl, Wr, dWl, dWr, a.fc, dt, Fdt, Fh);
@@ -532,8 +533,8 @@ __device__ __forceinline__ void face2d_tile(const StageArgs& a, int bx, int by, 
       Cl[q] = sW[perm[q]][ft + 2][fn + 2];
       Cr[q] = sW[perm[q]][ft + 2][fn + 3];
     }
-    fallback_side<NC, 2>(Wg[0], Dg[0], Cl, a.gamma);
-    fallback_side<NC, 2>(Wg[1], Dg[1], Cr, a.gamma);
+    const int nfb = fallback_side<NC, 2>(Wg[0], Dg[0], Cl, a.gamma) + fallback_side<NC, 2>(Wg[1], Dg[1], Cr, a.gamma);
+    if (nfb) atomicAdd(a.fail + 1, (unsigned long long)nfb);  // second counter: fallbacks
   }
   if (live) {
     double Fdt[NC], Fh[NC];

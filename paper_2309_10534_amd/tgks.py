@@ -66,6 +66,7 @@ def lib():
     L.tgks_step.argtypes = [vp, vp, vp, vp, vp, vp]
     L.tgks_run.argtypes = [vp, vp, C.c_int32, C.c_double, C.c_double, C.c_double, vp, C.c_int32]
     L.tgks_set_time.argtypes = [vp, C.c_double]
+    L.tgks_fallback_count.argtypes = [vp, C.POINTER(C.c_int64)]
     L.tgks_status.argtypes = [vp, C.POINTER(C.c_int64)]
     L.tgks_reset_status.argtypes = [vp]
     L.tgks_timing.argtypes = [vp, C.c_int32]
@@ -100,7 +101,8 @@ def lib():
         getattr(L, f).restype = C.c_int
     for f in ("tgks_params_default", "tgks_create", "tgks_destroy", "tgks_set_stream", "tgks_cfl_dt", "tgks_step",
               "tgks_run", "tgks_status", "tgks_reset_status", "tgks_timing", "tgks_kernel_time",
-              "tgks_flop_counts", "tgks_gp_flux_host", "tgks_set_tile", "tgks_tune", "tgks_set_time"):
+              "tgks_flop_counts", "tgks_gp_flux_host", "tgks_set_tile", "tgks_tune", "tgks_set_time",
+              "tgks_fallback_count"):
         getattr(L, f).restype = C.c_int
     _lib = L
     return L
@@ -213,6 +215,14 @@ def tgks_set_time(ctx, t0):
     """Time of the state that the next tgks_step / tgks_run advances (the
     prescribed boundary states depend on it)."""
     _check(lib().tgks_set_time(ctx, float(t0)), "tgks_set_time")
+
+
+def tgks_fallback_count(ctx):
+    """Gauss-point side states replaced by the first-order fallback since
+    the last reset (synchronises)."""
+    v = C.c_int64()
+    _check(lib().tgks_fallback_count(ctx, C.byref(v)), "tgks_fallback_count")
+    return v.value
 
 
 def tgks_status(ctx):

@@ -55,6 +55,7 @@ class GpuProblem:
         self.t.tgks_reset_status(self.ctx)
         self.t.tgks_step(self.ctx, Win, Wout, dtd, fl, Ws)
         bad = self.t.tgks_status(self.ctx)
+        self.fallbacks = self.t.tgks_fallback_count(self.ctx)
         torch.cuda.synchronize()
         return (Wout.cpu().numpy().reshape(W.shape), Ws.cpu().numpy().reshape(W.shape),
                 fl.cpu().numpy() if flags else None, bad)

@@ -85,7 +85,10 @@ int main() {
         std::vector<uint8_t> flags(orc_flag_bytes(&p));
         double dt = 0.0;
         if (orc_cfl_dt(&p, W.data(), 0.5, &dt) != 0) return 2;
-        if (orc_step(&p, W.data(), Wo.data(), dt, flags.data(), Ws.data(), 0.1) < 0) return 3;
+        long nfb = 0;
+        p.fallback = D <= 2 && tau == 1 ? 1 : 0;
+        if (orc_step(&p, W.data(), Wo.data(), dt, flags.data(), Ws.data(), 0.1, &nfb) < 0) return 3;
+        p.fallback = 0;
         if (orc_step_dual(&p, W.data(), dW.data(), Wo2.data(), dWo.data(), dt) < 0) return 4;
         std::vector<double> Wr(W);
         double t = 0.0;

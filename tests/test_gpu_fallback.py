@@ -3,8 +3,9 @@ Gauss-point states against the oracle.  Each step starts from a state on
 the oracle's own trajectory, so that both sides decide on the same input:
 the double Mach reflection (Sec. 5.7) at steps 0, 10 and 25 (its first step
 has non-physical states at the shock foot) and a periodic blast, 1e-10
-L1-relative with selection flags bit for bit; the device run of the blast
-keeps mass, momentum and energy."""
+L1-relative with selection flags bit for bit and the same number of
+replaced Gauss-point states; the device run of the blast keeps mass,
+momentum and energy."""
 import numpy as np
 import pytest
 
@@ -25,6 +26,7 @@ def torch_dev():
 def compare_on_trajectory(orc, pr, W0, marks, t_of=None):
     P = orc_params(orc, pr)
     W, t, k = W0.copy(), 0.0, 0
+    counts = []
     gp = GpuProblem(pr)
     try:
         while k <= max(marks):
@@ -32,8 +34,11 @@ def compare_on_trajectory(orc, pr, W0, marks, t_of=None):
             if k in marks:
                 print(f"[fallback] shape={pr['shape']} recon={pr.get('recon', 0)} step={k}", flush=True)
                 Wg, Wsg, fg, badg = gp.step(W, dt, flags=True, t0=t)
-                Wo, fo, Wso, bado = orc.step(P, W, dt, want_flags=True, want_wstar=True, t=t)
+                nfb = [0]
+                Wo, fo, Wso, bado = orc.step(P, W, dt, want_flags=True, want_wstar=True, t=t, fallbacks=nfb)
                 assert badg == bado == 0
+                assert gp.fallbacks == nfb[0], (gp.fallbacks, nfb[0])  # the same decisions
+                counts.append(nfb[0])
                 mism = np.flatnonzero(fg != fo)
                 assert mism.size == 0, f"{mism.size} flag mismatches, first at {mism[:10]}"
                 assert_close(Wsg, Wso, what=f"W* step {k}")
@@ -45,6 +50,7 @@ def compare_on_trajectory(orc, pr, W0, marks, t_of=None):
             k += 1
     finally:
         gp.close()
+    return counts
 
 
 @pytest.mark.parametrize("recon", [0, 1])
@@ -52,7 +58,8 @@ def test_double_mach_steps(orc, torch_dev, recon):
     W0, (dx, dy), spec = I.double_mach(96, 24)
     pr = problem([96, 24], [dx, dy], bc=spec["bc"], states=spec["states"], lines=spec["lines"], far=spec["far"],
                  recon=recon, fallback=1)
-    compare_on_trajectory(orc, pr, W0, (0, 10, 25))
+    counts = compare_on_trajectory(orc, pr, W0, (0, 10, 25))
+    assert counts[0] > 0  # the first step needs the fallback
 
 
 def blast(n):

@@ -18,6 +18,10 @@ def test_inactive_is_identity(orc):
     a = orc.run(orc.make_params([200], [dx]), W0, 1000, cfl=0.5, t_end=0.2)
     b = orc.run(orc.make_params([200], [dx], fallback=1), W0, 1000, cfl=0.5, t_end=0.2)
     assert a[3] == 0 and np.array_equal(a[0], b[0])
+    nfb = [-1]
+    P = orc.make_params([200], [dx], fallback=1)
+    orc.step(P, W0, orc.cfl_dt(P, W0, 0.5), fallbacks=nfb)
+    assert nfb == [0]
     W2, dx2, _ = I.quadrant_riemann(48, seed=3)
     for recon in (0, 1):
         P0 = orc.make_params([48, 48], [dx2, dx2], recon=recon)
@@ -39,8 +43,16 @@ def test_conservative_where_it_acts(orc):
     W0, dx = blast()
     with pytest.raises(ValueError):  # a non-physical state stops the run without it
         orc.run(orc.make_params([200], [dx], bc="periodic"), W0, 300, cfl=0.5)
-    W, t, s, bad = orc.run(orc.make_params([200], [dx], bc="periodic", fallback=1), W0, 300, cfl=0.5)
+    P = orc.make_params([200], [dx], bc="periodic", fallback=1)
+    W, t, s, bad = orc.run(P, W0, 300, cfl=0.5)
     assert s == 300 and bad == 0 and np.all(np.isfinite(W))
+    # it does act: the same steps one by one, counting replaced states
+    Wk, total = W0.copy(), 0
+    for _ in range(300):
+        nfb = [0]
+        Wk = orc.step(P, Wk, orc.cfl_dt(P, Wk, 0.5), fallbacks=nfb)[0]
+        total += nfb[0]
+    assert np.array_equal(Wk, W) and total > 0
     for c in range(3):
         scale = np.abs(W0[c]).sum() + np.abs(W0[2]).sum() * (c == 1)
         assert abs(W[c].sum() - W0[c].sum()) <= 1e-14 * scale, c
