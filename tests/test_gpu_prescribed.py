@@ -171,3 +171,48 @@ def test_rejections(torch_dev):
             tgks.tgks_step_adjoint(gp.ctx, Wd, dtd, g, torch.zeros_like(Wd))
     finally:
         gp.close()
+
+
+def test_corner_rule(orc, torch_dev):
+    """Corner ghost cells where the x and y sides prescribe different states
+    (x: A, y: B): the x side decides on both paths.  (Their influence is
+    small: the stencil selections avoid the inconsistent corner cells, and
+    giving the corners B instead moves the step by 4e-16.)"""
+    rng = np.random.default_rng(11)
+    nx, ny = 40, 23
+    W = I.conservative(1.0 + 0.3 * rng.random((ny, nx)), [0.3 * rng.standard_normal((ny, nx)),
+                       0.3 * rng.standard_normal((ny, nx))], 1.0 + 0.3 * rng.random((ny, nx)))
+    A = I.conservative(np.array(1.6), [np.array(0.4), np.array(-0.2)], np.array(1.8))
+    B = I.conservative(np.array(0.7), [np.array(-0.1), np.array(0.3)], np.array(0.6))
+    every, never = (math.inf, 0.0, 0.0), (-math.inf, 0.0, 0.0)
+    pr = problem([nx, ny], [1.0 / nx, 1.0 / ny], bc=[("prescribed", "prescribed"), ("prescribed", "prescribed")],
+                 states=(A.tolist(), B.tolist()),
+                 lines={(0, 0): every, (0, 1): every, (1, 0): never, (1, 1): never},
+                 far={(1, 0): "state_b", (1, 1): "state_b"})
+    dt = orc.cfl_dt(orc_params(orc, pr), W, 0.5)
+    Wg, Wsg, Wo, Wso, bad = compare_step(orc, pr, W, dt, 0.0)
+    assert bad == 0
+    assert_close(Wg, Wo, what="corner rule")
+
+
+def test_state_switch_inside_a_step(orc, torch_dev):
+    """1-D: the left side switches from B to A at t = 0.01 (s0 = -0.01,
+    s_t = 1); a step from just before, whose stage 2 (at t + dt/2) sees A
+    while stage 1 sees B, and steps on either side of it."""
+    n = 64
+    rng = np.random.default_rng(3)
+    W = I.conservative(1.0 + 0.2 * rng.random(n), [0.2 * rng.standard_normal(n)], 1.0 + 0.2 * rng.random(n))
+    A = I.conservative(np.array(1.5), [np.array(0.5)], np.array(1.4))
+    B = I.conservative(np.array(0.8), [np.array(-0.2)], np.array(0.7))
+    pr = problem([n], [1.0 / n], bc=[("prescribed", "transmissive")], states=(A.tolist(), B.tolist()),
+                 lines={(0, 0): (-0.01, 0.0, 1.0)})
+    dt = orc.cfl_dt(orc_params(orc, pr), W, 0.5)
+    results = []
+    for t0 in (0.01 - 0.75 * dt, 0.01 - 0.25 * dt, 0.01 + 0.25 * dt):
+        Wg, Wsg, Wo, Wso, bad = compare_step(orc, pr, W, dt, t0)
+        assert bad == 0
+        assert_close(Wsg, Wso, what=f"W* t0={t0}")
+        assert_close(Wg, Wo, what=f"t0={t0}")
+        results.append(Wo)
+    # B in both stages, B then A, A in both: three different steps
+    assert np.abs(results[0] - results[1]).max() > 1e-8 and np.abs(results[1] - results[2]).max() > 1e-8
