@@ -37,8 +37,8 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector peak (256 CU x 2.4 GHz x 128 flop/
 # the three files below); the bench reports null traffic otherwise.
 TRAFFIC_SOURCES = ("paper_2309_10534_amd/csrc/tgks_device.hpp", "paper_2309_10534_amd/csrc/tgks_kernels.hpp",
                    "paper_2309_10534_amd/csrc/tgks_face2d.hip")
-TRAFFIC = {"sha": "7ce67e175a16f25f", "tile": 2, "fetch_factor": 32768.0 / 16397.6, "write_factor": 1.0,
-           "face_xy": {"fetch_kib": 128474.9, "write_kib": 116846.4}}
+TRAFFIC = {"sha": "4586089973821d8d", "tile": 2, "fetch_factor": 32768.0 / 16397.6, "write_factor": 1.0,
+           "face_xy": {"fetch_kib": 128488.1, "write_kib": 116857.1}}
 
 
 def measured_traffic(kernel, tile):
@@ -118,7 +118,7 @@ def cpu_baseline(W0, dx, n, target_s):
                       f"of the same initial field, {el:.1f} s"}
 
 
-def batched(dim, seed, n_inst, steps, ranges=None, recon=0):
+def batched(dim, seed, n_inst, steps, ranges=None, recon=0, fallback=0):
     """Batched set of seeded uneven Riemann instances (1-D: N ~ U{64..1024};
     2-D: N x N, N ~ U{64..512}; rho log-uniform [0.1, 10], p log-uniform
     [0.01, 1000], velocities uniform [-2, 2]; transmissive, CFL 0.5): one
@@ -126,7 +126,8 @@ def batched(dim, seed, n_inst, steps, ranges=None, recon=0):
     single-grid runs (tgks_run per instance, no graph), outputs compared bit
     for bit.  Throughput counts the cell-updates actually performed: an
     instance that reaches a non-physical state stops there (the scheme has no
-    positivity limiter)."""
+    positivity limiter; `fallback` = 1 turns on the first-order fallback at
+    non-physical Gauss-point states)."""
     import numpy as np
     import torch
 
@@ -135,7 +136,8 @@ def batched(dim, seed, n_inst, steps, ranges=None, recon=0):
 
     inst, rej, _ = I.riemann_instances(n_inst, dim=dim, seed=seed, **(ranges or {}))
     shapes = [W.shape for W, _ in inst]
-    params = [tgks.tgks_params_default(dim, list(W.shape[1:])[::-1], [dx] * dim, recon=recon) for W, dx in inst]
+    params = [tgks.tgks_params_default(dim, list(W.shape[1:])[::-1], [dx] * dim, recon=recon, fallback=fallback)
+              for W, dx in inst]
     cells = np.array([W[0].size for W, _ in inst], dtype=np.int64)
     b = tgks.tgks_batch_create(params)
     W0 = torch.from_numpy(tgks.pack([W for W, _ in inst])).cuda()
@@ -177,7 +179,7 @@ def batched(dim, seed, n_inst, steps, ranges=None, recon=0):
     return {
         "workload": f"batched_{dim}d_riemann_{n_inst}_instances_seed{seed}_{steps}_steps"
                     + ("" if ranges is None else "_" + "_".join(f"{k}{v[0]}-{v[1]}" for k, v in ranges.items()))
-                    + ("_characteristic" if recon else ""),
+                    + ("_characteristic" if recon else "") + ("_fallback" if fallback else ""),
         "cells": int(cells.sum()), "cell_updates": updates,
         "instances_failure_free": int(sum(1 for f, k in zip(fails, taken) if f == 0 and k == steps)),
         "rejected_draws": rej,
@@ -658,7 +660,8 @@ def main():
         mild = dict(rho_range=(0.5, 2.0), p_range=(0.1, 1.5), vel_range=(-0.5, 0.5))
         out["batched"] = [batched(1, 1, args.batch_instances, args.batch_steps),
                           batched(2, 2, args.batch_instances, args.batch_steps),
-                          batched(2, 2, args.batch_instances, args.batch_steps, ranges=mild)]
+                          batched(2, 2, args.batch_instances, args.batch_steps, ranges=mild),
+                          batched(2, 2, args.batch_instances, args.batch_steps, fallback=1)]
     if not args.no_adjoint:
         out["adjoint"] = adjoint()
     if not args.no_3d:

@@ -267,10 +267,11 @@ typedef struct tgks_batch tgks_batch;
 
 /* per_instance: host array of n_inst parameter sets, all with the same ndim
  * (1 or 2), the same reconstruction variables, and all Euler or all
- * Navier-Stokes with a Prandtl correction (characteristic variables: one
- * 2-D tile shape, 2).  Allocates the batch's work buffers (about three packed states plus face
- * fluxes).  TGKS_EINVAL for invalid or mixed parameters, prescribed sides
- * and the first-order fallback. */
+ * Navier-Stokes with a Prandtl correction (characteristic variables or the
+ * first-order fallback: one 2-D tile shape, 2).  Allocates the batch's work buffers (about three packed states plus face
+ * fluxes).  TGKS_EINVAL for invalid or mixed parameters (the first-order
+ * fallback must be the same for every instance; batches do not count its
+ * replacements) and for prescribed sides. */
 int tgks_batch_create(const tgks_params* per_instance, int32_t n_inst, void* hip_stream, tgks_batch** out);
 int tgks_batch_destroy(tgks_batch* b);
 int tgks_batch_set_stream(tgks_batch* b, void* hip_stream);

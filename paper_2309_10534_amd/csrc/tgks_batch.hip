@@ -14,6 +14,7 @@ struct tgks_batch {
   int D = 0, nc = 0, ninst = 0;
   bool ns = false;
   bool chr = false;  // characteristic reconstruction variables
+  bool fb = false;   // first-order fallback
   int tile2 = 0;
   hipStream_t stream = nullptr;
   std::vector<BatchInst> host;   // per instance (offsets in doubles)
@@ -93,12 +94,13 @@ static BatchArgs batch_args(tgks_batch* b, const double* W, double* o1, double* 
   a.clock = b->clock;
   a.partial = b->partial;
   a.fail = b->fail;
+  a.fallback = b->fb ? 1 : 0;
   return a;
 }
 
 #define BLAUNCH(kern, nblk, threads, args) hipLaunchKernelGGL(kern, dim3((unsigned)(nblk)), dim3(threads), 0, b->stream, args)
 
-template <int TILE, bool CHAR = false>
+template <int TILE, bool CHAR = false, bool EX = false>
 static void batch_face2d(tgks_batch* b, const double* W, int ax, int stage) {
   constexpr int NT = 2 * tile2_tn(TILE) * tile2_tt(TILE);
   const int nw = b->nwface[TILE][ax];
@@ -106,11 +108,11 @@ static void batch_face2d(tgks_batch* b, const double* W, int ax, int stage) {
   BatchArgs a = batch_args(b, W, nullptr, nullptr, b->wface[TILE][ax]);
 #define BF2(AXV)                                                                                  \
   if (stage == 1) {                                                                               \
-    if (b->ns) BLAUNCH((batch_face2d_kernel<AXV, 1, true, TILE, CHAR>), nw, NT, a);               \
-    else BLAUNCH((batch_face2d_kernel<AXV, 1, false, TILE, CHAR>), nw, NT, a);                    \
+    if (b->ns) BLAUNCH((batch_face2d_kernel<AXV, 1, true, TILE, CHAR, EX>), nw, NT, a);               \
+    else BLAUNCH((batch_face2d_kernel<AXV, 1, false, TILE, CHAR, EX>), nw, NT, a);                    \
   } else {                                                                                        \
-    if (b->ns) BLAUNCH((batch_face2d_kernel<AXV, 2, true, TILE, CHAR>), nw, NT, a);               \
-    else BLAUNCH((batch_face2d_kernel<AXV, 2, false, TILE, CHAR>), nw, NT, a);                    \
+    if (b->ns) BLAUNCH((batch_face2d_kernel<AXV, 2, true, TILE, CHAR, EX>), nw, NT, a);               \
+    else BLAUNCH((batch_face2d_kernel<AXV, 2, false, TILE, CHAR, EX>), nw, NT, a);                    \
   }
   if (ax == 0) {
     BF2(0)
@@ -123,24 +125,30 @@ static void batch_face2d(tgks_batch* b, const double* W, int ax, int stage) {
 static int batch_faces(tgks_batch* b, const double* W, int stage) {
   if (b->D == 1) {
     BatchArgs a = batch_args(b, W, nullptr, nullptr, b->wface1);
-#define BF1(CH)                                                                     \
-  if (stage == 1) {                                                                 \
-    if (b->ns) BLAUNCH((batch_face1d_kernel<1, true, CH>), b->nwface1, 256, a);     \
-    else BLAUNCH((batch_face1d_kernel<1, false, CH>), b->nwface1, 256, a);          \
-  } else {                                                                          \
-    if (b->ns) BLAUNCH((batch_face1d_kernel<2, true, CH>), b->nwface1, 256, a);     \
-    else BLAUNCH((batch_face1d_kernel<2, false, CH>), b->nwface1, 256, a);          \
+#define BF1(CH, EX)                                                                     \
+  if (stage == 1) {                                                                     \
+    if (b->ns) BLAUNCH((batch_face1d_kernel<1, true, CH, EX>), b->nwface1, 256, a);     \
+    else BLAUNCH((batch_face1d_kernel<1, false, CH, EX>), b->nwface1, 256, a);          \
+  } else {                                                                              \
+    if (b->ns) BLAUNCH((batch_face1d_kernel<2, true, CH, EX>), b->nwface1, 256, a);     \
+    else BLAUNCH((batch_face1d_kernel<2, false, CH, EX>), b->nwface1, 256, a);          \
   }
-    if (b->chr) {
-      BF1(true)
+    if (b->chr && b->fb) {
+      BF1(true, true)
+    } else if (b->chr) {
+      BF1(true, false)
+    } else if (b->fb) {
+      BF1(false, true)
     } else {
-      BF1(false)
+      BF1(false, false)
     }
 #undef BF1
   } else {
     for (int ax = 0; ax < 2; ++ax) {
-      if (b->chr) {  // one tile shape on the characteristic path
-        batch_face2d<CHAR_TILE2, true>(b, W, ax, stage);
+      if (b->chr || b->fb) {  // one tile shape on the characteristic / fallback path
+        if (b->chr && b->fb) batch_face2d<CHAR_TILE2, true, true>(b, W, ax, stage);
+        else if (b->chr) batch_face2d<CHAR_TILE2, true>(b, W, ax, stage);
+        else batch_face2d<CHAR_TILE2, false, true>(b, W, ax, stage);
         continue;
       }
       switch (b->tile2) {
@@ -226,7 +234,7 @@ int tgks_batch_create(const tgks_params* p, int32_t n_inst, void* stream, tgks_b
   const bool ns = p[0].mu > 0.0 && p[0].prandtl != 1.0;
   for (int i = 0; i < n_inst; ++i) {
     if (check_params(&p[i]) || p[i].ndim != D || p[i].recon != p[0].recon) return TGKS_EINVAL;
-    if (has_prescribed(&p[i]) || p[i].fallback) return TGKS_EINVAL;
+    if (has_prescribed(&p[i]) || p[i].fallback != p[0].fallback) return TGKS_EINVAL;
     if ((p[i].mu > 0.0 && p[i].prandtl != 1.0) != ns) return TGKS_EINVAL;
   }
   tgks_batch* b = new (std::nothrow) tgks_batch();
@@ -236,6 +244,7 @@ int tgks_batch_create(const tgks_params* p, int32_t n_inst, void* stream, tgks_b
   b->ninst = n_inst;
   b->ns = ns;
   b->chr = p[0].recon == TGKS_RECON_CHARACTERISTIC;
+  b->fb = p[0].fallback != 0;
   b->stream = (hipStream_t)stream;
   std::vector<int2> wcell, wface1, wface[NTILE2][2];
   long long woff = 0, foff[2] = {0, 0};
@@ -359,7 +368,7 @@ int tgks_batch_offsets(const tgks_batch* b, int64_t* offsets) {
 
 int tgks_batch_set_tile(tgks_batch* b, int32_t tile) {
   if (!b || tile < -1 || tile >= NTILE2) return TGKS_EINVAL;
-  const int t = b->chr ? CHAR_TILE2 : (tile < 0 ? 0 : tile);  // one shape with characteristic variables
+  const int t = (b->chr || b->fb) ? CHAR_TILE2 : (tile < 0 ? 0 : tile);  // one shape: characteristic / fallback
   if (t == b->tile2) return TGKS_OK;
   drop_graph(b);
   // tiles along the normal axis of each direction for this shape
@@ -438,11 +447,11 @@ int tgks_batch_tune(tgks_batch* b, const double* W, int32_t steps, int32_t* chos
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   const int old = b->tile2;
-  int best = b->chr ? CHAR_TILE2 : 0;
+  int best = (b->chr || b->fb) ? CHAR_TILE2 : 0;
   float best_ms = 0.f;
   bool first = true;
   for (int k = 0; k < nvar && !r; ++k) {
-    if (b->chr && k != CHAR_TILE2) {  // one tile shape on the characteristic path
+    if ((b->chr || b->fb) && k != CHAR_TILE2) {  // one tile shape on the characteristic / fallback path
       if (ms_per_variant) ms_per_variant[k] = 0.f;
       continue;
     }

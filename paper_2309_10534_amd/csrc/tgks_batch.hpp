@@ -35,6 +35,9 @@ struct BatchArgs {
   double* clock;     // [instance][t, dt]
   double* partial;   // per cell block
   unsigned long long* fail;  // per instance
+  // first-order fallback, the same for every instance; a run-time value so
+  // that the batched face code compiles as the single-grid code does
+  int fallback;
 };
 
 __device__ __forceinline__ StageArgs batch_stage(const BatchArgs& b, const BatchInst& I, int inst, int ax) {
@@ -53,28 +56,29 @@ __device__ __forceinline__ StageArgs batch_stage(const BatchArgs& b, const Batch
   a.R = nullptr;
   a.Rout = nullptr;
   a.gamma = I.gamma;
-  a.pb.on = 0;  // batches have neither prescribed sides nor the fallback
-  a.fallback = 0;  // (and run the face bodies without them, EX = false)
+  a.pb.on = 0;  // batches have no prescribed sides
+  a.fallback = b.fallback;
+  a.fbc = nullptr;  // fallbacks are not counted in batches
   a.t0 = 0.0;
   a.tclk = nullptr;
   return a;
 }
 
-template <int STAGE, bool NS, bool CHAR = false>
+template <int STAGE, bool NS, bool CHAR = false, bool EX = false>
 __global__ __launch_bounds__(256) void batch_face1d_kernel(BatchArgs b) {
   const int2 w = b.work[blockIdx.x];
   const StageArgs a = batch_stage(b, b.inst[w.x], w.x, 0);
-  face1d_body<STAGE, NS, false, CHAR>(a, w.y * 256 + (int)threadIdx.x);
+  face1d_body<STAGE, NS, false, CHAR, EX>(a, w.y * 256 + (int)threadIdx.x);
 }
 
-template <int AX, int STAGE, bool NS, int TILE, bool CHAR = false>
+template <int AX, int STAGE, bool NS, int TILE, bool CHAR = false, bool EX = false>
 __global__ __launch_bounds__(2 * tile2_tn(TILE) * tile2_tt(TILE), 2) void batch_face2d_kernel(BatchArgs b) {
   const int2 w = b.work[blockIdx.x];
   const BatchInst& I = b.inst[w.x];
   const StageArgs a = batch_stage(b, I, w.x, AX);
   const int nt = I.ntile[AX];
   __shared__ double lds[CHAR ? tile2_lds_char(TILE) : tile2_lds(TILE)];
-  face2d_tile<AX, STAGE, NS, false, TILE, CHAR>(a, w.y % nt, w.y / nt, lds);
+  face2d_tile<AX, STAGE, NS, false, TILE, CHAR, EX>(a, w.y % nt, w.y / nt, lds);
 }
 
 template <int D, int STAGE, bool CFL>

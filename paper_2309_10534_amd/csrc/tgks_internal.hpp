@@ -185,6 +185,7 @@ inline StageArgs stage_args(tgks_ctx* c, const double* W, int ax, const double* 
   a.t0 = c->t0;
   a.tclk = c->tclk;
   a.fallback = c->p.fallback;
+  a.fbc = c->fail + 1;  // the context's second counter
   return a;
 }
 

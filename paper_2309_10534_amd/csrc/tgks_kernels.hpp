@@ -42,7 +42,7 @@ struct StageArgs {
   double* FA;
   double* FB;
   const double* dt;
-  unsigned long long* fail;  // [0] failing Gauss points; [1] fallbacks (contexts with the fallback)
+  unsigned long long* fail;
   uint8_t* nflags;  // normal flags [D][nc][cells] or null
   uint8_t* tflags;  // tangential flags of this direction or null
   const double* R;  // 3-D: normal reconstruction of this direction
@@ -52,6 +52,7 @@ struct StageArgs {
   double t0;        // time of W (prescribed states) is t0 + *tclk (tclk may be null)
   const double* tclk;
   int fallback;     // 1: first-order fallback at non-physical Gauss-point states
+  unsigned long long* fbc;  // fallback counter, or null (not counted)
 };
 
 __device__ __forceinline__ long long face_count(const Geom& g, int ax) {
@@ -229,7 +230,7 @@ __device__ __forceinline__ void face1d_body(const StageArgs& a, int f) {
       Cr[c] = cell_value(a.g, a.pb, a.W, c, f, 0, tb);
     }
     const int nfb = fallback_side<3, 1>(Wl, dWl, Cl, a.gamma) + fallback_side<3, 1>(Wr, dWr, Cr, a.gamma);
-    if (nfb) atomicAdd(a.fail + 1, (unsigned long long)nfb);  // second counter: fallbacks
+    if (nfb && a.fbc) atomicAdd(a.fbc, (unsigned long long)nfb);
   }
   double Fdt[3], Fh[3], A[3] = {0, 0, 0}, B[3] = {0, 0, 0};
   const bool ok = gp_flux<1, NS>(Wl, Wr, dWl, dWr, a.fc, dt, Fdt, Fh);
@@ -534,7 +535,7 @@ __device__ __forceinline__ void face2d_tile(const StageArgs& a, int bx, int by, 
       Cr[q] = sW[perm[q]][ft + 2][fn + 3];
     }
     const int nfb = fallback_side<NC, 2>(Wg[0], Dg[0], Cl, a.gamma) + fallback_side<NC, 2>(Wg[1], Dg[1], Cr, a.gamma);
-    if (nfb) atomicAdd(a.fail + 1, (unsigned long long)nfb);  // second counter: fallbacks
+    if (nfb && a.fbc) atomicAdd(a.fbc, (unsigned long long)nfb);
   }
   if (live) {
     double Fdt[NC], Fh[NC];

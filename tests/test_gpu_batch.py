@@ -239,3 +239,38 @@ def test_batch_full_sets_spot_oracle(orc, torch_dev):
             assert badb[i] == bado
             if bado == 0 and np.all(np.isfinite(Wo)):
                 assert_close(Wb[i], Wo, what=f"dim {dim} instance {i}")
+
+
+@pytest.mark.parametrize("dim,steps", [(1, 40), (2, 12)])
+def test_batch_fallback_bitwise_equals_single(torch_dev, dim, steps):
+    """The first-order fallback in a batch (the stated ranges, where it acts):
+    every instance bit-identical to its single-grid run with the fallback,
+    eager and graph-captured, and more instances run every step than
+    without it."""
+    probs = mixed_set(dim, 9, seed=1 if dim == 1 else 2, size_range=(16, 90) if dim == 1 else (12, 40))
+    probs = [(W, dict(pr, fallback=1)) for W, pr in probs]
+    print(f"[batch-fallback] dim={dim} instances={len(probs)} steps={steps}", flush=True)
+    ref = single_runs(probs, steps)
+    B = Batch(probs)
+    try:
+        (Wb, tb, badb), = B.run(steps)
+        full = sum(1 for i in range(len(probs)) if B.steps[i] == steps)
+        runs = B.run(steps, use_graph=True, replays=2)
+        for Wg, tg, badg in runs:
+            for i in range(len(probs)):
+                assert np.array_equal(Wg[i], Wb[i], equal_nan=True), f"graph replay, instance {i}"
+    finally:
+        B.close()
+    for i, (Ws, ts, bads) in enumerate(ref):
+        assert np.array_equal(Wb[i], Ws, equal_nan=True), f"instance {i} differs from its single-grid run"
+        assert np.array_equal(tb[i], ts, equal_nan=True), f"instance {i}: clock {tb[i]} vs {ts}"
+        assert badb[i] == bads
+    plain = [(W, dict(pr, fallback=0)) for W, pr in probs]
+    B0 = Batch(plain)
+    try:
+        B0.run(steps)
+        full0 = sum(1 for i in range(len(plain)) if B0.steps[i] == steps)
+    finally:
+        B0.close()
+    print(f"[batch-fallback] full runs {full} with the fallback, {full0} without", flush=True)
+    assert full >= full0

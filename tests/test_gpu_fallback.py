@@ -89,6 +89,7 @@ def test_rejections(torch_dev):
     from paper_2309_10534_amd import tgks
     with pytest.raises(tgks.TgksError):
         tgks.tgks_create(tgks.tgks_params_default(3, [8, 8, 8], [0.1] * 3, fallback=1))
-    p = tgks.tgks_params_default(2, [16, 16], [0.1, 0.1], fallback=1)
-    with pytest.raises(tgks.TgksError):
-        tgks.tgks_batch_create([p])
+    p1 = tgks.tgks_params_default(2, [16, 16], [0.1, 0.1], fallback=1)
+    p0 = tgks.tgks_params_default(2, [16, 16], [0.1, 0.1])
+    with pytest.raises(tgks.TgksError):  # mixed within one batch
+        tgks.tgks_batch_create([p1, p0])
