@@ -33,6 +33,19 @@ struct Prescribed {
   double line[2][2][3]; // [axis][end]: s0, s_n, s_t
 };
 
+// value of lane (lane ^ MASK), MASK = 1 or 2, by a DPP quad permute (a
+// VALU move; no LDS instruction, unlike a general lane shuffle)
+template <int MASK>
+__device__ __forceinline__ int lane_xor(int v) {
+  static_assert(MASK == 1 || MASK == 2, "quad permutes only");
+  return __builtin_amdgcn_mov_dpp(v, MASK == 1 ? 0xB1 : 0x4E, 0xF, 0xF, false);
+}
+template <int MASK>
+__device__ __forceinline__ double lane_xor(double v) {
+  const int lo = lane_xor<MASK>(__double2loint(v)), hi = lane_xor<MASK>(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+
 struct StageArgs {
   Geom g;
   FluxCfg fc;
@@ -483,7 +496,7 @@ __device__ __forceinline__ void face2d_tile(const StageArgs& a, int bx, int by, 
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
       const double sv = aV[q][1 - m], sd = aD[q][1 - m], sn = aN[q][1 - m];
-      const double rv = __shfl_xor(sv, 1), rd = __shfl_xor(sd, 1), rn = __shfl_xor(sn, 1);
+      const double rv = lane_xor<1>(sv), rd = lane_xor<1>(sd), rn = lane_xor<1>(sn);
       const double ov = aV[q][m], od = aD[q][m], on = aN[q][m];
       Wg[0][q] = m == 0 ? ov : rv;
       Wg[1][q] = m == 0 ? rv : ov;
@@ -516,7 +529,7 @@ __device__ __forceinline__ void face2d_tile(const StageArgs& a, int bx, int by, 
       // own side at own Gauss point; the partner's side at this Gauss point
       // arrives from the partner, which computed it
       const double sv = m ? v[0] : v[1], sd = m ? dv[0] : dv[1], sn = m ? vn[0] : vn[1];
-      const double rv = __shfl_xor(sv, 1), rd = __shfl_xor(sd, 1), rn = __shfl_xor(sn, 1);
+      const double rv = lane_xor<1>(sv), rd = lane_xor<1>(sd), rn = lane_xor<1>(sn);
       const double ov = m ? v[1] : v[0], od = m ? dv[1] : dv[0], on = m ? vn[1] : vn[0];
       Wg[0][q] = m == 0 ? ov : rv;
       Wg[1][q] = m == 0 ? rv : ov;
@@ -544,8 +557,8 @@ __device__ __forceinline__ void face2d_tile(const StageArgs& a, int bx, int by, 
   }
 #pragma unroll
   for (int q = 0; q < NC; ++q) {
-    A[q] += __shfl_xor(A[q], 1);
-    if (STAGE == 1) B[q] += __shfl_xor(B[q], 1);
+    A[q] += lane_xor<1>(A[q]);
+    if (STAGE == 1) B[q] += lane_xor<1>(B[q]);
   }
   wall_fluxes<NC>(g, AX, f, A, B);
   if (live && m == 0) {
@@ -742,7 +755,7 @@ __global__ __launch_bounds__(L3 * B3_1 * B3_2, 2) void face3d_kernel(StageArgs a
       teno_gauss(Q, teno_flag(Q, a.tt), v, d);
     }
     const double own = m3 ? v[1] : v[0], own_d = m3 ? d[1] : d[0];
-    const double rcv = __shfl_xor(m3 ? v[0] : v[1], 2), rcv_d = __shfl_xor(m3 ? d[0] : d[1], 2);
+    const double rcv = lane_xor<2>(m3 ? v[0] : v[1]), rcv_d = lane_xor<2>(m3 ? d[0] : d[1]);
     // item 2 r is lane m3 = 0's, item 2 r + 1 lane m3 = 1's
     item[2 * r] = m3 ? rcv : own;
     item_d[2 * r] = m3 ? rcv_d : own_d;
@@ -766,7 +779,7 @@ __global__ __launch_bounds__(L3 * B3_1 * B3_2, 2) void face3d_kernel(StageArgs a
   if (live) side_w0<3>(Ws, a.fc, m2 ? -1.0 : 1.0, gs, h0, h1, w0);
   double W0[NC];
 #pragma unroll
-  for (int q = 0; q < NC; ++q) W0[q] = w0[q] + __shfl_xor(w0[q], 1);
+  for (int q = 0; q < NC; ++q) W0[q] = w0[q] + lane_xor<1>(w0[q]);
   SidePart<3, double> P, T;
 #pragma unroll
   for (int q = 0; q < NC; ++q) {
@@ -786,20 +799,20 @@ __global__ __launch_bounds__(L3 * B3_1 * B3_2, 2) void face3d_kernel(StageArgs a
 #pragma unroll
   for (int q = 0; q < NC; ++q) {
 #pragma unroll
-    for (int d = 0; d < 3; ++d) T.dW0[d][q] = P.dW0[d][q] + __shfl_xor(P.dW0[d][q], 1);
-    T.S1[q] = P.S1[q] + __shfl_xor(P.S1[q], 1);
-    T.S2[q] = P.S2[q] + __shfl_xor(P.S2[q], 1);
-    T.S3[q] = P.S3[q] + __shfl_xor(P.S3[q], 1);
+    for (int d = 0; d < 3; ++d) T.dW0[d][q] = P.dW0[d][q] + lane_xor<1>(P.dW0[d][q]);
+    T.S1[q] = P.S1[q] + lane_xor<1>(P.S1[q]);
+    T.S2[q] = P.S2[q] + lane_xor<1>(P.S2[q]);
+    T.S3[q] = P.S3[q] + lane_xor<1>(P.S3[q]);
   }
   if (NS) {
-    T.H1 = P.H1 + __shfl_xor(P.H1, 1);
-    T.H2 = P.H2 + __shfl_xor(P.H2, 1);
-    T.H3 = P.H3 + __shfl_xor(P.H3, 1);
+    T.H1 = P.H1 + lane_xor<1>(P.H1);
+    T.H2 = P.H2 + lane_xor<1>(P.H2);
+    T.H3 = P.H3 + lane_xor<1>(P.H3);
   } else {
     T.H1 = T.H2 = T.H3 = 0.0;
   }
-  const double pp = __shfl_xor(ps, 1);
-  ok = ok && (__shfl_xor((int)ok, 1) != 0);
+  const double pp = lane_xor<1>(ps);
+  ok = ok && (lane_xor<1>((int)ok) != 0);
   double A[NC] = {0, 0, 0, 0, 0}, B[NC] = {0, 0, 0, 0, 0};
   if (live) {
     double Fdt[NC], Fh[NC];
@@ -811,10 +824,10 @@ __global__ __launch_bounds__(L3 * B3_1 * B3_2, 2) void face3d_kernel(StageArgs a
   // same flux
 #pragma unroll
   for (int q = 0; q < NC; ++q) {
-    A[q] += __shfl_xor(A[q], 2);
+    A[q] += lane_xor<2>(A[q]);
     A[q] += __shfl_xor(A[q], 4);
     if (STAGE == 1) {
-      B[q] += __shfl_xor(B[q], 2);
+      B[q] += lane_xor<2>(B[q]);
       B[q] += __shfl_xor(B[q], 4);
     }
   }
