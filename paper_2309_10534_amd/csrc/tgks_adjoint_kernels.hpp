@@ -205,7 +205,7 @@ __global__ __launch_bounds__(2 * ATN * ATT) void adj_face2d_kernel(AdjArgs a) {
       teno_gauss(Qw, fw, v, dv);
       teno_gauss(Qn, fq, vn, dn);
       const double sv = m ? v[0] : v[1], sd = m ? dv[0] : dv[1], sn = m ? vn[0] : vn[1];
-      const double rv = __shfl_xor(sv, 1), rd = __shfl_xor(sd, 1), rn = __shfl_xor(sn, 1);
+      const double rv = lane_xor<1>(sv), rd = lane_xor<1>(sd), rn = lane_xor<1>(sn);
       const double ov = m ? v[1] : v[0], od = m ? dv[1] : dv[0], on = m ? vn[1] : vn[0];
       Wg[0][q] = m == 0 ? ov : rv;
       Wg[1][q] = m == 0 ? rv : ov;

@@ -46,6 +46,15 @@ __device__ __forceinline__ double lane_xor(double v) {
   return __hiloint2double(hi, lo);
 }
 
+// value of lane 7 - i within the lane's group of eight (DPP half-row
+// mirror): for a value that is the same in the four lanes of each quad, the
+// other quad's value, as lane ^ 4 would give
+__device__ __forceinline__ double other_quad(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x141, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x141, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
 struct StageArgs {
   Geom g;
   FluxCfg fc;
@@ -825,10 +834,10 @@ __global__ __launch_bounds__(L3 * B3_1 * B3_2, 2) void face3d_kernel(StageArgs a
 #pragma unroll
   for (int q = 0; q < NC; ++q) {
     A[q] += lane_xor<2>(A[q]);
-    A[q] += __shfl_xor(A[q], 4);
+    A[q] += other_quad(A[q]);  // quads hold their sums after the two steps above
     if (STAGE == 1) {
       B[q] += lane_xor<2>(B[q]);
-      B[q] += __shfl_xor(B[q], 4);
+      B[q] += other_quad(B[q]);
     }
   }
   wall_fluxes<NC>(g, AX, fa, A, B);
