@@ -99,8 +99,8 @@ typedef struct tgks_params {
   double bc_state[2][5];   /* states A and B, conservative, (rho, m_0 .. m_{ndim-1}, E) */
   double bc_line[3][2][3]; /* per axis and end (0 low, 1 high): (s0, s_n, s_t) */
   int32_t bc_far[3][2];    /* per axis and end: kind beyond the line */
-  /* first-order fallback (not in the paper; 1-D and 2-D contexts; default
-   * 0): 1 replaces a reconstructed Gauss-point state of one side whose
+  /* first-order fallback (not in the paper; default 0; the reverse mode
+   * rejects it): 1 replaces a reconstructed Gauss-point state of one side whose
    * density or pressure, (gamma-1) (E - (0.5 sum_a m_a^2) / rho) evaluated in
    * that order, is not positive or not finite by the average of that side's
    * cell at the face, with zero slopes, before the flux is evaluated.  It is

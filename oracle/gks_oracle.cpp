@@ -65,8 +65,8 @@
 //    image.  The time of stage 1 is t^n, that of stage 2 t^n + dt/2 (W* is
 //    the state at the half step).  A corner ghost cell is decided by the
 //    x side first when that side is prescribed and gives a state.
-//  * Optional first-order fallback (not in the paper, off by default; 1-D
-//    and 2-D): a Gauss-point state of one side whose density or pressure is
+//  * Optional first-order fallback (not in the paper, off by default): a
+//    Gauss-point state of one side whose density or pressure is
 //    not positive or not finite is replaced by the average of that side's
 //    cell at the face, with zero slopes, before the flux is evaluated.  The
 //    pressure of the test is (gamma - 1) (E - (0.5 sum_a m_a^2) / rho), the
@@ -137,7 +137,7 @@ typedef struct {
   double bc_state[2][5];   // prescribed states A and B (rho, m_0 .. m_{D-1}, E)
   double bc_line[3][2][3]; // per axis and end: (s0, s_n, s_t) of the line bounding state A
   int bc_far[3][2];        // per axis and end: kind beyond the line (1, 2, or 4 = state B)
-  int fallback;            // 1: first-order fallback at non-physical Gauss-point states (1-D, 2-D)
+  int fallback;            // 1: first-order fallback at non-physical Gauss-point states
 } orc_params;
 }
 
@@ -1274,7 +1274,7 @@ static int check_params(const orc_params* P) {
   }
   if (!(P->gamma > 1.0)) return -1;
   if (P->recon < 0 || P->recon > 1 || (P->recon == 1 && P->ndim > 2)) return -1;
-  if (P->fallback < 0 || P->fallback > 1 || (P->fallback == 1 && P->ndim > 2)) return -1;
+  if (P->fallback < 0 || P->fallback > 1) return -1;
   return 0;
 }
 

@@ -99,20 +99,28 @@ int launch_faces(tgks_ctx* c, const double* W, const double* dt, int stage, uint
         const long long nbl = (long long)(c->g.n[ax] + 1) * ((n1 + B3_1 - 1) / B3_1) * ((n2 + B3_2 - 1) / B3_2);
         dim3 grid((unsigned)(8 * ((nbl + 7) / 8)));
         const dim3 blk3(L3 * B3_1 * B3_2);
-#define F3(AXV)                                                                       \
+#define F3(AXV, EX)                                                                   \
   if (stage == 1) {                                                                   \
-    if (c->ns) LAUNCH((face3d_kernel<AXV, 1, true>), grid, blk3, a);                  \
-    else LAUNCH((face3d_kernel<AXV, 1, false>), grid, blk3, a);                       \
+    if (c->ns) LAUNCH((face3d_kernel<AXV, 1, true, EX>), grid, blk3, a);              \
+    else LAUNCH((face3d_kernel<AXV, 1, false, EX>), grid, blk3, a);                   \
   } else {                                                                            \
-    if (c->ns) LAUNCH((face3d_kernel<AXV, 2, true>), grid, blk3, a);                  \
-    else LAUNCH((face3d_kernel<AXV, 2, false>), grid, blk3, a);                       \
+    if (c->ns) LAUNCH((face3d_kernel<AXV, 2, true, EX>), grid, blk3, a);              \
+    else LAUNCH((face3d_kernel<AXV, 2, false, EX>), grid, blk3, a);                   \
   }
-        if (ax == 0) {
-          F3(0)
+        if (c->ex) {  // the first-order fallback (3-D grids have no prescribed sides)
+          if (ax == 0) {
+            F3(0, true)
+          } else if (ax == 1) {
+            F3(1, true)
+          } else {
+            F3(2, true)
+          }
+        } else if (ax == 0) {
+          F3(0, false)
         } else if (ax == 1) {
-          F3(1)
+          F3(1, false)
         } else {
-          F3(2)
+          F3(2, false)
         }
 #undef F3
       }

@@ -103,7 +103,6 @@ inline int check_params(const tgks_params* p) {
   if (p->recon != TGKS_RECON_CONSERVATIVE && p->recon != TGKS_RECON_CHARACTERISTIC) return TGKS_EINVAL;
   if (p->recon == TGKS_RECON_CHARACTERISTIC && p->ndim > 2) return TGKS_EINVAL;
   if (p->fallback != 0 && p->fallback != 1) return TGKS_EINVAL;
-  if (p->fallback == 1 && p->ndim > 2) return TGKS_EINVAL;
   double cells = 1.0;
   for (int d = 0; d < p->ndim; ++d) cells *= p->n[d];
   if (cells > 4.0e9) return TGKS_EINVAL;

@@ -665,7 +665,7 @@ __global__ __launch_bounds__(256) void recon3d_kernel(StageArgs a) {
 // Tiles are dealt to the 8 XCDs in contiguous ranges.
 constexpr int B3_1 = 2, B3_2 = 16, L3 = 8;
 
-template <int AX, int STAGE, bool NS>
+template <int AX, int STAGE, bool NS, bool EX = false>
 __global__ __launch_bounds__(L3 * B3_1 * B3_2, 2) void face3d_kernel(StageArgs a) {
   constexpr int NC = 5, B1 = B3_1, B2 = B3_2, NT = L3 * B1 * B2;
   constexpr int L1 = B1 + 4, L2 = B2 + 4;
@@ -780,6 +780,15 @@ __global__ __launch_bounds__(L3 * B3_1 * B3_2, 2) void face3d_kernel(StageArgs a
     dWs[2][q] = item_d[3 * q] * i2d;
     dWs[1][q] = item[3 * q + 1];
     dWs[0][q] = item[3 * q + 2];
+  }
+  if (EX && live && a.fallback) {
+    // first-order fallback: this side's cell (fa - 1 + m2 along AX), frame order
+    int cp[3] = {fp[0], fp[1], fp[2]};
+    cp[AX] = fa - 1 + m2;
+    double C[NC];
+#pragma unroll
+    for (int q = 0; q < NC; ++q) C[q] = load_cell(g, a.W, perm[q], cp[0], cp[1], cp[2]);
+    if (fallback_side<NC, 3>(Ws, dWs, C, a.gamma) && a.fbc) atomicAdd(a.fbc, 1ull);
   }
 
   // 4. the Gauss-point flux, one side per lane

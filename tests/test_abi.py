@@ -115,13 +115,12 @@ def test_oracle_params_layout(tmp_path):
 
 
 def test_prescribed_and_fallback_checks_without_device(lib):
-    """Prescribed sides and the fallback: 3-D grids, far kinds other than
-    transmissive / reflective / state B, a NaN line and unknown fallback
-    values are rejected before any device work."""
+    """Prescribed sides on 3-D grids, far kinds other than transmissive /
+    reflective / state B, a NaN line and unknown fallback values are
+    rejected before any device work."""
     from paper_2309_10534_amd import tgks
     h = ctypes.c_void_p()
     bad = [tgks.tgks_params_default(3, [8] * 3, [0.1] * 3, bc=[("prescribed", "transmissive")] * 3),
-           tgks.tgks_params_default(3, [8] * 3, [0.1] * 3, fallback=1),
            tgks.tgks_params_default(2, [8, 8], [0.1, 0.1], fallback=2)]
     p = tgks.tgks_params_default(2, [8, 8], [0.1, 0.1], bc=[("prescribed", "transmissive")] * 2)
     p.bc_far[0][0] = tgks.BC_NOSLIP
