@@ -91,3 +91,17 @@ def assert_close(a, b, tol=TOL_L1, what=""):
     assert np.all(np.isfinite(a)), f"{what}: non-finite GPU values"
     assert np.all(e <= tol), f"{what}: L1-relative difference {e} > {tol}"
     return e
+
+
+def close_scaled(a, b, tol, what):
+    """L1 difference per component relative to its L1 norm, momenta against
+    the density's norm (a momentum that is zero up to rounding, as across a
+    uniform direction, has no scale of its own)."""
+    D = a.shape[0] - 2
+    assert np.all(np.isfinite(a)), f"{what}: non-finite GPU values"
+    for c in range(D + 2):
+        scale = np.abs(b[c]).sum()
+        if 1 <= c <= D:
+            scale = max(scale, np.abs(b[0]).sum())
+        e = np.abs(a[c] - b[c]).sum() / scale
+        assert e <= tol, f"{what}: component {c} L1 difference {e} > {tol}"

@@ -9,7 +9,7 @@ momentum and energy."""
 import numpy as np
 import pytest
 
-from gpu_common import GpuProblem, orc_params, problem
+from gpu_common import GpuProblem, close_scaled, orc_params, problem
 from paper_2309_10534_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
@@ -21,20 +21,6 @@ def torch_dev():
     if not torch.cuda.is_available():
         pytest.skip("no HIP device")
     return torch
-
-
-def close_scaled(a, b, tol, what):
-    """L1 difference per component relative to its L1 norm, momenta against
-    the density's norm (a momentum that is zero up to rounding, as across a
-    uniform direction, has no scale of its own)."""
-    D = a.shape[0] - 2
-    assert np.all(np.isfinite(a)), f"{what}: non-finite GPU values"
-    for c in range(D + 2):
-        scale = np.abs(b[c]).sum()
-        if 1 <= c <= D:
-            scale = max(scale, np.abs(b[0]).sum())
-        e = np.abs(a[c] - b[c]).sum() / scale
-        assert e <= tol, f"{what}: component {c} L1 difference {e} > {tol}"
 
 
 def compare_on_trajectory(orc, pr, W0, marks, t_of=None):

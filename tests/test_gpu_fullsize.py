@@ -11,7 +11,7 @@ boundary."""
 import numpy as np
 import pytest
 
-from gpu_common import GpuProblem, l1rel, orc_params, problem
+from gpu_common import GpuProblem, close_scaled, l1rel, orc_params, problem
 from paper_2309_10534_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
@@ -109,3 +109,45 @@ def test_3d_taylor_green_128(orc, torch_dev):
     # momenta are measured against the total momentum magnitude (rho W is zero)
     scale = np.array([a[0], a[1:4].sum(), a[1:4].sum(), a[1:4].sum(), a[4]])
     assert np.all(np.abs(tot - tot0) <= 1e-12 * scale), (tot - tot0) / scale
+
+
+@pytest.mark.parametrize("recon", [0, 1])
+def test_double_mach_960x240(orc, torch_dev, recon):
+    """The double Mach reflection (Sec. 5.7) at its benchmark size, 960 x 240,
+    with the first-order fallback: the whole grid after one step against the
+    oracle's (1e-10 L1-relative, momenta against the density's norm), the
+    selection flags bit for bit and the same number of replaced Gauss-point
+    states; once through tgks_step with flags and W*, once through tgks_run
+    (the launch bench.py times).  Conservative variables also take the
+    second step, from the oracle's first, with the boundary clock at its
+    time."""
+    nx, ny = 960, 240
+    W0, (dx, dy), spec = I.double_mach(nx, ny)
+    pr = problem([nx, ny], [dx, dy], bc=spec["bc"], states=spec["states"], lines=spec["lines"], far=spec["far"],
+                 recon=recon, fallback=1)
+    P = orc_params(orc, pr)
+    gp = GpuProblem(pr)
+    try:
+        W, t = W0, 0.0
+        for k in range(2 if recon == 0 else 1):
+            dt = orc.cfl_dt(P, W, 0.5)
+            print(f"[fullsize] double Mach recon={recon} step={k} t={t:.6e} dt={dt:.6e}", flush=True)
+            Wg, Wsg, fg, badg = gp.step(W, dt, flags=True, t0=t)
+            nfb = [0]
+            Wo, fo, Wso, bado = orc.step(P, W, dt, want_flags=True, want_wstar=True, t=t, fallbacks=nfb)
+            print(f"[fullsize] fallbacks gpu={gp.fallbacks} oracle={nfb[0]}", flush=True)
+            assert badg == bado == 0
+            assert gp.fallbacks == nfb[0]
+            if k == 0:
+                assert nfb[0] > 0  # the first step needs the fallback
+            mism = np.flatnonzero(fg != fo)
+            assert mism.size == 0, f"{mism.size} flag mismatches, first at {mism[:10]}"
+            close_scaled(Wsg, Wso, 1e-10, f"W* step {k}")
+            close_scaled(Wg, Wo, 1e-10, f"W^(n+1) step {k}")
+            Wr, td, badr = gp.run(W, 1, cfl=0.5, t0=t)
+            assert badr == 0 and abs(td[0] - dt) <= 1e-15 * dt, (td, dt)
+            assert gp.t.tgks_fallback_count(gp.ctx) == nfb[0]
+            close_scaled(Wr, Wo, 1e-10, f"tgks_run step {k}")
+            W, t = Wo, t + dt
+    finally:
+        gp.close()

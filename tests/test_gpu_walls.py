@@ -6,7 +6,7 @@ walls is checked with the other reverse-mode tests)."""
 import numpy as np
 import pytest
 
-from gpu_common import GpuProblem, orc_params, problem
+from gpu_common import GpuProblem, close_scaled, orc_params, problem
 from paper_2309_10534_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
@@ -18,20 +18,6 @@ def torch_dev():
     if not torch.cuda.is_available():
         pytest.skip("no HIP device")
     return torch
-
-
-def close_scaled(a, b, tol, what):
-    """L1 difference per component relative to the component's L1 norm, with
-    the momenta measured against the density's norm (a momentum that is zero
-    up to rounding, as across a uniform direction, has no scale of its own)."""
-    D = a.shape[0] - 2
-    assert np.all(np.isfinite(a)), f"{what}: non-finite GPU values"
-    for c in range(D + 2):
-        scale = np.abs(b[c]).sum()
-        if 1 <= c <= D:
-            scale = max(scale, np.abs(b[0]).sum())
-        e = np.abs(a[c] - b[c]).sum() / scale
-        assert e <= tol, f"{what}: component {c} L1 difference {e} > {tol}"
 
 
 def compare_step(orc, pr, W, dt, tol=1e-10):
