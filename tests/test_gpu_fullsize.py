@@ -151,3 +151,33 @@ def test_double_mach_960x240(orc, torch_dev, recon):
             W, t = Wo, t + dt
     finally:
         gp.close()
+
+
+@pytest.mark.parametrize("recon", [0, 1])
+def test_2d_riemann_1024_whole_grid(orc, torch_dev, recon):
+    """The benchmark workload (1024^2 four-quadrant Riemann problem, seed 0)
+    and the characteristic-variable workload (seed 1): the whole grid after
+    one step against the oracle's full-grid step, 1e-10 L1-relative per
+    component, selection flags bit for bit, W* included; and the same step
+    through tgks_run."""
+    n = 1024
+    W, dx, _ = I.quadrant_riemann(n, seed=recon)
+    pr = problem([n, n], [dx, dx], recon=recon)
+    P = orc_params(orc, pr)
+    dt = orc.cfl_dt(P, W, 0.5)
+    print(f"[fullsize] 1024^2 whole grid recon={recon} dt={dt:.6e}", flush=True)
+    gp = GpuProblem(pr)
+    try:
+        Wg, Wsg, fg, badg = gp.step(W, dt, flags=True)
+        Wr, td, badr = gp.run(W, 1, cfl=0.5)
+    finally:
+        gp.close()
+    print("[fullsize] oracle step", flush=True)
+    Wo, fo, Wso, bado = orc.step(P, W, dt, want_flags=True, want_wstar=True)
+    assert badg == bado == badr == 0
+    mism = np.flatnonzero(fg != fo)
+    assert mism.size == 0, f"{mism.size} flag mismatches, first at {mism[:10]}"
+    assert np.all(l1rel(Wsg, Wso) <= 1e-10), l1rel(Wsg, Wso)
+    assert np.all(l1rel(Wg, Wo) <= 1e-10), l1rel(Wg, Wo)
+    assert abs(td[0] - dt) <= 1e-15 * dt
+    assert np.all(l1rel(Wr, Wo) <= 1e-10), l1rel(Wr, Wo)
