@@ -181,3 +181,47 @@ def test_2d_riemann_1024_whole_grid(orc, torch_dev, recon):
     assert np.all(l1rel(Wg, Wo) <= 1e-10), l1rel(Wg, Wo)
     assert abs(td[0] - dt) <= 1e-15 * dt
     assert np.all(l1rel(Wr, Wo) <= 1e-10), l1rel(Wr, Wo)
+
+
+@pytest.mark.parametrize("recon", [0, 1])
+def test_double_mach_960x240_to_t02(torch_dev, recon):
+    """The bench's double Mach reflection run (960 x 240, fallback on) to
+    t = 0.2 on the device, checked by properties that hold at any size: no
+    failure, positive density and pressure, the top row's incident shock
+    (where the density crosses the mean of the two states) within a cell of
+    its exact position x = 1/6 + (y + 20 t) / sqrt 3, and the pre-shock state
+    to rounding six cells ahead of it.  (The row's mass-equivalent shock
+    position also carries the start-up error of the shock, a density defect
+    left behind it, and is only printed.)"""
+    import math
+    nx, ny, t_end = 960, 240, 0.2
+    W0, (dx, dy), spec = I.double_mach(nx, ny)
+    pr = problem([nx, ny], [dx, dy], bc=spec["bc"], states=spec["states"], lines=spec["lines"], far=spec["far"],
+                 recon=recon, fallback=1)
+    gp = GpuProblem(pr)
+    try:
+        print(f"[fullsize] double Mach to t = 0.2, recon={recon}", flush=True)
+        # more steps than t = 0.2 takes; those past t_end have dt = 0
+        W, td, bad = gp.run(W0, 2400, cfl=0.5, t_end=t_end, t0=0.0)
+        nfb = gp.t.tgks_fallback_count(gp.ctx)
+    finally:
+        gp.close()
+    print(f"[fullsize] t={td[0]:.15f} failures={bad} fallbacks={nfb}", flush=True)
+    assert bad == 0 and abs(td[0] - t_end) <= 1e-14 and nfb > 0
+    rho, _, p = I.primitive(W)
+    assert np.all(np.isfinite(W)) and rho.min() > 0.0 and p.min() > 0.0
+    y = 1.0 - 0.5 * dy
+    exact = 1.0 / 6.0 + (y + 20.0 * t_end) / math.sqrt(3.0)
+    x = (np.arange(nx) + 0.5) * dx
+    top = rho[-1]
+    mid = 0.5 * (8.0 + 1.4)
+    i = int(np.flatnonzero(top >= mid).max())  # last cell above the mean
+    xc = x[i] + (top[i] - mid) / (top[i] - top[i + 1]) * dx
+    xs = (W[0][-1].sum() * dx - 1.4 * 4.0) / (8.0 - 1.4)
+    print(f"[fullsize] top-row shock: crossing {(xc - exact) / dx:+.3f} cells, mass-equivalent "
+          f"{(xs - exact) / dx:+.3f} cells from exact", flush=True)
+    assert abs(xc - exact) < dx
+    B = np.array(spec["states"][1])
+    ahead = np.abs(W[:, :, x > exact + 6 * dx] - B[:, None, None]).max()
+    print(f"[fullsize] max deviation from the pre-shock state ahead: {ahead:.2e}", flush=True)
+    assert ahead < 1e-12
