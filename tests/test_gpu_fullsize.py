@@ -225,3 +225,32 @@ def test_double_mach_960x240_to_t02(torch_dev, recon):
     ahead = np.abs(W[:, :, x > exact + 6 * dx] - B[:, None, None]).max()
     print(f"[fullsize] max deviation from the pre-shock state ahead: {ahead:.2e}", flush=True)
     assert ahead < 1e-12
+
+
+@pytest.mark.parametrize("recon", [0, 1])
+def test_viscous_shock_tube_500x250_to_t1(torch_dev, recon):
+    """The bench's viscous shock tube run (Sec. 5.8: 500 x 250, Re 200,
+    Pr 0.73, CFL 0.2, fallback on) to t = 1 on the device, checked by
+    properties that hold at any size: the box is closed (no-slip adiabatic
+    walls, symmetry at the top), so mass and energy stay at their initial
+    totals to rounding over the whole run; no failure and positive density
+    and pressure."""
+    nx, ny, t_end = 500, 250, 1.0
+    W0, dx = I.viscous_shock_tube(nx, ny)
+    pr = problem([nx, ny], [dx, dx], bc=[("noslip", "noslip"), ("noslip", "reflective")], tau="viscous",
+                 mu=1.0 / 200.0, prandtl=0.73, recon=recon, fallback=1)
+    gp = GpuProblem(pr)
+    try:
+        print(f"[fullsize] viscous shock tube to t = 1, recon={recon}", flush=True)
+        # more steps than t = 1 takes; those past t_end have dt = 0
+        W, td, bad = gp.run(W0, 11000, cfl=0.2, t_end=t_end, t0=0.0)
+    finally:
+        gp.close()
+    print(f"[fullsize] t={td[0]:.15f} failures={bad}", flush=True)
+    assert bad == 0 and abs(td[0] - t_end) <= 1e-14
+    rho, _, p = I.primitive(W)
+    assert np.all(np.isfinite(W)) and rho.min() > 0.0 and p.min() > 0.0
+    for c in (0, 3):
+        rel = abs(W[c].sum() - W0[c].sum()) / W0[c].sum()
+        print(f"[fullsize] component {c}: relative change of the total {rel:.2e}", flush=True)
+        assert rel <= 1e-12, (c, rel)
