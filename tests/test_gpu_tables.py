@@ -69,3 +69,38 @@ def test_table8_2d_density_wave(torch_dev, n):
     # the 5-cell periodic grid (stencils wrap around the domain) agrees to 12 %
     tol = {5: 0.12, 10: 1e-5, 20: 1e-5, 40: 1e-5, 80: 1e-5}[n]
     np.testing.assert_allclose(err, load("table8_teno_d_density_wave_2d.txt")[n], rtol=tol)
+
+
+@pytest.mark.parametrize("table", [4, 8])
+def test_tables_batched(torch_dev, table):
+    """All grids of one table as the instances of one batched run (each with
+    its own CFL step and clock) reproduce the table as the single runs do."""
+    import torch
+    from paper_2309_10534_amd import tgks
+    if table == 4:
+        ns, make, dim, name = [10, 20, 40, 80, 160], I.density_wave_1d, 1, "table4_teno_d_density_wave_1d.txt"
+    else:
+        ns, make, dim, name = [5, 10, 20, 40, 80], I.density_wave_2d, 2, "table8_teno_d_density_wave_2d.txt"
+    ref = load(name)
+    Ws, params = [], []
+    for n in ns:
+        W0, dx = make(n)
+        Ws.append(W0)
+        params.append(tgks.tgks_params_default(dim, [n] * dim, [dx] * dim, "periodic", tau="zero"))
+    b = tgks.tgks_batch_create(params)
+    try:
+        print(f"[tables] table {table} batched, grids {ns}", flush=True)
+        W = torch.from_numpy(tgks.pack(Ws)).cuda()
+        td = torch.zeros(2 * len(ns), dtype=torch.float64, device="cuda")
+        tgks.tgks_batch_run(b, W, 4000, 0.5, 2.0, td)
+        bad = tgks.tgks_batch_status(b)
+        off = tgks.tgks_batch_offsets(b)
+        out = tgks.unpack(W.cpu().numpy(), off, [w.shape for w in Ws])
+        t = td.cpu().numpy().reshape(-1, 2)[:, 0]
+    finally:
+        tgks.tgks_batch_destroy(b)
+    assert all(x == 0 for x in bad) and np.all(np.abs(t - 2.0) < 1e-12), (bad, t)
+    for i, n in enumerate(ns):
+        err = errors(out[i], make(n, t=2.0)[0])
+        tol = 0.12 if n == 5 else (5e-3 if (table, n) == (4, 10) else 2e-5)
+        np.testing.assert_allclose(err, ref[n], rtol=tol, err_msg=f"table {table}, n={n}")
