@@ -3,7 +3,8 @@ independently of the oracle: Table 4 (Sec. 5.1, 1-D density wave) and
 Table 8 (Sec. 5.5, 2-D density wave), each grid run to t = 2 by tgks_run
 with the CFL step computed on the device (CFL 0.5, tau = 0), errors mean /
 rms / max over cells against the exact cell averages, with the tolerances
-the oracle's own pins use."""
+the oracle's own pins use; and Sod's tube (Sec. 5.2) against the exact
+Riemann solution."""
 import os
 
 import numpy as np
@@ -104,3 +105,32 @@ def test_tables_batched(torch_dev, table):
         err = errors(out[i], make(n, t=2.0)[0])
         tol = 0.12 if n == 5 else (5e-3 if (table, n) == (4, 10) else 2e-5)
         np.testing.assert_allclose(err, ref[n], rtol=tol, err_msg=f"table {table}, n={n}")
+
+
+def test_sod_exact_riemann(torch_dev):
+    """Sec. 5.2 (b) on the device: Sod's tube at 100, 200 and 400 cells to
+    t = 0.2 (CFL 0.5, the bench's workload at 400) converges to the exact
+    Riemann solution's cell averages at the rate of a flow with
+    discontinuities (L1 order between 0.6 and 1.3), within 2.5e-3 at 400
+    cells, with density and pressure inside the initial bounds."""
+    import math
+    from exact_riemann import cell_average_density
+    e = {}
+    for n in (100, 200, 400):
+        W0, dx = I.sod(n)
+        pr = problem([n], [dx], bc="transmissive")
+        gp = GpuProblem(pr)
+        try:
+            print(f"[tables] Sod, n={n}", flush=True)
+            W, td, bad = gp.run(W0, 4000, cfl=0.5, t_end=0.2)
+        finally:
+            gp.close()
+        assert bad == 0 and abs(td[0] - 0.2) < 1e-13
+        ex = cell_average_density((1.0, 0.0, 1.0), (0.125, 0.0, 0.1), n, 0.2)
+        e[n] = float(np.mean(np.abs(W[0] - ex)))
+        rho, _, p = I.primitive(W)
+        assert rho.min() > 0.1 and p.min() > 0.09 and rho.max() < 1.0 + 1e-3 and p.max() < 1.0 + 1e-3
+    print(f"[tables] Sod L1 errors {e}", flush=True)
+    assert e[400] < 2.5e-3 and e[100] > e[200] > e[400], e
+    order = math.log2(e[100] / e[400]) / 2
+    assert 0.6 < order < 1.3, (e, order)
