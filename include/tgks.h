@@ -138,10 +138,15 @@ int tgks_cfl_dt(tgks_ctx* ctx, const double* W, double cfl, double t, double t_e
  * flags (device, tgks_flag_bytes bytes, or NULL): stage-1 stencil
  * selections, one byte per decision: bit0 = delta_{3,1} (Eq. 4.7); when it
  * is 0, bits 1..3 = delta_{0,2}, delta_{1,2}, delta_{2,2} (Eq. 4.12).
- * Layout: normal reconstruction [ndim][nc][cells], then for ndim == 2 the
- * tangential reconstructions of each direction d (x-faces, then y-faces) as
- * [quantity (W, dW/dn)][side (left, right)][nc][faces_d], faces_d indexed
- * like a state whose axis d has n[d] + 1 entries.
+ * Layout: normal reconstruction [ndim][nc][cells], then for ndim >= 2 the
+ * tangential reconstructions of each direction d in turn (Sec. 3.2 Steps
+ * 1-3), faces_d indexed like a state whose axis d has n[d] + 1 entries:
+ *   ndim == 2: [quantity (W, dW/dn)][side (left, right)][nc][faces_d];
+ *   ndim == 3: the first sweep (along t1 = (d+1) mod 3) of the face's own
+ *     line as [quantity (W, dW/dn)][side][nc][faces_d], then the second
+ *     sweep (along t2 = (d+2) mod 3) as [t1 Gauss point (-, +)][quantity
+ *     (W, dW/dt1, dW/dn)][side][nc][faces_d]: 16 nc planes per direction.
+ * nc components in global order (rho, rho U, rho V, rho W, rho E).
  * W_star (device, one state, or NULL) receives the intermediate state W*
  * of Sec. 2.2. */
 int tgks_step(tgks_ctx* ctx, const double* W_in, double* W_out, const double* dt_dev, uint8_t* flags,

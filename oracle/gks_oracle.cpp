@@ -138,6 +138,10 @@ typedef struct {
   double bc_line[3][2][3]; // per axis and end: (s0, s_n, s_t) of the line bounding state A
   int bc_far[3][2];        // per axis and end: kind beyond the line (1, 2, or 4 = state B)
   int fallback;            // 1: first-order fallback at non-physical Gauss-point states
+  int scheme;              // 0 TENO-D (Sec. 4.2), 1 WENO-AO (Sec. 3.2), 2 TENO5 (Sec. 4.1),
+                           // 3 WENO-Z (Sec. 3.1); 1-2-3 on 1-D and 2-D grids
+  double d_hi, d_lo;       // WENO-AO linear weights of the large and the central small stencil
+  double eps_w;            // epsilon of the WENO-AO and WENO-Z weights (Eq. 3.5)
 } orc_params;
 }
 
@@ -312,6 +316,229 @@ static uint8_t select_T(const T Q[5], double ct1, double ct2, double eps, int q)
   double qv[5];
   for (int i = 0; i < 5; ++i) qv[i] = val(Q[i]);
   return teno_select(qv, ct1, ct2, eps, q);
+}
+
+// ---------------------------------------------------------------------------
+// The comparison schemes of the paper, each on the same five values Q_{-2..2}
+// and the same candidate polynomials p_0..p_2 (Sec. 3.1) and p_3 (Sec. 3.2).
+//  * WENO-AO (Sec. 3.2): linear weights d_3 = d_Hi, d_0 = d_2 =
+//    (1 - d_Hi)(1 - d_Lo)/2, d_1 = (1 - d_Hi) d_Lo; WENO-Z type weights
+//    omega_k = d_k (1 + (tau / (beta_k + eps))^2) (Eq. 3.5 with the ratio
+//    squared, as Table 2 requires) with
+//    tau = (|b3 - b0| + |b3 - b1| + |b3 - b2|) / 3, normalised over k = 0..3;
+//    p_AO = w3 (p_3 / d_3 - sum_k d_k / d_3 p_k) + sum_k w_k p_k, evaluated
+//    (value and derivative) wherever a value or slope is needed: the
+//    interfaces (Eqs. 3.22-3.24 are its pieces) and the Gauss points.
+//  * WENO-Z (Sec. 3.1): small stencils only, omega_k = d_k (1 + tau /
+//    (beta_k + eps)), tau = |b0 - b2| (Eqs. 3.5-3.8), d = (0.1, 0.6, 0.3) at
+//    x_{i+1/2}, mirrored at x_{i-1/2}, and at a Gauss point the linear
+//    weights that reproduce p_3 there.
+//  * TENO5 (Sec. 4.1): gamma_k = (C + tau / (beta_k + eps))^q, C = 1,
+//    tau = |b0 - b2|, cut-off delta_k = 0 where gamma_k / sum gamma < C_T
+//    (evaluated as gamma_k < C_T sum gamma), omega_k = d_k delta_k /
+//    sum d_j delta_j (Eqs. 4.1-4.4) with the same linear weights.
+//  * WENO-Z and TENO5 give the non-equilibrium interface values only; the
+//    slopes come from the quadratic with the cell average and the two
+//    interface values (Eq. 3.11).  Along a face (Gauss points) the slope is
+//    that quadratic's derivative at the Gauss point, built from the face
+//    segment's line average and its two end values.
+// ---------------------------------------------------------------------------
+static const double GPW = 1.7320508075688772 / 1080.0;  // sqrt(3)/1080
+
+// linear weights of p_0..p_2 that reproduce p_3 at x = -1/2 (where 0),
+// +1/2 (1), the Gauss point -1/(2 sqrt 3) (2) or +1/(2 sqrt 3) (3)
+static void lin_weights(int where, double d[3]) {
+  switch (where) {
+    case 0: d[0] = 0.3; d[1] = 0.6; d[2] = 0.1; break;
+    case 1: d[0] = 0.1; d[1] = 0.6; d[2] = 0.3; break;
+    case 2: d[0] = 7.0 / 36.0 + GPW; d[1] = 11.0 / 18.0; d[2] = 7.0 / 36.0 - GPW; break;
+    default: d[0] = 7.0 / 36.0 - GPW; d[1] = 11.0 / 18.0; d[2] = 7.0 / 36.0 + GPW;
+  }
+}
+
+// TENO5 cut-offs: bit k = delta_k
+static uint8_t teno5_select(const double Q[5], double ct, double eps, int qexp) {
+  double b[4];
+  teno_beta(Q, b);
+  const double tau = std::fabs(b[0] - b[2]);
+  double g[3];
+  for (int k = 0; k < 3; ++k) {
+    const double t = 1.0 + tau / (b[k] + eps);
+    double pw = 1.0;
+    if (qexp == 6) {
+      const double t2 = t * t;
+      const double t4 = t2 * t2;
+      pw = t4 * t2;
+    } else {
+      for (int r = 0; r < qexp; ++r) pw = pw * t;
+    }
+    g[k] = pw;
+  }
+  const double sg = (g[0] + g[1]) + g[2];
+  uint8_t f = 0;
+  for (int k = 0; k < 3; ++k)
+    if (!(g[k] < ct * sg)) f |= (uint8_t)(1u << k);
+  return f;
+}
+
+// normalised weights of p_0..p_2 at point `where` (WENO-Z or TENO5)
+static void small_weights(const orc_params& P, const double Q[5], int where, uint8_t flag, double ob[3]) {
+  double d[3];
+  lin_weights(where, d);
+  if (P.scheme == 2) {
+    double S = 0.0;
+    for (int k = 0; k < 3; ++k) S = S + ((flag >> k) & 1 ? d[k] : 0.0);
+    for (int k = 0; k < 3; ++k) ob[k] = (flag >> k) & 1 ? d[k] / S : 0.0;
+    return;
+  }
+  double b[4];
+  teno_beta(Q, b);
+  const double tau = std::fabs(b[0] - b[2]);
+  double om[3], S = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    om[k] = d[k] * (1.0 + tau / (b[k] + P.eps_w));
+    S = S + om[k];
+  }
+  for (int k = 0; k < 3; ++k) ob[k] = om[k] / S;
+}
+
+// coefficients of p_0..p_3 in the WENO-AO polynomial
+static void ao_weights(const orc_params& P, const double Q[5], double w[4]) {
+  double b[4];
+  teno_beta(Q, b);
+  const double dh = P.d_hi, dl = P.d_lo;
+  const double d[4] = {(1.0 - dh) * (1.0 - dl) / 2.0, (1.0 - dh) * dl, (1.0 - dh) * (1.0 - dl) / 2.0, dh};
+  const double tau = (std::fabs(b[3] - b[0]) + std::fabs(b[3] - b[1]) + std::fabs(b[3] - b[2])) / 3.0;
+  double om[4], S = 0.0;
+  for (int k = 0; k < 4; ++k) {
+    // the ratio enters squared (Table 2: the unsquared form of Eq. 3.5
+    // misses the printed errors by 1-4 %, the squared one matches them)
+    const double r = tau / (b[k] + P.eps_w);
+    om[k] = d[k] * (1.0 + r * r);
+    S = S + om[k];
+  }
+  double ob[4];
+  for (int k = 0; k < 4; ++k) ob[k] = om[k] / S;
+  w[3] = ob[3] / d[3];
+  for (int k = 0; k < 3; ++k) w[k] = ob[k] - ob[3] * d[k] / d[3];
+}
+
+// value and derivative (cell units) at x of sum_k w[k] p_k
+template <class T>
+static void poly_combo(const T Q[5], const double w[4], double x, T& v, T& dv) {
+  v = T(0.0);
+  dv = T(0.0);
+  for (int k = 0; k < 4; ++k) {
+    if (w[k] == 0.0) continue;
+    T co[5];
+    teno_poly(Q, k, co);
+    T pv = co[4];
+    for (int i = 3; i >= 0; --i) pv = pv * x + co[i];
+    T pd = 4.0 * co[4];
+    for (int i = 3; i >= 1; --i) pd = pd * x + double(i) * co[i];
+    v += w[k] * pv;
+    dv += w[k] * pd;
+  }
+}
+
+// interface values of p_0..p_2: vm at x_{i-1/2}, vp at x_{i+1/2} (Eq. 3.2 and
+// its mirror image)
+template <class T>
+static void small_face_values(const T Q[5], T vm[3], T vp[3]) {
+  const T a = Q[0], b = Q[1], c = Q[2], d = Q[3], e = Q[4];
+  vp[0] = ((2.0 * a - 7.0 * b) + 11.0 * c) * (1.0 / 6.0);
+  vp[1] = ((5.0 * c - b) + 2.0 * d) * (1.0 / 6.0);
+  vp[2] = ((2.0 * c + 5.0 * d) - e) * (1.0 / 6.0);
+  vm[0] = ((5.0 * b - a) + 2.0 * c) * (1.0 / 6.0);
+  vm[1] = ((2.0 * b + 5.0 * c) - d) * (1.0 / 6.0);
+  vm[2] = ((11.0 * c - 7.0 * d) + 2.0 * e) * (1.0 / 6.0);
+}
+
+// WENO-Z / TENO5 interface values v(-1/2), v(+1/2)
+template <class T>
+static uint8_t zt_face_values(const orc_params& P, const T Q[5], T& vm_out, T& vp_out) {
+  double q[5];
+  for (int i = 0; i < 5; ++i) q[i] = val(Q[i]);
+  const uint8_t f = P.scheme == 2 ? teno5_select(q, P.ct1, P.eps, P.q) : 0;
+  double om[3], op[3];
+  small_weights(P, q, 0, f, om);
+  small_weights(P, q, 1, f, op);
+  T vm[3], vp[3];
+  small_face_values(Q, vm, vp);
+  vm_out = T(0.0);
+  vp_out = T(0.0);
+  for (int k = 0; k < 3; ++k) {
+    vm_out += om[k] * vm[k];
+    vp_out += op[k] * vp[k];
+  }
+  return f;
+}
+
+// Normal reconstruction of a comparison scheme: {v(-1/2), s(-1/2), v(+1/2),
+// s(+1/2)} in cell units; returns the TENO5 cut-off flags (0 otherwise)
+template <class T>
+static uint8_t scheme_face(const orc_params& P, const T Q[5], T out[4]) {
+  if (P.scheme == 1) {
+    double q[5], w[4];
+    for (int i = 0; i < 5; ++i) q[i] = val(Q[i]);
+    ao_weights(P, q, w);
+    poly_combo(Q, w, -0.5, out[0], out[1]);
+    poly_combo(Q, w, 0.5, out[2], out[3]);
+    return 0;
+  }
+  T vm, vp;
+  const uint8_t f = zt_face_values(P, Q, vm, vp);
+  // the quadratic with average Q_0 and end values vm, vp (Eq. 3.11)
+  out[0] = vm;
+  out[1] = -2.0 * ((2.0 * vm + vp) - 3.0 * Q[2]);
+  out[2] = vp;
+  out[3] = 2.0 * ((vm + 2.0 * vp) - 3.0 * Q[2]);
+  return f;
+}
+
+// Tangential reconstruction of a comparison scheme at the two Gauss points:
+// {v(s-), d(s-), v(s+), d(s+)} in cell units; returns the TENO5 flags
+template <class T>
+static uint8_t scheme_gauss(const orc_params& P, const T Q[5], T out[4]) {
+  const double sg[2] = {-0.5 / std::sqrt(3.0), 0.5 / std::sqrt(3.0)};
+  double q[5];
+  for (int i = 0; i < 5; ++i) q[i] = val(Q[i]);
+  if (P.scheme == 1) {
+    double w[4];
+    ao_weights(P, q, w);
+    for (int m = 0; m < 2; ++m) poly_combo(Q, w, sg[m], out[2 * m], out[2 * m + 1]);
+    return 0;
+  }
+  T vm, vp;
+  const uint8_t f = zt_face_values(P, Q, vm, vp);
+  const T c1 = vp - vm, c2 = 3.0 * (vm + vp) - 6.0 * Q[2];
+  for (int m = 0; m < 2; ++m) {
+    double ob[3], w[4] = {0, 0, 0, 0};
+    small_weights(P, q, 2 + m, f, ob);
+    for (int k = 0; k < 3; ++k) w[k] = ob[k];
+    T dv;
+    poly_combo(Q, w, sg[m], out[2 * m], dv);
+    out[2 * m + 1] = c1 + (2.0 * sg[m]) * c2;
+  }
+  return f;
+}
+
+// the selection and reconstruction of the configured scheme: normal (face
+// values and slopes) or tangential (Gauss points)
+template <class T>
+static uint8_t recon_face(const orc_params& P, const T Q[5], T out[4]) {
+  if (P.scheme != 0) return scheme_face(P, Q, out);
+  const uint8_t f = select_T(Q, P.ct1, P.ct2, P.eps, P.q);
+  teno_face_values(Q, f, out);
+  return f;
+}
+
+template <class T>
+static uint8_t recon_gauss(const orc_params& P, const T Q[5], T out[4]) {
+  if (P.scheme != 0) return scheme_gauss(P, Q, out);
+  const uint8_t f = select_T(Q, P.ct1_tan, P.ct2_tan, P.eps, P.q);
+  teno_gauss_values(Q, f, out);
+  return f;
 }
 
 // ---------------------------------------------------------------------------
@@ -495,7 +722,7 @@ static inline bool state_ok(double rho, double p) {
 template <class T>
 static int gp_flux(const orc_params& P, int D, const T* Wl, const T* Wr, const T dWl[3][5],
                    const T dWr[3][5], double dt, int ndelta, const double* delta, T F[][5],
-                   T* W0out, T dW0out[3][5]) {
+                   T* W0out, T dW0out[3][5], const T* W0in = nullptr, const T (*dW0in)[5] = nullptr) {
   const int nc = D + 2;
   const double K = 2.0 / (P.gamma - 1.0) - D;
   int bad = 0;
@@ -509,9 +736,10 @@ static int gp_flux(const orc_params& P, int D, const T* Wl, const T* Wr, const T
   Poly<T> ps[5];
   for (int a = 0; a < nc; ++a) ps[a] = psi<T>(D, a);
 
-  // Equilibrium state by kinetic weighting (Eq. 2.6 / 3.25).
+  // Equilibrium state by kinetic weighting (Eq. 2.6 / 3.25), or given
+  // (separately reconstructed, Sec. 3.1)
   T W0[5];
-  for (int a = 0; a < nc; ++a) W0[a] = hl.rho * hl.mom(ps[a]) + hr.rho * hr.mom(ps[a]);
+  for (int a = 0; a < nc; ++a) W0[a] = W0in ? W0in[a] : hl.rho * hl.mom(ps[a]) + hr.rho * hr.mom(ps[a]);
 
   // Non-equilibrium micro slopes a^k_d: <a psi> = dW^k_d / rho_k (Eq. 2.7).
   T al[3][5], ar[3][5];
@@ -524,12 +752,13 @@ static int gp_flux(const orc_params& P, int D, const T* Wl, const T* Wr, const T
     solve_micro(fl, bl, al[d]);
     solve_micro(fr, br, ar[d]);
   }
-  // Equilibrium slopes by kinetic weighting (Eq. 2.6 lines 2-3 / 3.26).
+  // Equilibrium slopes by kinetic weighting (Eq. 2.6 lines 2-3 / 3.26), or
+  // given (Eq. 3.12 and its tangential reconstruction)
   T dW0[3][5];
   for (int d = 0; d < D; ++d) {
     const Poly<T> ml = micro(D, al[d]), mr = micro(D, ar[d]);
     for (int a = 0; a < nc; ++a)
-      dW0[d][a] = hl.rho * hl.mom(mul(ps[a], ml)) + hr.rho * hr.mom(mul(ps[a], mr));
+      dW0[d][a] = dW0in ? dW0in[d][a] : hl.rho * hl.mom(mul(ps[a], ml)) + hr.rho * hr.mom(mul(ps[a], mr));
   }
   if (W0out)
     for (int a = 0; a < nc; ++a) W0out[a] = W0[a];
@@ -650,6 +879,22 @@ static int gp_flux(const orc_params& P, int D, const T* Wl, const T* Wr, const T
   return bad;
 }
 
+// Equilibrium state of two reconstructed states by kinetic weighting
+// (Eq. 2.6): rho_l <psi>_{u>0} + rho_r <psi>_{u<0}, face frame.  Returns 1
+// when a state is non-physical.
+template <class T>
+static int kinetic_w0(const orc_params& P, int D, const T* Wl, const T* Wr, T* W0) {
+  const double K = 2.0 / (P.gamma - 1.0) - D;
+  Maxw<T> hl, hr;
+  hl.build(D, K, Wl, +1);
+  hr.build(D, K, Wr, -1);
+  for (int a = 0; a < D + 2; ++a) {
+    const Poly<T> pa = psi<T>(D, a);
+    W0[a] = hl.rho * hl.mom(pa) + hr.rho * hr.mom(pa);
+  }
+  return state_ok(val(hl.rho), val(hl.pressure())) && state_ok(val(hr.rho), val(hr.pressure())) ? 0 : 1;
+}
+
 // ---------------------------------------------------------------------------
 // Grid access with boundary conditions (ghost cells by an index map).
 // ---------------------------------------------------------------------------
@@ -729,9 +974,7 @@ static uint8_t normal_recon(const orc_params& P, const Grid& g, const T* W, int 
     j[d] += r;
     Q[r + 2] = cell(g, W, c, j);
   }
-  const uint8_t f = select_T(Q, P.ct1, P.ct2, P.eps, P.q);
-  teno_face_values(Q, f, out);
-  return f;
+  return recon_face(P, Q, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -946,6 +1189,9 @@ static long face_fluxes(const orc_params& P, const Grid& g, const T* W, int d, d
     const double wgp = 1.0 / (ngp1 * ngp2);
     // per Gauss point, per side: W, dW/dn, dW/dt1, dW/dt2 in frame order
     T Wg[2][2][2][5], Dg[2][2][2][3][5];
+    // WENO-Z / TENO5 (2-D): the line-averaged interface values of the five
+    // face segments of the tangential stencil, [side][row][frame component]
+    T Lrow[2][5][5];
     if (P.recon == 1) {
       if (D == 1) {
         T vl[5], sl[5], vr[5], sr[5];
@@ -1035,16 +1281,16 @@ static long face_fluxes(const orc_params& P, const Grid& g, const T* W, int d, d
             Wl[r + 2] = o[vo];
             Nl[r + 2] = o[vo + 1] * idn;
           }
-          const uint8_t fw = select_T(Wl, P.ct1_tan, P.ct2_tan, P.eps, P.q);
-          const uint8_t fn = select_T(Nl, P.ct1_tan, P.ct2_tan, P.eps, P.q);
+          T ow[4], on[4];
+          const uint8_t fw = recon_gauss(P, Wl, ow);
+          const uint8_t fn = recon_gauss(P, Nl, on);
           if (tflags) {
             // layout per direction: [(q*2 + side)*nc + c][face], q = 0 (W), 1 (W_n)
             tflags[(((long)0 * 2 + side) * nc + c) * nface + fidx] = fw;
             tflags[(((long)1 * 2 + side) * nc + c) * nface + fidx] = fn;
           }
-          T ow[4], on[4];
-          teno_gauss_values(Wl, fw, ow);
-          teno_gauss_values(Nl, fn, on);
+          if (P.scheme >= 2)
+            for (int r = 0; r < 5; ++r) Lrow[side][r][a] = Wl[r];
           for (int m = 0; m < 2; ++m) {
             Wg[m][0][side][a] = ow[2 * m];
             Dg[m][0][side][1][a] = ow[2 * m + 1] / dt1;
@@ -1070,12 +1316,20 @@ static long face_fluxes(const orc_params& P, const Grid& g, const T* W, int d, d
           for (int r2 = 0; r2 < 5; ++r2) {
             const uint8_t fw = select_T(Vw[r2], P.ct1_tan, P.ct2_tan, P.eps, P.q);
             const uint8_t fn = select_T(Vn[r2], P.ct1_tan, P.ct2_tan, P.eps, P.q);
+            if (tflags && r2 == 2) {
+              // sweep 1 of the face's own line: [(q*2 + side)*nc + c][face],
+              // q = 0 (W), 1 (W_n)
+              tflags[(((long)0 * 2 + side) * nc + c) * nface + fidx] = fw;
+              tflags[(((long)1 * 2 + side) * nc + c) * nface + fidx] = fn;
+            }
             T ow[4], on[4];
             teno_gauss_values(Vw[r2], fw, ow);
             teno_gauss_values(Vn[r2], fn, on);
             for (int m1 = 0; m1 < 2; ++m1) {
               S1w[m1][r2] = ow[2 * m1];
-              S1d[m1][r2] = ow[2 * m1 + 1] / dt1;
+              // scaled by the reciprocal width, like every slope that a
+              // later selection takes as input (one rounding order)
+              S1d[m1][r2] = ow[2 * m1 + 1] * (1.0 / dt1);
               S1n[m1][r2] = on[2 * m1];
             }
           }
@@ -1083,6 +1337,13 @@ static long face_fluxes(const orc_params& P, const Grid& g, const T* W, int d, d
             const uint8_t fw = select_T(S1w[m1], P.ct1_tan, P.ct2_tan, P.eps, P.q);
             const uint8_t fd = select_T(S1d[m1], P.ct1_tan, P.ct2_tan, P.eps, P.q);
             const uint8_t fn = select_T(S1n[m1], P.ct1_tan, P.ct2_tan, P.eps, P.q);
+            if (tflags) {
+              // sweep 2 at t1 Gauss point m1: [4 nc + ((m1*3 + kind)*2 + side)*nc
+              // + c][face], kind 0 (W), 1 (dW/dt1), 2 (W_n)
+              const uint8_t fk[3] = {fw, fd, fn};
+              for (int kind = 0; kind < 3; ++kind)
+                tflags[(4L * nc + ((long)(m1 * 3 + kind) * 2 + side) * nc + c) * nface + fidx] = fk[kind];
+            }
             T ow[4], od[4], on[4];
             teno_gauss_values(S1w[m1], fw, ow);
             teno_gauss_values(S1d[m1], fd, od);
@@ -1118,11 +1379,62 @@ static long face_fluxes(const orc_params& P, const Grid& g, const T* W, int d, d
             }
           }
     }
+    // WENO-Z / TENO5: the equilibrium state's slopes (and in 2-D its value)
+    // are reconstructed separately (Sec. 3.1): along the normal by the
+    // fifth-order linear formula of Eq. 3.12 on each face segment, whose
+    // equilibrium value is the kinetic weighting of its line-averaged
+    // interface values (Eq. 2.6); along the face by the linear quartic of
+    // the five segments (Steps 2 and 4), evaluated at the Gauss points
+    T E0[2][5], dE0[2][3][5];
+    const bool sep = P.scheme >= 2;
+    if (sep) {
+      const int nrow = D == 2 ? 5 : 1;
+      T W0row[5][5], W0xrow[5][5];
+      for (int r = 0; r < nrow; ++r) {
+        const int rr = D == 2 ? r - 2 : 0;
+        T Wl_[5], Wr_[5];
+        for (int a = 0; a < nc; ++a) {
+          Wl_[a] = D == 2 ? Lrow[0][r][a] : Wg[0][0][0][a];
+          Wr_[a] = D == 2 ? Lrow[1][r][a] : Wg[0][0][1][a];
+        }
+        nbad += kinetic_w0(P, D, Wl_, Wr_, W0row[r]);
+        for (int a = 0; a < nc; ++a) {
+          T q[4];
+          for (int k = 0; k < 4; ++k) {
+            long j[3] = {cl[0], cl[1], cl[2]};
+            j[d] += k - 1;
+            if (D == 2) j[t1] += rr;
+            q[k] = cell(g, W, perm[a], j);
+          }
+          // cells f-2, f-1, f, f+1 along the normal (Eq. 3.12)
+          W0xrow[r][a] = ((-1.0 / 12.0) * (q[3] - q[0]) + 1.25 * (q[2] - q[1])) * idn;
+        }
+      }
+      for (int m = 0; m < ngp1; ++m)
+        for (int a = 0; a < nc; ++a) {
+          if (D == 1) {
+            E0[m][a] = W0row[0][a];
+            dE0[m][0][a] = W0xrow[0][a];
+            continue;
+          }
+          T Qv[5], Qx[5], ov[4], ox[4];
+          for (int r = 0; r < 5; ++r) {
+            Qv[r] = W0row[r][a];
+            Qx[r] = W0xrow[r][a];
+          }
+          teno_gauss_values(Qv, 1, ov);  // flag 1: the quartic on all five segments
+          teno_gauss_values(Qx, 1, ox);
+          E0[m][a] = ov[2 * m];
+          dE0[m][1][a] = ov[2 * m + 1] / dt1;
+          dE0[m][0][a] = ox[2 * m];
+        }
+    }
     for (int m1 = 0; m1 < ngp1; ++m1)
       for (int m2 = 0; m2 < ngp2; ++m2) {
         T F[2][5];
         nbad += gp_flux(P, D, Wg[m1][m2][0], Wg[m1][m2][1], Dg[m1][m2][0], Dg[m1][m2][1], dt, 2,
-                        deltas, F, (T*)nullptr, (T(*)[5]) nullptr);
+                        deltas, F, (T*)nullptr, (T(*)[5]) nullptr, sep && D == 2 ? E0[m1] : (const T*)nullptr,
+                        sep ? dE0[m1] : (const T(*)[5]) nullptr);
         for (int i = 0; i < 2; ++i)
           for (int a = 0; a < nc; ++a) acc[i][a] += wgp * F[i][a];
       }
@@ -1159,15 +1471,16 @@ static long s2o4_step(const orc_params& P, const T* Wn, T* Wout, double dt, uint
   const long N = g.ncell;
   long nbad = 0;
   std::vector<T> Fdt[3], Fh[3], Gdt[3], Gh[3];
-  // flag layout: normal [D][nc][cells], then (2-D) tangential per direction
+  // flag layout: normal [D][nc][cells], then tangential per direction
+  // (2-D: 4 nc planes of faces; 3-D: 4 nc of sweep 1 and 12 nc of sweep 2)
   uint8_t* tfl[3] = {nullptr, nullptr, nullptr};
-  if (flags && D == 2) {
+  if (flags && D >= 2) {
     long off = (long)D * nc * N;
     for (int d = 0; d < D; ++d) {
       long nf[3] = {g.n[0], g.n[1], g.n[2]};
       nf[d] += 1;
       tfl[d] = flags + off;
-      off += 4L * nc * nf[0] * nf[1] * nf[2];
+      off += (D == 2 ? 4L : 16L) * nc * nf[0] * nf[1] * nf[2];
     }
   }
   for (int d = 0; d < D; ++d) nbad += face_fluxes(P, g, Wn, d, dt, Fdt[d], Fh[d], flags, tfl[d], nfallback);
@@ -1275,6 +1588,13 @@ static int check_params(const orc_params* P) {
   if (!(P->gamma > 1.0)) return -1;
   if (P->recon < 0 || P->recon > 1 || (P->recon == 1 && P->ndim > 2)) return -1;
   if (P->fallback < 0 || P->fallback > 1) return -1;
+  if (P->scheme < 0 || P->scheme > 3) return -1;
+  if (P->scheme != 0) {
+    // the comparison schemes: conservative variables on 1-D and 2-D grids
+    if (P->ndim > 2 || P->recon != 0 || P->fallback != 0) return -1;
+    if (P->scheme == 1 && !(P->d_hi > 0.0 && P->d_hi < 1.0 && P->d_lo > 0.0 && P->d_lo < 1.0)) return -1;
+    if ((P->scheme == 1 || P->scheme == 3) && !(P->eps_w > 0.0)) return -1;
+  }
   return 0;
 }
 
@@ -1314,6 +1634,21 @@ int orc_teno_gauss(const double* Q, double ct1, double ct2, double eps, int q, d
   const uint8_t f = teno_select(Q, ct1, ct2, eps, q);
   teno_gauss_values(Q, f, out);
   return f;
+}
+
+// Reconstruction of the configured scheme (P->scheme) from five values:
+// gauss = 0: {v(-1/2), s(-1/2), v(+1/2), s(+1/2)}, gauss = 1: {v(s-), d(s-),
+// v(s+), d(s+)} in cell units; returns the flags (TENO-D, TENO5) or 0.
+int orc_recon(const orc_params* P, const double* Q, int gauss, double* out) {
+  if (check_params(P)) return -1;
+  return gauss ? recon_gauss(*P, Q, out) : recon_face(*P, Q, out);
+}
+
+// Linear weights of p_0..p_2 at x = -1/2, +1/2, s-, s+ (where = 0..3).
+int orc_lin_weights(int where, double* d) {
+  if (where < 0 || where > 3) return -1;
+  lin_weights(where, d);
+  return 0;
 }
 
 // The same with a caller-forced flag (for exactness tests of each candidate).
@@ -1400,8 +1735,6 @@ int orc_gp_flux_dual(const orc_params* P, const double* Wl, const double* Wr, co
   return bad;
 }
 
-// Number of bytes of the flag buffer of one step (normal flags, then for
-// 2-D the tangential flags of both directions).
 // Characteristic basis along frame axis a at the frame-ordered state Wb:
 // L (rows) and R (columns), row-major nc x nc.  Returns 1 for a physical
 // state, 0 when the identity was returned.
@@ -1436,15 +1769,19 @@ int orc_char_recon(const orc_params* P, const double* C, double dx, double* out,
   return 0;
 }
 
+// Number of bytes of the flag buffer of one step: the normal flags, then the
+// tangential flags of every direction (2-D: [W, W_n][side][nc][faces]; 3-D:
+// sweep 1 of each face's own line as in 2-D, then sweep 2 as
+// [t1 Gauss point][W, dW/dt1, W_n][side][nc][faces]).
 long orc_flag_bytes(const orc_params* P) {
   if (check_params(P)) return -1;
   const Grid g(*P);
   long nb = (long)g.D * g.nc * g.ncell;
-  if (g.D == 2)
-    for (int d = 0; d < 2; ++d) {
+  if (g.D >= 2)
+    for (int d = 0; d < g.D; ++d) {
       long nf[3] = {g.n[0], g.n[1], g.n[2]};
       nf[d] += 1;
-      nb += 4L * g.nc * nf[0] * nf[1] * nf[2];
+      nb += (g.D == 2 ? 4L : 16L) * g.nc * nf[0] * nf[1] * nf[2];
     }
   return nb;
 }
@@ -1465,7 +1802,9 @@ long orc_step(const orc_params* P, const double* W, double* Wout, double dt, uin
 // Same step carrying one tangent direction (forward mode).
 long orc_step_dual(const orc_params* P, const double* W, const double* dW, double* Wout,
                    double* dWout, double dt) {
-  if (check_params(P) || !(dt > 0)) return -1;
+  // forward-mode derivatives of TENO-D steps only (the comparison schemes'
+  // nonlinear weights are evaluated on plain values)
+  if (check_params(P) || !(dt > 0) || P->scheme != 0) return -1;
   const Grid g(*P);
   const size_t n = (size_t)g.nc * g.ncell;
   std::vector<Dual> a(n), b(n);

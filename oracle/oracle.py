@@ -30,7 +30,11 @@ class OrcParams(C.Structure):
         ("eps", C.c_double), ("q", C.c_int), ("recon", C.c_int),
         ("bc_state", (C.c_double * 5) * 2), ("bc_line", ((C.c_double * 3) * 2) * 3),
         ("bc_far", (C.c_int * 2) * 3), ("fallback", C.c_int),
+        ("scheme", C.c_int), ("d_hi", C.c_double), ("d_lo", C.c_double), ("eps_w", C.c_double),
     ]
+
+
+SCHEME = {"teno_d": 0, "weno_ao": 1, "teno5": 2, "weno_z": 3}
 
 
 _lib = None
@@ -52,6 +56,8 @@ def lib():
         L.orc_teno_face.argtypes = [dp, C.c_double, C.c_double, C.c_double, C.c_int, dp]
         L.orc_teno_gauss.argtypes = [dp, C.c_double, C.c_double, C.c_double, C.c_int, dp]
         L.orc_teno_eval.argtypes = [dp, C.c_int, C.c_int, dp]
+        L.orc_recon.argtypes = [P, dp, C.c_int, dp]
+        L.orc_lin_weights.argtypes = [C.c_int, dp]
         L.orc_moments.argtypes = [C.c_double, C.c_double, C.c_int, dp]
         L.orc_micro_slope.argtypes = [C.c_int, C.c_double, dp, dp, dp]
         L.orc_moment_mono.argtypes = [C.c_int, C.c_double, dp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]
@@ -80,8 +86,9 @@ def set_threads(n: int) -> int:
 
 
 def make_params(shape, dx, bc="transmissive", gamma=1.4, mu=0.0, prandtl=1.0, tau="inviscid",
-                c1=0.01, c2=1.0, ct1=1e-7, ct2=1e-5, ct1_tan=None, ct2_tan=None, eps=1e-40, q=7,
-                recon=0, states=None, lines=None, far=None, fallback=0):
+                c1=0.01, c2=1.0, ct1=1e-7, ct2=1e-5, ct1_tan=None, ct2_tan=None, eps=1e-40, q=None,
+                recon=0, states=None, lines=None, far=None, fallback=0, scheme="teno_d", d_hi=0.85,
+                d_lo=0.85, eps_w=1e-8):
     """shape: cells per axis (x, y, z) truncated to D; bc: one name or a list of
     (lo, hi) names per axis; recon: 0 conservative, 1 characteristic variables
     (1-D, 2-D).  Prescribed sides ("prescribed", 1-D and 2-D): states = (A, B)
@@ -89,7 +96,11 @@ def make_params(shape, dx, bc="transmissive", gamma=1.4, mu=0.0, prandtl=1.0, ta
     {(axis, end): "transmissive" | "reflective" | "state_b"}: the ghost cell
     centred at (s, r) holds A where s < (s0 + s_n r) + s_t t, else what far
     gives.  fallback = 1: first-order fallback at non-physical Gauss-point
-    states (1-D, 2-D; not in the paper)."""
+    states (1-D, 2-D; not in the paper).  scheme: "teno_d" (Sec. 4.2, the
+    default), or one of the paper's comparison schemes on 1-D and 2-D grids
+    with conservative variables: "weno_ao" (Sec. 3.2; linear weights d_hi,
+    d_lo, epsilon eps_w), "teno5" (Sec. 4.1; C_T = ct1, epsilon eps, q = 6
+    unless given), "weno_z" (Sec. 3.1; epsilon eps_w)."""
     p = OrcParams()
     D = len(shape)
     p.ndim = D
@@ -108,7 +119,10 @@ def make_params(shape, dx, bc="transmissive", gamma=1.4, mu=0.0, prandtl=1.0, ta
     p.ct1, p.ct2 = ct1, ct2
     p.ct1_tan = ct1 if ct1_tan is None else ct1_tan
     p.ct2_tan = ct2 if ct2_tan is None else ct2_tan
-    p.eps, p.q = eps, q
+    p.scheme = SCHEME[scheme] if isinstance(scheme, str) else int(scheme)
+    # q: 7 for TENO-D (Sec. 4.2), 6 for TENO5 (Sec. 4.1)
+    p.eps, p.q = eps, (6 if p.scheme == 2 else 7) if q is None else q
+    p.d_hi, p.d_lo, p.eps_w = d_hi, d_lo, eps_w
     p.recon = int(recon)
     p.fallback = int(fallback)
     if states is not None:
@@ -146,6 +160,24 @@ def teno_eval(Q, flag, gauss=False):
     out = np.zeros(4)
     lib().orc_teno_eval(_arr(Q), int(flag), int(bool(gauss)), out)
     return out
+
+
+def recon(params, Q, gauss=False):
+    """Reconstruction of params' scheme from five values: (out, flags) with
+    out = {v(-1/2), s(-1/2), v(+1/2), s(+1/2)} or, gauss=True, the values and
+    derivatives at the Gauss points -+1/(2 sqrt 3) (cell units)."""
+    out = np.zeros(4)
+    f = lib().orc_recon(C.byref(params), _arr(Q), int(bool(gauss)), out)
+    if f < 0:
+        raise ValueError("invalid parameters")
+    return out, f
+
+
+def lin_weights(where):
+    """Linear weights of the three quadratics at x = -1/2, +1/2, s-, s+."""
+    d = np.zeros(3)
+    lib().orc_lin_weights(int(where), d)
+    return d
 
 
 def teno_select(Q, ct1=1e-7, ct2=1e-5, eps=1e-40, q=7):

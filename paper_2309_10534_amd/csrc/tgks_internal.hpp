@@ -192,6 +192,14 @@ inline StageArgs stage_args(tgks_ctx* c, const double* W, int ax, const double* 
 int launch_face2d_any(tgks_ctx* c, const StageArgs& a, int ax, int stage, bool fl);
 int launch_face2d_xy_any(tgks_ctx* c, const StageArgs& ax, const StageArgs& ay, int stage, bool fl);
 
+// 3-D normal reconstruction and face kernels of direction AX (tgks_face3d_*.hip)
+template <int AX>
+int launch_face3d_ax(tgks_ctx* c, const StageArgs& a, int stage, bool fl);
+
+// host-side description of a grid without device memory (tgks_capi.hip)
+void init_ctx_host(tgks_ctx* c, const tgks_params* p, void* stream);
+
 // forward pieces of one step (tgks_capi.hip)
+int do_step(tgks_ctx* c, const double* W, double* out, const double* dt, uint8_t* flags, bool cfl);
 int launch_faces(tgks_ctx* c, const double* W, const double* dt, int stage, uint8_t* flags);
 int launch_update(tgks_ctx* c, int stage, const double* W, double* o1, double* o2, const double* dt, bool cfl);

@@ -663,9 +663,14 @@ __global__ __launch_bounds__(256) void recon3d_kernel(StageArgs a) {
 //     both lanes evaluate the equilibrium part (flux_combine).  One side per
 //     lane keeps the flux within the register budget of two waves per SIMD.
 // Tiles are dealt to the 8 XCDs in contiguous ranges.
+// FLAGS: record the tangential selections (stage 1), per face of this
+// direction: sweep 1 of the face's own line as [(q*2 + side)*5 + c] (q = 0:
+// W, 1: W_n), then sweep 2 as [20 + ((m1*3 + kind)*2 + side)*5 + c] (kind 0:
+// W, 1: dW/dt1, 2: W_n at T1 Gauss point m1), c the global component, each a
+// plane of faces indexed like a state whose axis AX has n + 1 entries.
 constexpr int B3_1 = 2, B3_2 = 16, L3 = 8;
 
-template <int AX, int STAGE, bool NS, bool EX = false>
+template <int AX, int STAGE, bool NS, bool EX = false, bool FLAGS = false>
 __global__ __launch_bounds__(L3 * B3_1 * B3_2, 2) void face3d_kernel(StageArgs a) {
   constexpr int NC = 5, B1 = B3_1, B2 = B3_2, NT = L3 * B1 * B2;
   constexpr int L1 = B1 + 4, L2 = B2 + 4;
@@ -714,6 +719,9 @@ __global__ __launch_bounds__(L3 * B3_1 * B3_2, 2) void face3d_kernel(StageArgs a
 
   // 2. sweep 1 along T1 of every face line of the tile and its T2 halo
   const double i1d = 1.0 / g.dx[T1], i2d = 1.0 / g.dx[T2];
+  int nfa[3] = {g.n[0], g.n[1], g.n[2]};
+  nfa[AX] += 1;
+  const long long nf = (long long)nfa[0] * nfa[1] * nfa[2];
   for (int L = tid; L < 2 * NC * L2 * B1; L += NT) {
     const int j1 = L % B1;
     const int i2 = (L / B1) % L2;
@@ -726,8 +734,20 @@ __global__ __launch_bounds__(L3 * B3_1 * B3_2, 2) void face3d_kernel(StageArgs a
       Qn[r] = sR[s][c][1][i2][j1 + r];
     }
     double v[2], dv[2], vn[2], dvn[2];
-    teno_gauss(Qw, teno_flag(Qw, a.tt), v, dv);
-    teno_gauss(Qn, teno_flag(Qn, a.tt), vn, dvn);
+    const unsigned fw = teno_flag(Qw, a.tt), fq = teno_flag(Qn, a.tt);
+    teno_gauss(Qw, fw, v, dv);
+    teno_gauss(Qn, fq, vn, dvn);
+    if (FLAGS && i2 >= 2 && i2 < B2 + 2) {
+      int q3[3];
+      q3[AX] = fa;
+      q3[T1] = t10 + j1;
+      q3[T2] = t20 + i2 - 2;
+      if (q3[T1] < g.n[T1] && q3[T2] < g.n[T2]) {
+        const long long fid = ((long long)q3[2] * nfa[1] + q3[1]) * nfa[0] + q3[0];
+        a.tflags[((long long)(0 * 2 + s) * NC + c) * nf + fid] = (uint8_t)fw;
+        a.tflags[((long long)(1 * 2 + s) * NC + c) * nf + fid] = (uint8_t)fq;
+      }
+    }
     double* o = sS[s][c][i2][j1];
     o[0] = v[0];
     o[1] = v[1];
@@ -749,6 +769,7 @@ __global__ __launch_bounds__(L3 * B3_1 * B3_2, 2) void face3d_kernel(StageArgs a
   fp[T1] = t10 + j1;
   fp[T2] = t20 + j2;
   const bool live = fp[T1] < g.n[T1] && fp[T2] < g.n[T2];
+  const long long fid = ((long long)fp[2] * nfa[1] + fp[1]) * nfa[0] + fp[0];
   const int perm[NC] = {0, 1 + AX, 1 + T1, 1 + T2, 4};
   double item[15], item_d[15];  // at this lane's T2 point: value, T2 derivative (cell units)
 #pragma unroll
@@ -761,7 +782,9 @@ __global__ __launch_bounds__(L3 * B3_1 * B3_2, 2) void face3d_kernel(StageArgs a
       double Q[5];
 #pragma unroll
       for (int k = 0; k < 5; ++k) Q[k] = sS[m2][c][j2 + k][j1][2 * kind + m1];
-      teno_gauss(Q, teno_flag(Q, a.tt), v, d);
+      const unsigned fl = teno_flag(Q, a.tt);
+      teno_gauss(Q, fl, v, d);
+      if (FLAGS) a.tflags[((long long)4 * NC + ((m1 * 3 + kind) * 2 + m2) * NC + c) * nf + fid] = (uint8_t)fl;
     }
     const double own = m3 ? v[1] : v[0], own_d = m3 ? d[1] : d[0];
     const double rcv = lane_xor<2>(m3 ? v[0] : v[1]), rcv_d = lane_xor<2>(m3 ? d[0] : d[1]);
@@ -851,10 +874,6 @@ __global__ __launch_bounds__(L3 * B3_1 * B3_2, 2) void face3d_kernel(StageArgs a
   }
   wall_fluxes<NC>(g, AX, fa, A, B);
   if (live && (tid & 7) == 0) {
-    int nfa[3] = {g.n[0], g.n[1], g.n[2]};
-    nfa[AX] += 1;
-    const long long nf = (long long)nfa[0] * nfa[1] * nfa[2];
-    const long long fid = ((long long)fp[2] * nfa[1] + fp[1]) * nfa[0] + fp[0];
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
       a.FA[(long long)perm[q] * nf + fid] = A[q];

@@ -4,6 +4,12 @@ from its own parameter structure built from one plain dict."""
 import numpy as np
 
 TOL_L1 = 1e-10  # L1-relative tolerance per component (GPU vs oracle, FP64)
+# Per cell and component, on identical input: the device and the oracle
+# differ by the rounding of their transcendental functions and fused
+# products (a few ulps of each Gauss-point flux), which a step scales by
+# dt / dx < 1; 1e-12 of the cell's own magnitude leaves three orders of
+# magnitude for the sums of a step and no room for one wrong cell.
+TOL_CELL = 1e-12
 
 
 def problem(shape, dx, bc="transmissive", tau="inviscid", mu=0.0, prandtl=1.0, **kw):
@@ -86,10 +92,39 @@ def l1rel(a, b):
     return np.abs(a2 - b2).sum(axis=1) / np.maximum(np.abs(b2).sum(axis=1), 1e-300)
 
 
-def assert_close(a, b, tol=TOL_L1, what=""):
+def cell_scale(b):
+    """Magnitude of each cell's components: |b|, momenta at least
+    sqrt(rho E) (a momentum that vanishes, as across a uniform direction or
+    at rest, has no scale of its own)."""
+    D = b.shape[0] - 2
+    s = np.abs(b)
+    ref = np.sqrt(np.abs(b[0] * b[D + 1]))
+    for c in range(1, D + 1):
+        s[c] = np.maximum(s[c], ref)
+    return np.maximum(s, 1e-300)
+
+
+def assert_cells(a, b, tol=TOL_CELL, what=""):
+    """Element-wise bound: every component of every cell within tol of its
+    own magnitude."""
+    assert np.all(np.isfinite(a)), f"{what}: non-finite GPU values"
+    e = np.abs(a - b) / cell_scale(b)
+    k = int(np.argmax(e))
+    worst = float(e.reshape(-1)[k])
+    assert worst <= tol, f"{what}: cell difference {worst:.3e} > {tol} at {np.unravel_index(k, e.shape)}"
+    return worst
+
+
+def assert_close(a, b, tol=TOL_L1, what="", cell_tol=None):
+    """L1-relative bound per component and, for parity on identical input
+    (tol <= 1e-10), the element-wise bound of assert_cells."""
     e = l1rel(a, b)
     assert np.all(np.isfinite(a)), f"{what}: non-finite GPU values"
     assert np.all(e <= tol), f"{what}: L1-relative difference {e} > {tol}"
+    if cell_tol is None and tol <= TOL_L1:
+        cell_tol = TOL_CELL
+    if cell_tol is not None:
+        assert_cells(a, b, cell_tol, what)
     return e
 
 
@@ -105,3 +140,5 @@ def close_scaled(a, b, tol, what):
             scale = max(scale, np.abs(b[0]).sum())
         e = np.abs(a[c] - b[c]).sum() / scale
         assert e <= tol, f"{what}: component {c} L1 difference {e} > {tol}"
+    if tol <= TOL_L1:
+        assert_cells(a, b, TOL_CELL, what)

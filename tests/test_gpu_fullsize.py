@@ -11,7 +11,7 @@ boundary."""
 import numpy as np
 import pytest
 
-from gpu_common import GpuProblem, close_scaled, l1rel, orc_params, problem
+from gpu_common import GpuProblem, assert_cells, assert_close, close_scaled, orc_params, problem
 from paper_2309_10534_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
@@ -96,6 +96,92 @@ def test_2d_riemann_1024(orc, torch_dev):
     assert np.all(np.isfinite(Wg))
 
 
+@pytest.mark.timeout(900)
+def test_2d_riemann_1024_headline_prefix(orc, torch_dev):
+    """The headline workload exactly as the bench runs it (1024^2
+    four-quadrant Riemann problem, seed 1, conservative variables, CFL 0.5,
+    device dt, graph-captured tgks_run) over the ten-step prefix: at every
+    step the oracle's full-grid step, applied to the device's own state with
+    the device's dt, reproduces the device's next state (W*, W^{n+1}: 1e-10
+    L1-relative and 1e-12 per cell) with every selection flag bit for bit,
+    and the device's next dt equals the oracle's CFL step of that state."""
+    n = 1024
+    W0, dx, _ = I.quadrant_riemann(n, seed=1)
+    pr = problem([n, n], [dx, dx])
+    P = orc_params(orc, pr)
+    gp = GpuProblem(pr)
+    try:
+        W = W0
+        dt = gp.cfl_dt(W, 0.5)
+        assert abs(dt - orc.cfl_dt(P, W, 0.5)) <= 1e-15 * dt
+        for k in range(10):
+            print(f"[fullsize] headline prefix step {k} dt={dt:.9e}", flush=True)
+            Wr, td, badr = gp.run(W, 1, cfl=0.5, use_graph=True)
+            Wg, Wsg, fg, badg = gp.step(W, dt, flags=True)
+            assert badr == badg == 0 and abs(td[0] - dt) <= 1e-15 * dt
+            assert np.array_equal(Wr, Wg), "tgks_run and tgks_step differ"
+            Wo, fo, Wso, bado = orc.step(P, W, dt, want_flags=True, want_wstar=True)
+            assert bado == 0
+            mism = np.flatnonzero(fg != fo)
+            assert mism.size == 0, f"step {k}: {mism.size} flag mismatches, first at {mism[:10]}"
+            assert_close(Wsg, Wso, 1e-10, f"W* step {k}")
+            assert_close(Wg, Wo, 1e-10, f"W^(n+1) step {k}")
+            dtn = orc.cfl_dt(P, Wg, 0.5)
+            assert abs(td[1] - dtn) <= 1e-15 * dtn, (k, td[1], dtn)
+            W, dt = Wg, td[1]
+    finally:
+        gp.close()
+
+
+def check_patches(orc, pr, W, Wg, dt, centers, inner=2):
+    """Every cell within `inner` of each patch centre against the oracle's
+    step of the (2R+1)^3 patch around it: cells within R - 6 of the centre
+    depend only on cells inside the patch."""
+    assert inner <= R - 6
+    nchk = 0
+    for c in centers:
+        sub, Ws, off = patch_problem(pr, W, c, R)
+        Wo, _, _, bado = orc.step(orc_params(orc, sub), Ws, dt)
+        assert bado == 0
+        for dz in range(-inner, inner + 1):
+            for dy in range(-inner, inner + 1):
+                for dxx in range(-inner, inner + 1):
+                    d3 = (dxx, dy, dz)
+                    g = tuple((c[a] + d3[a]) % pr["shape"][a] for a in range(3))
+                    o = tuple(off[a] + d3[a] for a in range(3))
+                    got = Wg[(slice(None),) + tuple(reversed(g))][:, None]
+                    want = Wo[(slice(None),) + tuple(reversed(o))][:, None]
+                    assert_cells(got, want, 1e-12, f"cell {g} (patch {c})")
+                    nchk += 1
+        print(f"[fullsize] patch {c}: {(2 * inner + 1) ** 3} cells within 1e-12", flush=True)
+    return nchk
+
+
+def test_3d_taylor_green_128_tile_seams(orc, torch_dev):
+    """The 3-D benchmark step (128^3 Taylor-Green vortex, Navier-Stokes,
+    tgks_run) on the seams of the face kernel's tiles: the kernel tiles the
+    faces of each direction in 2 x 16 blocks along its two tangential axes
+    (x-faces: y, z; y-faces: z, x; z-faces: x, y), so seams lie at every
+    multiple of 16 along each axis (and every other cell along the short
+    side).  Eight patches centred on intersections of 16-seams (including
+    the periodic wrap at 0 / 127) check every cell within two of the
+    centre: 1,000 cells, each against the oracle's patch step."""
+    n = 128
+    W, dx = I.taylor_green_3d(n, m=2)
+    pr = problem([n, n, n], [dx] * 3, bc="periodic", tau="viscous", mu=1 / 1600, prandtl=0.72)
+    gp = GpuProblem(pr)
+    try:
+        dt = gp.cfl_dt(W, 0.4)
+        print(f"[fullsize] 3-D tile seams dt={dt:.6e}", flush=True)
+        Wg, td, bad = gp.run(W, 1, cfl=0.4)
+    finally:
+        gp.close()
+    assert bad == 0 and abs(td[0] - dt) <= 1e-15 * dt
+    centers = [(16, 16, 16), (0, 32, 48), (127, 64, 16), (48, 0, 127), (80, 112, 64), (64, 127, 0),
+               (31, 95, 111), (112, 48, 80)]
+    assert check_patches(orc, pr, W, Wg, dt, centers) == 1000
+
+
 def test_3d_taylor_green_128(orc, torch_dev):
     n = 128
     W, dx = I.taylor_green_3d(n, m=2)
@@ -177,10 +263,10 @@ def test_2d_riemann_1024_whole_grid(orc, torch_dev, recon):
     assert badg == bado == badr == 0
     mism = np.flatnonzero(fg != fo)
     assert mism.size == 0, f"{mism.size} flag mismatches, first at {mism[:10]}"
-    assert np.all(l1rel(Wsg, Wso) <= 1e-10), l1rel(Wsg, Wso)
-    assert np.all(l1rel(Wg, Wo) <= 1e-10), l1rel(Wg, Wo)
+    assert_close(Wsg, Wso, 1e-10, "W*")
+    assert_close(Wg, Wo, 1e-10, "W^(n+1)")
     assert abs(td[0] - dt) <= 1e-15 * dt
-    assert np.all(l1rel(Wr, Wo) <= 1e-10), l1rel(Wr, Wo)
+    assert_close(Wr, Wo, 1e-10, "tgks_run")
 
 
 @pytest.mark.parametrize("recon", [0, 1])
