@@ -76,7 +76,9 @@ def parse():
     ap.add_argument("--seed", type=int, default=1,
                     help="quadrant-state seed; 1 is the first seed whose run is failure-free "
                          "(seed 0 reaches negative pressure: the scheme has no positivity limiter)")
+    ap.add_argument("--reps", type=int, default=5, help="timed runs of the headline (median reported)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-schemes", action="store_true", help="skip the comparison-scheme workloads")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched 1-D/2-D Riemann sets")
     ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--batch-instances", type=int, default=256)
@@ -94,14 +96,20 @@ def parse():
 
 
 def cpu_baseline(W0, dx, n, target_s):
-    """The oracle, as it is, on a bounded sample: one S2O4 step on a strip of
-    rows of the same field (the strip's own transmissive boundaries), all host
-    threads."""
+    """The oracle, as it is, built on this host with -O3 -march=native
+    -ffp-contract=off, timed on bounded samples of the same workload: one
+    S2O4 step on a strip of rows of the same initial field (the strip's own
+    transmissive boundaries), once on one thread and once on every host
+    thread, each strip sized to about target_s seconds."""
+    import tempfile
+
     import numpy as np
 
+    from oracle import build as OB
     from oracle import oracle as O
-    threads = O.set_threads(os.cpu_count() or 1)
-    # calibrate on 8 rows, then size the strip to about target_s
+    tmp = tempfile.mkdtemp(prefix="tgks_oracle_")
+    O.use_library(OB.build(native=True, out=os.path.join(tmp, "liboracle_native.so")))
+
     def run(rows):
         Ws = np.ascontiguousarray(W0[:, n // 2 - rows // 2:n // 2 - rows // 2 + rows, :])
         P = O.make_params([n, rows], [dx, dx])
@@ -109,13 +117,23 @@ def cpu_baseline(W0, dx, n, target_s):
         t0 = time.perf_counter()
         O.step(P, Ws, dt)
         return time.perf_counter() - t0
-    t8 = run(8)
-    rows = int(max(8, min(n, 8 * target_s / max(t8, 1e-3))))
-    el = run(rows)
-    cells = n * rows
-    return {"value": cells / el / 1e6, "unit": "Mcell-updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"one S2O4 step on a {n}x{rows} strip (rows {n // 2 - rows // 2}..{n // 2 - rows // 2 + rows - 1}) "
-                      f"of the same initial field, {el:.1f} s"}
+
+    def sample(threads):
+        used = O.set_threads(threads)
+        t4 = run(4)  # calibration
+        rows = int(max(4, min(n, 4 * target_s / max(t4, 1e-3))))
+        el = run(rows)
+        return {"value": round(n * rows / el / 1e6, 5), "threads": used, "cells": n * rows, "seconds": round(el, 2),
+                "rows": f"{n // 2 - rows // 2}..{n // 2 - rows // 2 + rows - 1}"}
+
+    one = sample(1)
+    allc = sample(os.cpu_count() or 1)
+    return {"value": allc["value"], "unit": "Mcell-updates/s", "cores": allc["threads"], "kind": "oracle",
+            "sample": f"one S2O4 step on a {n}x(strip) of the same initial field: rows {allc['rows']} on "
+                      f"{allc['threads']} threads ({allc['seconds']} s), rows {one['rows']} on one thread "
+                      f"({one['seconds']} s)",
+            "single_thread": one, "all_threads": allc,
+            "build": "g++ -O3 -march=native -ffp-contract=off -fopenmp (oracle/build.py, native=True)"}
 
 
 def batched(dim, seed, n_inst, steps, ranges=None, recon=0, fallback=0):
@@ -565,6 +583,61 @@ def adjoint(n=512, steps=200, every=20, fd_dirs=range(10, 15)):
     }
 
 
+def schemes(n=1024, seed=1, steps=100, warmup=3):
+    """The paper's four schemes on the headline workload (1024^2 four-quadrant
+    Riemann problem, seed 1, CFL 0.5): TENO-D GKS (the paper's), WENO5-AO
+    GKS, TENO5 GKS and WENO5-Z GKS, `steps` steps each from t = 0.
+    Throughput, face-kernel time per launch and its fraction of the FP64
+    peak (the library's algorithmic operation count of each scheme); TENO5
+    and WENO-Z pay for the separate reconstruction of the equilibrium state
+    that TENO-D and WENO-AO avoid (the efficiency claim of the abstract and
+    Sec. 3.2)."""
+    import torch
+
+    from paper_2309_10534_amd import inputs as I
+    from paper_2309_10534_amd import tgks
+
+    W0, dx, _ = I.quadrant_riemann(n, seed=seed)
+    W0d = torch.from_numpy(W0).cuda()
+    out = {"workload": f"2d_euler_four_quadrant_riemann_{n}x{n}_seed{seed}_{steps}_steps"}
+    for name in ("teno_d", "weno_ao", "teno5", "weno_z"):
+        p = tgks.tgks_params_default(2, [n, n], [dx, dx], scheme=name)
+        ctx = tgks.tgks_create(p)
+        if name == "teno_d":
+            tgks.tgks_set_tile(ctx, 2)  # the tile shape the comparison schemes use
+        W = W0d.clone()
+        tgks.tgks_run(ctx, W, warmup, cfl=0.5)
+        W.copy_(W0d)
+        tgks.tgks_reset_status(ctx)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tgks.tgks_run(ctx, W, steps, cfl=0.5)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        W.copy_(W0d)
+        tgks.tgks_timing(ctx, True)
+        tgks.tgks_run(ctx, W, steps, cfl=0.5)
+        torch.cuda.synchronize()
+        ms, launches = tgks.tgks_kernel_time(ctx, "face_x")
+        tgks.tgks_timing(ctx, False)
+        fails = tgks.tgks_status(ctx)
+        flops = tgks.tgks_flop_counts(p)
+        tgks.tgks_destroy(ctx)
+        nface = 2 * (n + 1) * n
+        per_launch = nface * 0.5 * (flops["face"] + flops["face_stage2"]) + 2 * n * n * 4 * flops["normal"]
+        avg = ms / max(launches, 1)
+        ach = per_launch / (avg / 1e3) / 1e12
+        out[name] = {"value": round(n * n * steps / el / 1e6, 3), "unit": "Mcell-updates/s",
+                     "ms_per_step": round(el * 1e3 / steps, 4), "failures": fails,
+                     "face_kernel_ms": round(avg, 4), "flops_per_face": flops["face"],
+                     "flops_normal": flops["normal"], "achieved_tflops": round(ach, 3),
+                     "frac": round(ach / FP64_PEAK_TFLOPS, 4)}
+    base = out["teno_d"]["ms_per_step"]
+    for name in ("weno_ao", "teno5", "weno_z"):
+        out[name]["cost_vs_teno_d"] = round(out[name]["ms_per_step"] / base, 3)
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -593,14 +666,24 @@ def main():
         tgks.tgks_run(ctx, W, args.warmup, cfl=0.5, time_dev=tdev)
     torch.cuda.synchronize()
     W.copy_(Wdev0)
-    tgks.tgks_reset_status(ctx)
+    # timed runs (kernel timing off): the median of `reps` runs of K steps
+    runs = []
+    for _ in range(args.reps):
+        W.copy_(Wdev0)
+        tgks.tgks_reset_status(ctx)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tgks.tgks_run(ctx, W, args.steps, cfl=0.5, time_dev=tdev)
+        torch.cuda.synchronize()
+        runs.append(time.perf_counter() - t0)
+    el = sorted(runs)[len(runs) // 2]
+    fails = tgks.tgks_status(ctx)
+    # per-kernel breakdown: one more run with HIP events around every launch
+    W.copy_(Wdev0)
     tgks.tgks_timing(ctx, True)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
     tgks.tgks_run(ctx, W, args.steps, cfl=0.5, time_dev=tdev)
     torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    fails = tgks.tgks_status(ctx)
     kt = {k: tgks.tgks_kernel_time(ctx, k) for k in ("face_x", "face_y", "update1", "update2", "cfl")}
     tgks.tgks_timing(ctx, False)
     t_sim = float(tdev[0].cpu())
@@ -636,6 +719,9 @@ def main():
         "metric": METRIC, "value": round(value, 3), "unit": "Mcell-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(el * 1e3 / args.steps, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "timing": f"median of {args.reps} runs of {args.steps} steps (kernel timing off): "
+                  + ", ".join(f"{x * 1e3:.2f}" for x in runs) + " ms; the roofline from one more run "
+                  "with HIP events around every launch",
         "data": "synthetic",
         "config": {"workload": f"2d_euler_four_quadrant_riemann_{n}x{n}_seed{args.seed}", "cells": ncell,
                    "gamma": 1.4, "cfl": 0.5, "bc": "transmissive", "t_end_reached": t_sim,
@@ -662,6 +748,8 @@ def main():
                           batched(2, 2, args.batch_instances, args.batch_steps),
                           batched(2, 2, args.batch_instances, args.batch_steps, ranges=mild),
                           batched(2, 2, args.batch_instances, args.batch_steps, fallback=1)]
+    if not args.no_schemes:
+        out["schemes"] = schemes(n=n, seed=args.seed)
     if not args.no_adjoint:
         out["adjoint"] = adjoint()
     if not args.no_3d:

@@ -56,6 +56,11 @@ extern "C" {
  * for the state bc_state[1].  Stage 1 of a step from t uses time t, stage 2
  * time t + dt/2.  A ghost cell outside both axes is decided by the x side
  * first when that side is prescribed and gives a state. */
+#define TGKS_SCHEME_TENO_D 0
+#define TGKS_SCHEME_WENO_AO 1
+#define TGKS_SCHEME_TENO5 2
+#define TGKS_SCHEME_WENO_Z 3
+
 #define TGKS_BC_PERIODIC 0
 #define TGKS_BC_TRANSMISSIVE 1
 #define TGKS_BC_REFLECTIVE 2
@@ -107,6 +112,23 @@ typedef struct tgks_params {
    * not a positivity-preserving limiter: cell averages can still become
    * non-physical. */
   int32_t fallback;
+  /* reconstruction scheme (default TGKS_SCHEME_TENO_D, the paper's): one of
+   * the paper's comparison schemes on 1-D and 2-D grids with conservative
+   * variables (no prescribed sides, no fallback; batches and the reverse mode
+   * reject them):
+   *   TGKS_SCHEME_WENO_AO (Sec. 3.2): linear weights d_hi, d_lo (0.85, 0.85),
+   *     weights d_k (1 + (tau / (beta_k + eps_w))^2), eps_w 1e-8;
+   *   TGKS_SCHEME_TENO5 (Sec. 4.1): gamma_k = (1 + tau / (beta_k + eps))^q
+   *     with cut-off ct1 (set q = 6, the paper's, eps 1e-40, ct1 1e-7);
+   *   TGKS_SCHEME_WENO_Z (Sec. 3.1): weights d_k (1 + tau / (beta_k + eps_w)).
+   * TENO5 and WENO-Z reconstruct only the non-equilibrium interface values
+   * nonlinearly; slopes follow Eq. 3.11 and the equilibrium state is
+   * reconstructed separately (Eq. 3.12; in 2-D the linear quartic along the
+   * face).  Stencil flags: TENO5 records its cut-offs (bit k = delta_k),
+   * WENO-AO and WENO-Z record 0. */
+  int32_t scheme;
+  double d_hi, d_lo;
+  double eps_w;
 } tgks_params;
 
 typedef struct tgks_ctx tgks_ctx;
@@ -230,6 +252,14 @@ int tgks_measure_peaks(void* hip_stream, double* fp64_tflops, double* copy_gbps)
  * state is non-physical, or TGKS_EINVAL. */
 int tgks_gp_flux_host(const tgks_params* p, const double* Wl, const double* Wr, const double* dWl,
                       const double* dWr, double dt, double* F);
+
+/* The kernels' stencil selection of five values Q (host arrays), evaluated
+ * on the host: the TENO-D flag (bit0 = delta_{3,1}, bits 1..3 = the small
+ * stencils' cut-offs; Sec. 4.2) with the normal cut-offs of p, computed with
+ * the kernels' shortcut for certain large-stencil decisions (fast != 0) or
+ * from the weights of Eq. 4.5 alone (fast == 0).  For verification: both
+ * must agree for every input.  Returns the flag, or TGKS_EINVAL. */
+int tgks_teno_flag_host(const tgks_params* p, const double* Q, int32_t fast);
 
 /* ------------------------------------------------------------------------
  * Reverse mode.  The derivative of one S2O4 step W_out = S(W_in) with the

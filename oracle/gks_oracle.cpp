@@ -311,6 +311,57 @@ static void teno_gauss_values(const T Q[5], uint8_t flag, T out[4]) {
   }
 }
 
+// The same values and slopes in one fixed evaluation order (monomial
+// coefficients as multiples of correctly rounded reciprocals, even and odd
+// parts in the Gauss-point coordinate), for the 3-D first sweep, whose
+// results are the inputs of the second sweep's selections: identical data
+// must give identical selections in every implementation (reading R8).
+template <class T>
+static void teno_gauss_canonical(const T Q[5], uint8_t flag, T out[4]) {
+  const T a = Q[0], b = Q[1], c = Q[2], d = Q[3], e = Q[4];
+  const double s = 0.28867513459481288225;  // 1/(2 sqrt 3)
+  T c0, c1, c2, c3 = T(0.0), c4 = T(0.0);
+  if (flag & 1) {
+    c0 = ((2134.0 * c - 116.0 * (d + b)) + 9.0 * (e + a)) * (1.0 / 1920.0);
+    c1 = (34.0 * (d - b) - 5.0 * (e - a)) * (1.0 / 48.0);
+    c2 = ((12.0 * (d + b) - 22.0 * c) - (e + a)) * (1.0 / 16.0);
+    c3 = ((e - a) - 2.0 * (d - b)) * (1.0 / 12.0);
+    c4 = ((((a - 4.0 * b) + 6.0 * c) - 4.0 * d) + e) * (1.0 / 24.0);
+  } else {
+    // equal weights of the surviving quadratics (1, 1/2 or 1/3 each)
+    const int cnt = ((flag >> 1) & 1) + ((flag >> 2) & 1) + ((flag >> 3) & 1);
+    const double inv = cnt == 1 ? 1.0 : (cnt == 2 ? 0.5 : 1.0 / 3.0);
+    T s0 = T(0.0), s1 = T(0.0), s2 = T(0.0);
+    if (flag & 2) {
+      s0 = s0 + ((23.0 * c + 2.0 * b) - a) * (1.0 / 24.0);
+      s1 = s1 + ((3.0 * c - 4.0 * b) + a) * 0.5;
+      s2 = s2 + ((c - 2.0 * b) + a) * 0.5;
+    }
+    if (flag & 4) {
+      s0 = s0 + ((26.0 * c - d) - b) * (1.0 / 24.0);
+      s1 = s1 + (d - b) * 0.5;
+      s2 = s2 + ((d + b) - 2.0 * c) * 0.5;
+    }
+    if (flag & 8) {
+      s0 = s0 + ((23.0 * c + 2.0 * d) - e) * (1.0 / 24.0);
+      s1 = s1 + ((4.0 * d - 3.0 * c) - e) * 0.5;
+      s2 = s2 + ((c - 2.0 * d) + e) * 0.5;
+    }
+    c0 = s0 * inv;
+    c1 = s1 * inv;
+    c2 = s2 * inv;
+  }
+  const double ss = s * s;
+  const T even = c0 + ss * (c2 + ss * c4);
+  const T odd = s * (c1 + ss * c3);
+  const T deven = c1 + (3.0 * ss) * c3;
+  const T dodd = s * (2.0 * c2 + (4.0 * ss) * c4);
+  out[0] = even - odd;
+  out[1] = deven - dodd;
+  out[2] = even + odd;
+  out[3] = deven + dodd;
+}
+
 template <class T>
 static uint8_t select_T(const T Q[5], double ct1, double ct2, double eps, int q) {
   double qv[5];
@@ -1103,7 +1154,7 @@ static void char_recon_cells(const orc_params& P, int D, const T C[6][5], double
                              T vr[5], T sr[5], uint8_t fr[5]) {
   const int nc = D + 2;
   T Wb[5], L[5][5], R[5][5];
-  for (int a = 0; a < nc; ++a) Wb[a] = 0.5 * (C[2][a] + C[3][a]);
+  for (int a = 0; a < 5; ++a) Wb[a] = a < nc ? 0.5 * (C[2][a] + C[3][a]) : T(0.0);
   char_basis(D, P.gamma, Wb, 0, L, R);
   T V[6][5];
   for (int r = 0; r < 6; ++r) matvec(nc, L, C[r], V[r]);
@@ -1323,8 +1374,8 @@ static long face_fluxes(const orc_params& P, const Grid& g, const T* W, int d, d
               tflags[(((long)1 * 2 + side) * nc + c) * nface + fidx] = fn;
             }
             T ow[4], on[4];
-            teno_gauss_values(Vw[r2], fw, ow);
-            teno_gauss_values(Vn[r2], fn, on);
+            teno_gauss_canonical(Vw[r2], fw, ow);
+            teno_gauss_canonical(Vn[r2], fn, on);
             for (int m1 = 0; m1 < 2; ++m1) {
               S1w[m1][r2] = ow[2 * m1];
               // scaled by the reciprocal width, like every slope that a
@@ -1383,8 +1434,13 @@ static long face_fluxes(const orc_params& P, const Grid& g, const T* W, int d, d
     // are reconstructed separately (Sec. 3.1): along the normal by the
     // fifth-order linear formula of Eq. 3.12 on each face segment, whose
     // equilibrium value is the kinetic weighting of its line-averaged
-    // interface values (Eq. 2.6); along the face by the linear quartic of
-    // the five segments (Steps 2 and 4), evaluated at the Gauss points
+    // interface values (Eq. 2.6); along the face (Steps 2 and 4) by the
+    // fifth-order reconstruction of the five segments at the Gauss points
+    // with the ENO-like cut-off of Sec. 4.1 (TENO5, q = 6): the linear
+    // quartic wherever the segments' states are smooth (Tables 5 and 7),
+    // without its overshoot at a discontinuity, where the unlimited quartic
+    // gives non-physical equilibrium states in the first step of the 2-D
+    // Riemann problems the paper runs both schemes on (Sec. 5.6)
     T E0[2][5], dE0[2][3][5];
     const bool sep = P.scheme >= 2;
     if (sep) {
@@ -1397,7 +1453,9 @@ static long face_fluxes(const orc_params& P, const Grid& g, const T* W, int d, d
           Wl_[a] = D == 2 ? Lrow[0][r][a] : Wg[0][0][0][a];
           Wr_[a] = D == 2 ? Lrow[1][r][a] : Wg[0][0][1][a];
         }
-        nbad += kinetic_w0(P, D, Wl_, Wr_, W0row[r]);
+        // a non-physical segment state shows as a non-physical equilibrium
+        // at the Gauss points, counted there
+        (void)kinetic_w0(P, D, Wl_, Wr_, W0row[r]);
         for (int a = 0; a < nc; ++a) {
           T q[4];
           for (int k = 0; k < 4; ++k) {
@@ -1422,8 +1480,11 @@ static long face_fluxes(const orc_params& P, const Grid& g, const T* W, int d, d
             Qv[r] = W0row[r][a];
             Qx[r] = W0xrow[r][a];
           }
-          teno_gauss_values(Qv, 1, ov);  // flag 1: the quartic on all five segments
-          teno_gauss_values(Qx, 1, ox);
+          orc_params Pe = P;  // the cut-off reconstruction of Sec. 4.1 (TENO5)
+          Pe.scheme = 2;
+          Pe.q = 6;
+          scheme_gauss(Pe, Qv, ov);
+          scheme_gauss(Pe, Qx, ox);
           E0[m][a] = ov[2 * m];
           dE0[m][1][a] = ov[2 * m + 1] / dt1;
           dE0[m][0][a] = ox[2 * m];
@@ -1648,6 +1709,13 @@ int orc_recon(const orc_params* P, const double* Q, int gauss, double* out) {
 int orc_lin_weights(int where, double* d) {
   if (where < 0 || where > 3) return -1;
   lin_weights(where, d);
+  return 0;
+}
+
+// The canonical-order Gauss-point evaluation of the 3-D first sweep with a
+// caller-given flag: {v(s-), d(s-), v(s+), d(s+)}.
+int orc_teno_gauss_canonical(const double* Q, int flag, double* out) {
+  teno_gauss_canonical(Q, (uint8_t)flag, out);
   return 0;
 }
 

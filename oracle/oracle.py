@@ -40,6 +40,15 @@ SCHEME = {"teno_d": 0, "weno_ao": 1, "teno5": 2, "weno_z": 3}
 _lib = None
 
 
+def use_library(path):
+    """Load the oracle from another build of gks_oracle.cpp (the CPU
+    baseline's -march=native build); must precede the first call."""
+    global LIB_PATH, _lib
+    if _lib is not None:
+        raise RuntimeError("the oracle library is already loaded")
+    LIB_PATH = path
+
+
 def lib():
     global _lib
     if _lib is None:
@@ -57,6 +66,7 @@ def lib():
         L.orc_teno_gauss.argtypes = [dp, C.c_double, C.c_double, C.c_double, C.c_int, dp]
         L.orc_teno_eval.argtypes = [dp, C.c_int, C.c_int, dp]
         L.orc_recon.argtypes = [P, dp, C.c_int, dp]
+        L.orc_teno_gauss_canonical.argtypes = [dp, C.c_int, dp]
         L.orc_lin_weights.argtypes = [C.c_int, dp]
         L.orc_moments.argtypes = [C.c_double, C.c_double, C.c_int, dp]
         L.orc_micro_slope.argtypes = [C.c_int, C.c_double, dp, dp, dp]
@@ -171,6 +181,14 @@ def recon(params, Q, gauss=False):
     if f < 0:
         raise ValueError("invalid parameters")
     return out, f
+
+
+def teno_gauss_canonical(Q, flag):
+    """The 3-D first sweep's Gauss-point evaluation (canonical operation
+    order) with a given flag: {v(s-), d(s-), v(s+), d(s+)}."""
+    out = np.zeros(4)
+    lib().orc_teno_gauss_canonical(_arr(Q), int(flag), out)
+    return out
 
 
 def lin_weights(where):

@@ -171,7 +171,9 @@ int tgks_gp_flux_vjp_host(const tgks_params* p, const double* Wl, const double* 
 int tgks_step_adjoint(tgks_ctx* c, const double* W_n, const double* W_star, const double* dt_dev,
                       const double* gW_out, double* gW_in) {
   if (!c || !W_n || !dt_dev || !gW_out || !gW_in || gW_out == gW_in) return TGKS_EINVAL;
-  if (c->g.D > 2 || c->p.recon != TGKS_RECON_CONSERVATIVE || c->pb.on || c->p.fallback) return TGKS_EINVAL;
+  if (c->g.D > 2 || c->p.recon != TGKS_RECON_CONSERVATIVE || c->pb.on || c->p.fallback ||
+      c->p.scheme != TGKS_SCHEME_TENO_D)
+    return TGKS_EINVAL;
   int r;
   if ((r = ensure_adjoint_buffers(c))) return r;
   const int D = c->g.D;

@@ -234,6 +234,7 @@ int tgks_batch_create(const tgks_params* p, int32_t n_inst, void* stream, tgks_b
   const bool ns = p[0].mu > 0.0 && p[0].prandtl != 1.0;
   for (int i = 0; i < n_inst; ++i) {
     if (check_params(&p[i]) || p[i].ndim != D || p[i].recon != p[0].recon) return TGKS_EINVAL;
+    if (p[i].scheme != TGKS_SCHEME_TENO_D) return TGKS_EINVAL;  // TENO-D batches only
     if (has_prescribed(&p[i]) || p[i].fallback != p[0].fallback) return TGKS_EINVAL;
     if ((p[i].mu > 0.0 && p[i].prandtl != 1.0) != ns) return TGKS_EINVAL;
   }

@@ -14,6 +14,27 @@ using namespace tgks;
 // face fluxes of one stage in every direction
 int launch_faces(tgks_ctx* c, const double* W, const double* dt, int stage, uint8_t* flags) {
   const int D = c->g.D;
+  if (c->p.scheme != TGKS_SCHEME_TENO_D) {
+    const bool fl = flags != nullptr && stage == 1;
+    StageArgs a[2];
+    for (int ax = 0; ax < D; ++ax) {
+      a[ax] = stage_args(c, W, ax, dt);
+      if (fl) {
+        a[ax].nflags = flags;
+        long long off = (long long)D * c->nc * c->ncell;
+        for (int d = 0; d < ax; ++d) off += 4LL * c->nc * c->nface[d];
+        a[ax].tflags = D == 2 ? flags + off : nullptr;
+      }
+    }
+    switch (c->p.scheme) {
+      case TGKS_SCHEME_WENO_AO:
+        return launch_scheme_faces<SCHEME_WENO_AO>(c, a, stage, fl);
+      case TGKS_SCHEME_TENO5:
+        return launch_scheme_faces<SCHEME_TENO5>(c, a, stage, fl);
+      default:
+        return launch_scheme_faces<SCHEME_WENO_Z>(c, a, stage, fl);
+    }
+  }
   if (D == 2) {
     // both directions in one launch (timed as kind 0)
     const bool fl = flags != nullptr && stage == 1;
@@ -206,6 +227,9 @@ int tgks_params_default(tgks_params* p, int32_t ndim) {
   p->ct2 = p->ct2_tan = 1e-5;
   p->eps = 1e-40;
   p->q = 7;
+  p->scheme = TGKS_SCHEME_TENO_D;
+  p->d_hi = p->d_lo = 0.85;
+  p->eps_w = 1e-8;
   return TGKS_OK;
 }
 
@@ -242,6 +266,7 @@ void init_ctx_host(tgks_ctx* c, const tgks_params* p, void* stream) {
   c->fc.tau_mode = p->tau_mode;
   c->tn = {p->ct1, p->ct2, p->eps, p->q};
   c->tt = {p->ct1_tan, p->ct2_tan, p->eps, p->q};
+  c->sc = {p->ct1, p->eps, p->q, p->d_hi, p->d_lo, p->eps_w};
   for (int d = 0; d < 3; ++d) {
     long long nf = 1;
     for (int e = 0; e < 3; ++e) nf *= (long long)(g.n[e] + (e == d));
@@ -507,6 +532,12 @@ int host_flux(const tgks_params* p, const double* Wl, const double* Wr, const do
 }  // namespace
 
 extern "C" {
+
+int tgks_teno_flag_host(const tgks_params* p, const double* Q, int32_t fast) {
+  if (check_params(p) || !Q) return TGKS_EINVAL;
+  const TenoCfg c{p->ct1, p->ct2, p->eps, p->q};
+  return (int)(fast ? teno_flag<true>(Q, c) : teno_flag<false>(Q, c));
+}
 
 int tgks_gp_flux_host(const tgks_params* p, const double* Wl, const double* Wr, const double* dWl, const double* dWr,
                       double dt, double* F) {

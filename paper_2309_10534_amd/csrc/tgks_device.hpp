@@ -35,8 +35,17 @@ struct TenoCfg {
 // TENO-D selection (Sec. 4.2).  q[0..4] = Q_{-2..2}.
 // flag bit0 = delta_{3,1}; if it is 0, bits 1..3 = delta_{0,2}, delta_{1,2},
 // delta_{2,2}.
+//
+// FAST: decide the large stencil without the weights where that decision is
+// certain.  With b_k = beta_k + eps, q = 7 and b_3 <= 4 b_k for k = 0, 1, 2,
+// every gamma_k <= 4^7 gamma_3 (up to a few ulps), so gamma_3 / sum gamma >=
+// 1 / (3 4^7 + 1) = 2.03e-5 > C_T1 whenever C_T1 <= 1e-5: Eq. 4.7 keeps the
+// large stencil, and the weights (four divisions) evaluated below would
+// give the same flag bit for bit.  b_3 < 1e40 keeps b_3^7 finite; a NaN
+// fails the test and takes the full evaluation.  Smooth and constant data
+// take this path.
 // ---------------------------------------------------------------------------
-template <class R>
+template <bool FAST = true, class R>
 TGKS_HD unsigned teno_flag(const R* Q, const TenoCfg& c) {
 #pragma clang fp contract(off)
   const R a = Q[0], b = Q[1], cc = Q[2], d = Q[3], e = Q[4];
@@ -60,6 +69,11 @@ TGKS_HD unsigned teno_flag(const R* Q, const TenoCfg& c) {
   const R s2 = P2 + (123.0 / 455.0) * P4;
   beta[3] = (((s1 * s1) + (13.0 / 3.0) * (s2 * s2)) + (781.0 / 20.0) * (P3 * P3)) +
             (1421461.0 / 2275.0) * (P4 * P4);
+  if (FAST && c.q == 7 && c.ct1 <= 1e-5) {
+    const R b3 = beta[3] + c.eps;
+    if (b3 < 1e40 && b3 <= 4.0 * (beta[0] + c.eps) && b3 <= 4.0 * (beta[1] + c.eps) && b3 <= 4.0 * (beta[2] + c.eps))
+      return 1u;
+  }
   R g[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
@@ -172,6 +186,56 @@ TGKS_HD void teno_gauss(const R* Q, unsigned flag, R* val, R* der) {
   der[1] = deven + dodd;
 }
 
+// teno_gauss in one fixed evaluation order without contraction: the 3-D
+// first sweep's Gauss-point values are the inputs of the second sweep's
+// selections, whose flags must be a deterministic function of the data.
+template <class R>
+TGKS_HD void teno_gauss_exact(const R* Q, unsigned flag, R* val, R* der) {
+#pragma clang fp contract(off)
+  const R a = Q[0], b = Q[1], c = Q[2], d = Q[3], e = Q[4];
+  const double s = 0.28867513459481288225;  // 1/(2 sqrt 3)
+  R c0, c1, c2, c3 = R(0.0), c4 = R(0.0);
+  if (flag & 1u) {
+    c0 = ((2134.0 * c - 116.0 * (d + b)) + 9.0 * (e + a)) * (1.0 / 1920.0);
+    c1 = (34.0 * (d - b) - 5.0 * (e - a)) * (1.0 / 48.0);
+    c2 = ((12.0 * (d + b) - 22.0 * c) - (e + a)) * (1.0 / 16.0);
+    c3 = ((e - a) - 2.0 * (d - b)) * (1.0 / 12.0);
+    c4 = ((((a - 4.0 * b) + 6.0 * c) - 4.0 * d) + e) * (1.0 / 24.0);
+  } else {
+    const bool k0 = flag & 2u, k1 = flag & 4u, k2 = flag & 8u;
+    const int cnt = (int)k0 + (int)k1 + (int)k2;
+    const double inv = cnt == 1 ? 1.0 : (cnt == 2 ? 0.5 : 1.0 / 3.0);
+    R s0 = R(0.0), s1 = R(0.0), s2 = R(0.0);
+    if (k0) {
+      s0 = s0 + ((23.0 * c + 2.0 * b) - a) * (1.0 / 24.0);
+      s1 = s1 + ((3.0 * c - 4.0 * b) + a) * 0.5;
+      s2 = s2 + ((c - 2.0 * b) + a) * 0.5;
+    }
+    if (k1) {
+      s0 = s0 + ((26.0 * c - d) - b) * (1.0 / 24.0);
+      s1 = s1 + (d - b) * 0.5;
+      s2 = s2 + ((d + b) - 2.0 * c) * 0.5;
+    }
+    if (k2) {
+      s0 = s0 + ((23.0 * c + 2.0 * d) - e) * (1.0 / 24.0);
+      s1 = s1 + ((4.0 * d - 3.0 * c) - e) * 0.5;
+      s2 = s2 + ((c - 2.0 * d) + e) * 0.5;
+    }
+    c0 = s0 * inv;
+    c1 = s1 * inv;
+    c2 = s2 * inv;
+  }
+  const double ss = s * s;
+  const R even = c0 + ss * (c2 + ss * c4);
+  const R odd = s * (c1 + ss * c3);
+  val[0] = even - odd;
+  val[1] = even + odd;
+  const R deven = c1 + (3.0 * ss) * c3;
+  const R dodd = s * (2.0 * c2 + (4.0 * ss) * c4);
+  der[0] = deven - dodd;
+  der[1] = deven + dodd;
+}
+
 // The selected polynomial at one Gauss point m (0: s-, 1: s+), cell units.
 template <class R>
 TGKS_HD void teno_gauss_at(const R* Q, unsigned flag, int m, R& val, R& der) {
@@ -179,6 +243,290 @@ TGKS_HD void teno_gauss_at(const R* Q, unsigned flag, int m, R& val, R& der) {
   teno_gauss(Q, flag, v, d);
   val = m ? v[1] : v[0];
   der = m ? d[1] : d[0];
+}
+
+// ---------------------------------------------------------------------------
+// The paper's comparison schemes on the same five values and candidate
+// polynomials: WENO-AO (Sec. 3.2), TENO5 (Sec. 4.1) and WENO-Z (Sec. 3.1).
+//   * WENO-AO: linear weights d3 = d_Hi, d0 = d2 = (1 - d_Hi)(1 - d_Lo)/2,
+//     d1 = (1 - d_Hi) d_Lo; omega_k = d_k (1 + (tau / (beta_k + eps))^2)
+//     with tau the mean of |beta3 - beta_k| (the ratio squared, as Table 2
+//     requires), normalised over k = 0..3; the polynomial
+//     w3 (p3/d3 - sum d_k/d3 p_k) + sum w_k p_k gives values and slopes
+//     wherever they are needed (interfaces, Gauss points).
+//   * WENO-Z / TENO5: small stencils only, omega_k = d_k (1 + tau /
+//     (beta_k + eps)) (WENO-Z) or d_k delta_k with delta_k = 0 where
+//     (1 + tau / (beta_k + eps))^q < C_T sum (TENO5), tau = |beta0 - beta2|,
+//     d_k the linear weights of the evaluation point (0.1, 0.6, 0.3 at
+//     x_{i+1/2}, mirrored at x_{i-1/2}, (7/36 -+ sqrt 3/1080, 11/18, ...) at
+//     the Gauss points).  Interface slopes from the quadratic with the cell
+//     average and the two interface values (Eq. 3.11); along a face the
+//     same quadratic's derivative at the Gauss point.
+// The TENO5 cut-offs and the WENO-Z / TENO5 interface values follow one
+// fixed evaluation order without contraction (the interface values are the
+// inputs of the tangential selections, whose flags must be a deterministic
+// function of the data).
+// ---------------------------------------------------------------------------
+constexpr int SCHEME_TENO_D = 0, SCHEME_WENO_AO = 1, SCHEME_TENO5 = 2, SCHEME_WENO_Z = 3;
+
+struct SchemeCfg {
+  double ct, eps;      // TENO5 cut-off C_T and epsilon
+  int q;               // TENO5 power
+  double d_hi, d_lo;   // WENO-AO linear weights
+  double eps_w;        // WENO-AO / WENO-Z epsilon
+};
+
+// Jiang-Shu indicators of p0..p2 and Balsara's form for p3 (the same
+// arithmetic as teno_flag's)
+template <class R>
+TGKS_HD void indicators(const R* Q, R* beta) {
+#pragma clang fp contract(off)
+  const R a = Q[0], b = Q[1], cc = Q[2], d = Q[3], e = Q[4];
+  const double k13 = 13.0 / 12.0;
+  R t1, t2;
+  t1 = (a - 2.0 * b) + cc;
+  t2 = (a - 4.0 * b) + 3.0 * cc;
+  beta[0] = k13 * (t1 * t1) + 0.25 * (t2 * t2);
+  t1 = (b - 2.0 * cc) + d;
+  t2 = b - d;
+  beta[1] = k13 * (t1 * t1) + 0.25 * (t2 * t2);
+  t1 = (cc - 2.0 * d) + e;
+  t2 = (3.0 * cc - 4.0 * d) + e;
+  beta[2] = k13 * (t1 * t1) + 0.25 * (t2 * t2);
+  const R P1 = (82.0 * (d - b) - 11.0 * (e - a)) * (1.0 / 120.0);
+  const R P2 = ((((40.0 * b - 3.0 * a) - 74.0 * cc) + 40.0 * d) - 3.0 * e) * (1.0 / 56.0);
+  const R P3 = ((e - a) - 2.0 * (d - b)) * (1.0 / 12.0);
+  const R P4 = ((((a - 4.0 * b) + 6.0 * cc) - 4.0 * d) + e) * (1.0 / 24.0);
+  const R s1 = P1 + P3 * (1.0 / 10.0);
+  const R s2 = P2 + (123.0 / 455.0) * P4;
+  beta[3] = (((s1 * s1) + (13.0 / 3.0) * (s2 * s2)) + (781.0 / 20.0) * (P3 * P3)) +
+            (1421461.0 / 2275.0) * (P4 * P4);
+}
+
+// TENO5 cut-offs: bit k = delta_k (Eqs. 4.1-4.3)
+template <class R>
+TGKS_HD unsigned teno5_flags(const R* beta, const SchemeCfg& c) {
+#pragma clang fp contract(off)
+  const R tau = fabs(beta[0] - beta[2]);
+  R g[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const R t = 1.0 + tau / (beta[k] + c.eps);
+    R pw;
+    if (c.q == 6) {
+      const R t2 = t * t;
+      const R t4 = t2 * t2;
+      pw = t4 * t2;
+    } else {
+      pw = R(1.0);
+      for (int r = 0; r < c.q; ++r) pw = pw * t;
+    }
+    g[k] = pw;
+  }
+  const R sg = (g[0] + g[1]) + g[2];
+  unsigned f = 0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    if (!(g[k] < c.ct * sg)) f |= 1u << k;
+  return f;
+}
+
+// linear weights of p0..p2 at x_{i-1/2} (where 0), x_{i+1/2} (1), the Gauss
+// points -1/(2 sqrt 3) (2) and +1/(2 sqrt 3) (3)
+TGKS_HD void lin_weights(int where, double* d) {
+  const double gw = 1.7320508075688772 / 1080.0;
+  if (where == 0) {
+    d[0] = 0.3; d[1] = 0.6; d[2] = 0.1;
+  } else if (where == 1) {
+    d[0] = 0.1; d[1] = 0.6; d[2] = 0.3;
+  } else if (where == 2) {
+    d[0] = 7.0 / 36.0 + gw; d[1] = 11.0 / 18.0; d[2] = 7.0 / 36.0 - gw;
+  } else {
+    d[0] = 7.0 / 36.0 - gw; d[1] = 11.0 / 18.0; d[2] = 7.0 / 36.0 + gw;
+  }
+}
+
+// normalised weights of p0..p2 at point `where`: TENO5 from its flags,
+// WENO-Z from the indicators
+template <int SCHEME, class R>
+TGKS_HD void small_weights(const R* beta, unsigned flag, int where, const SchemeCfg& c, R* ob) {
+#pragma clang fp contract(off)
+  double d[3];
+  lin_weights(where, d);
+  if (SCHEME == SCHEME_TENO5) {
+    double S = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) S = S + ((flag >> k) & 1u ? d[k] : 0.0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) ob[k] = R((flag >> k) & 1u ? d[k] / S : 0.0);
+  } else {
+    const R tau = fabs(beta[0] - beta[2]);
+    R om[3], S = R(0.0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      om[k] = d[k] * (1.0 + tau / (beta[k] + c.eps_w));
+      S = S + om[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) ob[k] = om[k] / S;
+  }
+}
+
+// WENO-AO coefficients of p0..p2 (w[0..2]) and p3 (w[3])
+template <class R>
+TGKS_HD void ao_coeffs(const R* beta, const SchemeCfg& c, R* w) {
+  const double dh = c.d_hi, dl = c.d_lo;
+  const double d[4] = {(1.0 - dh) * (1.0 - dl) / 2.0, (1.0 - dh) * dl, (1.0 - dh) * (1.0 - dl) / 2.0, dh};
+  const R tau = ((fabs(beta[3] - beta[0]) + fabs(beta[3] - beta[1])) + fabs(beta[3] - beta[2])) * (1.0 / 3.0);
+  R om[4], S = R(0.0);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const R r = tau / (beta[k] + c.eps_w);
+    om[k] = d[k] * (1.0 + r * r);
+    S = S + om[k];
+  }
+  const R iS = R(1.0) / S;
+  const R o3 = om[3] * iS;
+  w[3] = o3 * (1.0 / dh);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) w[k] = om[k] * iS - o3 * (d[k] / dh);
+}
+
+// interface values of p0..p2 at x_{i-1/2} (vm) and x_{i+1/2} (vp)
+template <class R>
+TGKS_HD void small_face(const R* Q, R* vm, R* vp) {
+#pragma clang fp contract(off)
+  const R a = Q[0], b = Q[1], c = Q[2], d = Q[3], e = Q[4];
+  vp[0] = ((2.0 * a - 7.0 * b) + 11.0 * c) * (1.0 / 6.0);
+  vp[1] = ((5.0 * c - b) + 2.0 * d) * (1.0 / 6.0);
+  vp[2] = ((2.0 * c + 5.0 * d) - e) * (1.0 / 6.0);
+  vm[0] = ((5.0 * b - a) + 2.0 * c) * (1.0 / 6.0);
+  vm[1] = ((2.0 * b + 5.0 * c) - d) * (1.0 / 6.0);
+  vm[2] = ((11.0 * c - 7.0 * d) + 2.0 * e) * (1.0 / 6.0);
+}
+
+// WENO-Z / TENO5 interface values v(-1/2), v(+1/2); returns the flags
+template <int SCHEME, class R>
+TGKS_HD unsigned zt_face(const R* Q, const R* beta, const SchemeCfg& c, R& vm_o, R& vp_o) {
+#pragma clang fp contract(off)
+  const unsigned f = SCHEME == SCHEME_TENO5 ? teno5_flags(beta, c) : 0u;
+  R om[3], op[3], vm[3], vp[3];
+  small_weights<SCHEME>(beta, f, 0, c, om);
+  small_weights<SCHEME>(beta, f, 1, c, op);
+  small_face(Q, vm, vp);
+  R a = R(0.0), b = R(0.0);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    a = a + om[k] * vm[k];
+    b = b + op[k] * vp[k];
+  }
+  vm_o = a;
+  vp_o = b;
+  return f;
+}
+
+// Normal reconstruction: out = {v(-1/2), s(-1/2), v(+1/2), s(+1/2)} (cell
+// units); returns the flags (TENO5) or 0
+template <int SCHEME, class R>
+TGKS_HD unsigned scheme_face(const R* Q, const SchemeCfg& c, R* out) {
+#pragma clang fp contract(off)
+  R beta[4];
+  indicators(Q, beta);
+  if (SCHEME == SCHEME_WENO_AO) {
+    R w[4];
+    ao_coeffs(beta, c, w);
+    const R a = Q[0], b = Q[1], cc = Q[2], d = Q[3], e = Q[4];
+    R vm[3], vp[3];
+    small_face(Q, vm, vp);
+    const R Lp = ((((2.0 * a - 13.0 * b) + 47.0 * cc) + 27.0 * d) - 3.0 * e) * (1.0 / 60.0);
+    const R Lps = (((b - 15.0 * cc) + 15.0 * d) - e) * (1.0 / 12.0);
+    const R Lm = ((((27.0 * b - 3.0 * a) + 47.0 * cc) - 13.0 * d) + 2.0 * e) * (1.0 / 60.0);
+    const R Lms = (((a - 15.0 * b) + 15.0 * cc) - d) * (1.0 / 12.0);
+    const R dp0 = (a - 3.0 * b) + 2.0 * cc, dp12 = d - cc;
+    const R dm01 = cc - b, dm2 = (3.0 * d - 2.0 * cc) - e;
+    out[0] = ((w[3] * Lm + w[0] * vm[0]) + w[1] * vm[1]) + w[2] * vm[2];
+    out[1] = ((w[3] * Lms + w[0] * dm01) + w[1] * dm01) + w[2] * dm2;
+    out[2] = ((w[3] * Lp + w[0] * vp[0]) + w[1] * vp[1]) + w[2] * vp[2];
+    out[3] = ((w[3] * Lps + w[0] * dp0) + w[1] * dp12) + w[2] * dp12;
+    return 0u;
+  }
+  R vm, vp;
+  const unsigned f = zt_face<SCHEME>(Q, beta, c, vm, vp);
+  out[0] = vm;
+  out[1] = -2.0 * ((2.0 * vm + vp) - 3.0 * Q[2]);
+  out[2] = vp;
+  out[3] = 2.0 * ((vm + 2.0 * vp) - 3.0 * Q[2]);
+  return f;
+}
+
+// monomial coefficients (x in [-1/2, 1/2]) of the large-stencil quartic (L)
+// and the three quadratics (S[k][0..2])
+template <class R>
+TGKS_HD void cand_coeffs(const R* Q, R* L, R (*S)[3]) {
+  const R a = Q[0], b = Q[1], c = Q[2], d = Q[3], e = Q[4];
+  L[0] = ((2134.0 * c - 116.0 * (d + b)) + 9.0 * (e + a)) * (1.0 / 1920.0);
+  L[1] = (34.0 * (d - b) - 5.0 * (e - a)) * (1.0 / 48.0);
+  L[2] = ((12.0 * (d + b) - 22.0 * c) - (e + a)) * (1.0 / 16.0);
+  L[3] = ((e - a) - 2.0 * (d - b)) * (1.0 / 12.0);
+  L[4] = ((((a - 4.0 * b) + 6.0 * c) - 4.0 * d) + e) * (1.0 / 24.0);
+  S[0][0] = (23.0 * c + 2.0 * b - a) * (1.0 / 24.0);
+  S[0][1] = (3.0 * c - 4.0 * b + a) * 0.5;
+  S[0][2] = (c - 2.0 * b + a) * 0.5;
+  S[1][0] = (26.0 * c - d - b) * (1.0 / 24.0);
+  S[1][1] = (d - b) * 0.5;
+  S[1][2] = (d + b - 2.0 * c) * 0.5;
+  S[2][0] = (23.0 * c + 2.0 * d - e) * (1.0 / 24.0);
+  S[2][1] = (4.0 * d - 3.0 * c - e) * 0.5;
+  S[2][2] = (c - 2.0 * d + e) * 0.5;
+}
+
+// Tangential reconstruction at the Gauss points s = -+1/(2 sqrt 3): val[m],
+// der[m] (cell units); returns the flags (TENO5) or 0
+template <int SCHEME, class R>
+TGKS_HD unsigned scheme_gauss(const R* Q, const SchemeCfg& c, R* val, R* der) {
+  const double s = 0.28867513459481288225;  // 1/(2 sqrt 3)
+  const double ss = s * s;
+  R beta[4], L[5], S[3][3];
+  indicators(Q, beta);
+  cand_coeffs(Q, L, S);
+  if (SCHEME == SCHEME_WENO_AO) {
+    R w[4];
+    ao_coeffs(beta, c, w);
+    const R c0 = w[3] * L[0] + ((w[0] * S[0][0] + w[1] * S[1][0]) + w[2] * S[2][0]);
+    const R c1 = w[3] * L[1] + ((w[0] * S[0][1] + w[1] * S[1][1]) + w[2] * S[2][1]);
+    const R c2 = w[3] * L[2] + ((w[0] * S[0][2] + w[1] * S[1][2]) + w[2] * S[2][2]);
+    const R c3 = w[3] * L[3], c4 = w[3] * L[4];
+    const R even = c0 + ss * (c2 + ss * c4), odd = s * (c1 + ss * c3);
+    val[0] = even - odd;
+    val[1] = even + odd;
+    const R deven = c1 + (3.0 * ss) * c3, dodd = s * (2.0 * c2 + (4.0 * ss) * c4);
+    der[0] = deven - dodd;
+    der[1] = deven + dodd;
+    return 0u;
+  }
+  R vm, vp;
+  const unsigned f = zt_face<SCHEME>(Q, beta, c, vm, vp);
+  // slopes: the quadratic with the average Q_0 and the end values vm, vp
+  const R q1 = vp - vm, q2 = 3.0 * (vm + vp) - 6.0 * Q[2];
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    R ob[3];
+    small_weights<SCHEME>(beta, f, 2 + m, c, ob);
+    const R c0 = (ob[0] * S[0][0] + ob[1] * S[1][0]) + ob[2] * S[2][0];
+    const R c1 = (ob[0] * S[0][1] + ob[1] * S[1][1]) + ob[2] * S[2][1];
+    const R c2 = (ob[0] * S[0][2] + ob[1] * S[1][2]) + ob[2] * S[2][2];
+    const double x = m ? s : -s;
+    val[m] = c0 + x * (c1 + x * c2);
+    der[m] = q1 + (2.0 * x) * q2;
+  }
+  return f;
+}
+
+// Eq. 3.12: the equilibrium slope at x_{i+1/2} from the cells i-1 .. i+2
+// (cell units)
+template <class R>
+TGKS_HD R eq_slope(R wm1, R w0, R w1, R w2) {
+  return (-1.0 / 12.0) * (w2 - wm1) + 1.25 * (w1 - w0);
 }
 
 // ---------------------------------------------------------------------------
@@ -897,6 +1245,34 @@ TGKS_HD bool gp_flux(const R* Wl, const R* Wr, const R (*dWl)[D + 2], const R (*
   side_part<D, NS>(gl, hl0, hl1, Wl, dWl, P, g0, L);
   side_part<D, NS>(gr, hr0, hr1, Wr, dWr, P, g0, Rt);
   side_sum<D>(L, Rt, T);
+  flux_combine<D, NS>(W0, g0, T, gl.rho * gl.h, gr.rho * gr.h, P, dt, Fdt, Fh);
+  return gl.ok && gr.ok && g0.ok;
+}
+
+// The Gauss-point flux with a separately reconstructed equilibrium (WENO-Z
+// and TENO5 GKS, Sec. 3.1): the slopes of W0 along every frame axis are
+// given (dW0), and so is W0 itself when W0in is not null (2-D: the
+// tangential reconstruction of the face segments' equilibrium states);
+// otherwise W0 is the kinetic weighting of the two sides (Eq. 2.6).
+template <int D, bool NS, class R>
+TGKS_HD bool gp_flux_eq(const R* Wl, const R* Wr, const R (*dWl)[D + 2], const R (*dWr)[D + 2], const R* W0in,
+                        const R (*dW0)[D + 2], const FluxCfg& P, R dt, R* Fdt, R* Fh) {
+  constexpr int NC = D + 2;
+  Gas<D, R> gl, gr, g0;
+  R hl0, hl1, hr0, hr1, wl[NC], wr[NC], W0[NC];
+  side_w0<D>(Wl, P, 1.0, gl, hl0, hl1, wl);
+  side_w0<D>(Wr, P, -1.0, gr, hr0, hr1, wr);
+#pragma unroll
+  for (int q = 0; q < NC; ++q) W0[q] = W0in ? W0in[q] : wl[q] + wr[q];
+  make_gas<D>(W0, P.N, g0);
+  SidePart<D, R> L, Rt, T;
+  side_part<D, NS>(gl, hl0, hl1, Wl, dWl, P, g0, L);
+  side_part<D, NS>(gr, hr0, hr1, Wr, dWr, P, g0, Rt);
+  side_sum<D>(L, Rt, T);
+#pragma unroll
+  for (int d = 0; d < D; ++d)
+#pragma unroll
+    for (int q = 0; q < NC; ++q) T.dW0[d][q] = dW0[d][q];
   flux_combine<D, NS>(W0, g0, T, gl.rho * gl.h, gr.rho * gr.h, P, dt, Fdt, Fh);
   return gl.ok && gr.ok && g0.ok;
 }

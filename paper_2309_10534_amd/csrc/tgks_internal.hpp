@@ -26,6 +26,7 @@ struct tgks_ctx {
   Geom g;
   FluxCfg fc;
   TenoCfg tn, tt;
+  SchemeCfg sc;  // comparison schemes (p.scheme != TGKS_SCHEME_TENO_D)
   bool ns;
   int tile2 = 0;  // 2-D face-kernel tile shape (tile2_tn/tile2_tt index)
   hipStream_t stream;
@@ -103,6 +104,17 @@ inline int check_params(const tgks_params* p) {
   if (p->recon != TGKS_RECON_CONSERVATIVE && p->recon != TGKS_RECON_CHARACTERISTIC) return TGKS_EINVAL;
   if (p->recon == TGKS_RECON_CHARACTERISTIC && p->ndim > 2) return TGKS_EINVAL;
   if (p->fallback != 0 && p->fallback != 1) return TGKS_EINVAL;
+  if (p->scheme < TGKS_SCHEME_TENO_D || p->scheme > TGKS_SCHEME_WENO_Z) return TGKS_EINVAL;
+  if (p->scheme != TGKS_SCHEME_TENO_D) {
+    // the comparison schemes: conservative variables on 1-D and 2-D grids,
+    // no prescribed sides or fallback
+    if (p->ndim > 2 || p->recon != TGKS_RECON_CONSERVATIVE || p->fallback != 0) return TGKS_EINVAL;
+    for (int d = 0; d < p->ndim; ++d)
+      if (p->bc_lo[d] == TGKS_BC_PRESCRIBED || p->bc_hi[d] == TGKS_BC_PRESCRIBED) return TGKS_EINVAL;
+    if (p->scheme == TGKS_SCHEME_WENO_AO && !(p->d_hi > 0.0 && p->d_hi < 1.0 && p->d_lo > 0.0 && p->d_lo < 1.0))
+      return TGKS_EINVAL;
+    if (p->scheme != TGKS_SCHEME_TENO5 && !(p->eps_w > 0.0)) return TGKS_EINVAL;
+  }
   double cells = 1.0;
   for (int d = 0; d < p->ndim; ++d) cells *= p->n[d];
   if (cells > 4.0e9) return TGKS_EINVAL;
@@ -170,6 +182,7 @@ inline StageArgs stage_args(tgks_ctx* c, const double* W, int ax, const double* 
   a.fc = c->fc;
   a.tn = c->tn;
   a.tt = c->tt;
+  a.sc = c->sc;
   a.W = W;
   a.FA = c->FA[ax];
   a.FB = c->FB[ax];
@@ -191,6 +204,11 @@ inline StageArgs stage_args(tgks_ctx* c, const double* W, int ax, const double* 
 // 2-D face kernels of one direction and stage (tgks_face2d.hip)
 int launch_face2d_any(tgks_ctx* c, const StageArgs& a, int ax, int stage, bool fl);
 int launch_face2d_xy_any(tgks_ctx* c, const StageArgs& ax, const StageArgs& ay, int stage, bool fl);
+
+// face kernels of a comparison scheme, all directions of one stage
+// (tgks_scheme_*.hip)
+template <int SCHEME>
+int launch_scheme_faces(tgks_ctx* c, const StageArgs* a, int stage, bool fl);
 
 // 3-D normal reconstruction and face kernels of direction AX (tgks_face3d_*.hip)
 template <int AX>

@@ -60,6 +60,7 @@ struct StageArgs {
   FluxCfg fc;
   TenoCfg tn;  // normal reconstruction
   TenoCfg tt;  // tangential reconstruction
+  SchemeCfg sc;  // constants of the comparison schemes (WENO-AO, TENO5, WENO-Z)
   const double* W;
   double* FA;
   double* FB;
@@ -204,13 +205,15 @@ __device__ __forceinline__ void wall_fluxes(const Geom& g, int ax, int f, double
 // ---------------------------------------------------------------------------
 // EX: prescribed sides or the first-order fallback may be on (a separate
 // instantiation, so that grids without them run the plain code)
-template <int STAGE, bool NS, bool FLAGS, bool CHAR = false, bool EX = false>
+// SCHEME: the reconstruction (SCHEME_TENO_D, the paper's scheme, or one of
+// its comparison schemes)
+template <int STAGE, bool NS, bool FLAGS, bool CHAR = false, bool EX = false, int SCHEME = SCHEME_TENO_D>
 __device__ __forceinline__ void face1d_body(const StageArgs& a, int f) {
   const double dt = *a.dt;
   if (!(dt > 0.0)) return;
   const int n = a.g.n[0];
   if (f > n) return;
-  double Wl[3], Wr[3], dWl[1][3], dWr[1][3];
+  double Wl[3], Wr[3], dWl[1][3], dWr[1][3], dW0[1][3];
   const double idx = 1.0 / a.g.dx[0];  // normal slopes per unit length
   const double tb = EX ? boundary_time(a, STAGE, dt) : 0.0;
   if (CHAR) {
@@ -233,15 +236,27 @@ __device__ __forceinline__ void face1d_body(const StageArgs& a, int f) {
       for (int r = 0; r < 6; ++r)
         Q[r] = EX ? cell_value(a.g, a.pb, a.W, c, f - 3 + r, 0, tb) : load_cell(a.g, a.W, c, f - 3 + r, 0, 0);
       double o[4];
-      const unsigned fl = teno_flag(Q, a.tn);
-      teno_face(Q, fl, o);
-      Wl[c] = o[2];
-      dWl[0][c] = o[3] * idx;
-      const unsigned fr = teno_flag(Q + 1, a.tn);
-      teno_face(Q + 1, fr, o);
-      Wr[c] = o[0];
-      dWr[0][c] = o[1] * idx;
-      if (FLAGS && f < n) a.nflags[(long long)c * n + f] = (uint8_t)fr;
+      if (SCHEME == SCHEME_TENO_D) {
+        const unsigned fl = teno_flag(Q, a.tn);
+        teno_face(Q, fl, o);
+        Wl[c] = o[2];
+        dWl[0][c] = o[3] * idx;
+        const unsigned fr = teno_flag(Q + 1, a.tn);
+        teno_face(Q + 1, fr, o);
+        Wr[c] = o[0];
+        dWr[0][c] = o[1] * idx;
+        if (FLAGS && f < n) a.nflags[(long long)c * n + f] = (uint8_t)fr;
+      } else {
+        scheme_face<SCHEME>(Q, a.sc, o);
+        Wl[c] = o[2];
+        dWl[0][c] = o[3] * idx;
+        const unsigned fr = scheme_face<SCHEME>(Q + 1, a.sc, o);
+        Wr[c] = o[0];
+        dWr[0][c] = o[1] * idx;
+        if (FLAGS && f < n) a.nflags[(long long)c * n + f] = (uint8_t)fr;
+        // separately reconstructed equilibrium slope (Eq. 3.12)
+        if (SCHEME >= SCHEME_TENO5) dW0[0][c] = eq_slope(Q[1], Q[2], Q[3], Q[4]) * idx;
+      }
     }
   }
   if (EX && a.fallback) {
@@ -255,7 +270,9 @@ __device__ __forceinline__ void face1d_body(const StageArgs& a, int f) {
     if (nfb && a.fbc) atomicAdd(a.fbc, (unsigned long long)nfb);
   }
   double Fdt[3], Fh[3], A[3] = {0, 0, 0}, B[3] = {0, 0, 0};
-  const bool ok = gp_flux<1, NS>(Wl, Wr, dWl, dWr, a.fc, dt, Fdt, Fh);
+  const bool ok = SCHEME >= SCHEME_TENO5
+                      ? gp_flux_eq<1, NS>(Wl, Wr, dWl, dWr, (const double*)nullptr, dW0, a.fc, dt, Fdt, Fh)
+                      : gp_flux<1, NS>(Wl, Wr, dWl, dWr, a.fc, dt, Fdt, Fh);
   if (!ok) atomicAdd(a.fail, 1ull);
   write_combined<3>(STAGE, Fdt, Fh, 1.0, A, B);
   wall_fluxes<3>(a.g, 0, f, A, B);
@@ -267,9 +284,9 @@ __device__ __forceinline__ void face1d_body(const StageArgs& a, int f) {
   }
 }
 
-template <int STAGE, bool NS, bool FLAGS, bool CHAR = false, bool EX = false>
+template <int STAGE, bool NS, bool FLAGS, bool CHAR = false, bool EX = false, int SCHEME = SCHEME_TENO_D>
 __global__ __launch_bounds__(256) void face1d_kernel(StageArgs a) {
-  face1d_body<STAGE, NS, FLAGS, CHAR, EX>(a, blockIdx.x * blockDim.x + threadIdx.x);
+  face1d_body<STAGE, NS, FLAGS, CHAR, EX, SCHEME>(a, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -299,11 +316,20 @@ __host__ __device__ constexpr int tile2_lds_char(int k) {
   return tile2_lds(k) + 4 * (tile2_tt(k) + 4) * tile2_tn(k) * 4 + (tile2_tt(k) + 4) * tile2_tn(k) * 16;
 }
 
+// ... plus, with a separately reconstructed equilibrium (WENO-Z, TENO5),
+// the equilibrium state and its normal slope of every staged face segment
+__host__ __device__ constexpr int tile2_lds_eq(int k) {
+  return tile2_lds(k) + 2 * 4 * (tile2_tt(k) + 4) * tile2_tn(k);
+}
+
 // (bx, by): tile index along the normal and the tangential axis; lds: the
-// block's tile2_lds(TILE) (CHAR: tile2_lds_char(TILE)) doubles of shared
-// memory.  CHAR: reconstruction in characteristic variables (steps 2 and 3
-// below project onto the fields of each face and back).
-template <int AX, int STAGE, bool NS, bool FLAGS, int TILE, bool CHAR = false, bool EX = false>
+// block's tile2_lds(TILE) (CHAR: tile2_lds_char(TILE); SCHEME_TENO5 and
+// SCHEME_WENO_Z: tile2_lds_eq(TILE)) doubles of shared memory.  CHAR:
+// reconstruction in characteristic variables (steps 2 and 3 below project
+// onto the fields of each face and back).  SCHEME: the reconstruction
+// (SCHEME_TENO_D or a comparison scheme; conservative variables).
+template <int AX, int STAGE, bool NS, bool FLAGS, int TILE, bool CHAR = false, bool EX = false,
+          int SCHEME = SCHEME_TENO_D>
 __device__ __forceinline__ void face2d_tile(const StageArgs& a, int bx, int by, double* lds) {
   constexpr int TN = tile2_tn(TILE), TT = tile2_tt(TILE), NT = 2 * TN * TT;
   constexpr int NC = 4;
@@ -417,9 +443,14 @@ __device__ __forceinline__ void face2d_tile(const StageArgs& a, int bx, int by, 
       const int tl = (L / RN) % LT;
       const int c = L / (RN * LT);
       const double* Q = &sW[c][tl][nr];
-      const unsigned fl = teno_flag(Q, a.tn);
       double o[4];
-      teno_face(Q, fl, o);
+      unsigned fl;
+      if (SCHEME == SCHEME_TENO_D) {
+        fl = teno_flag(Q, a.tn);
+        teno_face(Q, fl, o);
+      } else {
+        fl = scheme_face<SCHEME>(Q, a.sc, o);
+      }
       sR[c][tl][nr][0] = o[0];
       sR[c][tl][nr][1] = o[1] * idn;
       sR[c][tl][nr][2] = o[2];
@@ -434,6 +465,33 @@ __device__ __forceinline__ void face2d_tile(const StageArgs& a, int bx, int by, 
     }
   }
   __syncthreads();
+
+  // 2b. WENO-Z / TENO5: the equilibrium state of every staged face segment,
+  //     the kinetic weighting of its two line-averaged interface states
+  //     (Eq. 2.6), and its normal slope from the cells (Eq. 3.12), frame
+  //     order; reconstructed along the face at the Gauss points in step 3
+  double(*sE)[2][LT][TN] = reinterpret_cast<double(*)[2][LT][TN]>(lds + tile2_lds(TILE));
+  if (SCHEME >= SCHEME_TENO5) {
+    for (int L = tid; L < LT * TN; L += NT) {
+      const int fn = L % TN, tl = L / TN;
+      double wl[NC], wr[NC], sl[NC], sr[NC], h0, h1, k0, k1;
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        wl[q] = sR[perm[q]][tl][fn][2];
+        wr[q] = sR[perm[q]][tl][fn + 1][0];
+      }
+      Gas<2, double> gl, gr;
+      side_w0<2>(wl, a.fc, 1.0, gl, h0, h1, sl);
+      side_w0<2>(wr, a.fc, -1.0, gr, k0, k1, sr);
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        const int c = perm[q];
+        sE[q][0][tl][fn] = sl[q] + sr[q];
+        sE[q][1][tl][fn] = eq_slope(sW[c][tl][fn + 1], sW[c][tl][fn + 2], sW[c][tl][fn + 3], sW[c][tl][fn + 4]) * idn;
+      }
+    }
+    __syncthreads();
+  }
 
   // 3. lanes 2k and 2k+1 share face k.  Lane m reconstructs side m (left: 0,
   //    right: 1) along the face at both Gauss points, keeps Gauss point m and
@@ -526,14 +584,20 @@ __device__ __forceinline__ void face2d_tile(const StageArgs& a, int bx, int by, 
           Qw[r] = sR[c][ft + r][nr][vo];
           Qn[r] = sR[c][ft + r][nr][vo + 1];
         }
-        const unsigned fw = teno_flag(Qw, a.tt);
-        const unsigned fq = teno_flag(Qn, a.tt);
+        unsigned fw, fq;
+        if (SCHEME == SCHEME_TENO_D) {
+          fw = teno_flag(Qw, a.tt);
+          fq = teno_flag(Qn, a.tt);
+          teno_gauss(Qw, fw, v, dv);
+          teno_gauss(Qn, fq, vn, dvn);
+        } else {
+          fw = scheme_gauss<SCHEME>(Qw, a.sc, v, dv);
+          fq = scheme_gauss<SCHEME>(Qn, a.sc, vn, dvn);
+        }
         if (FLAGS) {
           a.tflags[((long long)(0 * 2 + m) * NC + c) * nf + fidx] = (uint8_t)fw;
           a.tflags[((long long)(1 * 2 + m) * NC + c) * nf + fidx] = (uint8_t)fq;
         }
-        teno_gauss(Qw, fw, v, dv);
-        teno_gauss(Qn, fq, vn, dvn);
       }
       // own side at own Gauss point; the partner's side at this Gauss point
       // arrives from the partner, which computed it
@@ -561,7 +625,34 @@ __device__ __forceinline__ void face2d_tile(const StageArgs& a, int bx, int by, 
   }
   if (live) {
     double Fdt[NC], Fh[NC];
-    if (!gp_flux<2, NS>(Wg[0], Wg[1], Dg[0], Dg[1], a.fc, dt, Fdt, Fh)) atomicAdd(a.fail, 1ull);
+    bool ok;
+    if (SCHEME >= SCHEME_TENO5) {
+      // the equilibrium at this lane's Gauss point: the five face segments'
+      // states reconstructed with the cut-off of Sec. 4.1 (TENO5, q = 6;
+      // the linear quartic where they are smooth, Sec. 3.1 Step 4), value
+      // and derivatives
+      SchemeCfg se = a.sc;
+      se.q = 6;
+      double W0e[NC], dW0e[2][NC];
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        double Qe[5], Qx[5], v[2], d[2];
+#pragma unroll
+        for (int r = 0; r < 5; ++r) {
+          Qe[r] = sE[q][0][ft + r][fn];
+          Qx[r] = sE[q][1][ft + r][fn];
+        }
+        scheme_gauss<SCHEME_TENO5>(Qe, se, v, d);
+        W0e[q] = m ? v[1] : v[0];
+        dW0e[1][q] = (m ? d[1] : d[0]) * idt;
+        scheme_gauss<SCHEME_TENO5>(Qx, se, v, d);
+        dW0e[0][q] = m ? v[1] : v[0];
+      }
+      ok = gp_flux_eq<2, NS>(Wg[0], Wg[1], Dg[0], Dg[1], W0e, dW0e, a.fc, dt, Fdt, Fh);
+    } else {
+      ok = gp_flux<2, NS>(Wg[0], Wg[1], Dg[0], Dg[1], a.fc, dt, Fdt, Fh);
+    }
+    if (!ok) atomicAdd(a.fail, 1ull);
     write_combined<NC>(STAGE, Fdt, Fh, 0.5, A, B);
   }
 #pragma unroll
@@ -588,19 +679,19 @@ __global__ __launch_bounds__(2 * tile2_tn(TILE) * tile2_tt(TILE), 2) void face2d
 // Both directions in one launch: the first blocks take the x-face tiles,
 // the rest the y-face tiles (one shared LDS tile), so that neither
 // direction waits for the other's tail.
-template <int STAGE, bool NS, bool FLAGS, int TILE, bool CHAR = false, bool EX = false>
+template <int STAGE, bool NS, bool FLAGS, int TILE, bool CHAR = false, bool EX = false, int SCHEME = SCHEME_TENO_D>
 __global__ __launch_bounds__(2 * tile2_tn(TILE) * tile2_tt(TILE), 2) void face2d_xy_kernel(StageArgs ax,
                                                                                            StageArgs ay) {
   constexpr int TN = tile2_tn(TILE);
-  __shared__ double lds[CHAR ? tile2_lds_char(TILE) : tile2_lds(TILE)];
+  __shared__ double lds[CHAR ? tile2_lds_char(TILE) : (SCHEME >= SCHEME_TENO5 ? tile2_lds_eq(TILE) : tile2_lds(TILE))];
   const int nbx = (ax.g.n[0] + 1 + TN - 1) / TN;          // x faces: tiles along x
   const int nx = nbx * ((ax.g.n[1] + tile2_tt(TILE) - 1) / tile2_tt(TILE));
   const int b = blockIdx.x;
   if (b < nx) {
-    face2d_tile<0, STAGE, NS, FLAGS, TILE, CHAR, EX>(ax, b % nbx, b / nbx, lds);
+    face2d_tile<0, STAGE, NS, FLAGS, TILE, CHAR, EX, SCHEME>(ax, b % nbx, b / nbx, lds);
   } else {
     const int nby = (ay.g.n[1] + 1 + TN - 1) / TN;        // y faces: tiles along y
-    face2d_tile<1, STAGE, NS, FLAGS, TILE, CHAR, EX>(ay, (b - nx) % nby, (b - nx) / nby, lds);
+    face2d_tile<1, STAGE, NS, FLAGS, TILE, CHAR, EX, SCHEME>(ay, (b - nx) % nby, (b - nx) / nby, lds);
   }
 }
 
@@ -735,8 +826,9 @@ __global__ __launch_bounds__(L3 * B3_1 * B3_2, 2) void face3d_kernel(StageArgs a
     }
     double v[2], dv[2], vn[2], dvn[2];
     const unsigned fw = teno_flag(Qw, a.tt), fq = teno_flag(Qn, a.tt);
-    teno_gauss(Qw, fw, v, dv);
-    teno_gauss(Qn, fq, vn, dvn);
+    // the inputs of the second sweep's selections: one fixed evaluation order
+    teno_gauss_exact(Qw, fw, v, dv);
+    teno_gauss_exact(Qn, fq, vn, dvn);
     if (FLAGS && i2 >= 2 && i2 < B2 + 2) {
       int q3[3];
       q3[AX] = fa;

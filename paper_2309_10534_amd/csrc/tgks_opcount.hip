@@ -33,7 +33,7 @@ long long count_normal(const tgks_ctx* c) {
   F Q[5], o[4];
   tgks_opcount::graph().reset();
   for (int r = 0; r < 5; ++r) Q[r] = smooth(0, 0.1 * r, 0.0);
-  const unsigned fl = teno_flag(Q, c->tn);
+  const unsigned fl = teno_flag<false>(Q, c->tn);
   teno_face(Q, fl, o);
   const F idn(1.0 / c->g.dx[0]);
   F s1 = o[1] * idn, s3 = o[3] * idn;
@@ -64,8 +64,8 @@ long long count_face(const tgks_ctx* c, int stage, tgks_opcount::Tally* detail) 
           Qw[r] = smooth(q < 3 ? q : 4, 0.1 * r, 0.0);
           Qn[r] = F::input(0.01 * r);
         }
-        teno_gauss(Qw, teno_flag(Qw, c->tt), v, dv);
-        teno_gauss(Qn, teno_flag(Qn, c->tt), vn, dvn);
+        teno_gauss(Qw, teno_flag<false>(Qw, c->tt), v, dv);
+        teno_gauss(Qn, teno_flag<false>(Qn, c->tt), vn, dvn);
         for (int m = 0; m < 2; ++m) dv[m] = dv[m] * F(1.0 / c->g.dx[1]);
       }
   } else if (D == 3) {
@@ -83,8 +83,8 @@ long long count_face(const tgks_ctx* c, int stage, tgks_opcount::Tally* detail) 
               Qw[r] = smooth(q, 0.1 * r, 0.1 * r2);
               Qn[r] = F::input(0.01 * r);
             }
-            teno_gauss(Qw, teno_flag(Qw, c->tt), v, dv);
-            teno_gauss(Qn, teno_flag(Qn, c->tt), vn, dvn);
+            teno_gauss(Qw, teno_flag<false>(Qw, c->tt), v, dv);
+            teno_gauss(Qn, teno_flag<false>(Qn, c->tt), vn, dvn);
             for (int m1 = 0; m1 < 2; ++m1) {
               S1w[m1][r2] = v[m1];
               S1d[m1][r2] = dv[m1] * F(1.0 / c->g.dx[1]);
@@ -100,10 +100,10 @@ long long count_face(const tgks_ctx* c, int stage, tgks_opcount::Tally* detail) 
         }
         for (int m1 = 0; m1 < 2; ++m1) {
           F v[2], dv[2], x[2], dx_[2];
-          teno_gauss(S1w[m1], teno_flag(S1w[m1], c->tt), v, dv);
+          teno_gauss(S1w[m1], teno_flag<false>(S1w[m1], c->tt), v, dv);
           for (int m2 = 0; m2 < 2; ++m2) dv[m2] = dv[m2] * F(1.0 / c->g.dx[2]);
-          teno_gauss(S1d[m1], teno_flag(S1d[m1], c->tt), x, dx_);
-          teno_gauss(S1n[m1], teno_flag(S1n[m1], c->tt), x, dx_);
+          teno_gauss(S1d[m1], teno_flag<false>(S1d[m1], c->tt), x, dx_);
+          teno_gauss(S1n[m1], teno_flag<false>(S1n[m1], c->tt), x, dx_);
         }
       }
   }
@@ -171,8 +171,8 @@ long long count_face_char(const tgks_ctx* c, int stage, tgks_opcount::Tally* det
           Qw[r] = char_dot<NC>(L[k], X[r]);
           Qn[r] = char_dot<NC>(L[k], Xn[r]);
         }
-        teno_gauss(Qw, teno_flag(Qw, c->tt), v, dv);
-        teno_gauss(Qn, teno_flag(Qn, c->tt), vn, dvn);
+        teno_gauss(Qw, teno_flag<false>(Qw, c->tt), v, dv);
+        teno_gauss(Qn, teno_flag<false>(Qn, c->tt), vn, dvn);
         for (int q = 0; q < NC; ++q)
           for (int g = 0; g < 2; ++g) {
             aV[q][g] = k == 0 ? R[q][k] * v[g] : aV[q][g] + R[q][k] * v[g];
@@ -209,9 +209,134 @@ long long count_face_char(const tgks_ctx* c, int stage, tgks_opcount::Tally* det
   return tgks_opcount::tally().total();
 }
 
+// Comparison schemes (1-D, 2-D): the tangential reconstruction of both
+// sides (values and normal slopes), for WENO-Z and TENO5 the face's own
+// segment equilibrium (kinetic weighting of its two line-averaged states,
+// Eq. 3.12 slopes) and the linear quartic of the five segments at the Gauss
+// points (the other four segments are their own faces' work, inputs here),
+// and the Gauss-point fluxes.
+template <int D, bool NS, int SCHEME>
+long long count_face_scheme(const tgks_ctx* c, int stage, tgks_opcount::Tally* detail) {
+  constexpr int NC = D + 2;
+  constexpr int NG = D == 1 ? 1 : 2;
+  constexpr bool SEP = SCHEME >= SCHEME_TENO5;
+  tgks_opcount::graph().reset();
+  F Wg[2][2][NC], Dg[2][2][D][NC], W0[2][NC], dW0[2][D][NC];
+  for (int m = 0; m < NG; ++m)
+    for (int s = 0; s < 2; ++s)
+      for (int q = 0; q < NC; ++q) {
+        Wg[m][s][q] = smooth(q < D + 1 ? q : 4, 0.05 * s, 0.1 * m);
+        for (int d = 0; d < D; ++d) Dg[m][s][d][q] = F::input(0.01 * (q + 1) * (d + 1));
+      }
+  if (D == 2) {
+    for (int s = 0; s < 2; ++s)
+      for (int q = 0; q < NC; ++q) {
+        F Qw[5], Qn[5], v[2], dv[2], vn[2], dvn[2];
+        for (int r = 0; r < 5; ++r) {
+          Qw[r] = smooth(q < 3 ? q : 4, 0.1 * r, 0.0);
+          Qn[r] = F::input(0.01 * r);
+        }
+        scheme_gauss<SCHEME>(Qw, c->sc, v, dv);
+        scheme_gauss<SCHEME>(Qn, c->sc, vn, dvn);
+        for (int m = 0; m < 2; ++m) {
+          Wg[m][s][q] = v[m];
+          Dg[m][s][1][q] = dv[m] * F(1.0 / c->g.dx[1]);
+          Dg[m][s][0][q] = vn[m];
+        }
+      }
+  }
+  if (SEP) {
+    // the face's own segment: equilibrium state and its normal slope
+    F wl[NC], wr[NC], sl[NC], sr[NC], E[NC], Ex[NC], h0, h1, k0, k1;
+    for (int q = 0; q < NC; ++q) {
+      wl[q] = smooth(q < D + 1 ? q : 4, 0.0, 0.3);
+      wr[q] = smooth(q < D + 1 ? q : 4, 0.05, 0.3);
+    }
+    Gas<D, F> gl, gr;
+    side_w0<D>(wl, c->fc, 1.0, gl, h0, h1, sl);
+    side_w0<D>(wr, c->fc, -1.0, gr, k0, k1, sr);
+    for (int q = 0; q < NC; ++q) {
+      E[q] = sl[q] + sr[q];
+      Ex[q] = eq_slope(F::input(1.0 + q), F::input(1.1 + q), F::input(1.2 + q), F::input(1.25 + q)) *
+              F(1.0 / c->g.dx[0]);
+    }
+    for (int q = 0; q < NC; ++q) {
+      if (D == 1) {
+        W0[0][q] = E[q];
+        dW0[0][0][q] = Ex[q];
+        continue;
+      }
+      F Qe[5], Qx[5], v[2], d[2], vx[2], dx_[2];
+      for (int r = 0; r < 5; ++r) {
+        Qe[r] = r == 2 ? E[q] : F::input(0.9 + 0.01 * r + q);
+        Qx[r] = r == 2 ? Ex[q] : F::input(0.1 + 0.01 * r + q);
+      }
+      SchemeCfg se = c->sc;
+      se.q = 6;
+      scheme_gauss<SCHEME_TENO5>(Qe, se, v, d);
+      scheme_gauss<SCHEME_TENO5>(Qx, se, vx, dx_);
+      for (int m = 0; m < 2; ++m) {
+        W0[m][q] = v[m];
+        dW0[m][D - 1][q] = d[m] * F(1.0 / c->g.dx[1]);
+        dW0[m][0][q] = vx[m];
+      }
+    }
+  }
+  FluxCfg fc = c->fc;
+  const F dt(1e-3);
+  F A[NC], B[NC];
+  for (int q = 0; q < NC; ++q) A[q] = B[q] = F(0.0);
+  const double w = 1.0 / NG;
+  for (int m = 0; m < NG; ++m) {
+    F Fdt[NC], Fh[NC];
+    if (SEP)
+      gp_flux_eq<D, NS>(Wg[m][0], Wg[m][1], Dg[m][0], Dg[m][1], D == 1 ? (const F*)nullptr : W0[m], dW0[m], fc, dt,
+                        Fdt, Fh);
+    else
+      gp_flux<D, NS>(Wg[m][0], Wg[m][1], Dg[m][0], Dg[m][1], fc, dt, Fdt, Fh);
+    for (int q = 0; q < NC; ++q) {
+      if (stage == 1) {
+        A[q] += F(w) * Fh[q];
+        B[q] += F(w) * (F(8.0 / 3.0) * Fh[q] - F(1.0 / 3.0) * Fdt[q]);
+      } else {
+        A[q] += F(w) * (F(4.0 / 3.0) * Fdt[q] - F(8.0 / 3.0) * Fh[q]);
+      }
+    }
+  }
+  if (detail) *detail = tgks_opcount::tally();
+  return tgks_opcount::tally().total();
+}
+
+// normal reconstruction of one cell and component by a comparison scheme
+template <int SCHEME>
+long long count_normal_scheme(const tgks_ctx* c) {
+  F Q[5], o[4];
+  tgks_opcount::graph().reset();
+  for (int r = 0; r < 5; ++r) Q[r] = smooth(0, 0.1 * r, 0.0);
+  scheme_face<SCHEME>(Q, c->sc, o);
+  const F idn(1.0 / c->g.dx[0]);
+  F s1 = o[1] * idn, s3 = o[3] * idn;
+  (void)s1;
+  (void)s3;
+  return tgks_opcount::tally().total();
+}
+
 template <int D>
 long long count_face_dispatch(const tgks_ctx* c, int stage, tgks_opcount::Tally* t) {
   if constexpr (D <= 2) {
+    switch (c->p.scheme) {
+      case TGKS_SCHEME_WENO_AO:
+        return c->ns ? count_face_scheme<D, true, SCHEME_WENO_AO>(c, stage, t)
+                     : count_face_scheme<D, false, SCHEME_WENO_AO>(c, stage, t);
+      case TGKS_SCHEME_TENO5:
+        return c->ns ? count_face_scheme<D, true, SCHEME_TENO5>(c, stage, t)
+                     : count_face_scheme<D, false, SCHEME_TENO5>(c, stage, t);
+      case TGKS_SCHEME_WENO_Z:
+        return c->ns ? count_face_scheme<D, true, SCHEME_WENO_Z>(c, stage, t)
+                     : count_face_scheme<D, false, SCHEME_WENO_Z>(c, stage, t);
+      default:
+        break;
+    }
     if (c->p.recon == TGKS_RECON_CHARACTERISTIC)
       return c->ns ? count_face_char<D, true>(c, stage, t) : count_face_char<D, false>(c, stage, t);
   }
@@ -245,6 +370,7 @@ int tgks_flop_counts(const tgks_params* p, double* out, int32_t nout) {
   c.fc.tau_mode = p->tau_mode;
   c.tn = {p->ct1, p->ct2, p->eps, p->q};
   c.tt = {p->ct1_tan, p->ct2_tan, p->eps, p->q};
+  c.sc = {p->ct1, p->eps, p->q, p->d_hi, p->d_lo, p->eps_w};
   tgks_opcount::Tally t1;
   long long f1, f2;
   if (D == 1) {
@@ -258,7 +384,10 @@ int tgks_flop_counts(const tgks_params* p, double* out, int32_t nout) {
     f2 = count_face_dispatch<3>(&c, 2, nullptr);
   }
   // characteristic variables: the normal reconstruction is part of the face work
-  const long long nr = p->recon == TGKS_RECON_CHARACTERISTIC ? 0 : count_normal(&c);
+  long long nr = p->recon == TGKS_RECON_CHARACTERISTIC ? 0 : count_normal(&c);
+  if (p->scheme == TGKS_SCHEME_WENO_AO) nr = count_normal_scheme<SCHEME_WENO_AO>(&c);
+  if (p->scheme == TGKS_SCHEME_TENO5) nr = count_normal_scheme<SCHEME_TENO5>(&c);
+  if (p->scheme == TGKS_SCHEME_WENO_Z) nr = count_normal_scheme<SCHEME_WENO_Z>(&c);
   const int nc = D + 2;
   out[0] = (double)nr;                       // normal reconstruction, per cell, direction and component
   out[1] = (double)f1;                       // stage-1 face work beyond the normal reconstruction, per face

@@ -15,6 +15,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libtgks.so")
 
 BC_PERIODIC, BC_TRANSMISSIVE, BC_REFLECTIVE, BC_NOSLIP, BC_PRESCRIBED = 0, 1, 2, 3, 4
+SCHEME_TENO_D, SCHEME_WENO_AO, SCHEME_TENO5, SCHEME_WENO_Z = 0, 1, 2, 3
+_SCHEME = {"teno_d": 0, "weno_ao": 1, "teno5": 2, "weno_z": 3}
 TAU_INVISCID, TAU_VISCOUS, TAU_ZERO = 0, 1, 2
 _BC = {"periodic": 0, "transmissive": 1, "reflective": 2, "noslip": 3, "prescribed": 4}
 _FAR = {"transmissive": 1, "reflective": 2, "state_b": 4}
@@ -34,6 +36,7 @@ class TgksParams(C.Structure):
         ("eps", C.c_double), ("q", C.c_int32), ("recon", C.c_int32),
         ("bc_state", (C.c_double * 5) * 2), ("bc_line", ((C.c_double * 3) * 2) * 3),
         ("bc_far", (C.c_int32 * 2) * 3), ("fallback", C.c_int32),
+        ("scheme", C.c_int32), ("d_hi", C.c_double), ("d_lo", C.c_double), ("eps_w", C.c_double),
     ]
 
 
@@ -78,6 +81,8 @@ def lib():
     L.tgks_measure_peaks.argtypes = [vp, dp, dp]
     L.tgks_measure_peaks.restype = C.c_int
     L.tgks_gp_flux_host.argtypes = [P, dp, dp, dp, dp, C.c_double, dp]
+    L.tgks_teno_flag_host.argtypes = [P, dp, C.c_int32]
+    L.tgks_teno_flag_host.restype = C.c_int
     L.tgks_step_adjoint.argtypes = [vp, vp, vp, vp, vp, vp]
     L.tgks_step_adjoint.restype = C.c_int
     L.tgks_gp_flux_vjp_host.argtypes = [P, dp, dp, dp, dp, C.c_double, dp, dp]
@@ -133,7 +138,9 @@ def tgks_params_default(ndim, shape=None, dx=None, bc="transmissive", **kw):
     """tgks_params filled with the paper's constants; shape / dx / bc / keyword
     fields (gamma, mu, prandtl, tau, c1, c2, ct1, ct2, ct1_tan, ct2_tan, eps, q,
     recon: 0 conservative, 1 characteristic variables, fallback: 1 first-order
-    fallback at non-physical Gauss-point states) override them.  Prescribed
+    fallback at non-physical Gauss-point states, scheme: "teno_d" (default),
+    "weno_ao", "teno5" (q 6 unless given) or "weno_z", d_hi, d_lo, eps_w)
+    override them.  Prescribed
     sides (bc name "prescribed"): states = (A, B), lines = {(axis, end):
     (s0, s_n, s_t)}, far = {(axis, end): "transmissive" | "reflective" |
     "state_b"} (see tgks.h)."""
@@ -150,6 +157,11 @@ def tgks_params_default(ndim, shape=None, dx=None, bc="transmissive", **kw):
         p.bc_lo[d], p.bc_hi[d] = _BC[lo], _BC[hi]
     if "tau" in kw:
         p.tau_mode = _TAU[kw.pop("tau")]
+    if "scheme" in kw:
+        sch = kw.pop("scheme")
+        p.scheme = _SCHEME[sch] if isinstance(sch, str) else int(sch)
+        if p.scheme == SCHEME_TENO5 and "q" not in kw:
+            p.q = 6  # the TENO5 power of Sec. 4.1
     states, lines, far = kw.pop("states", None), kw.pop("lines", None), kw.pop("far", None)
     if states is not None:
         for k in range(2):
@@ -254,6 +266,15 @@ def tgks_flop_counts(params):
     _check(lib().tgks_flop_counts(C.byref(params), out, 8), "tgks_flop_counts")
     keys = ("normal", "face", "face_stage2", "update1", "update2", "face_transcendentals", "face_divisions", "cfl")
     return {k: out[i] for i, k in enumerate(keys)}
+
+
+def tgks_teno_flag_host(params, Q, fast=True):
+    """The kernels' TENO-D selection of five host values (verification)."""
+    q = (C.c_double * 5)(*[float(v) for v in Q])
+    f = lib().tgks_teno_flag_host(C.byref(params), q, int(bool(fast)))
+    if f < 0:
+        raise TgksError("tgks_teno_flag_host: invalid argument")
+    return f
 
 
 def tgks_measure_peaks(stream=None):

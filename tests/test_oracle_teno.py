@@ -181,3 +181,19 @@ def test_selection_on_roundoff_level_indicators(orc):
     out, f = orc.teno_face(Q)
     np.testing.assert_allclose(out, [3.7, 0.0, 3.7, 0.0], rtol=0, atol=1e-14)
     assert f != 1
+
+
+@pytest.mark.parametrize("flag", [1, 2, 4, 8, 6, 10, 12, 14])
+def test_canonical_gauss_order_matches_plain_evaluation(orc, flag):
+    """The 3-D first sweep evaluates the selected polynomial at the Gauss
+    points in a fixed operation order (its results feed the second sweep's
+    selections); on random data it equals the plain evaluation of the
+    selected candidates' monomials to rounding, for the large stencil and
+    every combination of surviving small stencils."""
+    rng = np.random.default_rng(flag)
+    for _ in range(20):
+        Q = rng.normal(size=5) * 10.0 ** rng.uniform(-3, 3)
+        a = orc.teno_gauss_canonical(Q, flag)
+        b = orc.teno_eval(Q, flag, gauss=True)
+        scale = np.abs(Q).max()
+        assert np.abs(a - b).max() <= 1e-14 * scale, (flag, a, b)
