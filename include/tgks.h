@@ -174,6 +174,28 @@ int tgks_cfl_dt(tgks_ctx* ctx, const double* W, double cfl, double t, double t_e
 int tgks_step(tgks_ctx* ctx, const double* W_in, double* W_out, const double* dt_dev, uint8_t* flags,
               double* W_star);
 
+/* tgks_step for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): one
+ * S2O4 step of the grid described by p, without a context.  The step's work
+ * buffers (W*, P, face fluxes, counters) are a fixed device array of
+ * tgks_noalloc_capacity() doubles (64 MiB) that each GPU the library runs
+ * on holds until the process ends; the call allocates nothing and calls no
+ * allocating routine.  Grids needing more scratch than that
+ * (tgks_noalloc_need(p) > tgks_noalloc_capacity(): 1-D beyond 698,815
+ * cells, 2-D beyond 590 x 590, 3-D beyond 51^3) return TGKS_EINVAL with
+ * nothing enqueued.  Work goes
+ * to hip_stream (NULL: the default stream); W_in, W_out, dt_dev, flags and
+ * W_star as in tgks_step (the caller's device buffers).  failures (host, or
+ * NULL): if given, the call synchronises the stream and stores the number
+ * of non-physical Gauss-point evaluations of the step.  Every call on one
+ * GPU uses that GPU's array, which keeps the last call's contents (the
+ * counters are cleared by each call): calls that overlap on one GPU, from
+ * two streams or two host threads, race. */
+int64_t tgks_noalloc_capacity(void);
+int64_t tgks_noalloc_need(const tgks_params* p);
+int tgks_step_noalloc(const tgks_params* p, void* hip_stream, const double* W_in, double* W_out,
+                      const double* dt_dev, uint8_t* flags, double* W_star, int64_t* failures);
+
 /* Advance W in place by n_steps S2O4 steps with the CFL step computed on the
  * device before every step (cfl > 0), the last step clipped so that the
  * time does not pass t_end when t_end > 0 (further steps are no-ops), or

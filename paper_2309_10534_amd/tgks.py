@@ -88,6 +88,12 @@ def lib():
     L.tgks_gp_flux_vjp_host.argtypes = [P, dp, dp, dp, dp, C.c_double, dp, dp]
     L.tgks_gp_flux_vjp_host.restype = C.c_int
     bp = C.POINTER(C.c_int64)
+    L.tgks_noalloc_capacity.argtypes = []
+    L.tgks_noalloc_capacity.restype = C.c_int64
+    L.tgks_noalloc_need.argtypes = [P]
+    L.tgks_noalloc_need.restype = C.c_int64
+    L.tgks_step_noalloc.argtypes = [P, vp, vp, vp, vp, vp, vp, bp]
+    L.tgks_step_noalloc.restype = C.c_int
     L.tgks_batch_create.argtypes = [P, C.c_int32, vp, C.POINTER(vp)]
     L.tgks_batch_destroy.argtypes = [vp]
     L.tgks_batch_set_stream.argtypes = [vp, vp]
@@ -215,6 +221,37 @@ def tgks_step(ctx, W_in, W_out, dt_dev, flags=None, W_star=None):
     n = tgks_state_size(ctx)
     fl = _ptr(flags, tgks_flag_bytes(ctx), torch.uint8) if flags is not None else None
     _check(lib().tgks_step(ctx, _ptr(W_in, n), _ptr(W_out, n), _ptr(dt_dev, 1), fl, _ptr(W_star, n)), "tgks_step")
+
+
+def tgks_noalloc_capacity():
+    """Doubles of the scratch array of tgks_step_noalloc."""
+    return int(lib().tgks_noalloc_capacity())
+
+
+def tgks_noalloc_need(params):
+    """Doubles of scratch one tgks_step_noalloc of this grid uses."""
+    return int(lib().tgks_noalloc_need(C.byref(params)))
+
+
+def tgks_step_noalloc(params, W_in, W_out, dt_dev, flags=None, W_star=None, stream=None, failures=False):
+    """tgks_step without a context: the library allocates nothing (its work
+    buffers are a fixed device array).  failures=True synchronises and
+    returns the count of non-physical Gauss-point evaluations."""
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    D, nc = params.ndim, params.ndim + 2
+    cells = params.n[0] * params.n[1] * params.n[2]
+    n = nc * cells
+    fl = None
+    if flags is not None:
+        # flag buffer of include/tgks.h: normal planes, then the tangential ones
+        faces = sum(cells // params.n[d] * (params.n[d] + 1) for d in range(D))
+        fl = _ptr(flags, D * n + (4 if D == 2 else 16 if D == 3 else 0) * nc * faces, torch.uint8)
+    f = C.c_int64(0)
+    _check(lib().tgks_step_noalloc(C.byref(params), C.c_void_p(s.cuda_stream), _ptr(W_in, n), _ptr(W_out, n),
+                                   _ptr(dt_dev, 1), fl, _ptr(W_star, n), C.byref(f) if failures else None),
+           "tgks_step_noalloc")
+    return f.value if failures else None
 
 
 def tgks_run(ctx, W, n_steps, cfl=0.0, t_end=0.0, fixed_dt=0.0, time_dev=None, use_graph=False):
