@@ -79,6 +79,9 @@ def parse():
     ap.add_argument("--reps", type=int, default=5, help="timed runs of the headline (median reported)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-schemes", action="store_true", help="skip the comparison-scheme workloads")
+    ap.add_argument("--only", choices=["schemes", "characteristic", "batched2d", "tgv3d"],
+                    help="after the headline, run this one workload alone in a short form (kernel profiles: "
+                         "no per-instance loops, --tgv-steps / --batch-steps steps)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched 1-D/2-D Riemann sets")
     ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--batch-instances", type=int, default=256)
@@ -136,7 +139,7 @@ def cpu_baseline(W0, dx, n, target_s):
             "build": "g++ -O3 -march=native -ffp-contract=off -fopenmp (oracle/build.py, native=True)"}
 
 
-def batched(dim, seed, n_inst, steps, ranges=None, recon=0, fallback=0):
+def batched(dim, seed, n_inst, steps, ranges=None, recon=0, fallback=0, per_instance=True):
     """Batched set of seeded uneven Riemann instances (1-D: N ~ U{64..1024};
     2-D: N x N, N ~ U{64..512}; rho log-uniform [0.1, 10], p log-uniform
     [0.01, 1000], velocities uniform [-2, 2]; transmissive, CFL 0.5): one
@@ -176,6 +179,11 @@ def batched(dim, seed, n_inst, steps, ranges=None, recon=0, fallback=0):
     tgks.tgks_batch_destroy(b)
     Wb = tgks.unpack(W, offs, shapes)
 
+    updates = int((cells * taken).sum())
+    if not per_instance:  # the batched run alone (kernel profiles)
+        return {"workload": f"batched_{dim}d_riemann_{n_inst}_instances_seed{seed}_{steps}_steps",
+                "cell_updates": updates, "batched": {"value": round(updates / t_batch / 1e6, 3),
+                                                     "unit": "Mcell-updates/s", "tile": tile}}
     # plain per-instance loop on the same stream, same tile shape
     ctxs = [tgks.tgks_create(p) for p in params]
     for c in ctxs:
@@ -193,7 +201,6 @@ def batched(dim, seed, n_inst, steps, ranges=None, recon=0, fallback=0):
                for a, s_ in zip(Wb, Ws))
     for c in ctxs:
         tgks.tgks_destroy(c)
-    updates = int((cells * taken).sum())
     return {
         "workload": f"batched_{dim}d_riemann_{n_inst}_instances_seed{seed}_{steps}_steps"
                     + ("" if ranges is None else "_" + "_".join(f"{k}{v[0]}-{v[1]}" for k, v in ranges.items()))
@@ -211,7 +218,7 @@ def batched(dim, seed, n_inst, steps, ranges=None, recon=0, fallback=0):
     }
 
 
-def characteristic(n=1024, seed=1, steps=100, n_inst=256):
+def characteristic(n=1024, seed=1, steps=100, n_inst=256, instances=True):
     """Characteristic-variable reconstruction (option): the 2-D
     four-quadrant workload (n^2, `seed`, CFL 0.5, `steps` steps from t = 0)
     timed with characteristic and with conservative variables, the face
@@ -261,6 +268,8 @@ def characteristic(n=1024, seed=1, steps=100, n_inst=256):
             out["conservative_value"] = round(n * n * steps / el / 1e6, 3)
         tgks.tgks_destroy(ctx)
     out["cost_ratio"] = round(out["conservative_value"] / out["value"], 3)
+    if not instances:  # the 1024^2 runs alone (kernel profiles)
+        return out
 
     free = {}
     for dim, iseed in ((1, 1), (2, 2)):
@@ -739,6 +748,18 @@ def main():
                                         "frac_of_measured_fp64": round(achieved / meas_tflops, 4)}},
         "kernel_ms_per_step": {k: round(v[0] / args.steps, 5) for k, v in kt.items()},
     }
+    if args.only:
+        print(f"[bench] only {args.only}", file=sys.stderr, flush=True)
+        if args.only == "schemes":
+            out["schemes"] = schemes(n=n, seed=args.seed, steps=args.batch_steps)
+        elif args.only == "characteristic":
+            out["characteristic"] = characteristic(steps=args.batch_steps, instances=False)
+        elif args.only == "batched2d":
+            out["batched"] = [batched(2, 2, args.batch_instances, args.batch_steps, per_instance=False)]
+        else:
+            out["tgv3d"] = tgv3d(steps=args.tgv_steps)
+        print(json.dumps(strict_json(out), allow_nan=False), flush=True)
+        return
     if not args.no_batched:
         # the stated state ranges, and a milder 2-D set in which every
         # instance runs all steps (without a positivity limiter most 2-D

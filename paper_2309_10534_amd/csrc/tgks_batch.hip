@@ -272,8 +272,8 @@ int tgks_batch_create(const tgks_params* p, int32_t n_inst, void* stream, tgks_b
     I.fc.c1 = p[i].c1;
     I.fc.c2 = p[i].c2;
     I.fc.tau_mode = p[i].tau_mode;
-    I.tn = {p[i].ct1, p[i].ct2, p[i].eps, p[i].q};
-    I.tt = {p[i].ct1_tan, p[i].ct2_tan, p[i].eps, p[i].q};
+    I.tn = teno_cfg(p[i].ct1, p[i].ct2, p[i].eps, p[i].q);
+    I.tt = teno_cfg(p[i].ct1_tan, p[i].ct2_tan, p[i].eps, p[i].q);
     I.gamma = p[i].gamma;
     I.mu = p[i].mu;
     I.woff = woff;

@@ -264,8 +264,8 @@ void init_ctx_host(tgks_ctx* c, const tgks_params* p, void* stream) {
   c->fc.c1 = p->c1;
   c->fc.c2 = p->c2;
   c->fc.tau_mode = p->tau_mode;
-  c->tn = {p->ct1, p->ct2, p->eps, p->q};
-  c->tt = {p->ct1_tan, p->ct2_tan, p->eps, p->q};
+  c->tn = teno_cfg(p->ct1, p->ct2, p->eps, p->q);
+  c->tt = teno_cfg(p->ct1_tan, p->ct2_tan, p->eps, p->q);
   c->sc = {p->ct1, p->eps, p->q, p->d_hi, p->d_lo, p->eps_w};
   for (int d = 0; d < 3; ++d) {
     long long nf = 1;
@@ -535,7 +535,7 @@ extern "C" {
 
 int tgks_teno_flag_host(const tgks_params* p, const double* Q, int32_t fast) {
   if (check_params(p) || !Q) return TGKS_EINVAL;
-  const TenoCfg c{p->ct1, p->ct2, p->eps, p->q};
+  const TenoCfg c = teno_cfg(p->ct1, p->ct2, p->eps, p->q);
   return (int)(fast ? teno_flag<true>(Q, c) : teno_flag<false>(Q, c));
 }
 

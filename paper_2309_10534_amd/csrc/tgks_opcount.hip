@@ -368,8 +368,8 @@ int tgks_flop_counts(const tgks_params* p, double* out, int32_t nout) {
   c.fc.c1 = p->c1;
   c.fc.c2 = p->c2;
   c.fc.tau_mode = p->tau_mode;
-  c.tn = {p->ct1, p->ct2, p->eps, p->q};
-  c.tt = {p->ct1_tan, p->ct2_tan, p->eps, p->q};
+  c.tn = teno_cfg(p->ct1, p->ct2, p->eps, p->q);
+  c.tt = teno_cfg(p->ct1_tan, p->ct2_tan, p->eps, p->q);
   c.sc = {p->ct1, p->eps, p->q, p->d_hi, p->d_lo, p->eps_w};
   tgks_opcount::Tally t1;
   long long f1, f2;

@@ -25,8 +25,22 @@ def test_strict_json():
     assert json.loads(line) == {"a": None, "b": [1.0, None], "c": {"d": None}}
 
 
-def test_traffic_bound_to_sources():
+def test_traffic_bound_to_sources(monkeypatch):
+    """The counters' traffic is reported only for the kernel sources, tile
+    shape and kernel they were taken with."""
+    import hashlib
+
     import bench
-    assert bench.measured_traffic("face_xy", bench.TRAFFIC["tile"]) is not None
-    assert bench.measured_traffic("face_xy", bench.TRAFFIC["tile"] + 1) is None
-    assert bench.measured_traffic("no_such_kernel", bench.TRAFFIC["tile"]) is None
+    h = hashlib.sha256()
+    for f in bench.TRAFFIC_SOURCES:
+        with open(os.path.join(bench.ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    current = h.hexdigest()[:16]
+    tile = bench.TRAFFIC["tile"]
+    monkeypatch.setitem(bench.TRAFFIC, "sha", current)
+    t = bench.measured_traffic("face_xy", tile)
+    assert t is not None and t > 0
+    assert bench.measured_traffic("face_xy", tile + 1) is None
+    assert bench.measured_traffic("no_such_kernel", tile) is None
+    monkeypatch.setitem(bench.TRAFFIC, "sha", "0" * 16)
+    assert bench.measured_traffic("face_xy", tile) is None

@@ -80,22 +80,116 @@ def stencils(rng, n):
     return out
 
 
-@pytest.mark.parametrize("ct1", [1e-7, 1e-5, 0.25])
-def test_teno_flag_shortcut_is_exact(orc, ct1):
-    """The kernels decide certain large-stencil selections without the
-    weights (b_3 <= 4 b_k, C_T1 <= 1e-5); over stencils of every kind the
-    flag equals the one from the weights of Eq. 4.5 bit for bit, and both
-    equal the oracle's selection (finite inputs)."""
+@pytest.mark.parametrize("ct1,ct2,eps", [(1e-7, 1e-5, 1e-40), (1e-5, 1e-6, 1e-40), (1e-7, 2e-6, 1e-6),
+                                         (0.25, 1e-5, 1e-40), (1e-7, 0.3, 1e-40), (1e-7, 1e-5, 1e-300)])
+def test_teno_flag_shortcut_is_exact(orc, ct1, ct2, eps):
+    """The kernels decide certain selections without the weights (ratios
+    of b_3 and b_k to min b_k derived from C_T1, C_T2); over stencils of
+    every kind the flag equals the one from the weights of Eq. 4.5 bit for
+    bit, and both equal the oracle's selection (finite inputs).  Constants
+    with last-bit noise reject the large stencil, smooth data keep it."""
     from paper_2309_10534_amd import tgks
     p = tgks.tgks_params_default(1, [10], [0.1])
-    p.ct1 = ct1
+    p.ct1, p.ct2, p.eps = ct1, ct2, eps
     rng = np.random.default_rng(7)
-    n_fast = 0
+    seen = set()
     for Q in stencils(rng, 20000):
         a = tgks.tgks_teno_flag_host(p, Q, fast=True)
         b = tgks.tgks_teno_flag_host(p, Q, fast=False)
         assert a == b, Q
         if np.all(np.isfinite(Q)):
-            assert a == orc.teno_select(Q, ct1=ct1), Q
-        n_fast += a == 1
-    assert n_fast > 2000
+            assert a == orc.teno_select(Q, ct1=ct1, ct2=ct2, eps=eps), Q
+        seen.add(a)
+    assert 1 in seen and 14 in seen and len(seen) >= 4, seen
+
+
+@pytest.mark.parametrize("ct1,ct2", [(1e-7, 1e-5), (1e-5, 1e-6), (0.2, 0.2)])
+def test_teno_flag_shortcut_at_decision_boundaries(ct1, ct2):
+    """Along segments between stencils of different flags, the point where
+    the weights' decision changes is found by bisection to the last bit;
+    at every stencil within a few ulps of it on either side the shortcut
+    returns the weights' flag (it never claims a decision that rounding
+    could flip)."""
+    from paper_2309_10534_amd import tgks
+    p = tgks.tgks_params_default(1, [10], [0.1])
+    p.ct1, p.ct2 = ct1, ct2
+    rng = np.random.default_rng(11)
+    flag = lambda Q, fast: tgks.tgks_teno_flag_host(p, Q, fast=fast)
+    found = 0
+    for _ in range(300):
+        A = rng.normal(size=5) * 10.0 ** rng.uniform(-3, 1)
+        B = A.copy()
+        B[rng.integers(0, 5)] += rng.normal() * 10.0 ** rng.uniform(-3, 1)
+        fa, fb = flag(A, False), flag(B, False)
+        if fa == fb:
+            continue
+        lo, hi = 0.0, 1.0
+        for _ in range(70):
+            mid = 0.5 * (lo + hi)
+            if mid in (lo, hi):
+                break
+            if flag(A + mid * (B - A), False) == fa:
+                lo = mid
+            else:
+                hi = mid
+        found += 1
+        t = lo
+        for _ in range(8):
+            t = np.nextafter(t, -1.0)
+        for _ in range(16):
+            Q = A + t * (B - A)
+            assert flag(Q, True) == flag(Q, False), (ct1, ct2, Q.tolist())
+            t = np.nextafter(t, 2.0)
+    assert found > 50
+
+
+# Stencils on which each certain-decision bound is (nearly) reached, and the
+# indicator that is placed at the bound relative to min(b_0, b_1, b_2):
+# equal small indicators (large stencil kept), one smooth small stencil
+# with two rougher ones (large stencil rejected: (0, 0, 0, 1, 4) has
+# beta_3 = 1.7 beta_1 and beta_2 = 3.3 beta_1; a small one dropped), two
+# equal smooth small stencils with a rougher third (a small one kept).
+BOUND_CASES = [
+    ("keep_large", [0.75, 1.0, 0.0, 1.0, 0.75], 3, lambda c1, c2: ((1 / c1 - 1) / 3) ** (1 / 7)),
+    ("reject_large", [0.0, 0.0, 0.0, 1.0, 4.0], 3, lambda c1, c2: (1 / c1 - 1) ** (1 / 7)),
+    ("keep_small", [2.5, 1.0, 0.0, 1.0, 2.5], 1, lambda c1, c2: ((1 / c2 - 1) / 2) ** (1 / 7)),
+    ("drop_small", [0.0, 0.0, 0.0, 1.0, 100.0], 1, lambda c1, c2: (1 / c2 - 1) ** (1 / 7)),
+]
+
+
+@pytest.mark.parametrize("ct1,ct2", [(1e-7, 1e-5), (1e-5, 1e-5), (1e-6, 2e-5)])
+@pytest.mark.parametrize("case", BOUND_CASES, ids=[c[0] for c in BOUND_CASES])
+def test_teno_flag_shortcut_at_worst_case_bounds(orc, ct1, ct2, case):
+    """The selection rule (Eqs. 4.6-4.7, 4.11-4.12) on gamma_k = b_k^-7
+    decides from ratios of the b_k alone at worst-case stencils: with the
+    three small b equal, the large stencil is kept iff b_3 / b <=
+    ((1 / C_T1 - 1) / 3)^(1/7); with one smooth small stencil and two
+    infinitely rough ones, it is kept iff b_3 / m <= (1 / C_T1 - 1)^(1/7),
+    and a second small stencil is kept iff b_k / m <= (1 / C_T2 - 1)^(1/7);
+    with two equal smooth ones, the third is kept iff b_k / m <=
+    ((1 / C_T2 - 1) / 2)^(1/7).  eps (b_k = beta_k + eps) places the ratio
+    at the bound times (1 +- delta); at every point the shortcut returns the
+    weights' flag and the oracle's.  A shortcut that claimed a decision a
+    thousandth beyond its bound fails here."""
+    from paper_2309_10534_amd import tgks
+    name, Q, k, bound = case
+    Q = np.array(Q)
+    be = np.asarray(orc.beta(Q), dtype=float)
+    p = tgks.tgks_params_default(1, [10], [0.1])
+    p.ct1, p.ct2 = ct1, ct2
+    rho0 = bound(ct1, ct2)
+    m = be[:3].min()
+    decided = set()
+    for delta in (-1e-3, -1e-6, -1e-9, -1e-12, 1e-12, 1e-9, 1e-6, 1e-3):
+        rho = rho0 * (1 + delta)
+        eps = (be[k] - rho * m) / (rho - 1)
+        assert eps > 1e-40, (name, be.tolist(), rho)
+        p.eps = eps
+        a = tgks.tgks_teno_flag_host(p, Q, fast=True)
+        b = tgks.tgks_teno_flag_host(p, Q, fast=False)
+        assert a == b == orc.teno_select(Q, ct1=ct1, ct2=ct2, eps=eps), (name, delta, a, b)
+        decided.add((delta > 0, b))
+    # the bound separates two decisions: it is reached exactly for equal
+    # small indicators and to a few parts in 1e6 (the rough stencils' own
+    # gamma) for the others
+    assert len({f for _, f in decided}) == 2, (name, sorted(decided))
