@@ -31,41 +31,34 @@ namespace tgks {
 struct TenoCfg {
   double ct1, ct2, eps;
   int q;
-  // ratios to min(b_0, b_1, b_2) at which teno_flag's decisions are certain
-  // (keep / reject the large stencil, keep / drop a small one); all 0 where
-  // the certain decisions are off
-  double r_keep, r_rej, r_skeep, r_sdrop;
+  int fast;  // teno_flag may decide from the fixed ratios (teno_cfg)
 };
 
-// The selection parameters with the ratios of the certain decisions.  With
-// b_k = beta_k + eps, gamma_k = b_k^-7 (q = 7) and m = min(b_0, b_1, b_2),
-// whose gamma is the largest of the small stencils':
-//   b_3 <= K m: gamma_3 / sum_{k<=3} gamma >= 1 / (3 K^7 + 1) (the three
-//       small gammas at most gamma_max each), at least C_T1 for
-//       3 K^7 = 1 / C_T1 - 1: the large stencil is kept (Eq. 4.7);
-//   b_3 > R m: gamma_3 / sum < 1 / (R^7 + 1) (the sum holds gamma_max),
-//       below C_T1 for R^7 = 1 / C_T1 - 1: rejected;
-//   then b_k <= S m: gamma_k / sum_{k<3} gamma >= 1 / (2 S^7 + 1), at least
-//       C_T2 for 2 S^7 = 1 / C_T2 - 1 (kept, Eq. 4.12), and b_k > T m:
-//       gamma_k / sum < 1 / (T^7 + 1), below C_T2 for T^7 = 1 / C_T2 - 1
-//       (dropped).
-// Each bound is reached in the limit (equal small indicators for K and S,
-// the other small stencils infinitely rough for R and T).  Each ratio
-// carries a relative margin of 1e-9 towards the undecided side, far above
-// the rounding of the weights' evaluation (a few ulps of b^7, its
-// reciprocal and the sums) and of pow here.  On only for q = 7,
-// eps >= 1e-40 (b^7 and 1 / b^7 stay finite and normal), 0 < C_T1 < 0.5,
-// 0 < C_T2 < 0.25.
+// The selection parameters, with fast set where the fixed ratios of
+// teno_flag's certain decisions hold.  With b_k = beta_k + eps,
+// gamma_k = b_k^-7 (q = 7) and m = min(b_0, b_1, b_2), whose gamma is the
+// largest of the small stencils':
+//   b_3 <= 4 m: gamma_3 / sum_{k<=3} gamma >= 1 / (3 4^7 + 1) (the three
+//       small gammas at most gamma_max each): the large stencil is kept
+//       (Eq. 4.7) if C_T1 <= 1 / (3 4^7 + 1) = 2.03e-5;
+//   b_3 > 16 m: gamma_3 / sum < 1 / (16^7 + 1) (the sum holds gamma_max):
+//       rejected if C_T1 >= 1 / (16^7 + 1) = 3.7e-9;
+//   then b_k <= 4 m: gamma_k / sum_{k<3} gamma >= 1 / (2 4^7 + 1): kept
+//       (Eq. 4.12) if C_T2 <= 3.05e-5; b_k > 8 m: gamma_k / sum <
+//       1 / (8^7 + 1): dropped if C_T2 >= 4.8e-7.
+// Each bound is reached in the limit (equal small indicators for the keeps,
+// the other small stencils infinitely rough for the rejections).  The
+// ratios are powers of two (exact products), and the cut-offs must clear
+// each bound by a relative 1e-9, far above the rounding of the weights'
+// evaluation (a few ulps of b^7, its reciprocal and the sums).  Also
+// q = 7 and eps >= 1e-40 (b^7 and 1 / b^7 stay finite and normal).  The
+// paper's C_T1 = 1e-7, C_T2 = 1e-5 are inside.
 inline TenoCfg teno_cfg(double ct1, double ct2, double eps, int q) {
-  TenoCfg c{ct1, ct2, eps, q, 0.0, 0.0, 0.0, 0.0};
-  if (q == 7 && eps >= 1e-40 && ct1 > 0.0 && ct1 < 0.5 && ct2 > 0.0 && ct2 < 0.25) {
-    const double d = 1e-9, p = 1.0 / 7.0;
-    c.r_keep = pow((1.0 / (ct1 * (1.0 + d)) - 1.0) / 3.0, p) * (1.0 - d);
-    c.r_rej = pow(1.0 / (ct1 * (1.0 - d)) - 1.0, p) * (1.0 + d);
-    c.r_skeep = pow((1.0 / (ct2 * (1.0 + d)) - 1.0) / 2.0, p) * (1.0 - d);
-    c.r_sdrop = pow(1.0 / (ct2 * (1.0 - d)) - 1.0, p) * (1.0 + d);
-  }
-  return c;
+  const double d = 1e-9;
+  const bool ok = q == 7 && eps >= 1e-40 && ct1 * (1.0 + d) <= 1.0 / (3.0 * 16384.0 + 1.0) &&
+                  ct1 * (1.0 - d) >= 1.0 / (268435456.0 + 1.0) && ct2 * (1.0 + d) <= 1.0 / (2.0 * 16384.0 + 1.0) &&
+                  ct2 * (1.0 - d) >= 1.0 / (2097152.0 + 1.0);
+  return TenoCfg{ct1, ct2, eps, q, ok ? 1 : 0};
 }
 
 // ---------------------------------------------------------------------------
@@ -74,17 +67,22 @@ inline TenoCfg teno_cfg(double ct1, double ct2, double eps, int q) {
 // delta_{2,2}.
 //
 // FAST: decide without the weights where the decision is certain (the
-// ratios of teno_cfg); the weights (four correctly rounded divisions) would
-// give the same flag bit for bit.  A NaN or b >= 1e40 fails the tests and
-// takes the full evaluation.  Smooth data keeps the large stencil here;
-// constant data (the quadratics' indicators vanish exactly, the quartic's
-// keeps a rounding residue) rejects it here with all three quadratics kept.
-// On the 1024^2 four-quadrant Riemann problem the merged 2-D face kernel
-// takes 0.548 ms per launch with fixed ratios 4, 16, 4, 8 (C_T <= 1e-5),
-// 0.585 ms without.  The operation-counting type and FAST = false (the host
-// check) always evaluate the weights.
+// fixed ratios of teno_cfg, when its fast flag is set); the weights (four
+// correctly rounded divisions) would give the same flag bit for bit.  A
+// NaN or b >= 1e40 fails the tests and takes the full evaluation.  Smooth
+// data keeps the large stencil here; constant data (the quadratics'
+// indicators vanish exactly, the quartic's keeps a rounding residue)
+// rejects it here with all three quadratics kept.  It pays only where
+// whole wavefronts are decided here: the 3-D kernels use it (Taylor-Green
+// vortex, smooth), the 1-D and 2-D kernels do not (on the four-quadrant
+// Riemann problem it saves 8 % of the face kernel's time in the first 20
+// steps and costs 4 % over 500, once most wavefronts mix both paths).
+// The ratios are literals so that they take no scalar registers (ratios
+// held in the kernel arguments made the 2-D face kernel spill scalar
+// registers into vector lanes: 286 lane reads instead of 54).  The
+// operation-counting type always evaluates the weights.
 // ---------------------------------------------------------------------------
-template <bool FAST = true, class R>
+template <bool FAST = false, class R>
 TGKS_HD unsigned teno_flag(const R* Q, const TenoCfg& c) {
 #pragma clang fp contract(off)
   const R a = Q[0], b = Q[1], cc = Q[2], d = Q[3], e = Q[4];
@@ -109,13 +107,13 @@ TGKS_HD unsigned teno_flag(const R* Q, const TenoCfg& c) {
   beta[3] = (((s1 * s1) + (13.0 / 3.0) * (s2 * s2)) + (781.0 / 20.0) * (P3 * P3)) +
             (1421461.0 / 2275.0) * (P4 * P4);
   if constexpr (FAST && std::is_same_v<R, double>) {
-    if (c.r_keep > 0.0) {
+    if (c.fast) {
       const R b0 = beta[0] + c.eps, b1 = beta[1] + c.eps, b2 = beta[2] + c.eps, b3 = beta[3] + c.eps;
       if ((b0 + b1) + (b2 + b3) < 1e40) {
         const R m = fmin(fmin(b0, b1), b2);
-        if (b3 <= c.r_keep * m) return 1u;
-        if (b3 > c.r_rej * m) {
-          const R lo = c.r_skeep * m, hi = c.r_sdrop * m;
+        if (b3 <= 4.0 * m) return 1u;
+        if (b3 > 16.0 * m) {
+          const R lo = 4.0 * m, hi = 8.0 * m;
           const bool sure = !(b0 > lo && b0 <= hi) && !(b1 > lo && b1 <= hi) && !(b2 > lo && b2 <= hi);
           if (sure) return (b0 <= lo ? 2u : 0u) | (b1 <= lo ? 4u : 0u) | (b2 <= lo ? 8u : 0u);
         }

@@ -723,7 +723,7 @@ __global__ __launch_bounds__(256) void recon3d_kernel(StageArgs a) {
     q3[AX] += s - 2;
     Q[s] = load_cell(g, a.W, c, q3[0], q3[1], q3[2]);
   }
-  const unsigned fl = teno_flag(Q, a.tn);
+  const unsigned fl = teno_flag<true>(Q, a.tn);
   double o[4];
   teno_face(Q, fl, o);
   const double idn = 1.0 / g.dx[AX];
@@ -773,15 +773,20 @@ __global__ __launch_bounds__(L3 * B3_1 * B3_2, 2) void face3d_kernel(StageArgs a
   const Geom& g = a.g;
   // XCD-aware order: workgroups are dealt to the 8 XCDs in turn; the
   // logical tiles are renumbered so that each XCD walks a contiguous range
-  // with the face plane fastest, and planes that share cache lines of the
-  // normal reconstruction meet in one L2
+  // in which tiles that share cache lines of the normal reconstruction
+  // (x fastest in memory) follow each other and meet in one L2: for the
+  // x faces the face plane is fastest (neighbouring planes share the lines
+  // along x), for the y and z faces the T1 tile (the z-rows of the y faces'
+  // tiles overlap by four of six, the z faces' tiles cover the x-lines two
+  // cells at a time), then the plane, then the T2 tile.
   const int nb1 = (g.n[T1] + B1 - 1) / B1, nb2 = (g.n[T2] + B2 - 1) / B2;
-  const int nbl = (g.n[AX] + 1) * nb1 * nb2;
+  const int np = g.n[AX] + 1;
+  const int nbl = np * nb1 * nb2;
   const int per = (nbl + 7) / 8;
   const int lb = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
   if (lb >= nbl) return;
-  const int fa = lb % (g.n[AX] + 1);
-  const int t10 = ((lb / (g.n[AX] + 1)) % nb1) * B1, t20 = (lb / ((g.n[AX] + 1) * nb1)) * B2;
+  const int fa = AX == 0 ? lb % np : (lb / nb1) % np;
+  const int t10 = (AX == 0 ? (lb / np) % nb1 : lb % nb1) * B1, t20 = (lb / (np * nb1)) * B2;
   const int tid = threadIdx.x;
   int ext[3] = {g.n[0], g.n[1], g.n[2]};
   ext[AX] += 2;
@@ -825,7 +830,7 @@ __global__ __launch_bounds__(L3 * B3_1 * B3_2, 2) void face3d_kernel(StageArgs a
       Qn[r] = sR[s][c][1][i2][j1 + r];
     }
     double v[2], dv[2], vn[2], dvn[2];
-    const unsigned fw = teno_flag(Qw, a.tt), fq = teno_flag(Qn, a.tt);
+    const unsigned fw = teno_flag<true>(Qw, a.tt), fq = teno_flag<true>(Qn, a.tt);
     // the inputs of the second sweep's selections: one fixed evaluation order
     teno_gauss_exact(Qw, fw, v, dv);
     teno_gauss_exact(Qn, fq, vn, dvn);
@@ -874,7 +879,7 @@ __global__ __launch_bounds__(L3 * B3_1 * B3_2, 2) void face3d_kernel(StageArgs a
       double Q[5];
 #pragma unroll
       for (int k = 0; k < 5; ++k) Q[k] = sS[m2][c][j2 + k][j1][2 * kind + m1];
-      const unsigned fl = teno_flag(Q, a.tt);
+      const unsigned fl = teno_flag<true>(Q, a.tt);
       teno_gauss(Q, fl, v, d);
       if (FLAGS) a.tflags[((long long)4 * NC + ((m1 * 3 + kind) * 2 + m2) * NC + c) * nf + fid] = (uint8_t)fl;
     }

@@ -148,18 +148,31 @@ def test_teno_flag_shortcut_at_decision_boundaries(ct1, ct2):
 # equal small indicators (large stencil kept), one smooth small stencil
 # with two rougher ones (large stencil rejected: (0, 0, 0, 1, 4) has
 # beta_3 = 1.7 beta_1 and beta_2 = 3.3 beta_1; a small one dropped), two
-# equal smooth small stencils with a rougher third (a small one kept).
+# equal smooth small stencils with a rougher third and a rougher quartic
+# (a small one kept: (1, 0, 0, -1, -1/2) has beta_0 = beta_1 exactly,
+# beta_2 = 4.1 beta_0, beta_3 = 18 beta_0, so the large stencil is
+# rejected for certain at the bound).
 BOUND_CASES = [
     ("keep_large", [0.75, 1.0, 0.0, 1.0, 0.75], 3, lambda c1, c2: ((1 / c1 - 1) / 3) ** (1 / 7)),
     ("reject_large", [0.0, 0.0, 0.0, 1.0, 4.0], 3, lambda c1, c2: (1 / c1 - 1) ** (1 / 7)),
-    ("keep_small", [2.5, 1.0, 0.0, 1.0, 2.5], 1, lambda c1, c2: ((1 / c2 - 1) / 2) ** (1 / 7)),
+    ("keep_small", [1.0, 0.0, 0.0, -1.0, -0.5], 2, lambda c1, c2: ((1 / c2 - 1) / 2) ** (1 / 7)),
     ("drop_small", [0.0, 0.0, 0.0, 1.0, 100.0], 1, lambda c1, c2: (1 / c2 - 1) ** (1 / 7)),
 ]
 
 
-@pytest.mark.parametrize("ct1,ct2", [(1e-7, 1e-5), (1e-5, 1e-5), (1e-6, 2e-5)])
-@pytest.mark.parametrize("case", BOUND_CASES, ids=[c[0] for c in BOUND_CASES])
-def test_teno_flag_shortcut_at_worst_case_bounds(orc, ct1, ct2, case):
+# cut-off pairs per bound: the paper's (where the stencil reaches the
+# bound), the cut-off at the edge of the range in which the kernels' fixed
+# ratios hold, and just outside it (shortcut off)
+BOUND_CTS = {"keep_large": [(1e-7, 1e-5), (2.0e-5, 1e-5), (2.1e-5, 1e-5)],
+             "reject_large": [(1e-7, 1e-5), (3.8e-9, 1e-5), (3.6e-9, 1e-5)],
+             "keep_small": [(1e-7, 3.0e-5), (1e-7, 3.2e-5)],
+             "drop_small": [(1e-7, 1e-5), (1e-7, 4.8e-7), (1e-7, 4.6e-7)]}
+BOUND_PARAMS = [pytest.param(case, ct1, ct2, id=f"{case[0]}-{ct1:g}-{ct2:g}")
+                for case in BOUND_CASES for ct1, ct2 in BOUND_CTS[case[0]]]
+
+
+@pytest.mark.parametrize("case,ct1,ct2", BOUND_PARAMS)
+def test_teno_flag_shortcut_at_worst_case_bounds(orc, case, ct1, ct2):
     """The selection rule (Eqs. 4.6-4.7, 4.11-4.12) on gamma_k = b_k^-7
     decides from ratios of the b_k alone at worst-case stencils: with the
     three small b equal, the large stencil is kept iff b_3 / b <=
@@ -169,8 +182,10 @@ def test_teno_flag_shortcut_at_worst_case_bounds(orc, ct1, ct2, case):
     with two equal smooth ones, the third is kept iff b_k / m <=
     ((1 / C_T2 - 1) / 2)^(1/7).  eps (b_k = beta_k + eps) places the ratio
     at the bound times (1 +- delta); at every point the shortcut returns the
-    weights' flag and the oracle's.  A shortcut that claimed a decision a
-    thousandth beyond its bound fails here."""
+    weights' flag and the oracle's.  At the edges of the cut-off range in
+    which the kernels' ratios hold the bound lies within 0.3 % of a ratio,
+    just outside the range on its wrong side: a range or ratio a little too
+    wide fails here."""
     from paper_2309_10534_amd import tgks
     name, Q, k, bound = case
     Q = np.array(Q)
@@ -180,10 +195,10 @@ def test_teno_flag_shortcut_at_worst_case_bounds(orc, ct1, ct2, case):
     rho0 = bound(ct1, ct2)
     m = be[:3].min()
     decided = set()
+    assert (be[k] - rho0 * (1 + 1e-3) * m) / (rho0 * (1 + 1e-3) - 1) > 1e-40, (name, rho0, "beyond reach")
     for delta in (-1e-3, -1e-6, -1e-9, -1e-12, 1e-12, 1e-9, 1e-6, 1e-3):
         rho = rho0 * (1 + delta)
         eps = (be[k] - rho * m) / (rho - 1)
-        assert eps > 1e-40, (name, be.tolist(), rho)
         p.eps = eps
         a = tgks.tgks_teno_flag_host(p, Q, fast=True)
         b = tgks.tgks_teno_flag_host(p, Q, fast=False)
