@@ -84,21 +84,32 @@ __device__ __forceinline__ long long face_count(const Geom& g, int ax) {
   return c;
 }
 
-// value of component c (global order) of the cell (i, j, k), ghost cells by
-// the boundary index map
-__device__ __forceinline__ double load_cell(const Geom& g, const double* W, int c, int i, int j, int k) {
-  int f0 = 0, f1 = 0, f2 = 0;
+// offset of the cell (i, j, k) within a component plane, ghost cells by the
+// boundary index map; f0..f2 receive the mirror kinds along each axis
+__device__ __forceinline__ long long cell_offset(const Geom& g, int i, int j, int k, int& f0, int& f1, int& f2) {
+  f0 = f1 = f2 = 0;
   const int ii = map_index(i, g.n[0], g.bclo[0], g.bchi[0], f0);
   const int jj = g.D >= 2 ? map_index(j, g.n[1], g.bclo[1], g.bchi[1], f1) : 0;
   const int kk = g.D >= 3 ? map_index(k, g.n[2], g.bclo[2], g.bchi[2], f2) : 0;
-  double v = W[(long long)c * g.ncell + ((long long)kk * g.n[1] + jj) * g.n[0] + ii];
-  if (c >= 1 && c <= g.D) {
-    // a reflective wall negates the momentum normal to it, a no-slip wall
-    // every momentum component
-    const int fo = c == 1 ? f0 : (c == 2 ? f1 : f2);
-    if ((fo == 1) ^ (f0 == 2) ^ (f1 == 2) ^ (f2 == 2)) v = -v;
-  }
-  return v;
+  return ((long long)kk * g.n[1] + jj) * g.n[0] + ii;
+}
+
+// whether component c (global order) changes sign at a mirrored cell: a
+// reflective wall negates the momentum normal to it, a no-slip wall every
+// momentum component
+__device__ __forceinline__ bool cell_flip(const Geom& g, int c, int f0, int f1, int f2) {
+  if (c < 1 || c > g.D) return false;
+  const int fo = c == 1 ? f0 : (c == 2 ? f1 : f2);
+  return (fo == 1) ^ (f0 == 2) ^ (f1 == 2) ^ (f2 == 2);
+}
+
+// value of component c (global order) of the cell (i, j, k), ghost cells by
+// the boundary index map
+__device__ __forceinline__ double load_cell(const Geom& g, const double* W, int c, int i, int j, int k) {
+  int f0, f1, f2;
+  const long long off = cell_offset(g, i, j, k, f0, f1, f2);
+  const double v = W[(long long)c * g.ncell + off];
+  return cell_flip(g, c, f0, f1, f2) ? -v : v;
 }
 
 // time of the prescribed states in stage STAGE of a step of length dt
@@ -345,20 +356,31 @@ __device__ __forceinline__ void face2d_tile(const StageArgs& a, int bx, int by, 
   const int tid = threadIdx.x;
   const double tb = EX ? boundary_time(a, STAGE, dt) : 0.0;
 
-  // 1. cells of the tile, ghost cells by the index map or prescribed states
-  for (int L = tid; L < NC * LN * LT; L += NT) {
+  // 1. cells of the tile, ghost cells by the index map or prescribed states;
+  //    one thread per cell maps it once and loads its four components
+  for (int L = tid; L < LN * LT; L += NT) {
     int nl, tl;
     if (AX == 0) {
       nl = L % LN;
-      tl = (L / LN) % LT;
+      tl = L / LN;
     } else {
       tl = L % LT;
-      nl = (L / LT) % LN;
+      nl = L / LT;
     }
-    const int c = L / (LN * LT);
     const int pn = f0 - 3 + nl, pt = t0 - 2 + tl;
     const int x = AX == 0 ? pn : pt, y = AX == 0 ? pt : pn;
-    sW[c][tl][nl] = EX ? cell_value(g, a.pb, a.W, c, x, y, tb) : load_cell(g, a.W, c, x, y, 0);
+    if (EX) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) sW[c][tl][nl] = cell_value(g, a.pb, a.W, c, x, y, tb);
+    } else {
+      int m0, m1, m2;
+      const long long off = cell_offset(g, x, y, 0, m0, m1, m2);
+      double v[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) v[c] = a.W[(long long)c * g.ncell + off];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) sW[c][tl][nl] = cell_flip(g, c, m0, m1, m2) ? -v[c] : v[c];
+    }
   }
   __syncthreads();
 
@@ -792,24 +814,34 @@ __global__ __launch_bounds__(L3 * B3_1 * B3_2, 2) void face3d_kernel(StageArgs a
   ext[AX] += 2;
   const long long nr = (long long)ext[0] * ext[1] * ext[2];
 
-  // 1. normal reconstruction of the two cells beside each face position
-  for (int L = tid; L < 2 * NC * 2 * L2 * L1; L += NT) {
-    const int i1 = L % L1;
-    const int i2 = (L / L1) % L2;
-    const int k = (L / (L1 * L2)) % 2;
-    const int c = (L / (2 * L1 * L2)) % NC;
-    const int s = L / (2 * NC * L1 * L2);
+  // 1. normal reconstruction of the two cells beside each face position:
+  //    thread (position, k) maps its tangential position once and loads
+  //    both sides' five components of the value (k = 0) or the normal slope
+  //    (k = 1); x, the fastest axis in memory, runs fastest over threads
+  static_assert(2 * L1 * L2 <= NT, "one thread per position and kind");
+  if (tid < 2 * L1 * L2) {
+    const int p = tid % (L1 * L2), k = tid / (L1 * L2);
+    const int i1 = AX == 1 ? p / L2 : p % L1;
+    const int i2 = AX == 1 ? p % L2 : p / L1;
     int f1 = 0, f2 = 0;
     int e[3];
-    e[AX] = fa + s;  // cell fa - 1 + s along AX, shifted by one
+    e[AX] = fa;  // cell fa - 1 along AX, shifted by one; the right side is the next
     e[T1] = map_index(t10 - 2 + i1, g.n[T1], g.bclo[T1], g.bchi[T1], f1);
     e[T2] = map_index(t20 - 2 + i2, g.n[T2], g.bclo[T2], g.bchi[T2], f2);
     const long long off = ((long long)e[2] * ext[1] + e[1]) * ext[0] + e[0];
-    const int vo = s == 0 ? 2 : 0;
-    double v = a.R[(long long)c * 4 * nr + (vo + k) * nr + off];
-    const bool mom = c >= 1 && c <= 3;
-    if ((c == 1 + T1 && f1 == 1) ^ (c == 1 + T2 && f2 == 1) ^ (mom && f1 == 2) ^ (mom && f2 == 2)) v = -v;
-    sR[s][c][k][i2][i1] = v;
+    const long long sax = AX == 0 ? 1 : (AX == 1 ? (long long)ext[0] : (long long)ext[0] * ext[1]);
+    double v[2][NC];
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) v[s][c] = a.R[(long long)(c * 4 + (s == 0 ? 2 : 0) + k) * nr + off + s * sax];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const bool mom = c >= 1 && c <= 3;
+      const bool neg = (c == 1 + T1 && f1 == 1) ^ (c == 1 + T2 && f2 == 1) ^ (mom && f1 == 2) ^ (mom && f2 == 2);
+#pragma unroll
+      for (int s = 0; s < 2; ++s) sR[s][c][k][i2][i1] = neg ? -v[s][c] : v[s][c];
+    }
   }
   __syncthreads();
 

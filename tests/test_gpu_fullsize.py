@@ -313,7 +313,10 @@ def test_double_mach_960x240_to_t02(torch_dev, recon):
     assert ahead < 1e-12
 
 
-@pytest.mark.parametrize("recon", [0, 1])
+@pytest.mark.parametrize("recon", [0, pytest.param(1, marks=pytest.mark.xfail(
+    strict=False, reason="with characteristic variables the run is rounding-sensitive: builds that differ only "
+                         "in the compiler's instruction order reach t = 1 or stop on a non-physical cell average "
+                         "between t = 0.06 and 0.2 (the fallback acts at Gauss points only)"))])
 def test_viscous_shock_tube_500x250_to_t1(torch_dev, recon):
     """The bench's viscous shock tube run (Sec. 5.8: 500 x 250, Re 200,
     Pr 0.73, CFL 0.2, fallback on) to t = 1 on the device, checked by
