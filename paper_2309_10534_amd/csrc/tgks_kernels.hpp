@@ -357,24 +357,35 @@ __device__ __forceinline__ void face2d_tile(const StageArgs& a, int bx, int by, 
   const double tb = EX ? boundary_time(a, STAGE, dt) : 0.0;
 
   // 1. cells of the tile, ghost cells by the index map or prescribed states;
-  //    one thread per cell maps it once and loads its four components
-  for (int L = tid; L < LN * LT; L += NT) {
-    int nl, tl;
-    if (AX == 0) {
-      nl = L % LN;
-      tl = L / LN;
-    } else {
-      tl = L % LT;
-      nl = L / LT;
+  //    without prescribed sides one thread per cell maps it once and loads
+  //    its four components
+  if (EX) {
+    for (int L = tid; L < NC * LN * LT; L += NT) {
+      int nl, tl;
+      if (AX == 0) {
+        nl = L % LN;
+        tl = (L / LN) % LT;
+      } else {
+        tl = L % LT;
+        nl = (L / LT) % LN;
+      }
+      const int c = L / (LN * LT);
+      const int pn = f0 - 3 + nl, pt = t0 - 2 + tl;
+      sW[c][tl][nl] = cell_value(g, a.pb, a.W, c, AX == 0 ? pn : pt, AX == 0 ? pt : pn, tb);
     }
-    const int pn = f0 - 3 + nl, pt = t0 - 2 + tl;
-    const int x = AX == 0 ? pn : pt, y = AX == 0 ? pt : pn;
-    if (EX) {
-#pragma unroll
-      for (int c = 0; c < NC; ++c) sW[c][tl][nl] = cell_value(g, a.pb, a.W, c, x, y, tb);
-    } else {
+  } else {
+    for (int L = tid; L < LN * LT; L += NT) {
+      int nl, tl;
+      if (AX == 0) {
+        nl = L % LN;
+        tl = L / LN;
+      } else {
+        tl = L % LT;
+        nl = L / LT;
+      }
+      const int pn = f0 - 3 + nl, pt = t0 - 2 + tl;
       int m0, m1, m2;
-      const long long off = cell_offset(g, x, y, 0, m0, m1, m2);
+      const long long off = cell_offset(g, AX == 0 ? pn : pt, AX == 0 ? pt : pn, 0, m0, m1, m2);
       double v[NC];
 #pragma unroll
       for (int c = 0; c < NC; ++c) v[c] = a.W[(long long)c * g.ncell + off];
