@@ -148,18 +148,24 @@ __global__ __launch_bounds__(2 * ATN * ATT) void adj_face2d_kernel(AdjArgs a) {
   const int nN = g.n[AX], nT = g.n[TA];
   const int f0 = blockIdx.x * TN, t0 = blockIdx.y * TT;
   const int tid = threadIdx.x;
-  for (int L = tid; L < NC * LN * LT; L += NT) {
+  // one thread per staged cell: one index map, four component loads
+  for (int L = tid; L < LN * LT; L += NT) {
     int nl, tl;
     if (AX == 0) {
       nl = L % LN;
-      tl = (L / LN) % LT;
+      tl = L / LN;
     } else {
       tl = L % LT;
-      nl = (L / LT) % LN;
+      nl = L / LT;
     }
-    const int c = L / (LN * LT);
     const int pn = f0 - 3 + nl, pt = t0 - 2 + tl;
-    sW[c][tl][nl] = load_cell(g, a.W, c, AX == 0 ? pn : pt, AX == 0 ? pt : pn, 0);
+    int m0, m1, m2;
+    const long long off = cell_offset(g, AX == 0 ? pn : pt, AX == 0 ? pt : pn, 0, m0, m1, m2);
+    double v[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) v[c] = a.W[(long long)c * g.ncell + off];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) sW[c][tl][nl] = cell_flip(g, c, m0, m1, m2) ? -v[c] : v[c];
   }
   __syncthreads();
   const double idn = 1.0 / g.dx[AX];
