@@ -749,12 +749,19 @@ __global__ __launch_bounds__(256) void recon3d_kernel(StageArgs a) {
   p[1] = (int)(r % ext[1]);
   p[2] = (int)(r / ext[1]);
   p[AX] -= 1;
+  // the stencil runs along AX only (the other indices are interior): one
+  // base offset, and the index map along AX for each of its five cells
+  const long long sax = AX == 0 ? 1 : (AX == 1 ? (long long)g.n[0] : (long long)g.n[0] * g.n[1]);
+  int pz[3] = {p[0], p[1], p[2]};
+  pz[AX] = 0;
+  const double* Wc = a.W + (long long)c * g.ncell + ((long long)pz[2] * g.n[1] + pz[1]) * g.n[0] + pz[0];
   double Q[5];
 #pragma unroll
   for (int s = 0; s < 5; ++s) {
-    int q3[3] = {p[0], p[1], p[2]};
-    q3[AX] += s - 2;
-    Q[s] = load_cell(g, a.W, c, q3[0], q3[1], q3[2]);
+    int f[3] = {0, 0, 0};
+    const int m = map_index(p[AX] + s - 2, g.n[AX], g.bclo[AX], g.bchi[AX], f[AX]);
+    const double v = Wc[m * sax];
+    Q[s] = cell_flip(g, c, f[0], f[1], f[2]) ? -v : v;
   }
   const unsigned fl = teno_flag<true>(Q, a.tn);
   double o[4];
