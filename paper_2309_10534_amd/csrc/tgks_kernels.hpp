@@ -595,9 +595,11 @@ __device__ __forceinline__ void face2d_tile(const StageArgs& a, int bx, int by, 
     }
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
-      const double sv = aV[q][1 - m], sd = aD[q][1 - m], sn = aN[q][1 - m];
+      // selects, not an index by the lane's m (which would place the
+      // arrays in scratch memory)
+      const double sv = m ? aV[q][0] : aV[q][1], sd = m ? aD[q][0] : aD[q][1], sn = m ? aN[q][0] : aN[q][1];
       const double rv = lane_xor<1>(sv), rd = lane_xor<1>(sd), rn = lane_xor<1>(sn);
-      const double ov = aV[q][m], od = aD[q][m], on = aN[q][m];
+      const double ov = m ? aV[q][1] : aV[q][0], od = m ? aD[q][1] : aD[q][0], on = m ? aN[q][1] : aN[q][0];
       Wg[0][q] = m == 0 ? ov : rv;
       Wg[1][q] = m == 0 ? rv : ov;
       Dg[0][1][q] = (m == 0 ? od : rd) * idt;
