@@ -277,10 +277,13 @@ int tgks_gp_flux_host(const tgks_params* p, const double* Wl, const double* Wr, 
 
 /* The kernels' stencil selection of five values Q (host arrays), evaluated
  * on the host: the TENO-D flag (bit0 = delta_{3,1}, bits 1..3 = the small
- * stencils' cut-offs; Sec. 4.2) with the normal cut-offs of p, computed with
- * the kernels' shortcut for certain large-stencil decisions (fast != 0) or
- * from the weights of Eq. 4.5 alone (fast == 0).  For verification: both
- * must agree for every input.  Returns the flag, or TGKS_EINVAL. */
+ * stencils' cut-offs; Sec. 4.2) with the normal cut-offs and eps of p,
+ * computed with the shortcut that the 3-D kernels take for certain
+ * decisions (fast != 0; fixed ratios of the smoothness indicators, on only
+ * for q = 7, eps >= 1e-40 and cut-offs in the range where the ratios
+ * hold) or from the weights of Eqs. 4.5-4.12 alone (fast == 0).  For
+ * verification: both must agree for every input.  Returns the flag, or
+ * TGKS_EINVAL. */
 int tgks_teno_flag_host(const tgks_params* p, const double* Q, int32_t fast);
 
 /* ------------------------------------------------------------------------
