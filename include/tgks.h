@@ -277,14 +277,28 @@ int tgks_gp_flux_host(const tgks_params* p, const double* Wl, const double* Wr, 
 
 /* The kernels' stencil selection of five values Q (host arrays), evaluated
  * on the host: the TENO-D flag (bit0 = delta_{3,1}, bits 1..3 = the small
- * stencils' cut-offs; Sec. 4.2) with the normal cut-offs and eps of p,
- * computed with the shortcut that the 3-D kernels take for certain
- * decisions (fast != 0; fixed ratios of the smoothness indicators, on only
- * for q = 7, eps >= 1e-40 and cut-offs in the range where the ratios
- * hold) or from the weights of Eqs. 4.5-4.12 alone (fast == 0).  For
- * verification: both must agree for every input.  Returns the flag, or
- * TGKS_EINVAL. */
+ * stencils' cut-offs; Sec. 4.2) with the normal cut-offs and eps of p.
+ * fast selects the evaluation: 0 from the weights of Eqs. 4.5-4.12 alone
+ * (correctly rounded divisions); 2 as the 1-D and 2-D kernels do, from
+ * approximate reciprocals where a margin makes the decision certain (on
+ * the host the reciprocal is 1/x cut to 24 significant bits); 1 as the 3-D
+ * kernels do, from fixed ratios of the smoothness indicators where they
+ * decide, else from the weights.  The shortcuts are on only for q = 7,
+ * eps >= 1e-40 and cut-offs in the ranges where they are exact; elsewhere
+ * every mode evaluates the weights.
+ * For verification: all three must agree for every input.  Returns the
+ * flag, or TGKS_EINVAL (also for fast outside 0..2). */
 int tgks_teno_flag_host(const tgks_params* p, const double* Q, int32_t fast);
+
+/* The kernels' complementary error function, evaluated on the host: the
+ * half-space moments of a Maxwellian in the flux (Sec. 2.1, the left and
+ * right half-space integrals that the Heaviside split of the initial
+ * distribution produces) hold erfc of the normal velocity times
+ * sqrt(lambda).  A polynomial (a cut Chebyshev series) for (1 + 2|x|)
+ * exp(x^2) erfc(|x|), multiplied by exp(-x^2), which the moments need
+ * anyway.  For
+ * verification.  Returns erfc(x) (0 or 2 at x = +-inf, NaN for NaN). */
+double tgks_erfc_host(double x);
 
 /* ------------------------------------------------------------------------
  * Reverse mode.  The derivative of one S2O4 step W_out = S(W_in) with the

@@ -91,10 +91,10 @@ __global__ __launch_bounds__(128) void adj_face1d_kernel(AdjArgs a) {
 #pragma unroll
     for (int r = 0; r < 6; ++r) Q[r] = load_cell(a.g, a.W, c, f - 3 + r, 0, 0);
     double o[4];
-    teno_face(Q, teno_flag(Q, a.tn), o);
+    teno_face(Q, teno_flag<SEL_FILTER>(Q, a.tn), o);
     Wl[c] = o[2];
     dWl[0][c] = o[3] * idx;
-    teno_face(Q + 1, teno_flag(Q + 1, a.tn), o);
+    teno_face(Q + 1, teno_flag<SEL_FILTER>(Q + 1, a.tn), o);
     Wr[c] = o[0];
     dWr[0][c] = o[1] * idx;
   }
@@ -175,7 +175,7 @@ __global__ __launch_bounds__(2 * ATN * ATT) void adj_face2d_kernel(AdjArgs a) {
     const int c = L / (RN * LT);
     const double* Q = &sW[c][tl][nr];
     double o[4];
-    teno_face(Q, teno_flag(Q, a.tn), o);
+    teno_face(Q, teno_flag<SEL_FILTER>(Q, a.tn), o);
     sR[c][tl][nr][0] = o[0];
     sR[c][tl][nr][1] = o[1] * idn;
     sR[c][tl][nr][2] = o[2];
@@ -205,7 +205,7 @@ __global__ __launch_bounds__(2 * ATN * ATT) void adj_face2d_kernel(AdjArgs a) {
         Qw[r] = sR[c][ft + r][nr][vo];
         Qn[r] = sR[c][ft + r][nr][vo + 1];
       }
-      const unsigned fw = teno_flag(Qw, a.tt), fq = teno_flag(Qn, a.tt);
+      const unsigned fw = teno_flag<SEL_FILTER>(Qw, a.tt), fq = teno_flag<SEL_FILTER>(Qn, a.tt);
       a.TF[((long long)(m * 2 + 0) * NC + c) * nf + fidx] = (uint8_t)fw;
       a.TF[((long long)(m * 2 + 1) * NC + c) * nf + fidx] = (uint8_t)fq;
       teno_gauss(Qw, fw, v, dv);
@@ -334,7 +334,7 @@ __global__ __launch_bounds__(256) void adj_nflags_kernel(AdjArgs a) {
     const int pa = i - 2 + q;
     Q[q] = D == 1 ? load_cell(g, a.W, c, pa, 0, 0) : load_cell(g, a.W, c, AX == 0 ? pa : r, AX == 0 ? r : pa, 0);
   }
-  a.NF[(long long)c * ne + e] = (uint8_t)teno_flag(Q, a.tn);
+  a.NF[(long long)c * ne + e] = (uint8_t)teno_flag<SEL_FILTER>(Q, a.tn);
 }
 
 // preimages of interior index x under the boundary index map among the

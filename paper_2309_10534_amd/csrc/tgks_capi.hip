@@ -536,8 +536,12 @@ extern "C" {
 int tgks_teno_flag_host(const tgks_params* p, const double* Q, int32_t fast) {
   if (check_params(p) || !Q) return TGKS_EINVAL;
   const TenoCfg c = teno_cfg(p->ct1, p->ct2, p->eps, p->q);
-  return (int)(fast ? teno_flag<true>(Q, c) : teno_flag<false>(Q, c));
+  if (fast < 0 || fast > 2) return TGKS_EINVAL;
+  return (int)(fast == 1 ? teno_flag<SEL_RATIO>(Q, c)
+                         : (fast == 2 ? teno_flag<SEL_FILTER>(Q, c) : teno_flag<SEL_EXACT>(Q, c)));
 }
+
+double tgks_erfc_host(double x) { return erfc_exp(x, exp(-x * x)); }
 
 int tgks_gp_flux_host(const tgks_params* p, const double* Wl, const double* Wr, const double* dWl, const double* dWr,
                       double dt, double* F) {

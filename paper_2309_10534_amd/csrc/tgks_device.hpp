@@ -28,16 +28,22 @@
 
 namespace tgks {
 
+// bits of TenoCfg::fast
+constexpr int TENO_RATIO_OK = 1;   // the fixed ratios of teno_flag hold (teno_cfg)
+constexpr int TENO_FILTER_OK = 2;  // the approximate-reciprocal test of teno_flag is valid
+
 struct TenoCfg {
   double ct1, ct2, eps;
   int q;
-  int fast;  // teno_flag may decide from the fixed ratios (teno_cfg)
+  int fast;  // TENO_RATIO_OK | TENO_FILTER_OK where they hold (teno_cfg)
 };
 
-// The selection parameters, with fast set where the fixed ratios of
-// teno_flag's certain decisions hold.  With b_k = beta_k + eps,
-// gamma_k = b_k^-7 (q = 7) and m = min(b_0, b_1, b_2), whose gamma is the
-// largest of the small stencils':
+// The selection parameters, with the fast bits set where teno_flag's
+// shortcuts are exact.
+//
+// TENO_RATIO_OK, fixed ratios of the certain decisions.  With b_k = beta_k
+// + eps, gamma_k = b_k^-7 (q = 7) and m = min(b_0, b_1, b_2), whose gamma
+// is the largest of the small stencils':
 //   b_3 <= 4 m: gamma_3 / sum_{k<=3} gamma >= 1 / (3 4^7 + 1) (the three
 //       small gammas at most gamma_max each): the large stencil is kept
 //       (Eq. 4.7) if C_T1 <= 1 / (3 4^7 + 1) = 2.03e-5;
@@ -53,12 +59,39 @@ struct TenoCfg {
 // evaluation (a few ulps of b^7, its reciprocal and the sums).  Also
 // q = 7 and eps >= 1e-40 (b^7 and 1 / b^7 stay finite and normal).  The
 // paper's C_T1 = 1e-7, C_T2 = 1e-5 are inside.
+//
+// TENO_FILTER_OK, the weights from approximate reciprocals with a margin
+// (teno_flag): q = 7, eps >= 1e-40 and 1e-20 <= C_T1, C_T2 <= 1/2, so that
+// every b^7, weight, sum and threshold of the test is a normal number
+// (b in [eps, 1e40): b^7 and 1 / b^7 in [1e-280, 1e280]; a threshold
+// C_T s >= 1e-20 1e-280 / 2, since the small weights hold at least half of
+// the sum when the large stencil is rejected, C_T1 <= 1/2).
 inline TenoCfg teno_cfg(double ct1, double ct2, double eps, int q) {
   const double d = 1e-9;
   const bool ok = q == 7 && eps >= 1e-40 && ct1 * (1.0 + d) <= 1.0 / (3.0 * 16384.0 + 1.0) &&
                   ct1 * (1.0 - d) >= 1.0 / (268435456.0 + 1.0) && ct2 * (1.0 + d) <= 1.0 / (2.0 * 16384.0 + 1.0) &&
                   ct2 * (1.0 - d) >= 1.0 / (2097152.0 + 1.0);
-  return TenoCfg{ct1, ct2, eps, q, ok ? 1 : 0};
+  const bool filt = q == 7 && eps >= 1e-40 && eps < 1e40 && ct1 >= 1e-20 && ct1 <= 0.5 && ct2 >= 1e-20 &&
+                    ct2 <= 0.5;
+  return TenoCfg{ct1, ct2, eps, q, (ok ? TENO_RATIO_OK : 0) | (filt ? TENO_FILTER_OK : 0)};
+}
+
+// An approximate reciprocal: the device's one-instruction estimate (its
+// error is not assumed: teno_flag measures it by the residual 1 - x r).  On
+// the host, 1 / x with the low 29 bits of the significand cleared (relative
+// error up to 2^-23), so that host checks exercise the same error handling.
+TGKS_HD double rcp_approx(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_rcp(x);
+#else
+  union {
+    double d;
+    uint64_t u;
+  } v;
+  v.d = 1.0 / x;
+  v.u &= ~((uint64_t(1) << 29) - 1);
+  return v.d;
+#endif
 }
 
 // ---------------------------------------------------------------------------
@@ -66,23 +99,48 @@ inline TenoCfg teno_cfg(double ct1, double ct2, double eps, int q) {
 // flag bit0 = delta_{3,1}; if it is 0, bits 1..3 = delta_{0,2}, delta_{1,2},
 // delta_{2,2}.
 //
-// FAST: decide without the weights where the decision is certain (the
-// fixed ratios of teno_cfg, when its fast flag is set); the weights (four
-// correctly rounded divisions) would give the same flag bit for bit.  A
-// NaN or b >= 1e40 fails the tests and takes the full evaluation.  Smooth
-// data keeps the large stencil here; constant data (the quadratics'
-// indicators vanish exactly, the quartic's keeps a rounding residue)
-// rejects it here with all three quadratics kept.  It pays only where
-// whole wavefronts are decided here: the 3-D kernels use it (Taylor-Green
-// vortex, smooth), the 1-D and 2-D kernels do not (on the four-quadrant
-// Riemann problem it saves 8 % of the face kernel's time in the first 20
-// steps and costs 4 % over 500, once most wavefronts mix both paths).
-// The ratios are literals so that they take no scalar registers (ratios
-// held in the kernel arguments made the 2-D face kernel spill scalar
-// registers into vector lanes: 286 lane reads instead of 54).  The
-// operation-counting type always evaluates the weights.
+// The flag is a function of the input bits: the weights gamma_k =
+// (beta_k + eps)^-7 by correctly rounded divisions, summed and compared in
+// one fixed order (SEL_EXACT).  The other modes reach the same flag, bit
+// for bit, with less work where the decision is certain, and evaluate the
+// weights exactly where it is not:
+//
+// SEL_FILTER: approximate reciprocals r_k of p_k = b_k^7 (one instruction
+// each instead of a division) with their residuals e_k = 1 - p_k r_k (one
+// fused multiply-add, rounded once).  If sum |e_k| <= 2^-18, each r_k is
+// within a relative E = 2^-18 (1 + 2^-52) of 1/p_k, so within E + 2^-53
+// of the correctly rounded weight g_k.  The sums of the positive r_k
+// (two or three additions, same order) are then within E + 7 2^-53 of
+// the exact path's sums, and the thresholds C_T s within E + 8 2^-53.  A
+// comparison is certain when r_k clears the threshold by a factor
+// 1 -+ 2^-12 (rounded once more): r_k > tau (1 + 2^-12) gives g_k > T and
+// r_k < tau (1 - 2^-12) gives g_k < T, since 2^-12 exceeds twice E plus
+// ten rounding errors 32-fold.  Undecided inputs (within 2.4e-4 of a
+// cut-off, or a failed residual or range test) take the exact weights;
+// on the benchmarks that is rare, so wavefronts seldom split.  All
+// comparisons are evaluated (no short-circuit branches): one branch, to
+// the exact weights, remains.
+//
+// SEL_RATIO: the fixed ratios of teno_cfg (when TENO_RATIO_OK; no
+// reciprocal at all), then the exact weights.  Smooth data keeps the large
+// stencil there; constant data (the quadratics' indicators vanish exactly,
+// the quartic's keeps a rounding residue) rejects it there with all three
+// quadratics kept.  The 3-D kernels use it (Taylor-Green vortex, smooth;
+// 2.09 ms per face launch, against 2.12 with SEL_FILTER after the ratios
+// and 2.28 with SEL_FILTER alone).  The 1-D and 2-D kernels use SEL_FILTER:
+// on the four-quadrant Riemann problem most wavefronts mix lanes that the
+// ratios decide and lanes they leave open after a few hundred steps (the
+// ratios cost 4 % over 500 steps there, SEL_FILTER saves 3.5 %).
+//
+// A NaN or b >= 1e40 fails the range test (b_0 + .. + b_3 < 1e40) and
+// takes the exact path.  The ratios and margins are literals so that they
+// take no scalar registers (ratios held in the kernel arguments made the
+// 2-D face kernel spill scalar registers into vector lanes).  The
+// operation-counting type always evaluates the exact weights.
 // ---------------------------------------------------------------------------
-template <bool FAST = false, class R>
+constexpr int SEL_EXACT = 0, SEL_FILTER = 1, SEL_RATIO = 2;
+
+template <int MODE = SEL_EXACT, class R>
 TGKS_HD unsigned teno_flag(const R* Q, const TenoCfg& c) {
 #pragma clang fp contract(off)
   const R a = Q[0], b = Q[1], cc = Q[2], d = Q[3], e = Q[4];
@@ -106,8 +164,8 @@ TGKS_HD unsigned teno_flag(const R* Q, const TenoCfg& c) {
   const R s2 = P2 + (123.0 / 455.0) * P4;
   beta[3] = (((s1 * s1) + (13.0 / 3.0) * (s2 * s2)) + (781.0 / 20.0) * (P3 * P3)) +
             (1421461.0 / 2275.0) * (P4 * P4);
-  if constexpr (FAST && std::is_same_v<R, double>) {
-    if (c.fast) {
+  if constexpr (MODE == SEL_RATIO && std::is_same_v<R, double>) {
+    if (c.fast & TENO_RATIO_OK) {
       const R b0 = beta[0] + c.eps, b1 = beta[1] + c.eps, b2 = beta[2] + c.eps, b3 = beta[3] + c.eps;
       if ((b0 + b1) + (b2 + b3) < 1e40) {
         const R m = fmin(fmin(b0, b1), b2);
@@ -118,6 +176,33 @@ TGKS_HD unsigned teno_flag(const R* Q, const TenoCfg& c) {
           if (sure) return (b0 <= lo ? 2u : 0u) | (b1 <= lo ? 4u : 0u) | (b2 <= lo ? 8u : 0u);
         }
       }
+    }
+  }
+  if constexpr (MODE == SEL_FILTER && std::is_same_v<R, double>) {
+    if (c.fast & TENO_FILTER_OK) {
+      const R b0 = beta[0] + c.eps, b1 = beta[1] + c.eps, b2 = beta[2] + c.eps, b3 = beta[3] + c.eps;
+      const bool inr = (b0 + b1) + (b2 + b3) < 1e40;
+      // every comparison evaluated, one branch to the exact weights
+      R p[4], r[4], es = R(0.0);
+      const R bb[4] = {b0, b1, b2, b3};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const R x2 = bb[k] * bb[k];
+        const R x4 = x2 * x2;
+        p[k] = (x4 * x2) * bb[k];
+        r[k] = rcp_approx(p[k]);
+        es += fabs(fma(-p[k], r[k], 1.0));
+      }
+      const R s3 = (r[0] + r[1]) + r[2];
+      const R th1 = c.ct1 * (s3 + r[3]), th2 = c.ct2 * s3;
+      const double up = 1.0 + 0x1p-12, dn = 1.0 - 0x1p-12;
+      const R h2 = th2 * up, l2 = th2 * dn;
+      const bool keep = r[3] > th1 * up, rej = r[3] < th1 * dn;
+      const bool k0 = r[0] > h2, k1 = r[1] > h2, k2 = r[2] > h2;
+      // (bitwise operators: no short-circuit branches)
+      const bool sure = inr & (es <= 0x1p-18) &
+                        (keep | (rej & (k0 | (r[0] < l2)) & (k1 | (r[1] < l2)) & (k2 | (r[2] < l2))));
+      if (sure) return keep ? 1u : ((k0 ? 2u : 0u) | (k1 ? 4u : 0u) | (k2 ? 8u : 0u));
     }
   }
   R g[4];
@@ -707,8 +792,8 @@ TGKS_HD void char_recon_face(double gamma, const R (*C)[D + 2], const TenoCfg& t
     R V[6];
 #pragma unroll
     for (int r = 0; r < 6; ++r) V[r] = char_dot<NC>(L[k], C[r]);
-    const unsigned f0 = teno_flag(V, tn);
-    const unsigned f1 = teno_flag(V + 1, tn);
+    const unsigned f0 = teno_flag<SEL_FILTER>(V, tn);
+    const unsigned f1 = teno_flag<SEL_FILTER>(V + 1, tn);
     teno_face(V, f0, ol[k]);
     teno_face(V + 1, f1, orr[k]);
     fr[k] = f1;
@@ -816,13 +901,63 @@ TGKS_HD void half_table(R U, R h, R m0, R m1, R* m) {
   for (int k = 1; k + 1 < NM1; ++k) m[k + 1] = U * m[k] + ((double)k * h) * m[k - 1];
 }
 
+// erfc(x) given ex2 = exp(-x^2), which the half-space moments need anyway.
+// With t = |x|: erfc(t) = ex2 f(y) / (1 + 2t), where f(y) = (1 + 2t)
+// exp(t^2) erfc(t) is a smooth function of y = (t - K) / (t + K) on
+// [-1, 1] (K = 3.75; the form of Shepherd and Laframboise, Math. Comp. 36,
+// 1981): its Chebyshev series cut after 23 terms, in powers of y, summed by
+// Horner's rule as even and odd parts in y^2 (two independent chains); the
+// power coefficients are small (sum of magnitudes 1.76), so the power form
+// is as accurate as the series.  erfc(-t) = 2 - erfc(t).  The
+// coefficients are written by paper_2309_10534_amd/erfc_coeffs.py from the
+// definition (mpmath, 40 digits); in this arithmetic f / (1 + 2t) is
+// within 5.6e-16 of exp(t^2) erfc(t) for t in [0, 27] (beyond, ex2
+// underflows).  One reciprocal of (t + K)(1 + 2t) (estimate and two Newton
+// steps, about 1 ulp) serves both divisions.  The operation-counting type
+// counts one erfc.
+constexpr double ERFC_POLY[23] = {
+    1.2375126308378275, -0.14024059858554525, 0.0035854154854790257,
+    0.08227673848999506, -0.10880393014244462, 0.09230432116428125,
+    -0.05869339857664934, 0.028362277372111139, -0.0097465796832652621,
+    0.0017556261651970652, 0.00029371437804495801, -0.00029015535246077655,
+    5.1646529741774162e-05, 2.2387565714911816e-05, -1.1438048033346894e-05,
+    -9.7926257073035231e-07, 1.7419821586224816e-06, -5.0844653786873023e-08,
+    -2.4857126248016745e-07, 1.8790823223700481e-08, 3.1979266716668042e-08,
+    -1.9551358868985616e-09, -2.6231073471334759e-09,
+};
+
+template <class R>
+TGKS_HD R erfc_exp(R x, R ex2) {
+  return erfc(x);
+}
+TGKS_HD double erfc_exp(double x, double ex2) {
+  const double K = 3.75;
+  const double t = fmin(fabs(x), 1e10);  // beyond, ex2 = 0 (x = +-inf: erfc = 0 or 2)
+  const double a = t + K, q = fma(2.0, t, 1.0);
+  const double d = a * q;
+  double r = rcp_approx(d);
+  r = fma(r, fma(-d, r, 1.0), r);
+  r = fma(r, fma(-d, r, 1.0), r);
+  const double y = ((t - K) * q) * r;
+  const double w = a * r;  // 1 / (1 + 2t)
+  const double z = y * y;
+  double ev = ERFC_POLY[22], od = ERFC_POLY[21];
+#pragma unroll
+  for (int j = 20; j >= 0; j -= 2) ev = fma(ev, z, ERFC_POLY[j]);
+#pragma unroll
+  for (int j = 19; j >= 1; j -= 2) od = fma(od, z, ERFC_POLY[j]);
+  const double e = ex2 * (fma(od, y, ev) * w);
+  return x < 0.0 ? 2.0 - e : e;
+}
+
 // first two half-space moments: sgn = +1 (u1 > 0) or -1 (u1 < 0)
 template <class R>
 TGKS_HD void half_seed(R U, R lam, double sgn, R& m0, R& m1) {
   const R isl = rsqrt_(lam);
   const R sl = lam * isl;
-  m0 = 0.5 * erfc(-sgn * (sl * U));
-  m1 = U * m0 + ((sgn * 0.28209479177387814347) * exp(-(lam * U) * U)) * isl;  // 1/(2 sqrt(pi))
+  const R ex = exp(-(lam * U) * U);
+  m0 = 0.5 * erfc_exp(-sgn * (sl * U), ex);
+  m1 = U * m0 + ((sgn * 0.28209479177387814347) * ex) * isl;  // 1/(2 sqrt(pi))
 }
 
 template <int D, class R>

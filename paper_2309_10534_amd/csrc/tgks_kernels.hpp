@@ -248,11 +248,11 @@ __device__ __forceinline__ void face1d_body(const StageArgs& a, int f) {
         Q[r] = EX ? cell_value(a.g, a.pb, a.W, c, f - 3 + r, 0, tb) : load_cell(a.g, a.W, c, f - 3 + r, 0, 0);
       double o[4];
       if (SCHEME == SCHEME_TENO_D) {
-        const unsigned fl = teno_flag(Q, a.tn);
+        const unsigned fl = teno_flag<SEL_FILTER>(Q, a.tn);
         teno_face(Q, fl, o);
         Wl[c] = o[2];
         dWl[0][c] = o[3] * idx;
-        const unsigned fr = teno_flag(Q + 1, a.tn);
+        const unsigned fr = teno_flag<SEL_FILTER>(Q + 1, a.tn);
         teno_face(Q + 1, fr, o);
         Wr[c] = o[0];
         dWr[0][c] = o[1] * idx;
@@ -428,7 +428,7 @@ __device__ __forceinline__ void face2d_tile(const StageArgs& a, int bx, int by, 
         double V[5];
 #pragma unroll
         for (int r = 0; r < 5; ++r) V[r] = char_dot<NC>(Lm[k], sd == 0 ? C[r] : C[r + 1]);
-        const unsigned fl = teno_flag(V, a.tn);
+        const unsigned fl = teno_flag<SEL_FILTER>(V, a.tn);
         double o[4];
         teno_face(V, fl, o);
         if (sd == 0) {
@@ -479,7 +479,7 @@ __device__ __forceinline__ void face2d_tile(const StageArgs& a, int bx, int by, 
       double o[4];
       unsigned fl;
       if (SCHEME == SCHEME_TENO_D) {
-        fl = teno_flag(Q, a.tn);
+        fl = teno_flag<SEL_FILTER>(Q, a.tn);
         teno_face(Q, fl, o);
       } else {
         fl = scheme_face<SCHEME>(Q, a.sc, o);
@@ -570,8 +570,8 @@ __device__ __forceinline__ void face2d_tile(const StageArgs& a, int bx, int by, 
           Qw[r] = char_dot<NC>(Lt[k], xw);
           Qn[r] = char_dot<NC>(Lt[k], xn);
         }
-        const unsigned fw = teno_flag(Qw, a.tt);
-        const unsigned fq = teno_flag(Qn, a.tt);
+        const unsigned fw = teno_flag<SEL_FILTER>(Qw, a.tt);
+        const unsigned fq = teno_flag<SEL_FILTER>(Qn, a.tt);
         if (FLAGS) {
           a.tflags[((long long)(0 * 2 + m) * NC + k) * nf + fidx] = (uint8_t)fw;
           a.tflags[((long long)(1 * 2 + m) * NC + k) * nf + fidx] = (uint8_t)fq;
@@ -621,8 +621,8 @@ __device__ __forceinline__ void face2d_tile(const StageArgs& a, int bx, int by, 
         }
         unsigned fw, fq;
         if (SCHEME == SCHEME_TENO_D) {
-          fw = teno_flag(Qw, a.tt);
-          fq = teno_flag(Qn, a.tt);
+          fw = teno_flag<SEL_FILTER>(Qw, a.tt);
+          fq = teno_flag<SEL_FILTER>(Qn, a.tt);
           teno_gauss(Qw, fw, v, dv);
           teno_gauss(Qn, fq, vn, dvn);
         } else {
@@ -765,7 +765,7 @@ __global__ __launch_bounds__(256) void recon3d_kernel(StageArgs a) {
     const double v = Wc[m * sax];
     Q[s] = cell_flip(g, c, f[0], f[1], f[2]) ? -v : v;
   }
-  const unsigned fl = teno_flag<true>(Q, a.tn);
+  const unsigned fl = teno_flag<SEL_RATIO>(Q, a.tn);
   double o[4];
   teno_face(Q, fl, o);
   const double idn = 1.0 / g.dx[AX];
@@ -882,7 +882,7 @@ __global__ __launch_bounds__(L3 * B3_1 * B3_2, 2) void face3d_kernel(StageArgs a
       Qn[r] = sR[s][c][1][i2][j1 + r];
     }
     double v[2], dv[2], vn[2], dvn[2];
-    const unsigned fw = teno_flag<true>(Qw, a.tt), fq = teno_flag<true>(Qn, a.tt);
+    const unsigned fw = teno_flag<SEL_RATIO>(Qw, a.tt), fq = teno_flag<SEL_RATIO>(Qn, a.tt);
     // the inputs of the second sweep's selections: one fixed evaluation order
     teno_gauss_exact(Qw, fw, v, dv);
     teno_gauss_exact(Qn, fq, vn, dvn);
@@ -931,7 +931,7 @@ __global__ __launch_bounds__(L3 * B3_1 * B3_2, 2) void face3d_kernel(StageArgs a
       double Q[5];
 #pragma unroll
       for (int k = 0; k < 5; ++k) Q[k] = sS[m2][c][j2 + k][j1][2 * kind + m1];
-      const unsigned fl = teno_flag<true>(Q, a.tt);
+      const unsigned fl = teno_flag<SEL_RATIO>(Q, a.tt);
       teno_gauss(Q, fl, v, d);
       if (FLAGS) a.tflags[((long long)4 * NC + ((m1 * 3 + kind) * 2 + m2) * NC + c) * nf + fid] = (uint8_t)fl;
     }

@@ -33,7 +33,7 @@ long long count_normal(const tgks_ctx* c) {
   F Q[5], o[4];
   tgks_opcount::graph().reset();
   for (int r = 0; r < 5; ++r) Q[r] = smooth(0, 0.1 * r, 0.0);
-  const unsigned fl = teno_flag<false>(Q, c->tn);
+  const unsigned fl = teno_flag<SEL_EXACT>(Q, c->tn);
   teno_face(Q, fl, o);
   const F idn(1.0 / c->g.dx[0]);
   F s1 = o[1] * idn, s3 = o[3] * idn;
@@ -64,8 +64,8 @@ long long count_face(const tgks_ctx* c, int stage, tgks_opcount::Tally* detail) 
           Qw[r] = smooth(q < 3 ? q : 4, 0.1 * r, 0.0);
           Qn[r] = F::input(0.01 * r);
         }
-        teno_gauss(Qw, teno_flag<false>(Qw, c->tt), v, dv);
-        teno_gauss(Qn, teno_flag<false>(Qn, c->tt), vn, dvn);
+        teno_gauss(Qw, teno_flag<SEL_EXACT>(Qw, c->tt), v, dv);
+        teno_gauss(Qn, teno_flag<SEL_EXACT>(Qn, c->tt), vn, dvn);
         for (int m = 0; m < 2; ++m) dv[m] = dv[m] * F(1.0 / c->g.dx[1]);
       }
   } else if (D == 3) {
@@ -83,8 +83,8 @@ long long count_face(const tgks_ctx* c, int stage, tgks_opcount::Tally* detail) 
               Qw[r] = smooth(q, 0.1 * r, 0.1 * r2);
               Qn[r] = F::input(0.01 * r);
             }
-            teno_gauss(Qw, teno_flag<false>(Qw, c->tt), v, dv);
-            teno_gauss(Qn, teno_flag<false>(Qn, c->tt), vn, dvn);
+            teno_gauss(Qw, teno_flag<SEL_EXACT>(Qw, c->tt), v, dv);
+            teno_gauss(Qn, teno_flag<SEL_EXACT>(Qn, c->tt), vn, dvn);
             for (int m1 = 0; m1 < 2; ++m1) {
               S1w[m1][r2] = v[m1];
               S1d[m1][r2] = dv[m1] * F(1.0 / c->g.dx[1]);
@@ -100,10 +100,10 @@ long long count_face(const tgks_ctx* c, int stage, tgks_opcount::Tally* detail) 
         }
         for (int m1 = 0; m1 < 2; ++m1) {
           F v[2], dv[2], x[2], dx_[2];
-          teno_gauss(S1w[m1], teno_flag<false>(S1w[m1], c->tt), v, dv);
+          teno_gauss(S1w[m1], teno_flag<SEL_EXACT>(S1w[m1], c->tt), v, dv);
           for (int m2 = 0; m2 < 2; ++m2) dv[m2] = dv[m2] * F(1.0 / c->g.dx[2]);
-          teno_gauss(S1d[m1], teno_flag<false>(S1d[m1], c->tt), x, dx_);
-          teno_gauss(S1n[m1], teno_flag<false>(S1n[m1], c->tt), x, dx_);
+          teno_gauss(S1d[m1], teno_flag<SEL_EXACT>(S1d[m1], c->tt), x, dx_);
+          teno_gauss(S1n[m1], teno_flag<SEL_EXACT>(S1n[m1], c->tt), x, dx_);
         }
       }
   }
@@ -171,8 +171,8 @@ long long count_face_char(const tgks_ctx* c, int stage, tgks_opcount::Tally* det
           Qw[r] = char_dot<NC>(L[k], X[r]);
           Qn[r] = char_dot<NC>(L[k], Xn[r]);
         }
-        teno_gauss(Qw, teno_flag<false>(Qw, c->tt), v, dv);
-        teno_gauss(Qn, teno_flag<false>(Qn, c->tt), vn, dvn);
+        teno_gauss(Qw, teno_flag<SEL_EXACT>(Qw, c->tt), v, dv);
+        teno_gauss(Qn, teno_flag<SEL_EXACT>(Qn, c->tt), vn, dvn);
         for (int q = 0; q < NC; ++q)
           for (int g = 0; g < 2; ++g) {
             aV[q][g] = k == 0 ? R[q][k] * v[g] : aV[q][g] + R[q][k] * v[g];

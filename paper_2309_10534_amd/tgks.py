@@ -83,6 +83,8 @@ def lib():
     L.tgks_gp_flux_host.argtypes = [P, dp, dp, dp, dp, C.c_double, dp]
     L.tgks_teno_flag_host.argtypes = [P, dp, C.c_int32]
     L.tgks_teno_flag_host.restype = C.c_int
+    L.tgks_erfc_host.argtypes = [C.c_double]
+    L.tgks_erfc_host.restype = C.c_double
     L.tgks_step_adjoint.argtypes = [vp, vp, vp, vp, vp, vp]
     L.tgks_step_adjoint.restype = C.c_int
     L.tgks_gp_flux_vjp_host.argtypes = [P, dp, dp, dp, dp, C.c_double, dp, dp]
@@ -305,13 +307,20 @@ def tgks_flop_counts(params):
     return {k: out[i] for i, k in enumerate(keys)}
 
 
-def tgks_teno_flag_host(params, Q, fast=True):
-    """The kernels' TENO-D selection of five host values (verification)."""
+def tgks_teno_flag_host(params, Q, fast=1):
+    """The kernels' TENO-D selection of five host values (verification).
+    fast: 0 exact weights, 1 the 3-D kernels' evaluation, 2 the 1-D/2-D
+    kernels' (a bool selects 0 or 1)."""
     q = (C.c_double * 5)(*[float(v) for v in Q])
-    f = lib().tgks_teno_flag_host(C.byref(params), q, int(bool(fast)))
+    f = lib().tgks_teno_flag_host(C.byref(params), q, int(fast))
     if f < 0:
         raise TgksError("tgks_teno_flag_host: invalid argument")
     return f
+
+
+def tgks_erfc_host(x):
+    """The kernels' erfc (half-space moments) evaluated on the host."""
+    return lib().tgks_erfc_host(float(x))
 
 
 def tgks_measure_peaks(stream=None):
