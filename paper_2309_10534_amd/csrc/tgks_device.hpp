@@ -94,6 +94,21 @@ TGKS_HD double rcp_approx(double x) {
 #endif
 }
 
+// 1/x to about one ulp (not always correctly rounded): the estimate and two
+// Newton steps, each of which squares its relative error; for quantities
+// that feed only the flux.  0 and infinities give NaN (the states they come
+// from are rejected as non-physical).  The operation-counting type counts
+// one division.
+template <class R>
+TGKS_HD R recip(R x) {
+  return R(1.0) / x;
+}
+TGKS_HD double recip(double x) {
+  double r = rcp_approx(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+
 // ---------------------------------------------------------------------------
 // TENO-D selection (Sec. 4.2).  q[0..4] = Q_{-2..2}.
 // flag bit0 = delta_{3,1}; if it is 0, bits 1..3 = delta_{0,2}, delta_{1,2},
@@ -866,7 +881,7 @@ TGKS_HD double opaque(double x) {
   return x;
 }
 
-// (rho, 1/rho, U, lambda, h) of W with one division:
+// (rho, 1/rho, U, lambda, h) of W with one reciprocal:
 // re = rho (rho E) - |rho U|^2 / 2 = rho^2 e_int, inv = 1 / (rho re)
 template <int D, class R>
 TGKS_HD void make_gas(const R* W, double N, Gas<D, R>& g) {
@@ -875,7 +890,7 @@ TGKS_HD void make_gas(const R* W, double N, Gas<D, R>& g) {
 #pragma unroll
   for (int d = 0; d < D; ++d) m2 += W[d + 1] * W[d + 1];
   const R re = g.rho * W[D + 1] - 0.5 * m2;
-  const R inv = R(1.0) / (g.rho * re);
+  const R inv = recip(g.rho * re);
   g.irho = re * inv;
 #pragma unroll
   for (int d = 0; d < D; ++d) g.U[d] = W[d + 1] * g.irho;
@@ -1342,13 +1357,13 @@ TGKS_HD void flux_combine(const R* W0, const Gas<D, R>& g0, const SidePart<D, R>
   const R S = pl + pr, A = fabs(pl - pr);
   R tau = R(0.0), xh = R(0.0);
   if (P.tau_mode == 1) {
-    tau = P.mu / (g0.rho * g0.h) + (P.c2 * (A / S)) * dt;
-    xh = -(0.5 * dt) / tau;
+    tau = P.mu * recip(g0.rho * g0.h) + (P.c2 * (A * recip(S))) * dt;
+    xh = -(0.5 * dt) * recip(tau);
   } else if (P.tau_mode == 0) {
-    // tau = (c1 + c2 A/S) dt = dt T/S with T = c1 S + c2 A; one division
+    // tau = (c1 + c2 A/S) dt = dt T/S with T = c1 S + c2 A; one reciprocal
     const R T = P.c1 * S + P.c2 * A;
     if (T > 0.0) {
-      const R inv = R(1.0) / (S * T);
+      const R inv = recip(S * T);
       tau = dt * ((T * T) * inv);
       xh = -0.5 * ((S * S) * inv);
     }
