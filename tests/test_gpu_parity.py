@@ -152,6 +152,65 @@ def test_cutoff_ties(orc, torch_dev, ct1, ct2):
     compare_step(orc, pr, W, orc.cfl_dt(orc_params(orc, pr), W, 0.5))
 
 
+def margin_stencils(orc, ct1, ct2, rng, segments=12):
+    """Density stencils around 1 on both sides of a cut-off decision of
+    Eqs. 4.5-4.12, at relative distances 1e-15 .. 1e-2 of the boundary
+    along random segments and within a few ulps of it (the boundary found
+    by bisection with the oracle's selection)."""
+    sel = lambda Q: orc.teno_select(Q, ct1=ct1, ct2=ct2, eps=1e-40)
+    out, found = [], 0
+    for _ in range(2000):
+        if found == segments:
+            break
+        A = 1.0 + 0.05 * rng.normal(size=5)
+        B = A.copy()
+        B[rng.integers(0, 5)] += 0.05 * rng.normal()
+        fa = sel(A)
+        if fa == sel(B):
+            continue
+        lo, hi = 0.0, 1.0
+        for _ in range(70):
+            mid = 0.5 * (lo + hi)
+            if mid in (lo, hi):
+                break
+            if sel(A + mid * (B - A)) == fa:
+                lo = mid
+            else:
+                hi = mid
+        found += 1
+        ts = [lo * (1.0 + sg * 10.0 ** -j) for j in (2, 4, 6, 8, 10, 12, 15) for sg in (-1.0, 1.0)]
+        t = lo
+        for _ in range(4):
+            t = np.nextafter(t, -1.0)
+        for _ in range(8):
+            ts.append(t)
+            t = np.nextafter(t, 2.0)
+        out += [A + t * (B - A) for t in ts]
+    assert found == segments
+    return out
+
+
+@pytest.mark.parametrize("ct1,ct2", [(1e-7, 1e-5), (0.2, 0.2)])
+def test_cutoff_margin(orc, torch_dev, ct1, ct2):
+    """The kernels decide a cut-off from approximate reciprocals of the
+    weights where a margin of 2^-12 makes it certain and from the exact
+    weights elsewhere.  Density stencils at relative distances 1e-15 ..
+    1e-2 of a decision boundary (and within ulps of it), each in five cells
+    of a 1-D grid with a constant filler between them, exercise both paths
+    on the device's own reciprocal: every normal flag equals the oracle's
+    bit for bit, and the step agrees to the usual bar."""
+    rng = np.random.default_rng(23 if ct1 < 0.1 else 29)
+    st = margin_stencils(orc, ct1, ct2, rng)
+    n = 10 * len(st)
+    rho = np.ones(n)
+    for k, Q in enumerate(st):
+        rho[10 * k + 2:10 * k + 7] = Q
+    W = I.conservative(rho, [np.zeros(n)], np.ones(n))
+    pr = problem([n], [1.0 / n], ct1=ct1, ct2=ct2)
+    print(f"[parity] cut-off margin ct1={ct1} ct2={ct2} stencils={len(st)}", flush=True)
+    compare_step(orc, pr, W, 0.1 * orc.cfl_dt(orc_params(orc, pr), W, 0.5))
+
+
 def test_step_2d_tau_zero_density_wave(orc, torch_dev):
     W, dx = I.density_wave_2d(20)
     pr = problem([20, 20], [dx, dx], bc="periodic", tau="zero")
