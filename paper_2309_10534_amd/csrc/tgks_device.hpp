@@ -84,13 +84,12 @@ TGKS_HD double rcp_approx(double x) {
 #if defined(__HIP_DEVICE_COMPILE__)
   return __builtin_amdgcn_rcp(x);
 #else
-  union {
-    double d;
-    uint64_t u;
-  } v;
-  v.d = 1.0 / x;
-  v.u &= ~((uint64_t(1) << 29) - 1);
-  return v.d;
+  double r = 1.0 / x;
+  uint64_t u;
+  __builtin_memcpy(&u, &r, sizeof u);
+  u &= ~((uint64_t(1) << 29) - 1);
+  __builtin_memcpy(&r, &u, sizeof r);
+  return r;
 #endif
 }
 
