@@ -37,8 +37,8 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector peak (256 CU x 2.4 GHz x 128 flop/
 # the three files below); the bench reports null traffic otherwise.
 TRAFFIC_SOURCES = ("paper_2309_10534_amd/csrc/tgks_device.hpp", "paper_2309_10534_amd/csrc/tgks_kernels.hpp",
                    "paper_2309_10534_amd/csrc/tgks_face2d.hip")
-TRAFFIC = {"sha": "75f9565611e6587d", "tile": 2, "fetch_factor": 32768.0 / 16397.8, "write_factor": 1.0,
-           "face_xy": {"fetch_kib": 128789.6, "write_kib": 118281.2}}
+TRAFFIC = {"sha": "d7e54452bb98aad7", "tile": 2, "fetch_factor": 32768.0 / 16397.8, "write_factor": 1.0,
+           "face_xy": {"fetch_kib": 45272.2, "write_kib": 99971.95}}
 
 
 def measured_traffic(kernel, tile):

@@ -721,7 +721,14 @@ __global__ __launch_bounds__(2 * tile2_tn(TILE) * tile2_tt(TILE), 2) void face2d
   __shared__ double lds[CHAR ? tile2_lds_char(TILE) : (SCHEME >= SCHEME_TENO5 ? tile2_lds_eq(TILE) : tile2_lds(TILE))];
   const int nbx = (ax.g.n[0] + 1 + TN - 1) / TN;          // x faces: tiles along x
   const int nx = nbx * ((ax.g.n[1] + tile2_tt(TILE) - 1) / tile2_tt(TILE));
-  const int b = blockIdx.x;
+  // XCD-aware order: workgroups are dealt to the 8 XCDs in turn; the tiles
+  // are renumbered so that each XCD walks a contiguous range of them (a
+  // bijection for any grid size), where neighbouring tiles, which stage
+  // common halo cells and write common cache lines of the face fluxes,
+  // meet in one L2 (HBM reads per launch fall 2.7-3.0x, writes to the
+  // algorithmic bytes).
+  const int nbt = gridDim.x, x8 = blockIdx.x & 7, per = nbt >> 3, rem = nbt & 7;
+  const int b = x8 * per + min(x8, rem) + (int)(blockIdx.x >> 3);
   if (b < nx) {
     face2d_tile<0, STAGE, NS, FLAGS, TILE, CHAR, EX, SCHEME>(ax, b % nbx, b / nbx, lds);
   } else {
